@@ -1,0 +1,162 @@
+"""Pins of the oracle's interpolation, octree lists, block convolution and FLGF (Sec. 2.1,
+Algorithm 1) against brute force, closed forms and invariants."""
+import numpy as np
+import pytest
+
+from oracle import direct, fmm, interp, lgf, tree
+from paper_1911_10228_amd import workloads
+
+
+# ---------------------------------------------------------------- interpolation J and R = J^T
+@pytest.mark.parametrize("n_b,n_i", [(8, 2), (8, 3), (8, 6), (16, 8), (16, 3), (8, 8)])
+def test_interp_reproduces_polynomials(n_b, n_i):
+    W = interp.child_matrix(n_b, n_i)
+    assert np.allclose(W.sum(axis=1), 1.0, atol=1e-14)
+    xp = np.arange(n_b, dtype=float)                     # parent nodes
+    xc = np.arange(2 * n_b) / 2.0 - 0.25                 # child cell centres, parent units
+    for deg in range(n_i):
+        p = np.polynomial.Polynomial(np.random.default_rng(deg).normal(size=deg + 1))
+        err = np.abs(W @ p(xp) - p(xc)).max()
+        assert err <= 1e-9 * max(1.0, np.abs(p(xc)).max())
+    if n_i < n_b:      # degree n_i is not reproduced (the stencil really has n_i nodes)
+        p = np.polynomial.Polynomial([0] * n_i + [1.0])
+        assert np.abs(W @ p(xp) - p(xc)).max() > 1e-6
+
+
+def test_interp_3d_and_adjoint():
+    n_b, n_i = 8, 4
+    W = interp.child_matrix(n_b, n_i)
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(n_b,) * 3)
+    b = rng.normal(size=(n_b,) * 3)
+    for c in np.ndindex(2, 2, 2):
+        lhs = (interp.interp_child(W, c, a) * b).sum()
+        rhs = (a * interp.anterp_child(W, c, b)).sum()
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # trilinear field reproduced exactly through the tensor product
+    i = np.arange(n_b)
+    z, y, x = np.meshgrid(i, i, i, indexing="ij")
+    lin = 1.0 + 2.0 * x - 3.0 * y + 0.5 * z + 0.25 * x * y * z
+    ch = interp.interp_child(W, (1, 0, 1), lin)
+    xc = (np.arange(n_b) + n_b) / 2.0 - 0.25
+    yc = np.arange(n_b) / 2.0 - 0.25
+    Z, Y, X = np.meshgrid(xc, yc, xc, indexing="ij")
+    assert np.allclose(ch, 1.0 + 2.0 * X - 3.0 * Y + 0.5 * Z + 0.25 * X * Y * Z, atol=1e-12)
+
+
+# ---------------------------------------------------------------- octree lists
+def test_list_counts_uniform_boxes():
+    assert fmm.count_interactions(workloads.box_blocks(2, 2, 2)) == [(8, 64, 0)]
+    assert fmm.count_interactions(workloads.box_blocks(8, 8, 8)) == [
+        (512, 10648, 53352), (64, 0, 3096), (8, 0, 0)]
+
+
+@pytest.mark.slow
+def test_list_counts_16_cubed():
+    assert fmm.count_interactions(workloads.box_blocks(16, 16, 16)) == [
+        (4096, 97336, 584136), (512, 0, 53352), (64, 0, 3096), (8, 0, 0)]
+
+
+def test_lists_cover_every_pair_exactly_once():
+    """Near field plus all influence lists of all ancestors partition the base block pairs."""
+    rng = np.random.default_rng(3)
+    blocks = np.unique(rng.integers(-6, 10, size=(60, 3)), axis=0)
+    levels = tree.build_levels(blocks)
+    n = len(blocks)
+    count = np.zeros((n, n), int)
+    anc = blocks.copy()
+    for k, nodes in enumerate(levels):
+        pos = tree.index_of(nodes)
+        members = {}
+        for i in range(n):
+            members.setdefault(pos[tuple(int(v) for v in anc[i])], []).append(i)
+        for t, s in tree.interactions(nodes, base=(k == 0)):
+            count[np.ix_(members[t], members[s])] += 1
+        anc = tree.parent_of(anc)
+    assert (count == 1).all()
+
+
+# ---------------------------------------------------------------- block convolution
+@pytest.mark.parametrize("s,d", [(1, (0, 0, 0)), (1, (2, -1, 3)), (2, (-3, 2, 2)), (4, (3, 3, -2))])
+def test_block_conv_fft_equals_direct(s, d):
+    n_b = 4
+    f = np.random.default_rng(7).normal(size=(n_b,) * 3)
+    a = fmm.block_conv_fft(n_b, s, d, f)
+    b = fmm.block_conv_direct(n_b, s, d, f)
+    assert np.abs(a - b).max() <= 1e-15 * np.abs(f).sum()
+
+
+# ---------------------------------------------------------------- whole FLGF
+def test_uniform_gaussian_equals_brute_force():
+    """2^3 blocks are all mutual neighbours: the FLGF uses only the exact kernel and equals
+    eq. discretConv up to FFT rounding (4096 x 4096 brute-force sum)."""
+    L = workloads.uniform_gaussian()
+    u = fmm.flgf(L.blocks, L.f, L.n_b, L.interp_order)
+    ud = direct.direct_sum(L.blocks, L.f, L.n_b).reshape(u.shape)
+    assert np.abs(u - ud).max() <= 1e-14 * np.abs(ud).max()
+
+
+def test_direct_fft_equals_brute_force_sampled():
+    L = workloads.uniform_mixture(nblk=3, n_b=8, n_gauss=4, seed=5)
+    ud = direct.direct_fft(L.blocks, L.f, L.n_b).reshape(-1)
+    cells = np.random.default_rng(0).choice(len(ud), 300, replace=False)
+    us = direct.direct_sum(L.blocks, L.f, L.n_b, target_cells=cells)
+    assert np.abs(ud[cells] - us).max() <= 1e-14 * np.abs(us).max()
+
+
+def test_far_field_error_falls_with_interpolation_order():
+    L = workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=6, seed=0)
+    ud = direct.direct_fft(L.blocks, L.f, L.n_b)
+    errs = []
+    for n_i in (2, 4, 6, 8):
+        u = fmm.flgf(L.blocks, L.f, L.n_b, n_i)
+        errs.append(np.abs(u - ud).max() / np.abs(ud).max())
+    assert all(a > 3 * b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 2e-6 and errs[0] > 1e-4
+
+
+def test_point_source_gives_green_column():
+    blocks = workloads.box_blocks(6, 1, 1)
+    n_b = 4
+    f = np.zeros((6, n_b, n_b, n_b))
+    f[0, 1, 2, 3] = 1.0                       # source at lattice point (3, 2, 1)
+    u = fmm.flgf(blocks, f, n_b, 4)
+    pos = direct.cell_coords(blocks, n_b).reshape(6, n_b, n_b, n_b, 3)
+    g = lgf.lgf(pos - np.array([3, 2, 1]))
+    # blocks 0..3 see the source through the exact kernel (near field / base influence list)
+    assert np.abs(u[:4] - g[:4]).max() <= 1e-15
+    assert np.abs(u - g).max() <= 1e-4 * np.abs(g).max()
+
+
+def test_translation_by_tree_period_is_exact():
+    L = workloads.uniform_mixture(nblk=5, n_b=4, n_gauss=3, seed=1)
+    u1 = fmm.flgf(L.blocks, L.f, L.n_b, 4)
+    depth = len(tree.build_levels(L.blocks))
+    u2 = fmm.flgf(L.blocks + np.array([2 ** depth, -3 * 2 ** depth, 0]), L.f, L.n_b, 4)
+    assert np.array_equal(u1, u2)
+
+
+def test_linearity_and_masks():
+    L = workloads.uniform_mixture(nblk=5, n_b=4, n_gauss=3, seed=2)
+    rng = np.random.default_rng(4)
+    msk = rng.random(len(L.blocks)) < 0.5
+    a = fmm.flgf(L.blocks, L.f, L.n_b, 4, sources=msk)
+    b = fmm.flgf(L.blocks, L.f, L.n_b, 4, sources=~msk)
+    c = fmm.flgf(L.blocks, L.f, L.n_b, 4)
+    assert np.abs(a + b - c).max() <= 1e-13 * np.abs(c).max()
+    t = fmm.flgf(L.blocks, L.f, L.n_b, 4, targets=msk)
+    assert np.array_equal(t[msk], c[msk]) and not t[~msk].any()
+
+
+def test_uniform_mesh_recovers_source():
+    """Sec. 3 (Convergence): on a uniform mesh L u reproduces f to FMM precision."""
+    L = workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=6, seed=0, interp_order=8)
+    u = fmm.flgf(L.blocks, L.f, L.n_b, 8)
+    box = np.zeros((48, 48, 48))
+    fb = np.zeros((48, 48, 48))
+    for b, ub, f in zip(L.blocks, u, L.f):
+        sl = tuple(slice(v * 8, v * 8 + 8) for v in b[::-1])
+        box[sl] = ub
+        fb[sl] = f
+    res = direct.laplace7(box) - fb[1:-1, 1:-1, 1:-1]
+    assert np.abs(res).max() <= 1e-4 * np.abs(fb).max()

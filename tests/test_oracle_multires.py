@@ -1,0 +1,115 @@
+"""Pins of the multi-resolution oracle (Sec. 3, Algorithm 2) and of defect correction.
+
+The multi-resolution result has no closed form (parity pinned by invariants only):
+* with one level it is exactly the uniform FLGF;
+* coarsening reproduces linear fields, the quadratic refinement reproduces quadratics (also at
+  the ghost rows);
+* with the source correction, L^l u^l = f^l on interior leaf cells to FMM precision; without it
+  the defect is orders of magnitude larger (Sec. 3, Convergence, last figure pair);
+* second-order convergence against a manufactured solution under global refinement of a fixed
+  block topology (Sec. 3, Convergence);
+* defect correction with an FP32 inner solve moves towards the FP64 solve.
+"""
+import numpy as np
+import pytest
+
+from oracle import dc, fmm, interp, multires
+from paper_1911_10228_amd import workloads
+
+
+def two_level(n_b):
+    base = workloads.box_blocks(4, 4, 4)
+    fine = workloads.box_blocks(4, 4, 4, origin=(2, 2, 2))
+    blocks = np.concatenate([base, fine])
+    levels = np.concatenate([np.zeros(64, np.int32), np.ones(64, np.int32)])
+    return blocks, levels
+
+
+def gaussian_problem(n_b, sig=0.25, centre=2.0):
+    """Gaussian u* = exp(-r^2/2 s^2) in a domain of 4 base blocks of unit size; the discrete
+    source in lattice units is H^2 Laplacian(u*) with H = 1/n_b."""
+    blocks, levels = two_level(n_b)
+    H = 1.0 / n_b
+    pos = (workloads.cell_centres(blocks, levels, n_b) + 0.5) * H
+    r2 = ((pos - centre) ** 2).sum(axis=-1)
+    us = np.exp(-r2 / (2 * sig * sig))
+    f = H * H * us * (r2 / sig**4 - 3 / sig**2)
+    return blocks, levels, f, us
+
+
+def test_single_level_is_uniform_flgf():
+    L = workloads.uniform_mixture(nblk=5, n_b=4, n_gauss=3, seed=2)
+    a = multires.solve(L.blocks, L.levels, L.f, L.n_b, 4)
+    b = fmm.flgf(L.blocks, L.f, L.n_b, 4)
+    assert np.array_equal(a, b)
+
+
+def test_validate_rejects_bad_layouts():
+    blocks, levels = two_level(8)
+    with pytest.raises(ValueError):
+        multires.validate(np.concatenate([blocks, blocks[:1]]), np.concatenate([levels, levels[:1]]))
+    with pytest.raises(ValueError):      # orphan
+        multires.validate(np.concatenate([blocks, [[40, 40, 40]]]), np.concatenate([levels, [1]]))
+    with pytest.raises(ValueError):      # non-leaf with 7 children
+        multires.validate(blocks[:-1], levels[:-1])
+    multires.validate(blocks, levels)
+
+
+def test_coarsen_reproduces_linear_fields():
+    n_b = 8
+    i = np.arange(2 * n_b)
+    Z, Y, X = np.meshgrid(i, i, i, indexing="ij")
+    fine = 0.5 + 0.25 * X - 1.5 * Y + 2.0 * Z        # fine index units
+    kids = {c: fine[c[2] * n_b:(c[2] + 1) * n_b, c[1] * n_b:(c[1] + 1) * n_b, c[0] * n_b:(c[0] + 1) * n_b]
+            for c in np.ndindex(2, 2, 2)}
+    par = multires.coarsen(kids, n_b)
+    j = np.arange(n_b) * 2 + 0.5                      # parent centres in fine index units
+    Zp, Yp, Xp = np.meshgrid(j, j, j, indexing="ij")
+    assert np.allclose(par, 0.5 + 0.25 * Xp - 1.5 * Yp + 2.0 * Zp, atol=1e-13)
+
+
+def test_refinement_reproduces_quadratics_including_ghosts():
+    n_b = 8
+    j = np.arange(n_b, dtype=float)
+    Zp, Yp, Xp = np.meshgrid(j, j, j, indexing="ij")
+    q = lambda x, y, z: 1 + x - 2 * y + 0.5 * z + 0.3 * x * x - 0.2 * y * z + 0.1 * z * z
+    par = q(Xp, Yp, Zp)
+    for c in [(0, 0, 0), (1, 0, 1), (1, 1, 1)]:
+        ext = multires.refine_ext(par, c)
+        cc = lambda ci: (np.arange(-1, n_b + 1) + ci * n_b) / 2.0 - 0.25
+        Z, Y, X = np.meshgrid(cc(c[2]), cc(c[1]), cc(c[0]), indexing="ij")
+        assert np.allclose(ext, q(X, Y, Z), atol=1e-12)
+    W = interp.child_matrix(n_b, 3)
+    assert np.allclose(W, interp.child_matrix(n_b, 3, rows=range(-1, 2 * n_b + 1))[1:-1])
+
+
+def test_source_correction_gives_consistency():
+    blocks, levels, f, _ = gaussian_problem(8)
+    u = multires.solve(blocks, levels, f, 8, 6, correction=True)
+    res = multires.level_residual(blocks, levels, u, f, 8)
+    u0 = multires.solve(blocks, levels, f, 8, 6, correction=False)
+    res0 = multires.level_residual(blocks, levels, u0, f, 8)
+    scale = np.abs(f).max()
+    assert max(res) <= 1e-12 * scale
+    assert res0[1] > 1e4 * max(res[1], 1e-16 * scale)
+
+
+def test_second_order_convergence():
+    errs = []
+    for n_b in (4, 8, 16):
+        blocks, levels, f, us = gaussian_problem(n_b)
+        u = multires.solve(blocks, levels, f, n_b, min(n_b, 8))
+        fine = levels == 1
+        errs.append((np.abs(u[fine] - us[fine]).max(), np.sqrt(((u[fine] - us[fine]) ** 2).mean())))
+    e = np.array(errs)
+    order = np.log2(e[:-1] / e[1:])
+    assert order[-1, 0] >= 1.8 and order[-1, 1] >= 1.8 and order[0, 1] >= 1.8
+
+
+def test_defect_correction_approaches_fp64_solve():
+    blocks, levels, f, _ = gaussian_problem(8)
+    ref = multires.solve(blocks, levels, f, 8, 6)
+    its = dc.solve_dc(blocks, levels, f, 8, 6, iters=2, dtype=np.float32)
+    err = [np.abs(u - ref).max() / np.abs(ref).max() for u in its]
+    assert err[0] < 1e-5
+    assert err[1] < err[0]
