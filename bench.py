@@ -1,0 +1,182 @@
+"""Benchmark: grid points/s per Poisson solve on one MI355X.
+
+Workload (the uniform benchmark configuration): 8x8x8 blocks of 16^3 cells (2,097,152 unknowns),
+source = 16 seeded Gaussians (centres uniform in the inner half, widths U[1.5, 4] cells,
+amplitudes N(0, 1)), Lagrange order 8.  One step = one complete solve (all FMM levels, both
+FFT directions, the spectral MAC, anterpolation/interpolation and, for the FP32 form, the FP64
+residual + FP32 re-solve + FP64 update of defect correction) with f and u resident in HBM.
+
+Headline value: FP32 FFT/MAC on the base octree level (FP64 on the coarse far-field levels)
+with one FP64 defect-correction iteration.  The FP64 plain solve of the same plan shape is timed
+beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def spectrum_size(n_b):
+    P = 2 * n_b
+    return P * P * (n_b + 1)
+
+
+def algorithmic(entry, n_b):
+    """(amount, unit, bound) per launch-summed entry: flops for the MAC, HBM bytes otherwise."""
+    es = 4 if entry["precision"] == "fp32" else 8
+    S = spectrum_size(n_b)
+    N3 = n_b ** 3
+    k = entry["kernel"]
+    if k == "mac":
+        return 8.0 * S * entry["work"], "flop", "alu"
+    if k == "fft_fwd":
+        return float(entry["work"]) * (N3 * es + 2 * S * es), "byte", "hbm"
+    if k == "fft_inv":
+        return float(entry["work"]) * (2 * S * es + N3 * es), "byte", "hbm"
+    return None, None, None
+
+
+def time_solves(plan, f, u, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.solve(f, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(f, u)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(n_b=16, nblk=8, order=8):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same workload recipe."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fmm
+    from paper_1911_10228_amd import workloads
+    L = workloads.uniform_mixture(nblk=nblk, n_b=n_b, n_gauss=16, seed=2, interp_order=order)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fmm.flgf(L.blocks, L.f, L.n_b, order)
+        dt = time.perf_counter() - t0
+    return {"value": L.unknowns / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 oracle solve of {nblk}^3 blocks of {n_b}^3 ({L.unknowns} unknowns, "
+                      f"same recipe, order {order}) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dc", type=int, default=1, help="defect-correction iterations of the FP32 form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_10228_amd import lgf, workloads
+
+    torch.cuda.set_device(0)
+    L = workloads.uniform_mixture(nblk=8, n_b=16, n_gauss=16, seed=2, interp_order=8)
+    f = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
+    u32 = torch.zeros_like(f)
+    u64 = torch.zeros_like(f)
+    u0 = torch.zeros_like(f)
+    p32 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, args.dc)
+    p64 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP64_PLAIN, 0)
+    p0 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, 0)
+    info = p32.info()
+    print(f"# plan: {info}", file=sys.stderr, flush=True)
+
+    # headline: FP32 + DC, kernels timed with HIP events during the timed region
+    for _ in range(args.warmup):
+        p32.solve(f, u32)
+    torch.cuda.synchronize()
+    lgf.profile_read()
+    lgf.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p32.solve(f, u32)
+    torch.cuda.synchronize()
+    dt32 = (time.perf_counter() - t0) / args.steps
+    lgf.profile(False)
+    prof = lgf.profile_read()
+    print(f"# fp32+dc{args.dc}: {dt32 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
+
+    dt64 = time_solves(p64, f, u64, args.steps, args.warmup, torch)
+    print(f"# fp64 plain: {dt64 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
+    dt0 = time_solves(p0, f, u0, args.steps, args.warmup, torch)
+    print(f"# fp32 no dc: {dt0 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
+
+    a32, a64, a0 = u32.cpu().numpy(), u64.cpu().numpy(), u0.cpu().numpy()
+    err32 = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+    err0 = float(np.abs(a0 - a64).max() / np.abs(a64).max())
+
+    # dominant kernel of the headline form
+    kern = []
+    for e in prof:
+        amt, unit, bound = algorithmic(e, L.n_b)
+        e = dict(e, avg_us=1e3 * e["ms"] / max(e["launches"], 1))
+        if amt is not None:
+            rate = amt / (e["ms"] * 1e-3)
+            e.update(algorithmic=amt / e["launches"], unit=unit, bound=bound,
+                     rate=rate / (1e12 if unit == "flop" else 1e9))
+        kern.append(e)
+    kern.sort(key=lambda e: -e["ms"])
+    dom = kern[0]
+    if dom.get("unit") == "flop":
+        peak = PEAK["fp32_vector_tflops"] if dom["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
+        roof = {"bound": "alu", "achieved": round(dom["rate"], 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(dom["rate"] / peak, 4), "traffic": None,
+                "kernel": f"spectral MAC ({dom['precision']}, n_b={dom['n_b']})",
+                "avg_launch_us": round(dom["avg_us"], 2)}
+    elif dom.get("unit") == "byte":
+        roof = {"bound": "hbm", "achieved": round(dom["rate"], 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                "frac": round(dom["rate"] / PEAK["hbm_gbs"], 4), "traffic": None,
+                "kernel": f"{dom['kernel']} ({dom['precision']}, n_b={dom['n_b']})",
+                "avg_launch_us": round(dom["avg_us"], 2)}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": None,
+                "traffic": None, "kernel": dom["kernel"]}
+
+    out = {
+        "metric": "grid points/s per Poisson solve (FP32+refine; FP64 plain beside it)",
+        "value": L.unknowns / dt32,
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "uniform 8x8x8 blocks of 16^3 (2,097,152 unknowns), 16 seeded "
+                               "Gaussians, Lagrange order 8",
+                   "precision": f"FP32 base-level FFT/MAC, FP64 far field, {args.dc} FP64 DC iteration(s)"},
+        "roofline": roof,
+        "fp64_plain": {"value": L.unknowns / dt64, "ms_per_step": dt64 * 1e3},
+        "fp32_no_dc": {"value": L.unknowns / dt0, "ms_per_step": dt0 * 1e3, "err_vs_fp64": err0},
+        "err_vs_fp64": err32,
+        "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()} for e in kern],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

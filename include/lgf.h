@@ -1,0 +1,150 @@
+/*
+ * C ABI of the MI355X lattice Green's function solver.
+ *
+ * Problem (Dorschner, Yu, Mengaldo & Colonius, "A fast multi-resolution lattice Green's function
+ * method for elliptic difference equations", Sec. 2, discrete Poisson equation and
+ * eq. discretConv): L u = f on the unbounded cell-centred lattice, L the 7-point Laplacian
+ * (sum of the 6 neighbours - 6 u), supp f a union of Cartesian blocks.  On one uniform level the
+ * result is u(n) = sum_m G(n - m) f(m) with the lattice Green's function G, evaluated by the fast
+ * lattice Green's function method (Sec. 2.1, Algorithm 1: octree of blocks, Lagrange
+ * anterpolation/interpolation, zero-padded block FFT convolutions against LGF spectra).  With
+ * refinement levels (Sec. 3, Algorithm 2) each level l has spacing h_l = 2^-l, operator
+ * L^l = h_l^-2 (7-point) and kernel h_l^2 G; sources are coarsened onto non-leaf blocks, each
+ * level is solved in order with the source correction, and coarse fields are interpolated to
+ * the next level.
+ *
+ * Conventions
+ *  - blocks[i] = (bx, by, bz) in units of N_b cells of level levels[i]; cell (x, y, z) of block i
+ *    is the level lattice point b N_b + (x, y, z).  A level-(l+1) block's parent is floor(b / 2)
+ *    at level l.  Every level-l block with children must have all 8 of them.
+ *  - Field arrays f and u are device pointers to [n][N_b][N_b][N_b] doubles, x fastest, in the
+ *    order of `blocks`.  f on non-leaf blocks is ignored (recomputed by coarsening);
+ *    u on a non-leaf block receives that level's total field.
+ *  - Ownership: the caller owns f and u (device memory, e.g. torch tensors).  The plan owns all
+ *    internal device buffers; the LGF table and kernel spectra are process-wide and shared.
+ *  - Errors are returned as lgf_status; nothing throws across the ABI.  HIP launch errors give
+ *    LGF_EHIP; asynchronous faults surface at the caller's next synchronisation.
+ *  - Solves are asynchronous on the given stream.  A plan's workspace is used by one solve at a
+ *    time: solves of one plan on different streams must be serialised by the caller.
+ */
+#ifndef LGF_H_
+#define LGF_H_
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lgf_plan_s* lgf_plan_t;
+typedef struct lgf_server_s* lgf_server_t;
+typedef void* lgf_stream_t;   /* a hipStream_t; NULL = the default stream */
+
+typedef enum {
+  LGF_OK = 0,
+  LGF_EINVAL = -1,    /* bad argument (null pointer, size, option) */
+  LGF_ELAYOUT = -2,   /* invalid block layout (duplicate, orphan, incomplete children, N_b) */
+  LGF_ENOMEM = -3,    /* device allocation failed or HBM budget exceeded */
+  LGF_EHIP = -4,      /* HIP runtime or launch error */
+  LGF_EBUSY = -5      /* server: request not admitted yet / still running */
+} lgf_status;
+
+typedef enum {
+  LGF_FP64_PLAIN = 0,   /* FFTs, spectral MAC and operators in FP64 */
+  LGF_FP32_REFINE = 1   /* FP32 FFTs/MAC/operators; FP64 residual r = f - L u and update,
+                           repeated dc_iters times (defect correction) */
+} lgf_precision;
+
+typedef struct {
+  int32_t precision;     /* lgf_precision */
+  int32_t dc_iters;      /* defect-correction iterations for LGF_FP32_REFINE (0..8) */
+  int32_t autotune;      /* reserved for launch-shape selection; 0 = defaults */
+  int32_t reserved;
+  uint64_t hbm_budget;   /* bytes the plan may allocate; 0 = unlimited */
+} lgf_options;
+
+typedef struct {
+  int64_t blocks;             /* blocks in the layout */
+  int64_t unknowns;           /* blocks * N_b^3 */
+  int32_t refinement_levels;
+  int32_t max_octree_levels;
+  int64_t interactions;       /* (target, source) block pairs over all FMM levels and channels */
+  int64_t fft_forward;        /* forward block FFTs per solve pass */
+  int64_t fft_inverse;        /* inverse block FFTs per solve pass */
+  int64_t mac_rows;
+  int64_t workspace_bytes;    /* device bytes owned by the plan */
+  int64_t spectra;            /* distinct kernel spectra referenced */
+} lgf_plan_info;
+
+/* Builds the FP64 LGF table on the current device (Sec. 2: quadrature of eq. GL_B for
+ * |n| <= 100).  Called implicitly by lgf_plan; idempotent. */
+lgf_status lgf_init(void);
+
+/* Plans a solve for the block layout.  N_b in {8, 16}; interp_order = n_I Lagrange nodes of the
+ * FMM interpolation (Sec. 2.1, n_I <= 10 in the paper), 2 <= n_I <= N_b.  opt may be NULL
+ * (FP64 plain).  Copies what it needs from the host arrays; builds kernel spectra on first use. */
+lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int32_t N_b,
+                    int32_t interp_order, const lgf_options* opt, lgf_plan_t* out);
+
+/* u = solution for source f (device pointers, layout above); asynchronous on stream. */
+lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream);
+
+/* n independent solves advanced together: every phase of all plans runs in shared launches.
+ * Plans must be distinct.  Results equal n separate lgf_solve calls. */
+lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* const* u, int32_t n,
+                           lgf_stream_t stream);
+
+lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out);
+lgf_status lgf_plan_destroy(lgf_plan_t p);
+const char* lgf_status_string(lgf_status s);
+
+/* Diagnostics used by the tests.
+ * lgf_green_eval: out[i] = G(n[i]) with the paper's policy (table / A_G^3 / A_G^2); n is a device
+ *   array [m][3] of int32, out a device array [m] of doubles.
+ * lgf_green_table: copies the dense table cube [101][101][101] (entries for sorted
+ *   a >= b >= c with a^2+b^2+c^2 <= 100^2 are valid) to the device array out.
+ * lgf_kernel_spectrum: FP64 half spectrum [2N_b][2N_b][N_b+1] (kx fastest) of the zero-padded
+ *   kernel block G(s (d N_b + r)) to the device array out (complex as interleaved doubles). */
+lgf_status lgf_green_eval(const int32_t* n, int64_t m, double* out, lgf_stream_t stream);
+lgf_status lgf_green_table(double* out, lgf_stream_t stream);
+lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, int32_t dz,
+                               double* out, lgf_stream_t stream);
+
+/* Launch timing (diagnostics for benchmarks).  lgf_profile(1) brackets every subsequent
+ * kernel launch with HIP events on its stream; lgf_profile_read synchronises on them and returns
+ * one entry per (kernel kind, element type, N_b) with the launch count, the summed elapsed time
+ * and the summed work (spectral MAC: block interactions), then clears the record.
+ * Kinds: 0 coarsen, 1 convert, 2 refine, 3 correct, 4 anterpolate, 5 forward FFT, 6 spectral MAC,
+ * 7 inverse FFT, 8 interpolate, 9 combine, 10 residual.  precision: 0 FP32, 1 FP64,
+ * 2 FP32 child level / FP64 parent level. */
+typedef struct {
+  int32_t kind;
+  int32_t precision;
+  int32_t n_b;
+  int32_t reserved;
+  int64_t launches;
+  double ms;
+  int64_t work;
+} lgf_profile_entry;
+lgf_status lgf_profile(int32_t enable);
+lgf_status lgf_profile_read(lgf_profile_entry* out, int32_t cap, int32_t* n);
+
+/* Serving: continuous batching of solve requests under an HBM budget.
+ * submit enqueues (plan, f, u); requests are admitted while the plans' workspace fits the budget
+ * and advanced one refinement-level phase per step, all admitted requests sharing launches.
+ * A background thread steps the server; poll reports completion (1) or not (0).
+ * Latency = completion - submission, reported as p50/p99 over completed requests. */
+lgf_status lgf_server_create(uint64_t hbm_budget, lgf_stream_t stream, lgf_server_t* out);
+lgf_status lgf_server_submit(lgf_server_t s, lgf_plan_t p, const double* f, double* u, int64_t* req_id);
+lgf_status lgf_server_poll(lgf_server_t s, int64_t req_id, int32_t* done);
+lgf_status lgf_server_wait_all(lgf_server_t s);
+lgf_status lgf_server_stats(lgf_server_t s, double* p50_us, double* p99_us, double* points_per_s,
+                            int64_t* completed);
+lgf_status lgf_server_destroy(lgf_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGF_H_ */

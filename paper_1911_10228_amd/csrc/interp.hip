@@ -1,0 +1,339 @@
+// Block-local operators of the FLGF and of the block-refined scheme:
+//   * anterpolation R = J^T (upward pass) and interpolation J (downward pass) with Lagrange
+//     weights on the block grid (Sec. 2.1, Algorithm 1, steps 1 and 3), separable, staged in LDS;
+//   * coarsening C: average of the 2x2x2 child cells (Sec. 3, regularization);
+//   * quadratic refinement J^l of the parent's leaf-only field onto a child block and the source
+//     correction g = f - L^l(J^l w^l) (Sec. 3, Algorithm 2, step 2b, reading: the operator acts
+//     on the interpolated field); neighbour values come from the adjacent same-level block, or,
+//     where there is none, from the parent's quadratic extended one child cell outward;
+//   * FP64 residual r = f - L^l u of defect correction and the update u += e.
+// The 1-D weight tables are computed on the host in FP64.
+#include "kernels.hpp"
+
+namespace lgf {
+
+namespace {
+
+constexpr int kOpThreads = 256;
+
+
+// child += (Wz (x) Wy (x) Wx) parent for octant c; W is [2 NB][NB] row-major (FP64).
+// Arithmetic in the parent's type TP, stored in the child's type TC.
+template <int NB, typename TC, typename TP>
+__global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
+  using T = TP;
+  constexpr int N3 = NB * NB * NB;
+  __shared__ T b0[N3];
+  __shared__ T b1[N3];
+  __shared__ T w[3][NB][NB];
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const InterpItem<TC, TP>& it = ((const InterpItem<TC, TP>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double* __restrict__ W = ws.w;
+  const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) b0[i] = it.parent[i];
+  for (int i = threadIdx.x; i < 3 * NB * NB; i += kOpThreads) {
+    const int d = i / (NB * NB), r = (i / NB) % NB, m = i % NB;
+    w[d][r][m] = T(W[(c[d] * NB + r) * NB + m]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {       // x
+    const int X = i % NB, yz = i / NB;
+    T s = 0;
+#pragma unroll
+    for (int x = 0; x < NB; ++x) s += w[0][X][x] * b0[yz * NB + x];
+    b1[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {       // y
+    const int X = i % NB, Y = (i / NB) % NB, z = i / (NB * NB);
+    T s = 0;
+#pragma unroll
+    for (int y = 0; y < NB; ++y) s += w[1][Y][y] * b1[(z * NB + y) * NB + X];
+    b0[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {       // z
+    const int XY = i % (NB * NB), Z = i / (NB * NB);
+    T s = 0;
+#pragma unroll
+    for (int z = 0; z < NB; ++z) s += w[2][Z][z] * b0[z * NB * NB + XY];
+    it.child[i] = TC(it.accumulate ? T(it.child[i]) + s : s);
+  }
+}
+
+// parent = sum_c (Wz (x) Wy (x) Wx)^T child_c, arithmetic in the parent's type TP
+template <int NB, typename TC, typename TP>
+__global__ __launch_bounds__(kOpThreads) void anterp_kernel(SetTable sets) {
+  using T = TP;
+  constexpr int N3 = NB * NB * NB;
+  constexpr int PER = N3 / kOpThreads;
+  __shared__ T b0[N3];
+  __shared__ T b1[N3];
+  __shared__ T w[2][NB][NB];      // W rows of octant 0 and 1: w[c][r][m] = W[(c NB + r)][m]
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const AnterpItem<TC, TP>& it = ((const AnterpItem<TC, TP>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double* __restrict__ W = ws.w;
+  for (int i = threadIdx.x; i < 2 * NB * NB; i += kOpThreads) {
+    const int cc = i / (NB * NB), r = (i / NB) % NB, m = i % NB;
+    w[cc][r][m] = T(W[(cc * NB + r) * NB + m]);
+  }
+  T acc[PER > 0 ? PER : 1];
+#pragma unroll
+  for (int j = 0; j < (PER > 0 ? PER : 1); ++j) acc[j] = T(0);
+  for (int oc = 0; oc < 8; ++oc) {
+    const TC* ch = it.child[oc];
+    if (!ch) continue;
+    const int cx = oc & 1, cy = (oc >> 1) & 1, cz = (oc >> 2) & 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < N3; i += kOpThreads) b0[i] = T(ch[i]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < N3; i += kOpThreads) {     // x: t1[Z][Y][x] = sum_X W[X][x] c[Z][Y][X]
+      const int x = i % NB, YZ = i / NB;
+      T s = 0;
+#pragma unroll
+      for (int X = 0; X < NB; ++X) s += w[cx][X][x] * b0[YZ * NB + X];
+      b1[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N3; i += kOpThreads) {     // y
+      const int x = i % NB, y = (i / NB) % NB, Z = i / (NB * NB);
+      T s = 0;
+#pragma unroll
+      for (int Y = 0; Y < NB; ++Y) s += w[cy][Y][y] * b1[(Z * NB + Y) * NB + x];
+      b0[i] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {                            // z
+      const int i = threadIdx.x + j * kOpThreads;
+      const int xy = i % (NB * NB), z = i / (NB * NB);
+      T s = 0;
+#pragma unroll
+      for (int Z = 0; Z < NB; ++Z) s += w[cz][Z][z] * b0[Z * NB * NB + xy];
+      acc[j] += s;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) it.dst[threadIdx.x + j * kOpThreads] = acc[j];
+}
+
+template <int NB, typename T>
+__global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
+  constexpr int N3 = NB * NB * NB;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const CombineItem<T>& it = ((const CombineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double sc = it.scale;
+  double* dd = it.dst_d ? it.dst_d : (it.dst_t ? nullptr : ws.out + it.dst_out);
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+    double v = it.v ? sc * double(it.v[i]) : 0.0;
+    if (it.base) v += double(it.base[i]);
+    if (dd) dd[i] = v;
+    else it.dst_t[i] = T(v);
+  }
+}
+
+template <int NB, typename T>
+__global__ __launch_bounds__(kOpThreads) void convert_kernel(SetTable sets) {
+  constexpr int N3 = NB * NB * NB;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const ConvertItem<T>& it = ((const ConvertItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double* src = it.src ? it.src : ws.in + it.src_in;
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) it.dst[i] = T(src[i]);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kOpThreads) void coarsen_kernel(SetTable sets) {
+  constexpr int N3 = NB * NB * NB, HB = NB / 2;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const CoarsenItem& it = ((const CoarsenItem*)ws.items)[blockIdx.x - ws.wg_begin];
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    const int oc = (x / HB) + 2 * (y / HB) + 4 * (z / HB);
+    const double* ch = it.child[oc] ? it.child[oc] : ws.in + it.child_in[oc];
+    const int fx = 2 * (x % HB), fy = 2 * (y % HB), fz = 2 * (z % HB);
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) s += ch[((fz + dz) * NB + fy + dy) * NB + fx + dx];
+    it.dst[i] = 0.125 * s;
+  }
+}
+
+// Quadratic refinement table: row j in [-1, 2 NB] at index j + 1 holds {lo, w0, w1, w2}.
+template <int NB, typename T>
+__device__ __forceinline__ T refine_point(const T* __restrict__ pw, const double* __restrict__ w3,
+                                          int jx, int jy, int jz) {
+  const double* rx = w3 + 4 * (jx + 1);
+  const double* ry = w3 + 4 * (jy + 1);
+  const double* rz = w3 + 4 * (jz + 1);
+  const int lx = (int)rx[0], ly = (int)ry[0], lz = (int)rz[0];
+  T s = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T sy = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const T* row = pw + ((lz + a) * NB + (ly + b)) * NB + lx;
+      const T sx = T(rx[1]) * row[0] + T(rx[2]) * row[1] + T(rx[3]) * row[2];
+      sy += T(ry[1 + b]) * sx;
+    }
+    s += T(rz[1 + a]) * sy;
+  }
+  return s;
+}
+
+template <int NB, typename T>
+__global__ __launch_bounds__(kOpThreads) void refine_kernel(SetTable sets) {
+  constexpr int N3 = NB * NB * NB;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const RefineItem<T>& it = ((const RefineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double* __restrict__ w3 = ws.w;
+  const int cx = it.octant & 1, cy = (it.octant >> 1) & 1, cz = (it.octant >> 2) & 1;
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    it.jw[i] = refine_point<NB>(it.parent_w, w3, cx * NB + x, cy * NB + y, cz * NB + z);
+  }
+}
+
+template <int NB, typename T>
+__global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
+  constexpr int N3 = NB * NB * NB;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const CorrectItem<T>& it = ((const CorrectItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double* __restrict__ w3 = ws.w;
+  const double* __restrict__ f = it.f ? it.f : ws.in + it.f_in;
+  const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+    const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
+    const T centre = it.jw[i];
+    T sum = T(0);
+#pragma unroll
+    for (int face = 0; face < 6; ++face) {
+      const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
+      int q[3] = {p[0], p[1], p[2]};
+      q[ax] += sg;
+      T v;
+      if (q[ax] >= 0 && q[ax] < NB) {
+        v = it.jw[(q[2] * NB + q[1]) * NB + q[0]];
+      } else if (it.nbr[face]) {
+        q[ax] = sg > 0 ? 0 : NB - 1;
+        v = it.nbr[face][(q[2] * NB + q[1]) * NB + q[0]];
+      } else {
+        v = refine_point<NB>(it.parent_w, w3, c[0] * NB + (ax == 0 ? q[0] : p[0]),
+                             c[1] * NB + (ax == 1 ? q[1] : p[1]), c[2] * NB + (ax == 2 ? q[2] : p[2]));
+      }
+      sum += v;
+    }
+    const double lap = double(sum) - 6.0 * double(centre);
+    it.g[i] = T(f[i] - it.inv_h2 * lap);
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(kOpThreads) void residual_kernel(SetTable sets) {
+  constexpr int N3 = NB * NB * NB;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const ResidualItem& it = ((const ResidualItem*)ws.items)[blockIdx.x - ws.wg_begin];
+  const double* __restrict__ f = ws.in + it.off;
+  const double* __restrict__ u = ws.out + it.off;
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+    if (!it.leaf) { it.r[i] = 0.0; continue; }
+    const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
+    double sum = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int face = 0; face < 6; ++face) {
+      const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
+      int q[3] = {p[0], p[1], p[2]};
+      q[ax] += sg;
+      if (q[ax] >= 0 && q[ax] < NB) {
+        sum += u[(q[2] * NB + q[1]) * NB + q[0]];
+      } else if (it.nbr_off[face] >= 0) {
+        q[ax] = sg > 0 ? 0 : NB - 1;
+        sum += ws.out[it.nbr_off[face] + (q[2] * NB + q[1]) * NB + q[0]];
+      } else {
+        ok = false;
+      }
+    }
+    it.r[i] = ok ? f[i] - it.inv_h2 * (sum - 6.0 * u[i]) : 0.0;
+  }
+}
+
+__global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+
+}  // namespace
+
+#define LGF_NB_DISPATCH(nb, ...)                                           \
+  do {                                                                     \
+    if ((nb) == 16) { constexpr int NB = 16; __VA_ARGS__; }                \
+    else if ((nb) == 8) { constexpr int NB = 8; __VA_ARGS__; }             \
+    else return hipErrorInvalidValue;                                      \
+  } while (0)
+
+#define LGF_LAUNCH_SIMPLE(...)                                                   \
+  const int64_t wg = assign_wg(t, 1);                                             \
+  if (wg == 0) return hipSuccess;                                                 \
+  LGF_NB_DISPATCH(nb, __VA_ARGS__<<<(unsigned)wg, kOpThreads, 0, st>>>(t));       \
+  return hipGetLastError();
+
+template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(anterp_kernel<NB, TC, TP>)
+}
+template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(interp_kernel<NB, TC, TP>)
+}
+template <typename T> hipError_t launch_combine(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(combine_kernel<NB, T>)
+}
+template <typename T> hipError_t launch_convert(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(convert_kernel<NB, T>)
+}
+hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(coarsen_kernel<NB>)
+}
+template <typename T> hipError_t launch_refine(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(refine_kernel<NB, T>)
+}
+template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(correct_kernel<NB, T>)
+}
+hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(residual_kernel<NB>)
+}
+hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  axpy_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(y, x, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_anterp<float, float>(int, SetTable&, hipStream_t);
+template hipError_t launch_anterp<double, double>(int, SetTable&, hipStream_t);
+template hipError_t launch_anterp<float, double>(int, SetTable&, hipStream_t);
+template hipError_t launch_interp<float, float>(int, SetTable&, hipStream_t);
+template hipError_t launch_interp<double, double>(int, SetTable&, hipStream_t);
+template hipError_t launch_interp<float, double>(int, SetTable&, hipStream_t);
+
+#define LGF_INST(T)                                                       \
+  template hipError_t launch_combine<T>(int, SetTable&, hipStream_t);     \
+  template hipError_t launch_convert<T>(int, SetTable&, hipStream_t);     \
+  template hipError_t launch_refine<T>(int, SetTable&, hipStream_t);      \
+  template hipError_t launch_correct<T>(int, SetTable&, hipStream_t);
+LGF_INST(float)
+LGF_INST(double)
+
+}  // namespace lgf

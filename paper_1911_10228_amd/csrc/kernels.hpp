@@ -1,0 +1,156 @@
+// Device work items and kernel launchers of the LGF library.
+#pragma once
+
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace lgf {
+
+constexpr int kTableKmax = 100;           // table holds |n_i| <= 100 (n.n <= 100^2)
+constexpr int kMacL = 8;                  // target blocks per MAC row (x run, starts even)
+constexpr int kMacSlots = kMacL + 6;      // source x slots per (dy, dz) pair
+
+// ----------------------------------------------------------------------------- Green function
+// Paper's policy: table for n.n <= 100^2, A_G^3 up to 600^2, A_G^2 beyond.
+__device__ __forceinline__ double green(int nx, int ny, int nz, const double* __restrict__ cube) {
+  int a = nx < 0 ? -nx : nx, b = ny < 0 ? -ny : ny, c = nz < 0 ? -nz : nz;
+  const long r2 = (long)a * a + (long)b * b + (long)c * c;
+  if (r2 <= 10000) {
+    if (a < b) { int t = a; a = b; b = t; }
+    if (b < c) { int t = b; b = c; c = t; }
+    if (a < b) { int t = a; a = b; b = t; }
+    return cube[((size_t)a * (kTableKmax + 1) + b) * (kTableKmax + 1) + c];
+  }
+  const double x2 = double(nx) * nx, y2 = double(ny) * ny, z2 = double(nz) * nz;
+  const double rr = x2 + y2 + z2;
+  const double r = sqrt(rr);
+  const double inv_r = 1.0 / r;
+  const double inv_r2 = inv_r * inv_r;
+  const double inv_r4 = inv_r2 * inv_r2;
+  const double quart = x2 * x2 + y2 * y2 + z2 * z2 - 3.0 * (x2 * y2 + x2 * z2 + y2 * z2);
+  double g = -inv_r / (4.0 * kPi) - quart * inv_r4 * inv_r2 * inv_r / (16.0 * kPi);
+  if (r2 <= 360000) {
+    const double oct = -228.0 * (y2 * z2 * x2 * x2 + y2 * z2 * z2 * x2 + y2 * y2 * z2 * x2) +
+                       621.0 * (x2 * x2 * y2 * y2 + z2 * z2 * y2 * y2 + x2 * x2 * z2 * z2) -
+                       244.0 * (y2 * x2 * x2 * x2 + z2 * x2 * x2 * x2 + y2 * y2 * y2 * x2 +
+                                z2 * z2 * z2 * x2 + y2 * z2 * z2 * z2 + y2 * y2 * y2 * z2) +
+                       23.0 * (x2 * x2 * x2 * x2 + y2 * y2 * y2 * y2 + z2 * z2 * z2 * z2);
+    const double inv_r13 = inv_r4 * inv_r4 * inv_r4 * inv_r;
+    g -= oct * inv_r13 / (128.0 * kPi);
+  }
+  return g;
+}
+
+// ----------------------------------------------------------------------------- work items
+template <typename T> struct FftFwdItem {
+  const T* src;          // n_b^3 real block [z][y][x]
+  cpx<T>* dst;           // half spectrum [kz][ky][kx], kx in [0, n_b]
+};
+template <typename T> struct FftInvItem {
+  const cpx<T>* src;     // half spectrum
+  T* dst;                // n_b^3 real block, receives IFFT / P^3
+};
+template <typename T> struct MacRow {
+  int32_t tgt[kMacL];                  // target slots (-1: none)
+  int32_t src[36][kMacSlots];          // source slots per (jz, jy) and x slot (-1: none)
+  uint64_t pair_mask;                  // bit jz*6+jy set if src[jz*6+jy] has a source
+  int32_t flags;                       // bit0 base level (near field on), bit1 y parity, bit2 z parity
+  int32_t pad;
+  const cpx<T>* fhat;                  // source spectra arena (slot * S)
+  cpx<T>* uhat;                        // target spectra arena (slot * S)
+  const cpx<T>* const* kptr;           // 343 kernel-spectrum pointers, index (dz+3)*49+(dy+3)*7+dx+3
+};
+// TC: element type of the child level, TP: of the parent level (they differ where an FP32
+// base level meets FP64 coarse levels).
+template <typename TC, typename TP> struct AnterpItem {
+  TP* dst;               // parent block, overwritten with sum_c R_c child_c
+  const TC* child[8];    // octant c = cx + 2 cy + 4 cz (nullptr: absent)
+};
+template <typename TC, typename TP> struct InterpItem {
+  TC* child;             // child block: child (+)= J_c parent
+  const TP* parent;
+  int32_t octant;
+  int32_t accumulate;    // 1: add to the child's own level-interaction result, 0: overwrite
+};
+// Fields that come from the solve pass's input / output are addressed by offsets into
+// WorkSet::in / WorkSet::out; plan-owned buffers by pointers.
+template <typename T> struct CombineItem {
+  double* dst_d;         // double destination (plan buffer), or
+  T* dst_t;              // T destination (plan buffer), or, if both null,
+  int64_t dst_out;       // offset into WorkSet::out
+  const T* v;            // level field (nullptr: zero)
+  const T* base;         // added field (nullptr: zero)
+  double scale;          // dst = base + scale * v
+};
+template <typename T> struct ConvertItem {
+  T* dst;
+  const double* src;     // plan buffer, or nullptr: WorkSet::in + src_in
+  int64_t src_in;
+};
+struct CoarsenItem {
+  double* dst;           // non-leaf block source = mean of the 2x2x2 child cells
+  const double* child[8];
+  int64_t child_in[8];   // used where child[c] is null: WorkSet::in + child_in[c]
+};
+template <typename T> struct RefineItem {
+  T* jw;                 // child block values of J^{l-1} w^{l-1}
+  const T* parent_w;     // parent's leaf-only field
+  int32_t octant;
+  int32_t pad;
+};
+template <typename T> struct CorrectItem {
+  T* g;                  // corrected source g = f - h^-2 L(Jw)
+  const double* f;       // (coarsened) level source, or nullptr: WorkSet::in + f_in
+  int64_t f_in;
+  const T* jw;           // own Jw
+  const T* nbr[6];       // neighbour blocks' Jw (-x,+x,-y,+y,-z,+z), nullptr: ghost from parent
+  const T* parent_w;     // parent field for ghost values
+  int32_t octant;
+  int32_t pad;
+  double inv_h2;
+};
+struct ResidualItem {
+  double* r;             // r = f - h^-2 L u where all 6 neighbours exist, 0 elsewhere
+  int64_t off;           // block offset of f (in WorkSet::in) and u (in WorkSet::out)
+  int64_t nbr_off[6];    // same-level neighbour blocks of u in WorkSet::out (-1: absent)
+  double inv_h2;
+  int32_t leaf;          // 0: whole block r = 0
+  int32_t pad;
+};
+
+// ----------------------------------------------------------------------------- launchers
+int quad_nodes();
+hipError_t launch_green_table(double* d_cube, double* d_nodes, double* d_wts, const int16_t* d_tri,
+                              int ntri, hipStream_t st);
+hipError_t launch_green_eval(const int32_t* d_n, int64_t m, const double* d_cube, double* d_out,
+                             hipStream_t st);
+hipError_t launch_kernel_spectra(int nb, int nspec, const int32_t* d_sd, const double* d_cube,
+                                 double* d_real, c64* d_tmp, c64* d_out64, c32* d_out32,
+                                 hipStream_t st);
+
+// Each launcher takes a set table whose WorkSet.items point at device arrays of the item type.
+// The launcher fills wg_begin from the counts and returns the number of workgroups used.
+template <typename T> hipError_t launch_fft_fwd(int nb, SetTable& t, hipStream_t st);
+template <typename T> hipError_t launch_fft_inv(int nb, SetTable& t, hipStream_t st);
+template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st);
+template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
+template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
+template <typename T> hipError_t launch_combine(int nb, SetTable& t, hipStream_t st);
+template <typename T> hipError_t launch_convert(int nb, SetTable& t, hipStream_t st);
+hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st);
+template <typename T> hipError_t launch_refine(int nb, SetTable& t, hipStream_t st);   // ws.w = W3
+template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st);  // ws.w = W3
+hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
+hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);
+
+// number of workgroups each item of a kernel needs (for set-table bookkeeping)
+inline int64_t assign_wg(SetTable& t, int64_t per_item_num, int64_t per_item_den = 1) {
+  int64_t wg = 0;
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (t.s[i].count * per_item_num + per_item_den - 1) / per_item_den;
+  }
+  return wg;
+}
+
+}  // namespace lgf

@@ -1,0 +1,897 @@
+// Plan construction and step execution (host side).
+//
+// Per refinement level l (Sec. 3, Algorithm 2) the plan holds up to two FMM instances over the
+// octree of that level's blocks (Sec. 2.1): channel T (all blocks are sources, all are targets:
+// the total field of eq. amr_convs for leaf targets) and channel A (leaf blocks are sources,
+// non-leaf blocks are targets: the leaf-only field passed to level l+1).  Both use the same tree,
+// so A equals the paper's "FMM of all sources minus FMM of non-leaf sources".
+//
+// Tree: level k+1 holds floor(b/2) of level k; it stops at the first level whose nodes are all
+// mutual neighbours (no influence list can be non-empty above it).  Lists: N(B) (Chebyshev
+// distance <= 1, base level only) and I(B) (distance >= 2, parents neighbours), Fig. fmm_regions.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <unordered_map>
+
+namespace lgf {
+
+namespace {
+
+struct I3 {
+  int x, y, z;
+  bool operator==(const I3& o) const { return x == o.x && y == o.y && z == o.z; }
+  bool operator<(const I3& o) const {
+    if (z != o.z) return z < o.z;
+    if (y != o.y) return y < o.y;
+    return x < o.x;
+  }
+};
+struct I3Hash {
+  size_t operator()(const I3& a) const {
+    uint64_t h = (uint64_t)(uint32_t)a.x * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)(uint32_t)a.y * 0xC2B2AE3D27D4EB4Full + (h << 6) + (h >> 2);
+    h ^= (uint64_t)(uint32_t)a.z * 0x165667B19E3779F9ull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+using I3Map = std::unordered_map<I3, int, I3Hash>;
+
+inline int floordiv2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+inline int floordiv(int v, int d) { return v >= 0 ? v / d : -((-v + d - 1) / d); }
+inline I3 parent_of(I3 a) { return {floordiv2(a.x), floordiv2(a.y), floordiv2(a.z)}; }
+inline int octant_of(I3 a) {
+  const I3 p = parent_of(a);
+  return (a.x - 2 * p.x) + 2 * (a.y - 2 * p.y) + 4 * (a.z - 2 * p.z);
+}
+inline int cheb(I3 a, I3 b) {
+  return std::max(std::abs(a.x - b.x), std::max(std::abs(a.y - b.y), std::abs(a.z - b.z)));
+}
+
+// ----------------------------------------------------------------------------- 1-D weights
+// Lagrange stencil for coordinate x (parent node units): n_i nodes, even counts around the
+// bracketing pair, odd counts centred on the nearest node, shifted inside [0, nb-1].
+void lagrange_row(double x, int n_i, int nb, int* lo_out, double* w) {
+  int lo = (n_i % 2 == 0) ? (int)std::floor(x) - n_i / 2 + 1 : (int)std::floor(x + 0.5) - (n_i - 1) / 2;
+  lo = std::min(std::max(lo, 0), nb - n_i);
+  for (int j = 0; j < n_i; ++j) {
+    double v = 1.0;
+    for (int m = 0; m < n_i; ++m)
+      if (m != j) v *= (x - double(lo + m)) / double(j - m);
+    w[j] = v;
+  }
+  *lo_out = lo;
+}
+
+std::vector<double> lagrange_matrix(int nb, int n_i) {
+  std::vector<double> W((size_t)2 * nb * nb, 0.0);
+  std::vector<double> w(n_i);
+  for (int j = 0; j < 2 * nb; ++j) {
+    int lo;
+    lagrange_row(j / 2.0 - 0.25, n_i, nb, &lo, w.data());
+    for (int m = 0; m < n_i; ++m) W[(size_t)j * nb + lo + m] = w[m];
+  }
+  return W;
+}
+
+std::vector<double> refine_table(int nb) {
+  std::vector<double> t((size_t)(2 * nb + 2) * 4);
+  double w[3];
+  for (int j = -1; j <= 2 * nb; ++j) {
+    int lo;
+    lagrange_row(j / 2.0 - 0.25, 3, nb, &lo, w);
+    double* r = &t[(size_t)(j + 1) * 4];
+    r[0] = lo; r[1] = w[0]; r[2] = w[1]; r[3] = w[2];
+  }
+  return t;
+}
+
+// ----------------------------------------------------------------------------- FMM instance
+struct OctLevel {
+  std::vector<I3> nodes;
+  I3Map index;
+  std::vector<int> parent;             // index into the next level
+  std::vector<char> is_src, is_tgt, has_ifft, has_val, referenced, need_src;
+  std::vector<int> src_slot, tgt_slot;
+};
+
+struct RowDesc {
+  int k;
+  I3 key;                              // (window, y, z)
+  int tgt_node[kMacL];
+  int src_node[36][kMacSlots];
+  uint64_t mask;
+};
+
+struct Fmm {
+  std::vector<OctLevel> lv;
+  std::vector<RowDesc> rows;
+  int64_t interactions = 0;
+  std::vector<int64_t> level_interactions;
+};
+
+// valid offset d = t - src for target parity c (per dimension): c-3 <= d <= c+2
+inline bool parity_ok(int d, int c) { return d >= c - 3 && d <= c + 2; }
+
+void fmm_build(const std::vector<I3>& base, const std::vector<char>& src, const std::vector<char>& tgt,
+               Fmm& F) {
+  F.lv.clear();
+  F.lv.emplace_back();
+  {
+    OctLevel& L0 = F.lv[0];
+    L0.nodes = base;
+    for (size_t i = 0; i < base.size(); ++i) L0.index[base[i]] = (int)i;
+    L0.is_src = src;
+    L0.is_tgt = tgt;
+  }
+  auto extent = [](const std::vector<I3>& v) {
+    I3 lo = v[0], hi = v[0];
+    for (const I3& a : v) {
+      lo = {std::min(lo.x, a.x), std::min(lo.y, a.y), std::min(lo.z, a.z)};
+      hi = {std::max(hi.x, a.x), std::max(hi.y, a.y), std::max(hi.z, a.z)};
+    }
+    return std::max(hi.x - lo.x, std::max(hi.y - lo.y, hi.z - lo.z));
+  };
+  while (extent(F.lv.back().nodes) > 1) {
+    OctLevel& cur = F.lv.back();
+    std::vector<I3> par;
+    par.reserve(cur.nodes.size());
+    for (const I3& a : cur.nodes) par.push_back(parent_of(a));
+    std::sort(par.begin(), par.end());
+    par.erase(std::unique(par.begin(), par.end()), par.end());
+    OctLevel nxt;
+    nxt.nodes = par;
+    for (size_t i = 0; i < par.size(); ++i) nxt.index[par[i]] = (int)i;
+    nxt.is_src.assign(par.size(), 0);
+    nxt.is_tgt.assign(par.size(), 0);
+    cur.parent.resize(cur.nodes.size());
+    for (size_t i = 0; i < cur.nodes.size(); ++i) {
+      const int pi = nxt.index.at(parent_of(cur.nodes[i]));
+      cur.parent[i] = pi;
+      if (cur.is_src[i]) nxt.is_src[pi] = 1;
+      if (cur.is_tgt[i]) nxt.is_tgt[pi] = 1;
+    }
+    F.lv.push_back(std::move(nxt));
+  }
+  const int K = (int)F.lv.size();
+  F.level_interactions.assign(K, 0);
+  // rows, interactions, referenced sources
+  for (int k = 0; k < K; ++k) {
+    OctLevel& L = F.lv[k];
+    const size_t n = L.nodes.size();
+    L.has_ifft.assign(n, 0);
+    L.referenced.assign(n, 0);
+    const bool base_level = (k == 0);
+    std::map<I3, RowDesc> rows;
+    for (size_t t = 0; t < n; ++t) {
+      if (!L.is_tgt[t]) continue;
+      const I3 a = L.nodes[t];
+      const int cx = a.x & 1, cy = a.y & 1, cz = a.z & 1;
+      int64_t cnt = 0;
+      for (int dz = cz - 3; dz <= cz + 2; ++dz)
+        for (int dy = cy - 3; dy <= cy + 2; ++dy)
+          for (int dx = cx - 3; dx <= cx + 2; ++dx) {
+            const bool near = std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1;
+            if (near && !base_level) continue;
+            auto it = L.index.find({a.x - dx, a.y - dy, a.z - dz});
+            if (it == L.index.end() || !L.is_src[it->second]) continue;
+            L.referenced[it->second] = 1;
+            ++cnt;
+          }
+      if (cnt == 0) continue;
+      L.has_ifft[t] = 1;
+      F.interactions += cnt;
+      F.level_interactions[k] += cnt;
+      const int wx = floordiv(a.x, kMacL);
+      const I3 key{wx, a.y, a.z};
+      auto rit = rows.find(key);
+      if (rit == rows.end()) {
+        RowDesc r;
+        r.k = k;
+        r.key = key;
+        for (int i = 0; i < kMacL; ++i) r.tgt_node[i] = -1;
+        r.mask = 0;
+        for (int jz = 0; jz < 6; ++jz)
+          for (int jy = 0; jy < 6; ++jy) {
+            const int dz = cz - 3 + jz, dy = cy - 3 + jy;
+            for (int s = 0; s < kMacSlots; ++s) {
+              auto it = L.index.find({wx * kMacL - 3 + s, a.y - dy, a.z - dz});
+              const int id = (it != L.index.end() && L.is_src[it->second]) ? it->second : -1;
+              r.src_node[jz * 6 + jy][s] = id;
+              if (id >= 0) r.mask |= 1ull << (jz * 6 + jy);
+            }
+          }
+        rit = rows.emplace(key, r).first;
+      }
+      rit->second.tgt_node[a.x - wx * kMacL] = (int)t;
+    }
+    for (auto& kv : rows) F.rows.push_back(kv.second);
+  }
+  // values: top-down; source needs: top-down from referenced
+  for (int k = K - 1; k >= 0; --k) {
+    OctLevel& L = F.lv[k];
+    const size_t n = L.nodes.size();
+    L.has_val.assign(n, 0);
+    L.need_src.assign(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+      const bool pv = (k + 1 < K) && F.lv[k + 1].has_val[L.parent[i]];
+      const bool pn = (k + 1 < K) && F.lv[k + 1].need_src[L.parent[i]];
+      L.has_val[i] = L.is_tgt[i] && (L.has_ifft[i] || pv);
+      L.need_src[i] = L.is_src[i] && (L.referenced[i] || pn);
+    }
+    L.src_slot.assign(n, -1);
+    L.tgt_slot.assign(n, -1);
+  }
+}
+
+// ----------------------------------------------------------------------------- device memory
+struct Arena {
+  Plan* p;
+  uint64_t budget;
+  hipError_t alloc(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) return hipSuccess;
+    if (budget && (uint64_t)(p->bytes + (int64_t)bytes) > budget) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return e;
+    p->allocs.push_back(*ptr);
+    p->bytes += (int64_t)bytes;
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- device context
+namespace {
+std::mutex g_ctx_mu;
+std::map<int, DeviceCtx*> g_ctx;
+}  // namespace
+
+hipError_t device_ctx(DeviceCtx** out) {
+  int dev = 0;
+  LGF_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  DeviceCtx* c = new DeviceCtx();
+  c->device = dev;
+  LGF_HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  const size_t cube_n = (size_t)(kTableKmax + 1) * (kTableKmax + 1) * (kTableKmax + 1);
+  LGF_HIP_CHECK(hipMalloc(&c->cube, cube_n * sizeof(double)));
+  LGF_HIP_CHECK(hipMemsetAsync(c->cube, 0, cube_n * sizeof(double), c->stream));
+  std::vector<int16_t> tri;
+  for (int a = 0; a <= kTableKmax; ++a)
+    for (int b = 0; b <= a; ++b)
+      for (int cc = 0; cc <= b; ++cc)
+        if (a * a + b * b + cc * cc <= 10000) {
+          tri.push_back((int16_t)a);
+          tri.push_back((int16_t)b);
+          tri.push_back((int16_t)cc);
+        }
+  const int ntri = (int)(tri.size() / 3);
+  double *nodes = nullptr, *wts = nullptr;
+  int16_t* d_tri = nullptr;
+  const int nq = quad_nodes();
+  LGF_HIP_CHECK(hipMalloc(&nodes, (size_t)nq * (kTableKmax + 1) * sizeof(double)));
+  LGF_HIP_CHECK(hipMalloc(&wts, (size_t)nq * sizeof(double)));
+  LGF_HIP_CHECK(hipMalloc(&d_tri, tri.size() * sizeof(int16_t)));
+  LGF_HIP_CHECK(hipMemcpyAsync(d_tri, tri.data(), tri.size() * sizeof(int16_t), hipMemcpyHostToDevice,
+                               c->stream));
+  LGF_HIP_CHECK(launch_green_table(c->cube, nodes, wts, d_tri, ntri, c->stream));
+  LGF_HIP_CHECK(hipStreamSynchronize(c->stream));
+  (void)hipFree(nodes);
+  (void)hipFree(wts);
+  (void)hipFree(d_tri);
+  c->bytes = (int64_t)(cube_n * sizeof(double));
+  g_ctx[dev] = c;
+  *out = c;
+  return hipSuccess;
+}
+
+hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto key = std::make_pair(nb, s);
+  auto it = ctx->spectra.find(key);
+  if (it != ctx->spectra.end()) {
+    *out = &it->second;
+    return hipSuccess;
+  }
+  const int P = 2 * nb, H = nb + 1;
+  const size_t S = (size_t)P * P * H, P3 = (size_t)P * P * P;
+  std::vector<int32_t> sd;
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        sd.push_back(s); sd.push_back(dx); sd.push_back(dy); sd.push_back(dz);
+      }
+  SpecSet ss;
+  ss.nb = nb;
+  ss.s = s;
+  int32_t* d_sd = nullptr;
+  double* d_real = nullptr;
+  c64* d_tmp = nullptr;
+  LGF_HIP_CHECK(hipMalloc(&d_sd, sd.size() * sizeof(int32_t)));
+  LGF_HIP_CHECK(hipMalloc(&d_real, 343 * P3 * sizeof(double)));
+  LGF_HIP_CHECK(hipMalloc(&d_tmp, 343 * (size_t)P * P * H * sizeof(c64)));
+  LGF_HIP_CHECK(hipMalloc(&ss.d64, 343 * S * sizeof(c64)));
+  LGF_HIP_CHECK(hipMalloc(&ss.d32, 343 * S * sizeof(c32)));
+  LGF_HIP_CHECK(hipMalloc(&ss.kp64, 343 * sizeof(void*)));
+  LGF_HIP_CHECK(hipMalloc(&ss.kp32, 343 * sizeof(void*)));
+  LGF_HIP_CHECK(hipMemcpyAsync(d_sd, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               ctx->stream));
+  LGF_HIP_CHECK(launch_kernel_spectra(nb, 343, d_sd, ctx->cube, d_real, d_tmp, ss.d64, ss.d32, ctx->stream));
+  std::vector<const void*> p64(343), p32(343);
+  for (int i = 0; i < 343; ++i) {
+    p64[i] = ss.d64 + i * S;
+    p32[i] = ss.d32 + i * S;
+  }
+  LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp64, p64.data(), 343 * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp32, p32.data(), 343 * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  LGF_HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  (void)hipFree(d_sd);
+  (void)hipFree(d_real);
+  (void)hipFree(d_tmp);
+  ctx->bytes += (int64_t)(343 * S * (sizeof(c64) + sizeof(c32)));
+  auto res = ctx->spectra.emplace(key, ss);
+  *out = &res.first->second;
+  return hipSuccess;
+}
+
+// ----------------------------------------------------------------------------- plan build
+namespace {
+
+struct HostItems {
+  std::vector<uint8_t> buf;
+  template <typename X> size_t add(const std::vector<X>& v) {
+    size_t off = (buf.size() + 255) / 256 * 256;
+    buf.resize(off + v.size() * sizeof(X));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(X));
+    return off;
+  }
+};
+
+struct PendingStep {
+  int l, phase, sub, kind, ty;
+  size_t off;
+  int32_t count;
+  const double* w;
+  int64_t work;
+};
+
+// Element type of octree level k: the FP32 mode runs the base level of every refinement level
+// in FP32 and the coarse (far-field) levels in FP64; the FP64 mode runs everything in FP64.
+// Items are built with the <double> layouts, which are identical to the <float> ones (only
+// pointers change type); each step records the element type its kernel is instantiated for.
+enum : int { TY_F32 = 0, TY_F64 = 1, TY_MIX = 2 };   // TY_MIX: FP32 child level, FP64 parent level
+
+hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<int>& lev,
+                      uint64_t budget, std::string* err) {
+  const int nb = p->nb;
+  const int64_t N3 = (int64_t)nb * nb * nb;
+  const int P = 2 * nb;
+  const int64_t S = (int64_t)P * P * (nb + 1);
+  const int64_t n = p->nblocks;
+  const int LR = p->LR;
+  const int tyb = p->fp32 ? TY_F32 : TY_F64;
+  auto ty_of = [&](int k) { return k == 0 ? tyb : TY_F64; };
+  auto es = [](int ty) { return ty == TY_F32 ? (int64_t)4 : (int64_t)8; };
+  Arena ar{p, budget};
+
+  std::vector<std::vector<int>> ids(LR);
+  for (int64_t i = 0; i < n; ++i) ids[lev[i]].push_back((int)i);
+  std::vector<I3Map> cmap(LR);
+  for (int l = 0; l < LR; ++l)
+    for (int i : ids[l]) cmap[l][coords[i]] = i;
+  std::vector<char> leaf(n, 1);
+  for (int l = 0; l + 1 < LR; ++l)
+    for (int i : ids[l]) {
+      const I3 c = coords[i];
+      if (cmap[l + 1].count({2 * c.x, 2 * c.y, 2 * c.z})) leaf[i] = 0;
+    }
+  auto child_of = [&](int i, int oc) {
+    const I3 c = coords[i];
+    return cmap[lev[i] + 1].at({2 * c.x + (oc & 1), 2 * c.y + ((oc >> 1) & 1), 2 * c.z + ((oc >> 2) & 1)});
+  };
+  auto face_nbr = [&](int i, int face) {
+    I3 c = coords[i];
+    const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
+    if (ax == 0) c.x += sg; else if (ax == 1) c.y += sg; else c.z += sg;
+    auto it = cmap[lev[i]].find(c);
+    return it == cmap[lev[i]].end() ? -1 : it->second;
+  };
+
+  // FMM instances and slots (per element type)
+  std::vector<Fmm> chT(LR), chA(LR);
+  std::vector<char> hasA(LR, 0);
+  int64_t nsrc[2] = {0, 0}, ntgt[2] = {0, 0};
+  std::vector<int> base_src_slot(n, -1);
+  for (int l = 0; l < LR; ++l) {
+    std::vector<I3> bc;
+    std::vector<char> all(ids[l].size(), 1), lf(ids[l].size()), nl(ids[l].size());
+    for (size_t a = 0; a < ids[l].size(); ++a) {
+      bc.push_back(coords[ids[l][a]]);
+      lf[a] = leaf[ids[l][a]];
+      nl[a] = !leaf[ids[l][a]];
+      if (nl[a]) hasA[l] = 1;
+    }
+    fmm_build(bc, all, all, chT[l]);
+    if (hasA[l]) fmm_build(bc, lf, nl, chA[l]);
+    for (size_t a = 0; a < ids[l].size(); ++a) {
+      chT[l].lv[0].src_slot[a] = (int)nsrc[tyb];
+      base_src_slot[ids[l][a]] = (int)nsrc[tyb];
+      ++nsrc[tyb];
+    }
+    for (int ch = 0; ch < 2; ++ch) {
+      if (ch == 1 && !hasA[l]) continue;
+      Fmm& F = ch == 0 ? chT[l] : chA[l];
+      for (size_t k = 0; k < F.lv.size(); ++k) {
+        OctLevel& L = F.lv[k];
+        const int ty = ty_of((int)k);
+        for (size_t i = 0; i < L.nodes.size(); ++i) {
+          if (k == 0 && L.is_src[i]) L.src_slot[i] = chT[l].lv[0].src_slot[i];
+          else if (k > 0 && L.need_src[i]) L.src_slot[i] = (int)nsrc[ty]++;
+          if (L.has_val[i]) L.tgt_slot[i] = (int)ntgt[ty]++;
+        }
+      }
+    }
+    p->Kmax = std::max(p->Kmax, (int)chT[l].lv.size());
+  }
+
+  // arenas
+  void* tmp = nullptr;
+  if (LR > 1) {
+    LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
+    p->fe = (double*)tmp;
+    LGF_HIP_CHECK(ar.alloc(&p->jw, n * N3 * es(tyb)));
+    LGF_HIP_CHECK(ar.alloc(&p->w, n * N3 * es(tyb)));
+  }
+  uint8_t *srcA[2], *fhatA[2], *uhatA[2], *vA[2];
+  for (int ty = 0; ty < 2; ++ty) {
+    void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+    LGF_HIP_CHECK(ar.alloc(&a, nsrc[ty] * N3 * es(ty)));
+    LGF_HIP_CHECK(ar.alloc(&b, nsrc[ty] * S * 2 * es(ty)));
+    LGF_HIP_CHECK(ar.alloc(&c, ntgt[ty] * S * 2 * es(ty)));
+    LGF_HIP_CHECK(ar.alloc(&d, ntgt[ty] * N3 * es(ty)));
+    srcA[ty] = (uint8_t*)a; fhatA[ty] = (uint8_t*)b; uhatA[ty] = (uint8_t*)c; vA[ty] = (uint8_t*)d;
+  }
+  p->src = srcA[tyb];
+  p->fhat = fhatA[tyb];
+  p->uhat = uhatA[tyb];
+  p->v = vA[tyb];
+  if (p->fp32 && p->dc_iters > 0) {
+    LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
+    p->r = (double*)tmp;
+    LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
+    p->e = (double*)tmp;
+  }
+  {
+    const std::vector<double> W = lagrange_matrix(nb, p->n_i), W3 = refine_table(nb);
+    LGF_HIP_CHECK(ar.alloc(&tmp, W.size() * sizeof(double)));
+    p->d_w = (double*)tmp;
+    LGF_HIP_CHECK(hipMemcpy(p->d_w, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+    LGF_HIP_CHECK(ar.alloc(&tmp, W3.size() * sizeof(double)));
+    p->d_w3 = (double*)tmp;
+    LGF_HIP_CHECK(hipMemcpy(p->d_w3, W3.data(), W3.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  using D = double;
+  auto SRC = [&](int ty, int64_t slot) { return (D*)(srcA[ty] + slot * N3 * es(ty)); };
+  auto FH = [&](int ty, int64_t slot) { return (cpx<D>*)(fhatA[ty] + slot * S * 2 * es(ty)); };
+  auto UH = [&](int ty, int64_t slot) { return (cpx<D>*)(uhatA[ty] + slot * S * 2 * es(ty)); };
+  auto V = [&](int ty, int64_t slot) { return (D*)(vA[ty] + slot * N3 * es(ty)); };
+  auto JW = [&](int64_t blk) { return (D*)((uint8_t*)p->jw + blk * N3 * es(tyb)); };
+  auto WW = [&](int64_t blk) { return (D*)((uint8_t*)p->w + blk * N3 * es(tyb)); };
+
+  HostItems hi;
+  std::vector<PendingStep> steps, rsteps;
+  auto push = [&](std::vector<PendingStep>& dst, int l, int phase, int sub, int kind, int ty, size_t off,
+                  size_t count, const double* wt, int64_t work = 0) {
+    if (count) dst.push_back({l, phase, sub, kind, ty, off, (int32_t)count, wt, work});
+  };
+
+  // coarsening (before level 0), bottom-up over levels
+  for (int l = LR - 2; l >= 0; --l) {
+    std::vector<CoarsenItem> it;
+    for (int i : ids[l]) {
+      if (leaf[i]) continue;
+      CoarsenItem c{};
+      c.dst = p->fe + i * N3;
+      for (int oc = 0; oc < 8; ++oc) {
+        const int ch = child_of(i, oc);
+        c.child[oc] = leaf[ch] ? nullptr : p->fe + ch * N3;
+        c.child_in[oc] = ch * N3;
+      }
+      it.push_back(c);
+    }
+    push(steps, 0, 0, LR - 2 - l, K_COARSEN, TY_F64, hi.add(it), it.size(), nullptr);
+  }
+
+  for (int l = 0; l < LR; ++l) {
+    const double h = std::ldexp(1.0, -l);
+    if (l == 0) {
+      std::vector<ConvertItem<D>> it;
+      for (int i : ids[0]) {
+        ConvertItem<D> c{};
+        c.dst = SRC(tyb, base_src_slot[i]);
+        c.src = leaf[i] ? nullptr : p->fe + i * N3;
+        c.src_in = i * N3;
+        it.push_back(c);
+      }
+      push(steps, l, 1, 0, K_CONVERT, tyb, hi.add(it), it.size(), nullptr);
+    } else {
+      std::vector<RefineItem<D>> rit;
+      std::vector<CorrectItem<D>> cit;
+      for (int i : ids[l]) {
+        const I3 c = coords[i];
+        const int par = cmap[l - 1].at(parent_of(c));
+        RefineItem<D> r{};
+        r.jw = JW(i);
+        r.parent_w = WW(par);
+        r.octant = octant_of(c);
+        rit.push_back(r);
+        CorrectItem<D> q{};
+        q.g = SRC(tyb, base_src_slot[i]);
+        q.f = leaf[i] ? nullptr : p->fe + i * N3;
+        q.f_in = i * N3;
+        q.jw = JW(i);
+        for (int face = 0; face < 6; ++face) {
+          const int nbi = face_nbr(i, face);
+          q.nbr[face] = nbi >= 0 ? JW(nbi) : nullptr;
+        }
+        q.parent_w = WW(par);
+        q.octant = octant_of(c);
+        q.inv_h2 = 1.0 / (h * h);
+        cit.push_back(q);
+      }
+      push(steps, l, 1, 0, K_REFINE, tyb, hi.add(rit), rit.size(), p->d_w3);
+      push(steps, l, 1, 1, K_CORRECT, tyb, hi.add(cit), cit.size(), p->d_w3);
+    }
+    const int K = (int)chT[l].lv.size();
+    std::vector<std::vector<AnterpItem<D, D>>> ant(K);
+    std::vector<std::vector<InterpItem<D, D>>> itp(K);
+    std::vector<FftFwdItem<D>> fwd[2];
+    std::vector<FftInvItem<D>> inv[2];
+    std::vector<MacRow<D>> rows[2];
+    int64_t work[2] = {0, 0};
+    std::vector<char> fwd_done[2] = {std::vector<char>(nsrc[0], 0), std::vector<char>(nsrc[1], 0)};
+    for (int ch = 0; ch < 2; ++ch) {
+      if (ch == 1 && !hasA[l]) continue;
+      Fmm& F = ch == 0 ? chT[l] : chA[l];
+      p->interactions += F.interactions;
+      work[tyb] += F.level_interactions.empty() ? 0 : F.level_interactions[0];
+      for (size_t k = 1; k < F.level_interactions.size(); ++k) work[TY_F64] += F.level_interactions[k];
+      for (int k = 1; k < (int)F.lv.size(); ++k) {
+        OctLevel& L = F.lv[k];
+        OctLevel& C = F.lv[k - 1];
+        const int tp = ty_of(k), tc = ty_of(k - 1);
+        std::vector<AnterpItem<D, D>> tmpi(L.nodes.size());
+        for (size_t i = 0; i < L.nodes.size(); ++i) {
+          tmpi[i].dst = L.need_src[i] ? SRC(tp, L.src_slot[i]) : nullptr;
+          for (int oc = 0; oc < 8; ++oc) tmpi[i].child[oc] = nullptr;
+        }
+        for (size_t c = 0; c < C.nodes.size(); ++c) {
+          const int pi = C.parent[c];
+          if (!L.need_src[pi] || !C.is_src[c]) continue;
+          tmpi[pi].child[octant_of(C.nodes[c])] = SRC(tc, C.src_slot[c]);
+        }
+        for (size_t i = 0; i < L.nodes.size(); ++i)
+          if (L.need_src[i]) ant[k].push_back(tmpi[i]);
+      }
+      for (size_t k = 0; k < F.lv.size(); ++k) {
+        OctLevel& L = F.lv[k];
+        const int ty = ty_of((int)k);
+        for (size_t i = 0; i < L.nodes.size(); ++i) {
+          if (L.referenced[i] && !fwd_done[ty][L.src_slot[i]]) {
+            fwd_done[ty][L.src_slot[i]] = 1;
+            fwd[ty].push_back({SRC(ty, L.src_slot[i]), FH(ty, L.src_slot[i])});
+          }
+          if (L.has_ifft[i]) inv[ty].push_back({UH(ty, L.tgt_slot[i]), V(ty, L.tgt_slot[i])});
+          if (k + 1 < F.lv.size() && L.has_val[i] && F.lv[k + 1].has_val[L.parent[i]]) {
+            InterpItem<D, D> q{};
+            q.child = V(ty, L.tgt_slot[i]);
+            q.parent = V(ty_of((int)k + 1), F.lv[k + 1].tgt_slot[L.parent[i]]);
+            q.octant = octant_of(L.nodes[i]);
+            q.accumulate = L.has_ifft[i];
+            itp[k].push_back(q);
+          }
+        }
+      }
+      for (const RowDesc& rd : F.rows) {
+        const SpecSet* ss = nullptr;
+        LGF_HIP_CHECK(spectra_for(p->ctx, nb, 1 << rd.k, &ss));
+        OctLevel& L = F.lv[rd.k];
+        const int ty = ty_of(rd.k);
+        MacRow<D> m{};
+        for (int i = 0; i < kMacL; ++i) {
+          const int t = rd.tgt_node[i];
+          m.tgt[i] = (t >= 0 && L.has_ifft[t]) ? L.tgt_slot[t] : -1;
+        }
+        for (int j = 0; j < 36; ++j)
+          for (int q = 0; q < kMacSlots; ++q) {
+            const int id = rd.src_node[j][q];
+            m.src[j][q] = id >= 0 ? L.src_slot[id] : -1;
+          }
+        m.pair_mask = rd.mask;
+        m.flags = (rd.k == 0 ? 1 : 0) | ((rd.key.y & 1) << 1) | ((rd.key.z & 1) << 2);
+        m.fhat = FH(ty, 0);
+        m.uhat = UH(ty, 0);
+        m.kptr = ty == TY_F32 ? (const cpx<D>* const*)ss->kp32 : (const cpx<D>* const*)ss->kp64;
+        rows[ty].push_back(m);
+      }
+    }
+    for (int ty = 0; ty < 2; ++ty) {
+      p->n_fwd += (int64_t)fwd[ty].size();
+      p->n_inv += (int64_t)inv[ty].size();
+      p->n_rows += (int64_t)rows[ty].size();
+      push(steps, l, 3, 0, K_FWD, ty, hi.add(fwd[ty]), fwd[ty].size(), nullptr);
+      push(steps, l, 4, 0, K_MAC, ty, hi.add(rows[ty]), rows[ty].size(), nullptr, work[ty]);
+      push(steps, l, 5, 0, K_INV, ty, hi.add(inv[ty]), inv[ty].size(), nullptr);
+    }
+    for (int k = 1; k < K; ++k) {
+      const int ty = (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
+      push(steps, l, 2, k, K_ANTERP, ty, hi.add(ant[k]), ant[k].size(), p->d_w);
+    }
+    for (int k = K - 2; k >= 0; --k) {
+      const int ty = (ty_of(k) == TY_F32 && ty_of(k + 1) == TY_F64) ? TY_MIX : ty_of(k);
+      push(steps, l, 6, 100 - k, K_INTERP, ty, hi.add(itp[k]), itp[k].size(), p->d_w);
+    }
+    std::vector<CombineItem<D>> cmb;
+    const double h2 = h * h;
+    for (size_t a = 0; a < ids[l].size(); ++a) {
+      const int i = ids[l][a];
+      CombineItem<D> c{};
+      c.dst_out = i * N3;
+      const int ts = chT[l].lv[0].tgt_slot[a];
+      c.v = ts >= 0 ? V(tyb, ts) : nullptr;
+      c.base = l > 0 ? JW(i) : nullptr;
+      c.scale = h2;
+      cmb.push_back(c);
+      if (!leaf[i]) {
+        CombineItem<D> q{};
+        q.dst_t = WW(i);
+        const int ta = chA[l].lv[0].tgt_slot[a];
+        q.v = ta >= 0 ? V(tyb, ta) : nullptr;
+        q.base = l > 0 ? JW(i) : nullptr;
+        q.scale = h2;
+        cmb.push_back(q);
+      }
+    }
+    push(steps, l, 7, 0, K_COMBINE, tyb, hi.add(cmb), cmb.size(), nullptr);
+  }
+
+  if (p->fp32 && p->dc_iters > 0) {
+    std::vector<ResidualItem> it;
+    for (int64_t i = 0; i < n; ++i) {
+      ResidualItem r{};
+      r.r = p->r + i * N3;
+      r.off = i * N3;
+      for (int face = 0; face < 6; ++face) {
+        const int nbi = face_nbr((int)i, face);
+        r.nbr_off[face] = nbi >= 0 ? (int64_t)nbi * N3 : -1;
+      }
+      const double h = std::ldexp(1.0, -lev[i]);
+      r.inv_h2 = 1.0 / (h * h);
+      r.leaf = leaf[i];
+      it.push_back(r);
+    }
+    push(rsteps, 0, 0, 0, K_RESIDUAL, TY_F64, hi.add(it), it.size(), nullptr);
+  }
+
+  void* d_items = nullptr;
+  LGF_HIP_CHECK(ar.alloc(&d_items, hi.buf.size()));
+  if (!hi.buf.empty())
+    LGF_HIP_CHECK(hipMemcpy(d_items, hi.buf.data(), hi.buf.size(), hipMemcpyHostToDevice));
+  p->d_items = d_items;
+  auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
+    for (const PendingStep& s : in)
+      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work});
+  };
+  fin(steps, p->pass);
+  fin(rsteps, p->residual);
+  std::set<int> used;
+  for (int l = 0; l < LR; ++l)
+    for (const RowDesc& rd : chT[l].rows) used.insert(rd.k);
+  p->n_spectra = 0;
+  for (int k : used) p->n_spectra += k == 0 ? 343 : 316;
+  (void)err;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
+                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err) {
+  Plan* p = new Plan();
+  p->nb = nb;
+  p->n_i = n_i;
+  p->fp32 = fp32;
+  p->dc_iters = fp32 ? dc_iters : 0;
+  p->nblocks = n;
+  hipError_t e = device_ctx(&p->ctx);
+  if (e != hipSuccess) {
+    delete p;
+    return e;
+  }
+  std::vector<I3> coords(n);
+  std::vector<int> lev(n);
+  int LR = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    coords[i] = {blocks[3 * i], blocks[3 * i + 1], blocks[3 * i + 2]};
+    lev[i] = levels ? levels[i] : 0;
+    LR = std::max(LR, lev[i] + 1);
+  }
+  p->LR = LR;
+  e = build_plan(p, coords, lev, budget, err);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return e;
+  }
+  *out = p;
+  return hipSuccess;
+}
+
+void plan_free(Plan* p) {
+  if (!p) return;
+  for (void* a : p->allocs) (void)hipFree(a);
+  delete p;
+}
+
+// ----------------------------------------------------------------------------- execution
+namespace {
+
+template <typename T>
+hipError_t launch_kind(int kind, int nb, SetTable& t, hipStream_t st) {
+  switch (kind) {
+    case K_CONVERT: return launch_convert<T>(nb, t, st);
+    case K_REFINE: return launch_refine<T>(nb, t, st);
+    case K_CORRECT: return launch_correct<T>(nb, t, st);
+    case K_ANTERP: return launch_anterp<T, T>(nb, t, st);
+    case K_FWD: return launch_fft_fwd<T>(nb, t, st);
+    case K_MAC: return launch_mac<T>(nb, t, st);
+    case K_INV: return launch_fft_inv<T>(nb, t, st);
+    case K_INTERP: return launch_interp<T, T>(nb, t, st);
+    case K_COMBINE: return launch_combine<T>(nb, t, st);
+    case K_COARSEN: return launch_coarsen(nb, t, st);
+    case K_RESIDUAL: return launch_residual(nb, t, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_typed(int kind, int ty, int nb, SetTable& t, hipStream_t st) {
+  if (ty == 0) return launch_kind<float>(kind, nb, t, st);
+  if (ty == 1) return launch_kind<double>(kind, nb, t, st);
+  if (kind == K_ANTERP) return launch_anterp<float, double>(nb, t, st);
+  if (kind == K_INTERP) return launch_interp<float, double>(nb, t, st);
+  return hipErrorInvalidValue;
+}
+
+struct Ref {
+  int l, phase, sub, kind, nb, ty;
+  int member;
+  const Step* step;
+  bool operator<(const Ref& o) const {
+    if (l != o.l) return l < o.l;
+    if (phase != o.phase) return phase < o.phase;
+    if (sub != o.sub) return sub < o.sub;
+    if (kind != o.kind) return kind < o.kind;
+    if (nb != o.nb) return nb < o.nb;
+    if (ty != o.ty) return ty < o.ty;
+    return member < o.member;
+  }
+};
+
+}  // namespace
+
+namespace {
+struct ProfRec { int kind, ty, nb; int64_t work; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+void profile_enable(bool on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on;
+}
+
+hipError_t profile_collect(std::vector<ProfileEntry>* out) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  std::map<std::array<int, 3>, ProfileEntry> acc;
+  for (ProfRec& r : g_prof) {
+    LGF_HIP_CHECK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    LGF_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+    ProfileEntry& e = acc[{r.kind, r.ty, r.nb}];
+    e.kind = r.kind; e.ty = r.ty; e.nb = r.nb;
+    e.launches += 1;
+    e.ms += ms;
+    e.work += r.work;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  out->clear();
+  for (auto& kv : acc) out->push_back(kv.second);
+  return hipSuccess;
+}
+
+hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st) {
+  std::vector<Ref> refs;
+  for (size_t i = 0; i < m.size(); ++i) {
+    const std::vector<Step>& sv = residual ? m[i].p->residual : m[i].p->pass;
+    for (const Step& s : sv)
+      refs.push_back({s.l, s.phase, s.sub, s.kind, m[i].p->nb, s.ty, (int)i, &s});
+  }
+  std::sort(refs.begin(), refs.end());
+  size_t a = 0;
+  while (a < refs.size()) {
+    size_t b = a;
+    SetTable t;
+    t.n = 0;
+    t.pad = 0;
+    while (b < refs.size() && t.n < kMaxSets && refs[b].l == refs[a].l && refs[b].phase == refs[a].phase &&
+           refs[b].sub == refs[a].sub && refs[b].kind == refs[a].kind && refs[b].nb == refs[a].nb &&
+           refs[b].ty == refs[a].ty) {
+      const Member& mm = m[refs[b].member];
+      WorkSet& ws = t.s[t.n++];
+      ws.items = refs[b].step->items;
+      ws.count = refs[b].step->count;
+      ws.wg_begin = 0;
+      ws.aux = 0;
+      ws.in = mm.in;
+      ws.out = mm.out;
+      ws.w = refs[b].step->w;
+      ++b;
+    }
+    bool prof;
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      prof = g_prof_on;
+    }
+    ProfRec rec{refs[a].kind, refs[a].ty, refs[a].nb, 0, nullptr, nullptr};
+    if (prof) {
+      for (size_t q = a; q < b; ++q) rec.work += refs[q].step->work;
+      LGF_HIP_CHECK(hipEventCreate(&rec.a));
+      LGF_HIP_CHECK(hipEventCreate(&rec.b));
+      LGF_HIP_CHECK(hipEventRecord(rec.a, st));
+    }
+    hipError_t e = launch_typed(refs[a].kind, refs[a].ty, refs[a].nb, t, st);
+    if (e != hipSuccess) return e;
+    if (prof) {
+      LGF_HIP_CHECK(hipEventRecord(rec.b, st));
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof.push_back(rec);
+    }
+    a = b;
+  }
+  return hipSuccess;
+}
+
+hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
+  LGF_HIP_CHECK(run_steps(m, false, st));
+  int iters = 0;
+  for (const Member& x : m) iters = std::max(iters, x.p->dc_iters);
+  for (int it = 0; it < iters; ++it) {
+    std::vector<Member> act, corr;
+    for (const Member& x : m)
+      if (x.p->dc_iters > it) {
+        act.push_back(x);
+        corr.push_back({x.p, x.p->r, x.p->e});
+      }
+    LGF_HIP_CHECK(run_steps(act, true, st));      // r = f - L u
+    LGF_HIP_CHECK(run_steps(corr, false, st));    // e = S(r)
+    for (const Member& x : act) {
+      const int64_t N3 = (int64_t)x.p->nb * x.p->nb * x.p->nb;
+      LGF_HIP_CHECK(launch_axpy(x.out, x.p->e, x.p->nblocks * N3, st));
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace lgf

@@ -1,0 +1,106 @@
+// Host-side plan of a (multi-resolution) FLGF solve: octree per refinement level and channel,
+// interaction rows, slots of the device arenas, and the ordered list of kernel steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace lgf {
+
+// ----------------------------------------------------------------------------- device context
+struct SpecSet {
+  int nb = 0, s = 0;
+  c64* d64 = nullptr;                  // 343 spectra, index (dz+3)*49+(dy+3)*7+(dx+3)
+  c32* d32 = nullptr;
+  const c64** kp64 = nullptr;          // device arrays of 343 pointers
+  const c32** kp32 = nullptr;
+};
+
+struct DeviceCtx {
+  int device = -1;
+  double* cube = nullptr;              // LGF table [101][101][101]
+  std::map<std::pair<int, int>, SpecSet> spectra;
+  std::mutex mu;
+  hipStream_t stream = nullptr;        // plan-time work
+  int64_t bytes = 0;                   // table + spectra
+};
+
+// Returns the context of the current device, building the LGF table on first use.
+hipError_t device_ctx(DeviceCtx** out);
+hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out);
+
+// ----------------------------------------------------------------------------- steps
+enum StepKind : int {
+  K_COARSEN = 0, K_CONVERT, K_REFINE, K_CORRECT, K_ANTERP, K_FWD, K_MAC, K_INV, K_INTERP,
+  K_COMBINE, K_RESIDUAL, K_COUNT
+};
+
+struct Step {
+  int l, phase, sub;                   // ordering key: refinement level, phase, sub-step
+  int kind;
+  int ty;                              // element type: 0 FP32, 1 FP64, 2 FP32 child / FP64 parent
+  const void* items;                   // device pointer into the plan's item buffer
+  int32_t count;
+  const double* w;                     // weight table for the kernel (or nullptr)
+  int64_t work;                        // MAC: block interactions in the step (for flop counts)
+};
+
+// Optional launch timing: when enabled, every launch is bracketed by HIP events on its stream
+// and the elapsed times are accumulated per (kind, element type) at profile_collect().
+void profile_enable(bool on);
+struct ProfileEntry { int kind, ty, nb; int64_t launches; double ms; int64_t work; };
+hipError_t profile_collect(std::vector<ProfileEntry>* out);
+
+struct Plan {
+  int nb = 0, n_i = 0, LR = 0, Kmax = 0;
+  bool fp32 = false;
+  int dc_iters = 0;
+  int64_t nblocks = 0;
+  DeviceCtx* ctx = nullptr;
+
+  std::vector<Step> pass;              // one solve pass: input field -> output field
+  std::vector<Step> residual;          // r = f - L u (FP32 refine only)
+
+  // owned device memory
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  double* fe = nullptr;                // coarsened source (multi-level)
+  void* jw = nullptr;                  // T [n][N3]
+  void* w = nullptr;                   // T [n][N3]
+  void* src = nullptr;                 // T [nsrc][N3]
+  void* fhat = nullptr;                // cpx<T> [nsrc][S]
+  void* uhat = nullptr;                // cpx<T> [ntgt][S]
+  void* v = nullptr;                   // T [ntgt][N3]
+  double* r = nullptr;                 // DC residual [n][N3]
+  double* e = nullptr;                 // DC correction [n][N3]
+  double* d_w = nullptr;               // Lagrange matrix [2 nb][nb]
+  double* d_w3 = nullptr;              // quadratic refinement table [(2 nb + 2)][4]
+  void* d_items = nullptr;
+
+  // statistics
+  int64_t interactions = 0, n_fwd = 0, n_inv = 0, n_rows = 0, n_spectra = 0;
+};
+
+hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
+                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err);
+void plan_free(Plan* p);
+
+struct Member {
+  Plan* p;
+  const double* in;
+  double* out;
+};
+// Runs the given step lists of several plans with shared launches, in key order.
+hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st);
+// Full solve of several plans (pass, then defect-correction iterations), shared launches.
+hipError_t solve_members(const std::vector<Member>& m, hipStream_t st);
+
+}  // namespace lgf

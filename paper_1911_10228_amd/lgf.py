@@ -1,0 +1,257 @@
+"""Thin ctypes binding of ``liblgf.so`` (C ABI in ``include/lgf.h``).
+
+Argument marshalling only: every step of a solve runs in the library's HIP kernels.  Torch is
+used for device memory (tensors passed by ``data_ptr()``) and streams.  Loading fails loudly if
+the library has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblgf.so")
+
+LGF_FP64_PLAIN = 0
+LGF_FP32_REFINE = 1
+
+EXPORTS = ["lgf_init", "lgf_plan", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
+           "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
+           "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
+           "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy"]
+
+
+class LgfError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("dc_iters", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32), ("hbm_budget", C.c_uint64)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("blocks", C.c_int64), ("unknowns", C.c_int64), ("refinement_levels", C.c_int32),
+                ("max_octree_levels", C.c_int32), ("interactions", C.c_int64),
+                ("fft_forward", C.c_int64), ("fft_inverse", C.c_int64), ("mac_rows", C.c_int64),
+                ("workspace_bytes", C.c_int64), ("spectra", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1911_10228_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    sig = {
+        "lgf_init": ([], I32),
+        "lgf_plan": ([P, P, I64, I32, I32, P, P], I32),
+        "lgf_solve": ([P, P, P, P], I32),
+        "lgf_solve_batch": ([P, P, P, I32, P], I32),
+        "lgf_plan_get_info": ([P, P], I32),
+        "lgf_plan_destroy": ([P], I32),
+        "lgf_status_string": ([I32], C.c_char_p),
+        "lgf_green_eval": ([P, I64, P, P], I32),
+        "lgf_green_table": ([P, P], I32),
+        "lgf_kernel_spectrum": ([I32, I32, I32, I32, I32, P, P], I32),
+        "lgf_profile": ([I32], I32),
+        "lgf_profile_read": ([P, I32, P], I32),
+        "lgf_server_create": ([U64, P, P], I32),
+        "lgf_server_submit": ([P, P, P, P, P], I32),
+        "lgf_server_poll": ([P, I64, P], I32),
+        "lgf_server_wait_all": ([P], I32),
+        "lgf_server_stats": ([P, P, P, P, P], I32),
+        "lgf_server_destroy": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().lgf_status_string(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise LgfError(code, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def init():
+    _check(load().lgf_init(), "lgf_init")
+
+
+class Plan:
+    """A planned solve for a block layout (see include/lgf.h for the conventions)."""
+
+    def __init__(self, blocks, levels, n_b: int, interp_order: int,
+                 precision: int = LGF_FP64_PLAIN, dc_iters: int = 0, hbm_budget: int = 0):
+        lib = load()
+        b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+        lv = np.ascontiguousarray(np.zeros(len(b), np.int32) if levels is None
+                                  else np.asarray(levels, dtype=np.int32).reshape(-1))
+        opt = Options(precision, dc_iters, 0, 0, hbm_budget)
+        h = C.c_void_p()
+        _check(lib.lgf_plan(b.ctypes.data, lv.ctypes.data, len(b), n_b, interp_order,
+                            C.byref(opt), C.byref(h)), "lgf_plan")
+        self._h = h
+        self.n_b = n_b
+        self.nblocks = len(b)
+        self.precision = precision
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(load().lgf_plan_get_info(self._h, C.byref(inf)), "lgf_plan_get_info")
+        return inf.as_dict()
+
+    def solve(self, f, u, stream=None):
+        """u <- solution for source f; both float64 CUDA tensors [n, N_b, N_b, N_b]."""
+        self._check_field(f)
+        self._check_field(u)
+        _check(load().lgf_solve(self._h, _ptr(f), _ptr(u), _stream(stream)), "lgf_solve")
+
+    def _check_field(self, t):
+        import torch
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == self.nblocks * self.n_b ** 3):
+            raise ValueError("fields must be contiguous float64 CUDA tensors [n, N_b, N_b, N_b]")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().lgf_plan_destroy(self._h), "lgf_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(plans, fs, us, stream=None):
+    n = len(plans)
+    for p, f, u in zip(plans, fs, us):
+        p._check_field(f)
+        p._check_field(u)
+    hp = (C.c_void_p * n)(*[p.handle.value for p in plans])
+    fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+    up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+    _check(load().lgf_solve_batch(hp, fp, up, n, _stream(stream)), "lgf_solve_batch")
+
+
+def green_eval(n_dev, out_dev, stream=None):
+    """out[i] = G(n[i]) on the device: n int32 CUDA tensor [m, 3], out float64 [m]."""
+    _check(load().lgf_green_eval(_ptr(n_dev), n_dev.shape[0], _ptr(out_dev), _stream(stream)),
+           "lgf_green_eval")
+
+
+def green_table(out_dev, stream=None):
+    """Copy the dense FP64 table cube [101, 101, 101] into out (float64 CUDA tensor)."""
+    _check(load().lgf_green_table(_ptr(out_dev), _stream(stream)), "lgf_green_table")
+
+
+def kernel_spectrum(n_b, s, d, out_dev, stream=None):
+    """FP64 half spectrum [2N_b, 2N_b, N_b+1] complex of G(s (d N_b + r)) into out (float64
+    CUDA tensor [2N_b, 2N_b, N_b+1, 2])."""
+    _check(load().lgf_kernel_spectrum(n_b, s, int(d[0]), int(d[1]), int(d[2]), _ptr(out_dev),
+                                      _stream(stream)), "lgf_kernel_spectrum")
+
+
+class ProfileEntry(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("precision", C.c_int32), ("n_b", C.c_int32),
+                ("reserved", C.c_int32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("work", C.c_int64)]
+
+
+KIND_NAMES = ["coarsen", "convert", "refine", "correct", "anterp", "fft_fwd", "mac", "fft_inv",
+              "interp", "combine", "residual"]
+
+
+def profile(enable: bool):
+    _check(load().lgf_profile(1 if enable else 0), "lgf_profile")
+
+
+def profile_read() -> list:
+    """Per (kernel, precision, N_b): launches, summed ms (HIP events), summed work."""
+    arr = (ProfileEntry * 64)()
+    n = C.c_int32()
+    _check(load().lgf_profile_read(arr, 64, C.byref(n)), "lgf_profile_read")
+    return [{"kernel": KIND_NAMES[e.kind], "precision": ["fp32", "fp64", "fp32/fp64"][e.precision],
+             "n_b": e.n_b, "launches": e.launches, "ms": e.ms, "work": e.work}
+            for e in arr[:min(n.value, 64)]]
+
+
+class Server:
+    """Continuous-batching solve server (lgf_server_* in include/lgf.h)."""
+
+    def __init__(self, hbm_budget: int = 0, stream=None):
+        h = C.c_void_p()
+        _check(load().lgf_server_create(hbm_budget, _stream(stream), C.byref(h)), "lgf_server_create")
+        self._h = h
+
+    def submit(self, plan: Plan, f, u) -> int:
+        plan._check_field(f)
+        plan._check_field(u)
+        rid = C.c_int64()
+        _check(load().lgf_server_submit(self._h, plan.handle, _ptr(f), _ptr(u), C.byref(rid)),
+               "lgf_server_submit")
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        done = C.c_int32()
+        _check(load().lgf_server_poll(self._h, rid, C.byref(done)), "lgf_server_poll")
+        return bool(done.value)
+
+    def wait_all(self):
+        _check(load().lgf_server_wait_all(self._h), "lgf_server_wait_all")
+
+    def stats(self) -> dict:
+        p50, p99, pts = C.c_double(), C.c_double(), C.c_double()
+        n = C.c_int64()
+        _check(load().lgf_server_stats(self._h, C.byref(p50), C.byref(p99), C.byref(pts), C.byref(n)),
+               "lgf_server_stats")
+        return {"p50_us": p50.value, "p99_us": p99.value, "points_per_s": pts.value,
+                "completed": n.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().lgf_server_destroy(self._h), "lgf_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

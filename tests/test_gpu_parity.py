@@ -1,0 +1,185 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: FP64 solves within 1e-12 relative L-inf (max |u_gpu - u_oracle| / max |u_oracle|);
+FP32 + defect correction within 1e-6; the LGF table within 1e-14 relative; integer bookkeeping
+(interaction counts) exact.
+"""
+import numpy as np
+import pytest
+
+from oracle import direct, fmm, lgf as olgf, multires
+from paper_1911_10228_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lgf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_10228_amd import lgf as m
+    m.init()
+    return m
+
+
+def rel_linf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def gpu_solve(lgf, L, precision=0, dc=0, order=None, plan=None):
+    p = plan or lgf.Plan(L.blocks, L.levels, L.n_b, order or L.interp_order, precision, dc)
+    f = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
+    u = torch.zeros_like(f)
+    p.solve(f, u)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), p
+
+
+# ----------------------------------------------------------------------------- LGF table
+def test_green_table_matches_oracle(lgf):
+    cube = torch.zeros((101, 101, 101), dtype=torch.float64, device="cuda")
+    lgf.green_table(cube)
+    torch.cuda.synchronize()
+    g = cube.cpu().numpy()
+    tri = olgf.sorted_triples()
+    ref = olgf.table()[tri[:, 0], tri[:, 1], tri[:, 2]]
+    got = g[tri[:, 0], tri[:, 1], tri[:, 2]]
+    err = np.abs(got - ref) / np.abs(ref)
+    assert err.max() <= 1e-14, (err.max(), tri[err.argmax()])
+    # the GPU table satisfies L G = delta by itself
+    assert abs(g[1, 0, 0] - g[0, 0, 0] - 1.0 / 6.0) <= 1e-15
+    assert abs(g[0, 0, 0] - olgf.watson_g0()) <= 2e-15 * abs(g[0, 0, 0])
+
+
+def test_green_eval_policy_regions(lgf):
+    rng = np.random.default_rng(0)
+    pts = np.concatenate([rng.integers(-60, 61, size=(400, 3)), rng.integers(-400, 401, size=(400, 3)),
+                          rng.integers(-3000, 3001, size=(200, 3)),
+                          np.array([[100, 0, 0], [101, 0, 0], [600, 0, 0], [601, 0, 0], [0, 0, 0],
+                                    [36, 48, 80], [360, 480, 0]])]).astype(np.int32)
+    nd = torch.from_numpy(pts).cuda()
+    out = torch.zeros(len(pts), dtype=torch.float64, device="cuda")
+    lgf.green_eval(nd, out)
+    torch.cuda.synchronize()
+    ref = olgf.lgf(pts)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert (np.abs(out.cpu().numpy() - ref) / np.abs(ref)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n_b,s,d", [(8, 1, (0, 0, 0)), (8, 2, (3, -2, 1)), (16, 1, (-1, 2, 0)),
+                                     (16, 4, (2, 3, -3)), (16, 16, (-3, 0, 2))])
+def test_kernel_spectra_match_oracle(lgf, n_b, s, d):
+    P = 2 * n_b
+    out = torch.zeros((P, P, n_b + 1, 2), dtype=torch.float64, device="cuda")
+    lgf.kernel_spectrum(n_b, s, d, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = np.fft.rfftn(fmm.kernel_block(n_b, s, d))
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+# ----------------------------------------------------------------------------- uniform FLGF
+def test_uniform_gaussian_fp64_matches_oracle_and_brute_force(lgf):
+    L = workloads.uniform_gaussian()
+    u, p = gpu_solve(lgf, L)
+    ref = fmm.flgf(L.blocks, L.f, L.n_b, L.interp_order)
+    assert rel_linf(u, ref) <= 1e-12
+    brute = direct.direct_sum(L.blocks, L.f, L.n_b).reshape(u.shape)
+    assert rel_linf(u, brute) <= 1e-12
+    assert p.info()["interactions"] == 64
+
+
+@pytest.mark.parametrize("nblk,n_b,order", [(6, 8, 4), (5, 8, 8), (3, 16, 6)])
+def test_uniform_multilevel_fp64(lgf, nblk, n_b, order):
+    L = workloads.uniform_mixture(nblk=nblk, n_b=n_b, n_gauss=5, seed=nblk + n_b)
+    u, p = gpu_solve(lgf, L, order=order)
+    ref = fmm.flgf(L.blocks, L.f, L.n_b, order)
+    assert rel_linf(u, ref) <= 1e-12
+    counts = fmm.count_interactions(L.blocks)
+    assert p.info()["interactions"] == sum(a + b for _, a, b in counts)
+
+
+def test_sparse_negative_ragged_layout_fp64(lgf):
+    rng = np.random.default_rng(11)
+    blocks = np.unique(rng.integers(-9, 7, size=(70, 3)), axis=0).astype(np.int32)
+    n_b = 8
+    levels = np.zeros(len(blocks), np.int32)
+    pos = workloads.cell_centres(blocks, levels, n_b)
+    f = workloads.gaussian_mixture(pos, [(-10, 5, 0), (20, -30, 10)], [3.0, 2.0], [1.0, -0.5])
+    f = f + 0.01 * rng.normal(size=f.shape)
+    L = workloads.Layout(blocks, levels, n_b, f, 6)
+    u, _ = gpu_solve(lgf, L)
+    ref = fmm.flgf(blocks, f, n_b, 6)
+    assert rel_linf(u, ref) <= 1e-12
+
+
+def test_single_block(lgf):
+    L = workloads.Layout(np.array([[3, -2, 5]], np.int32), np.zeros(1, np.int32), 16,
+                         np.random.default_rng(2).normal(size=(1, 16, 16, 16)), 4)
+    u, _ = gpu_solve(lgf, L)
+    ref = fmm.flgf(L.blocks, L.f, 16, 4)
+    assert rel_linf(u, ref) <= 1e-12
+
+
+def test_uniform_fp32_defect_correction(lgf):
+    L = workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=6, seed=3, interp_order=8)
+    ref = fmm.flgf(L.blocks, L.f, L.n_b, 8)
+    errs = []
+    for dc in (0, 1, 2):
+        u, _ = gpu_solve(lgf, L, precision=1, dc=dc)
+        errs.append(rel_linf(u, ref))
+    assert max(errs) <= 1e-6, errs
+
+
+# ----------------------------------------------------------------------------- multi-resolution
+def two_level(n_b):
+    base = workloads.box_blocks(4, 4, 4)
+    fine = workloads.box_blocks(4, 4, 4, origin=(2, 2, 2))
+    blocks = np.concatenate([base, fine]).astype(np.int32)
+    levels = np.concatenate([np.zeros(64, np.int32), np.ones(64, np.int32)])
+    pos = workloads.cell_centres(blocks, levels, n_b)
+    f = workloads.gaussian_mixture(pos, [(2.0 * n_b - 0.5,) * 3], [0.3 * n_b], [1.0])
+    return workloads.Layout(blocks, levels, n_b, f, 6)
+
+
+def three_level(n_b=8):
+    base = workloads.box_blocks(4, 4, 4)
+    l1 = workloads.box_blocks(4, 4, 4, origin=(2, 2, 2))
+    l2 = workloads.box_blocks(2, 4, 2, origin=(6, 4, 6))
+    blocks = np.concatenate([base, l1, l2]).astype(np.int32)
+    levels = np.concatenate([np.zeros(64), np.ones(64), np.full(16, 2)]).astype(np.int32)
+    pos = workloads.cell_centres(blocks, levels, n_b)
+    f = workloads.gaussian_mixture(pos, [(2.0 * n_b, 2.2 * n_b, 2.0 * n_b)], [0.25 * n_b], [1.0])
+    return workloads.Layout(blocks, levels, n_b, f, 6)
+
+
+@pytest.mark.parametrize("make", [lambda: two_level(8), three_level])
+def test_multires_fp64(lgf, make):
+    L = make()
+    u, _ = gpu_solve(lgf, L)
+    ref = multires.solve(L.blocks, L.levels, L.f, L.n_b, L.interp_order)
+    assert rel_linf(u, ref) <= 1e-12
+
+
+def test_multires_fp32_defect_correction(lgf):
+    L = three_level()
+    ref = multires.solve(L.blocks, L.levels, L.f, L.n_b, L.interp_order)
+    u, _ = gpu_solve(lgf, L, precision=1, dc=2)
+    assert rel_linf(u, ref) <= 1e-6
+
+
+# ----------------------------------------------------------------------------- batching
+def test_batch_equals_alone(lgf):
+    Ls = [workloads.uniform_gaussian(), two_level(8),
+          workloads.uniform_mixture(nblk=3, n_b=16, n_gauss=3, seed=9, interp_order=6)]
+    alone = [gpu_solve(lgf, L)[0] for L in Ls]
+    plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order) for L in Ls]
+    fs = [torch.from_numpy(np.ascontiguousarray(L.f)).cuda() for L in Ls]
+    us = [torch.zeros_like(f) for f in fs]
+    lgf.solve_batch(plans, fs, us)
+    torch.cuda.synchronize()
+    for a, u in zip(alone, us):
+        assert np.array_equal(a, u.cpu().numpy())
