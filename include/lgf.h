@@ -96,6 +96,13 @@ lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* 
                            lgf_stream_t stream);
 
 lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out);
+
+/* Builds the plan on the host only (no device memory, no GPU needed) and checks that every
+ * kernel work item stays inside the plan's buffers; fills *info (may be NULL) with the counts
+ * lgf_plan_get_info would report.  Returns LGF_OK, a validation code, or LGF_EINVAL if an
+ * internal consistency check fails (with a message on stderr). */
+lgf_status lgf_plan_check(const int32_t* blocks, const int32_t* levels, int64_t n, int32_t N_b,
+                          int32_t interp_order, const lgf_options* opt, lgf_plan_info* info);
 lgf_status lgf_plan_destroy(lgf_plan_t p);
 const char* lgf_status_string(lgf_status s);
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -68,8 +69,37 @@ lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int
   std::string err;
   hipError_t e = lgf::plan_build(blocks, levels, n, N_b, interp_order, o.precision == LGF_FP32_REFINE,
                                  o.dc_iters, o.hbm_budget, &p, &err);
-  if (e != hipSuccess) return from_hip(e);
+  if (e != hipSuccess) {
+    if (!err.empty()) std::fprintf(stderr, "lgf_plan: %s\n", err.c_str());
+    return from_hip(e);
+  }
   *out = new lgf_plan_s{p};
+  return LGF_OK;
+}
+
+lgf_status lgf_plan_check(const int32_t* blocks, const int32_t* levels, int64_t n, int32_t N_b,
+                          int32_t interp_order, const lgf_options* opt, lgf_plan_info* info) {
+  if (!blocks || n <= 0) return LGF_EINVAL;
+  if (N_b != 8 && N_b != 16) return LGF_ELAYOUT;
+  if (interp_order < 2 || interp_order > N_b) return LGF_ELAYOUT;
+  lgf_options o{};
+  if (opt) o = *opt;
+  if (o.precision != LGF_FP64_PLAIN && o.precision != LGF_FP32_REFINE) return LGF_EINVAL;
+  if (o.dc_iters < 0 || o.dc_iters > 8) return LGF_EINVAL;
+  if (!validate_layout(blocks, levels, n)) return LGF_ELAYOUT;
+  lgf::Plan* p = nullptr;
+  std::string err;
+  hipError_t e = lgf::plan_build(blocks, levels, n, N_b, interp_order, o.precision == LGF_FP32_REFINE,
+                                 o.dc_iters, o.hbm_budget, &p, &err, /*dry=*/true);
+  if (e != hipSuccess) {
+    if (!err.empty()) std::fprintf(stderr, "lgf_plan_check: %s\n", err.c_str());
+    return e == hipErrorOutOfMemory ? LGF_ENOMEM : LGF_EINVAL;
+  }
+  if (info) {
+    lgf_plan_s tmp{p};
+    lgf_plan_get_info(&tmp, info);
+  }
+  lgf::plan_free(p);
   return LGF_OK;
 }
 

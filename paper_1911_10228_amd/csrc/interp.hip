@@ -62,61 +62,63 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
   }
 }
 
-// parent = sum_c (Wz (x) Wy (x) Wx)^T child_c, arithmetic in the parent's type TP
+// parent = sum_c (Wz (x) Wy (x) Wx)^T child_c, arithmetic in the parent's type TP.
+// One workgroup computes a slab of NB/8 parent z-planes: the z pass comes first (it mixes child
+// planes into the slab's parent planes), so the y and x passes of different slabs are
+// independent and eight workgroups share a parent without redundant arithmetic.
 template <int NB, typename TC, typename TP>
-__global__ __launch_bounds__(kOpThreads) void anterp_kernel(SetTable sets) {
+__global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
   using T = TP;
-  constexpr int N3 = NB * NB * NB;
-  constexpr int PER = N3 / kOpThreads;
-  __shared__ T b0[N3];
-  __shared__ T b1[N3];
-  __shared__ T w[2][NB][NB];      // W rows of octant 0 and 1: w[c][r][m] = W[(c NB + r)][m]
+  constexpr int SL = NB / 8;           // parent z-planes per workgroup
+  __shared__ T w[2][NB][NB];           // w[c][r][m] = W[c NB + r][m]
+  __shared__ T t1[SL][NB][NB];
+  __shared__ T t2[SL][NB][NB];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
-  const AnterpItem<TC, TP>& it = ((const AnterpItem<TC, TP>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const AnterpItem<TC, TP>& it = ((const AnterpItem<TC, TP>*)ws.items)[local / 8];
+  const int z0 = (int)(local % 8) * SL;
   const double* __restrict__ W = ws.w;
-  for (int i = threadIdx.x; i < 2 * NB * NB; i += kOpThreads) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * NB * NB; i += NB * NB) {
     const int cc = i / (NB * NB), r = (i / NB) % NB, m = i % NB;
     w[cc][r][m] = T(W[(cc * NB + r) * NB + m]);
   }
-  T acc[PER > 0 ? PER : 1];
+  const int a = tid % NB, b = tid / NB;          // (X, Y) in the z pass; (x or X, y) later
+  T acc[SL];
 #pragma unroll
-  for (int j = 0; j < (PER > 0 ? PER : 1); ++j) acc[j] = T(0);
+  for (int zz = 0; zz < SL; ++zz) acc[zz] = T(0);
   for (int oc = 0; oc < 8; ++oc) {
     const TC* ch = it.child[oc];
     if (!ch) continue;
     const int cx = oc & 1, cy = (oc >> 1) & 1, cz = (oc >> 2) & 1;
     __syncthreads();
-    for (int i = threadIdx.x; i < N3; i += kOpThreads) b0[i] = T(ch[i]);
-    __syncthreads();
-    for (int i = threadIdx.x; i < N3; i += kOpThreads) {     // x: t1[Z][Y][x] = sum_X W[X][x] c[Z][Y][X]
-      const int x = i % NB, YZ = i / NB;
+#pragma unroll
+    for (int zz = 0; zz < SL; ++zz) {                            // z: t1[z][Y][X]
       T s = 0;
 #pragma unroll
-      for (int X = 0; X < NB; ++X) s += w[cx][X][x] * b0[YZ * NB + X];
-      b1[i] = s;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < N3; i += kOpThreads) {     // y
-      const int x = i % NB, y = (i / NB) % NB, Z = i / (NB * NB);
-      T s = 0;
-#pragma unroll
-      for (int Y = 0; Y < NB; ++Y) s += w[cy][Y][y] * b1[(Z * NB + Y) * NB + x];
-      b0[i] = s;
+      for (int Z = 0; Z < NB; ++Z) s += w[cz][Z][z0 + zz] * T(ch[(Z * NB + b) * NB + a]);
+      t1[zz][b][a] = s;
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {                            // z
-      const int i = threadIdx.x + j * kOpThreads;
-      const int xy = i % (NB * NB), z = i / (NB * NB);
+    for (int zz = 0; zz < SL; ++zz) {                            // y: t2[z][y][X]
       T s = 0;
 #pragma unroll
-      for (int Z = 0; Z < NB; ++Z) s += w[cz][Z][z] * b0[Z * NB * NB + xy];
-      acc[j] += s;
+      for (int Y = 0; Y < NB; ++Y) s += w[cy][Y][b] * t1[zz][Y][a];
+      t2[zz][b][a] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int zz = 0; zz < SL; ++zz) {                            // x: out[z][y][x]
+      T s = 0;
+#pragma unroll
+      for (int X = 0; X < NB; ++X) s += w[cx][X][a] * t2[zz][b][X];
+      acc[zz] += s;
     }
   }
 #pragma unroll
-  for (int j = 0; j < PER; ++j) it.dst[threadIdx.x + j * kOpThreads] = acc[j];
+  for (int zz = 0; zz < SL; ++zz) it.dst[((z0 + zz) * NB + b) * NB + a] = acc[zz];
 }
 
 template <int NB, typename T>
@@ -292,7 +294,10 @@ __global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x
   return hipGetLastError();
 
 template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st) {
-  LGF_LAUNCH_SIMPLE(anterp_kernel<NB, TC, TP>)
+  const int64_t wg = assign_wg(t, 8);
+  if (wg == 0) return hipSuccess;
+  LGF_NB_DISPATCH(nb, anterp_kernel<NB, TC, TP><<<(unsigned)wg, NB * NB, 0, st>>>(t));
+  return hipGetLastError();
 }
 template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t, hipStream_t st) {
   LGF_LAUNCH_SIMPLE(interp_kernel<NB, TC, TP>)

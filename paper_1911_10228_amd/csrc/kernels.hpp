@@ -50,15 +50,19 @@ template <typename T> struct FftInvItem {
   const cpx<T>* src;     // half spectrum
   T* dst;                // n_b^3 real block, receives IFFT / P^3
 };
-template <typename T> struct MacRow {
-  int32_t tgt[kMacL];                  // target slots (-1: none)
-  int32_t src[36][kMacSlots];          // source slots per (jz, jy) and x slot (-1: none)
-  uint64_t pair_mask;                  // bit jz*6+jy set if src[jz*6+jy] has a source
-  int32_t flags;                       // bit0 base level (near field on), bit1 y parity, bit2 z parity
-  int32_t pad;
+// A MAC tile: the 2x2 sibling rows y in {2py, 2py+1}, z in {2pz, 2pz+1} of an x window of 8
+// blocks starting at x0 = 8 wx.  Siblings share their parent's neighbours, so all four rows draw
+// from the same 6x6 source rows y' = 2py-2+jy, z' = 2pz-2+jz (jy, jz in 0..5).
+template <typename T> struct MacTile {
+  int32_t tgt[4][kMacL];               // target slots of row r = ry + 2 rz, x = x0 + i (-1: none)
+  int32_t src[36][kMacSlots];          // source slots of source row jz*6+jy, x' = x0 - 3 + s
+                                       // (absent sources: the arena's all-zero spectrum)
+  uint64_t pair_mask;                  // bit jz*6+jy set if that source row has a source
+  int32_t flags;                       // bit0: base level (near field included)
+  int32_t row_mask;                    // bit r set if row r has a target
   const cpx<T>* fhat;                  // source spectra arena (slot * S)
   cpx<T>* uhat;                        // target spectra arena (slot * S)
-  const cpx<T>* const* kptr;           // 343 kernel-spectrum pointers, index (dz+3)*49+(dy+3)*7+dx+3
+  const cpx<T>* const* kptr;           // 343 kernel spectra of the tile's level, (dz+3)*49+(dy+3)*7+dx+3
 };
 // TC: element type of the child level, TP: of the parent level (they differ where an FP32
 // base level meets FP64 coarse levels).

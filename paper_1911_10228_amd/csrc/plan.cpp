@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <set>
+#include <tuple>
 #include <unordered_map>
 
 namespace lgf {
@@ -98,17 +99,17 @@ struct OctLevel {
   std::vector<int> src_slot, tgt_slot;
 };
 
-struct RowDesc {
+struct TileDesc {
   int k;
-  I3 key;                              // (window, y, z)
-  int tgt_node[kMacL];
+  I3 key;                              // (x window, y pair, z pair)
+  int tgt_node[4][kMacL];
   int src_node[36][kMacSlots];
   uint64_t mask;
 };
 
 struct Fmm {
   std::vector<OctLevel> lv;
-  std::vector<RowDesc> rows;
+  std::vector<TileDesc> rows;
   int64_t interactions = 0;
   std::vector<int64_t> level_interactions;
 };
@@ -165,7 +166,7 @@ void fmm_build(const std::vector<I3>& base, const std::vector<char>& src, const 
     L.has_ifft.assign(n, 0);
     L.referenced.assign(n, 0);
     const bool base_level = (k == 0);
-    std::map<I3, RowDesc> rows;
+    std::map<I3, TileDesc> rows;
     for (size_t t = 0; t < n; ++t) {
       if (!L.is_tgt[t]) continue;
       const I3 a = L.nodes[t];
@@ -185,28 +186,27 @@ void fmm_build(const std::vector<I3>& base, const std::vector<char>& src, const 
       L.has_ifft[t] = 1;
       F.interactions += cnt;
       F.level_interactions[k] += cnt;
-      const int wx = floordiv(a.x, kMacL);
-      const I3 key{wx, a.y, a.z};
+      const int wx = floordiv(a.x, kMacL), py = floordiv2(a.y), pz = floordiv2(a.z);
+      const I3 key{wx, py, pz};
       auto rit = rows.find(key);
       if (rit == rows.end()) {
-        RowDesc r;
+        TileDesc r;
         r.k = k;
         r.key = key;
-        for (int i = 0; i < kMacL; ++i) r.tgt_node[i] = -1;
+        for (int q = 0; q < 4; ++q)
+          for (int i = 0; i < kMacL; ++i) r.tgt_node[q][i] = -1;
         r.mask = 0;
         for (int jz = 0; jz < 6; ++jz)
-          for (int jy = 0; jy < 6; ++jy) {
-            const int dz = cz - 3 + jz, dy = cy - 3 + jy;
-            for (int s = 0; s < kMacSlots; ++s) {
-              auto it = L.index.find({wx * kMacL - 3 + s, a.y - dy, a.z - dz});
+          for (int jy = 0; jy < 6; ++jy)
+            for (int q = 0; q < kMacSlots; ++q) {
+              auto it = L.index.find({wx * kMacL - 3 + q, 2 * py - 2 + jy, 2 * pz - 2 + jz});
               const int id = (it != L.index.end() && L.is_src[it->second]) ? it->second : -1;
-              r.src_node[jz * 6 + jy][s] = id;
+              r.src_node[jz * 6 + jy][q] = id;
               if (id >= 0) r.mask |= 1ull << (jz * 6 + jy);
             }
-          }
         rit = rows.emplace(key, r).first;
       }
-      rit->second.tgt_node[a.x - wx * kMacL] = (int)t;
+      rit->second.tgt_node[(a.y - 2 * py) + 2 * (a.z - 2 * pz)][a.x - wx * kMacL] = (int)t;
     }
     for (auto& kv : rows) F.rows.push_back(kv.second);
   }
@@ -228,6 +228,14 @@ void fmm_build(const std::vector<I3>& base, const std::vector<char>& src, const 
 }
 
 // ----------------------------------------------------------------------------- device memory
+void* fake_alloc(Plan* p, size_t bytes) {
+  if (!p->next_fake) p->next_fake = (uintptr_t)1 << 44;
+  void* q = (void*)p->next_fake;
+  p->next_fake += (bytes + 2 * 4096 + 4095) / 4096 * 4096;     // guard gap between ranges
+  p->ranges.push_back({(uintptr_t)q, bytes});
+  return q;
+}
+
 struct Arena {
   Plan* p;
   uint64_t budget;
@@ -235,13 +243,46 @@ struct Arena {
     *ptr = nullptr;
     if (bytes == 0) return hipSuccess;
     if (budget && (uint64_t)(p->bytes + (int64_t)bytes) > budget) return hipErrorOutOfMemory;
-    hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) return e;
-    p->allocs.push_back(*ptr);
+    if (p->dry) {
+      *ptr = fake_alloc(p, bytes);
+    } else {
+      hipError_t e = hipMalloc(ptr, bytes);
+      if (e != hipSuccess) return e;
+      p->allocs.push_back(*ptr);
+      p->ranges.push_back({(uintptr_t)*ptr, bytes});
+    }
     p->bytes += (int64_t)bytes;
     return hipSuccess;
   }
 };
+
+// kernel spectra of (nb, s) for a plan: the shared cache, or fake ranges in a dry build
+hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
+  if (!p->dry) {
+    LGF_HIP_CHECK(spectra_for(p->ctx, nb, s, out));
+    const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
+    p->ranges.push_back({(uintptr_t)(*out)->d64, 343 * S * sizeof(c64)});
+    p->ranges.push_back({(uintptr_t)(*out)->d32, 343 * S * sizeof(c32)});
+    p->ranges.push_back({(uintptr_t)(*out)->kp64, 343 * sizeof(void*)});
+    p->ranges.push_back({(uintptr_t)(*out)->kp32, 343 * sizeof(void*)});
+    return hipSuccess;
+  }
+  auto key = std::make_pair(nb, s);
+  auto it = p->dry_spectra.find(key);
+  if (it == p->dry_spectra.end()) {
+    const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
+    SpecSet ss;
+    ss.nb = nb;
+    ss.s = s;
+    ss.d64 = (c64*)fake_alloc(p, 343 * S * sizeof(c64));
+    ss.d32 = (c32*)fake_alloc(p, 343 * S * sizeof(c32));
+    ss.kp64 = (const c64**)fake_alloc(p, 343 * sizeof(void*));
+    ss.kp32 = (const c32**)fake_alloc(p, 343 * sizeof(void*));
+    it = p->dry_spectra.emplace(key, ss).first;
+  }
+  *out = &it->second;
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -365,6 +406,116 @@ struct PendingStep {
   int64_t work;
 };
 
+// ----------------------------------------------------------------------------- item validation
+bool in_ranges(const Plan* p, const void* ptr, size_t len) {
+  const uintptr_t a = (uintptr_t)ptr;
+  for (const auto& r : p->ranges)
+    if (a >= r.first && a + len <= r.first + r.second) return true;
+  return false;
+}
+
+bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int count, int64_t n,
+                   const int64_t nsrc[2], const int64_t ntgt[2], std::string* err) {
+  const int nb = p->nb;
+  const size_t N3 = (size_t)nb * nb * nb;
+  const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
+  const size_t es = ty == 0 ? 4 : 8, esc = ty == 1 ? 8 : 4, esp = ty == 0 ? 4 : 8;  // MIX: child 4, parent 8
+  const int64_t nmax = n * (int64_t)N3;
+  auto bad = [&](const char* what, int i) {
+    if (err) *err = std::string("internal plan check failed: ") + what + " (kind " + std::to_string(kind) +
+                    ", item " + std::to_string(i) + ")";
+    return false;
+  };
+  auto off_ok = [&](int64_t o) { return o >= 0 && o % (int64_t)N3 == 0 && o + (int64_t)N3 <= nmax; };
+  for (int i = 0; i < count; ++i) {
+    switch (kind) {
+      case K_FWD: {
+        const auto& it = ((const FftFwdItem<double>*)items)[i];
+        if (!in_ranges(p, it.src, N3 * es) || !in_ranges(p, it.dst, 2 * S * es)) return bad("fft_fwd", i);
+        break;
+      }
+      case K_INV: {
+        const auto& it = ((const FftInvItem<double>*)items)[i];
+        if (!in_ranges(p, it.src, 2 * S * es) || !in_ranges(p, it.dst, N3 * es)) return bad("fft_inv", i);
+        break;
+      }
+      case K_MAC: {
+        const auto& it = ((const MacTile<double>*)items)[i];
+        const int t = ty == 0 ? 0 : 1;
+        for (int j = 0; j < 36; ++j)
+          for (int q = 0; q < kMacSlots; ++q)
+            if (it.src[j][q] < 0 || it.src[j][q] > nsrc[t]) return bad("mac source slot", i);
+        for (int r = 0; r < 4; ++r)
+          for (int q = 0; q < kMacL; ++q)
+            if (it.tgt[r][q] < -1 || it.tgt[r][q] >= ntgt[t]) return bad("mac target slot", i);
+        if (!in_ranges(p, it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("mac source arena", i);
+        if (ntgt[t] && !in_ranges(p, it.uhat, ntgt[t] * 2 * S * es)) return bad("mac target arena", i);
+        if (!in_ranges(p, it.kptr, 343 * sizeof(void*))) return bad("mac kernel table", i);
+        break;
+      }
+      case K_ANTERP: {
+        const auto& it = ((const AnterpItem<double, double>*)items)[i];
+        if (!in_ranges(p, it.dst, N3 * esp)) return bad("anterp parent", i);
+        for (int c = 0; c < 8; ++c)
+          if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("anterp child", i);
+        break;
+      }
+      case K_INTERP: {
+        const auto& it = ((const InterpItem<double, double>*)items)[i];
+        if (!in_ranges(p, it.child, N3 * esc) || !in_ranges(p, it.parent, N3 * esp)) return bad("interp", i);
+        if (it.octant < 0 || it.octant > 7) return bad("interp octant", i);
+        break;
+      }
+      case K_COMBINE: {
+        const auto& it = ((const CombineItem<double>*)items)[i];
+        if (it.dst_d && !in_ranges(p, it.dst_d, N3 * 8)) return bad("combine dst", i);
+        if (it.dst_t && !in_ranges(p, it.dst_t, N3 * es)) return bad("combine dst", i);
+        if (!it.dst_d && !it.dst_t && !off_ok(it.dst_out)) return bad("combine out offset", i);
+        if (it.v && !in_ranges(p, it.v, N3 * es)) return bad("combine v", i);
+        if (it.base && !in_ranges(p, it.base, N3 * es)) return bad("combine base", i);
+        break;
+      }
+      case K_CONVERT: {
+        const auto& it = ((const ConvertItem<double>*)items)[i];
+        if (!in_ranges(p, it.dst, N3 * es)) return bad("convert dst", i);
+        if (it.src ? !in_ranges(p, it.src, N3 * 8) : !off_ok(it.src_in)) return bad("convert src", i);
+        break;
+      }
+      case K_COARSEN: {
+        const auto& it = ((const CoarsenItem*)items)[i];
+        if (!in_ranges(p, it.dst, N3 * 8)) return bad("coarsen dst", i);
+        for (int c = 0; c < 8; ++c)
+          if (it.child[c] ? !in_ranges(p, it.child[c], N3 * 8) : !off_ok(it.child_in[c])) return bad("coarsen child", i);
+        break;
+      }
+      case K_REFINE: {
+        const auto& it = ((const RefineItem<double>*)items)[i];
+        if (!in_ranges(p, it.jw, N3 * es) || !in_ranges(p, it.parent_w, N3 * es)) return bad("refine", i);
+        break;
+      }
+      case K_CORRECT: {
+        const auto& it = ((const CorrectItem<double>*)items)[i];
+        if (!in_ranges(p, it.g, N3 * es) || !in_ranges(p, it.jw, N3 * es) || !in_ranges(p, it.parent_w, N3 * es))
+          return bad("correct", i);
+        if (it.f ? !in_ranges(p, it.f, N3 * 8) : !off_ok(it.f_in)) return bad("correct f", i);
+        for (int f = 0; f < 6; ++f)
+          if (it.nbr[f] && !in_ranges(p, it.nbr[f], N3 * es)) return bad("correct neighbour", i);
+        break;
+      }
+      case K_RESIDUAL: {
+        const auto& it = ((const ResidualItem*)items)[i];
+        if (!in_ranges(p, it.r, N3 * 8) || !off_ok(it.off)) return bad("residual", i);
+        for (int f = 0; f < 6; ++f)
+          if (it.nbr_off[f] != -1 && !off_ok(it.nbr_off[f])) return bad("residual neighbour", i);
+        break;
+      }
+      default:
+        return bad("unknown kind", i);
+    }
+  }
+  return true;
+}
+
 // Element type of octree level k: the FP32 mode runs the base level of every refinement level
 // in FP32 and the coarse (far-field) levels in FP64; the FP64 mode runs everything in FP64.
 // Items are built with the <double> layouts, which are identical to the <float> ones (only
@@ -456,7 +607,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   for (int ty = 0; ty < 2; ++ty) {
     void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
     LGF_HIP_CHECK(ar.alloc(&a, nsrc[ty] * N3 * es(ty)));
-    LGF_HIP_CHECK(ar.alloc(&b, nsrc[ty] * S * 2 * es(ty)));
+    // one extra all-zero spectrum (slot nsrc[ty]) stands in for absent sources in MAC tiles
+    LGF_HIP_CHECK(ar.alloc(&b, (nsrc[ty] + 1) * S * 2 * es(ty)));
+    if (!p->dry) LGF_HIP_CHECK(hipMemset((uint8_t*)b + nsrc[ty] * S * 2 * es(ty), 0, S * 2 * es(ty)));
     LGF_HIP_CHECK(ar.alloc(&c, ntgt[ty] * S * 2 * es(ty)));
     LGF_HIP_CHECK(ar.alloc(&d, ntgt[ty] * N3 * es(ty)));
     srcA[ty] = (uint8_t*)a; fhatA[ty] = (uint8_t*)b; uhatA[ty] = (uint8_t*)c; vA[ty] = (uint8_t*)d;
@@ -475,10 +628,10 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     const std::vector<double> W = lagrange_matrix(nb, p->n_i), W3 = refine_table(nb);
     LGF_HIP_CHECK(ar.alloc(&tmp, W.size() * sizeof(double)));
     p->d_w = (double*)tmp;
-    LGF_HIP_CHECK(hipMemcpy(p->d_w, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!p->dry) LGF_HIP_CHECK(hipMemcpy(p->d_w, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
     LGF_HIP_CHECK(ar.alloc(&tmp, W3.size() * sizeof(double)));
     p->d_w3 = (double*)tmp;
-    LGF_HIP_CHECK(hipMemcpy(p->d_w3, W3.data(), W3.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!p->dry) LGF_HIP_CHECK(hipMemcpy(p->d_w3, W3.data(), W3.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   using D = double;
   auto SRC = [&](int ty, int64_t slot) { return (D*)(srcA[ty] + slot * N3 * es(ty)); };
@@ -557,15 +710,14 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     std::vector<std::vector<InterpItem<D, D>>> itp(K);
     std::vector<FftFwdItem<D>> fwd[2];
     std::vector<FftInvItem<D>> inv[2];
-    std::vector<MacRow<D>> rows[2];
-    int64_t work[2] = {0, 0};
+    std::vector<std::vector<MacTile<D>>> rows(K);      // per octree level (one kernel set each)
+    std::vector<int64_t> work(K, 0);
     std::vector<char> fwd_done[2] = {std::vector<char>(nsrc[0], 0), std::vector<char>(nsrc[1], 0)};
     for (int ch = 0; ch < 2; ++ch) {
       if (ch == 1 && !hasA[l]) continue;
       Fmm& F = ch == 0 ? chT[l] : chA[l];
       p->interactions += F.interactions;
-      work[tyb] += F.level_interactions.empty() ? 0 : F.level_interactions[0];
-      for (size_t k = 1; k < F.level_interactions.size(); ++k) work[TY_F64] += F.level_interactions[k];
+      for (size_t k = 0; k < F.level_interactions.size(); ++k) work[k] += F.level_interactions[k];
       for (int k = 1; k < (int)F.lv.size(); ++k) {
         OctLevel& L = F.lv[k];
         OctLevel& C = F.lv[k - 1];
@@ -602,36 +754,44 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
           }
         }
       }
-      for (const RowDesc& rd : F.rows) {
+      for (const TileDesc& rd : F.rows) {
         const SpecSet* ss = nullptr;
-        LGF_HIP_CHECK(spectra_for(p->ctx, nb, 1 << rd.k, &ss));
+        LGF_HIP_CHECK(plan_spectra(p, nb, 1 << rd.k, &ss));
         OctLevel& L = F.lv[rd.k];
         const int ty = ty_of(rd.k);
-        MacRow<D> m{};
-        for (int i = 0; i < kMacL; ++i) {
-          const int t = rd.tgt_node[i];
-          m.tgt[i] = (t >= 0 && L.has_ifft[t]) ? L.tgt_slot[t] : -1;
-        }
+        MacTile<D> m{};
+        m.row_mask = 0;
+        for (int q = 0; q < 4; ++q)
+          for (int i = 0; i < kMacL; ++i) {
+            const int t = rd.tgt_node[q][i];
+            m.tgt[q][i] = (t >= 0 && L.has_ifft[t]) ? L.tgt_slot[t] : -1;
+            if (m.tgt[q][i] >= 0) m.row_mask |= 1 << q;
+          }
         for (int j = 0; j < 36; ++j)
           for (int q = 0; q < kMacSlots; ++q) {
+            // a node with no source slot (absent, or a source no target here pairs with) reads
+            // the all-zero spectrum
             const int id = rd.src_node[j][q];
-            m.src[j][q] = id >= 0 ? L.src_slot[id] : -1;
+            const int sl = id >= 0 ? L.src_slot[id] : -1;
+            m.src[j][q] = sl >= 0 ? sl : (int)nsrc[ty];
           }
         m.pair_mask = rd.mask;
-        m.flags = (rd.k == 0 ? 1 : 0) | ((rd.key.y & 1) << 1) | ((rd.key.z & 1) << 2);
+        m.flags = rd.k == 0 ? 1 : 0;
         m.fhat = FH(ty, 0);
         m.uhat = UH(ty, 0);
         m.kptr = ty == TY_F32 ? (const cpx<D>* const*)ss->kp32 : (const cpx<D>* const*)ss->kp64;
-        rows[ty].push_back(m);
+        rows[rd.k].push_back(m);
       }
     }
     for (int ty = 0; ty < 2; ++ty) {
       p->n_fwd += (int64_t)fwd[ty].size();
       p->n_inv += (int64_t)inv[ty].size();
-      p->n_rows += (int64_t)rows[ty].size();
-      push(steps, l, 3, 0, K_FWD, ty, hi.add(fwd[ty]), fwd[ty].size(), nullptr);
-      push(steps, l, 4, 0, K_MAC, ty, hi.add(rows[ty]), rows[ty].size(), nullptr, work[ty]);
-      push(steps, l, 5, 0, K_INV, ty, hi.add(inv[ty]), inv[ty].size(), nullptr);
+      push(steps, l, 3, 0, K_FWD, ty, hi.add(fwd[ty]), fwd[ty].size(), nullptr, (int64_t)fwd[ty].size());
+      push(steps, l, 5, 0, K_INV, ty, hi.add(inv[ty]), inv[ty].size(), nullptr, (int64_t)inv[ty].size());
+    }
+    for (int k = 0; k < K; ++k) {
+      p->n_rows += (int64_t)rows[k].size();
+      push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k]);
     }
     for (int k = 1; k < K; ++k) {
       const int ty = (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
@@ -683,9 +843,17 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     push(rsteps, 0, 0, 0, K_RESIDUAL, TY_F64, hi.add(it), it.size(), nullptr);
   }
 
+  // every item must stay inside the plan's device ranges before anything is launched
+  {
+    const int64_t nsrc_[2] = {nsrc[0], nsrc[1]}, ntgt_[2] = {ntgt[0], ntgt[1]};
+    for (const auto* list : {&steps, &rsteps})
+      for (const PendingStep& st : *list)
+        if (!validate_step(p, st.kind, st.ty, hi.buf.data() + st.off, st.count, n, nsrc_, ntgt_, err))
+          return hipErrorInvalidValue;
+  }
   void* d_items = nullptr;
   LGF_HIP_CHECK(ar.alloc(&d_items, hi.buf.size()));
-  if (!hi.buf.empty())
+  if (!hi.buf.empty() && !p->dry)
     LGF_HIP_CHECK(hipMemcpy(d_items, hi.buf.data(), hi.buf.size(), hipMemcpyHostToDevice));
   p->d_items = d_items;
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
@@ -696,7 +864,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   fin(rsteps, p->residual);
   std::set<int> used;
   for (int l = 0; l < LR; ++l)
-    for (const RowDesc& rd : chT[l].rows) used.insert(rd.k);
+    for (const TileDesc& rd : chT[l].rows) used.insert(rd.k);
   p->n_spectra = 0;
   for (int k : used) p->n_spectra += k == 0 ? 343 : 316;
   (void)err;
@@ -706,14 +874,15 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 }  // namespace
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
-                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err) {
+                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err, bool dry) {
   Plan* p = new Plan();
   p->nb = nb;
   p->n_i = n_i;
   p->fp32 = fp32;
   p->dc_iters = fp32 ? dc_iters : 0;
   p->nblocks = n;
-  hipError_t e = device_ctx(&p->ctx);
+  p->dry = dry;
+  hipError_t e = dry ? hipSuccess : device_ctx(&p->ctx);
   if (e != hipSuccess) {
     delete p;
     return e;
@@ -738,7 +907,8 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
 
 void plan_free(Plan* p) {
   if (!p) return;
-  for (void* a : p->allocs) (void)hipFree(a);
+  if (!p->dry)
+    for (void* a : p->allocs) (void)hipFree(a);
   delete p;
 }
 

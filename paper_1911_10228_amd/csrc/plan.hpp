@@ -62,6 +62,10 @@ hipError_t profile_collect(std::vector<ProfileEntry>* out);
 struct Plan {
   int nb = 0, n_i = 0, LR = 0, Kmax = 0;
   bool fp32 = false;
+  bool dry = false;                    // host-only build: fake addresses, no device calls
+  std::vector<std::pair<uintptr_t, size_t>> ranges;   // every device range items may touch
+  uintptr_t next_fake = 0;
+  std::map<std::pair<int, int>, SpecSet> dry_spectra;   // fake kernel spectra of a dry build
   int dc_iters = 0;
   int64_t nblocks = 0;
   DeviceCtx* ctx = nullptr;
@@ -90,7 +94,8 @@ struct Plan {
 };
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
-                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err);
+                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err,
+                      bool dry = false);
 void plan_free(Plan* p);
 
 struct Member {

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblgf.so")
 LGF_FP64_PLAIN = 0
 LGF_FP32_REFINE = 1
 
-EXPORTS = ["lgf_init", "lgf_plan", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
+EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
            "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy"]
@@ -60,6 +60,7 @@ def load() -> C.CDLL:
     sig = {
         "lgf_init": ([], I32),
         "lgf_plan": ([P, P, I64, I32, I32, P, P], I32),
+        "lgf_plan_check": ([P, P, I64, I32, I32, P, P], I32),
         "lgf_solve": ([P, P, P, P], I32),
         "lgf_solve_batch": ([P, P, P, I32, P], I32),
         "lgf_plan_get_info": ([P, P], I32),
@@ -158,6 +159,19 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def plan_check(blocks, levels, n_b: int, interp_order: int, precision: int = LGF_FP64_PLAIN,
+               dc_iters: int = 0) -> dict:
+    """Host-only plan build with validation of every kernel work item (no GPU needed)."""
+    b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+    lv = np.ascontiguousarray(np.zeros(len(b), np.int32) if levels is None
+                              else np.asarray(levels, dtype=np.int32).reshape(-1))
+    opt = Options(precision, dc_iters, 0, 0, 0)
+    inf = PlanInfo()
+    _check(load().lgf_plan_check(b.ctypes.data, lv.ctypes.data, len(b), n_b, interp_order,
+                                 C.byref(opt), C.byref(inf)), "lgf_plan_check")
+    return inf.as_dict()
 
 
 def solve_batch(plans, fs, us, stream=None):

@@ -191,7 +191,7 @@ def batch(seed: int = 4, count: int = 64, min_blocks: int = 8, max_blocks: int =
         srcf = lambda p, c_=centres, s_=sigmas, a_=amps: gaussian_mixture(p, c_, s_, a_)
         blocks, levels = refine_by_criterion(box_blocks(a, b, c), n_b, nl, srcf)
         f = srcf(cell_centres(blocks, levels, n_b))
-        order = 10 if n_b == 8 else 8
+        order = 8                      # the most nodes a block of 8 cells holds
         out.append(Layout(blocks, levels, n_b, f, order,
                           f"batch[{i}] {a}x{b}x{c} blocks of {n_b}^3, {nl} levels"))
     return out

@@ -1,0 +1,101 @@
+"""Host-only plan builds (no GPU): every kernel work item of every step stays inside the
+plan's buffers, and the interaction counts equal the oracle's octree lists (bit-exact
+integer bookkeeping).  This runs the same C++ planner the GPU path uses."""
+import numpy as np
+import pytest
+
+from oracle import fmm, multires
+from paper_1911_10228_amd import lgf, workloads
+
+
+def oracle_interactions(blocks, levels):
+    """Sum over refinement levels of near + far pairs, channel T (all -> all) plus channel A
+    (leaf sources -> non-leaf targets) where a level has non-leaf blocks."""
+    blocks = np.asarray(blocks)
+    levels = np.asarray(levels)
+    have = {(int(l),) + tuple(int(v) for v in b) for b, l in zip(blocks, levels)}
+    leaf = np.array([(int(l) + 1,) + tuple(int(v) for v in 2 * b) not in have
+                     for b, l in zip(blocks, levels)])
+    total = 0
+    from oracle import tree
+    for l in range(int(levels.max()) + 1):
+        ids = np.nonzero(levels == l)[0]
+        lb = blocks[ids]
+        tl = tree.build_levels(lb)
+        # ancestors of leaf / non-leaf base blocks per tree level
+        src = leaf[ids].copy()
+        tgt = ~leaf[ids]
+        for k, nodes in enumerate(tl):
+            pairs = tree.interactions(nodes, base=(k == 0))
+            total += len(pairs)
+            if tgt.any():
+                total += sum(1 for t, s in pairs if tgt[t] and src[s])
+            if k + 1 < len(tl):
+                pidx = tree.index_of(tl[k + 1])
+                par = np.array([pidx[tuple(int(v) for v in p)] for p in tree.parent_of(nodes)])
+                s2 = np.zeros(len(tl[k + 1]), bool)
+                t2 = np.zeros(len(tl[k + 1]), bool)
+                s2[par[src]] = True
+                t2[par[tgt]] = True
+                src, tgt = s2, t2
+    return total
+
+
+LAYOUTS = {
+    "gauss2": lambda: workloads.uniform_gaussian(),
+    "box6x8": lambda: workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=3, seed=1),
+    "box8x16": lambda: workloads.uniform_mixture(nblk=8, n_b=16, n_gauss=3, seed=2),
+    "slab": lambda: workloads.Layout(workloads.box_blocks(13, 3, 1, origin=(-5, 2, 7)),
+                                     np.zeros(39, np.int32), 8, None, 6),
+    "sparse_neg": lambda: workloads.Layout(
+        np.unique(np.random.default_rng(11).integers(-9, 7, size=(70, 3)), axis=0).astype(np.int32),
+        None, 8, None, 6),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUTS))
+@pytest.mark.parametrize("precision,dc", [(0, 0), (1, 0), (1, 2)])
+def test_uniform_layouts_validate_and_count(name, precision, dc):
+    L = LAYOUTS[name]()
+    levels = L.levels if L.levels is not None else np.zeros(len(L.blocks), np.int32)
+    info = lgf.plan_check(L.blocks, levels, L.n_b, L.interp_order, precision, dc)
+    counts = fmm.count_interactions(L.blocks)
+    assert info["interactions"] == sum(a + b for _, a, b in counts)
+    assert info["blocks"] == len(L.blocks)
+
+
+def multi_layouts():
+    out = []
+    base = workloads.box_blocks(4, 4, 4)
+    l1 = workloads.box_blocks(4, 4, 4, origin=(2, 2, 2))
+    l2 = workloads.box_blocks(2, 4, 2, origin=(6, 4, 6))
+    out.append((np.concatenate([base, l1, l2]), np.repeat([0, 1, 2], [64, 64, 16]), 8))
+    # refinement touching the domain edge and a negative-coordinate base
+    b0 = workloads.box_blocks(3, 3, 3, origin=(-1, -2, 0))
+    kids = np.array([[2 * x + i, 2 * y + j, 2 * z + k] for x, y, z in [(-1, -2, 0), (1, 0, 2)]
+                     for i in (0, 1) for j in (0, 1) for k in (0, 1)])
+    out.append((np.concatenate([b0, kids]), np.repeat([0, 1], [27, 16]), 16))
+    return out
+
+
+@pytest.mark.parametrize("case", range(2))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multilevel_layouts_validate_and_count(case, precision):
+    blocks, levels, n_b = multi_layouts()[case]
+    info = lgf.plan_check(blocks, levels, n_b, 6, precision, 1)
+    assert info["refinement_levels"] == int(levels.max()) + 1
+    assert info["interactions"] == oracle_interactions(blocks, levels)
+
+
+def test_batch_generator_layouts_validate():
+    rng_layouts = workloads.batch(seed=4, count=6, max_blocks=120)
+    for L in rng_layouts:
+        for precision in (0, 1):
+            info = lgf.plan_check(L.blocks, L.levels, L.n_b, L.interp_order, precision, 1)
+            assert info["unknowns"] == L.unknowns
+
+
+def test_torus_layout_validates():
+    L = workloads.torus(nblk=4, n_b=8, n_levels=3)
+    info = lgf.plan_check(L.blocks, L.levels, L.n_b, 6, 1, 1)
+    assert info["refinement_levels"] == 3
