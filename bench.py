@@ -46,15 +46,27 @@ def algorithmic(entry, n_b):
     return None, None, None
 
 
-def time_solves(plan, f, u, steps, warmup, torch):
+def time_solves(plan, f, u, steps, warmup, torch, stream):
+    """Seconds per solve on a non-default stream (repeat solves replay a captured graph)."""
     for _ in range(warmup):
-        plan.solve(f, u)
+        plan.solve(f, u, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        plan.solve(f, u)
+        plan.solve(f, u, stream=stream)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def profiled(lgf, plan, f, u, steps, torch, stream):
+    """Per-kernel HIP-event times over `steps` solves (direct launches: events bracket each)."""
+    lgf.profile_read()
+    lgf.profile(True)
+    for _ in range(steps):
+        plan.solve(f, u, stream=stream)
+    torch.cuda.synchronize()
+    lgf.profile(False)
+    return lgf.profile_read()
 
 
 def cpu_baseline(n_b=16, nblk=8, order=8):
@@ -100,24 +112,14 @@ def main():
     info = p32.info()
     print(f"# plan: {info}", file=sys.stderr, flush=True)
 
-    # headline: FP32 + DC, kernels timed with HIP events during the timed region
-    for _ in range(args.warmup):
-        p32.solve(f, u32)
-    torch.cuda.synchronize()
-    lgf.profile_read()
-    lgf.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        p32.solve(f, u32)
-    torch.cuda.synchronize()
-    dt32 = (time.perf_counter() - t0) / args.steps
-    lgf.profile(False)
-    prof = lgf.profile_read()
+    stream = torch.cuda.Stream()
+    # headline: FP32 + DC; then the same number of solves with every kernel bracketed by events
+    dt32 = time_solves(p32, f, u32, args.steps, args.warmup, torch, stream)
     print(f"# fp32+dc{args.dc}: {dt32 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
-
-    dt64 = time_solves(p64, f, u64, args.steps, args.warmup, torch)
+    prof = profiled(lgf, p32, f, u32, args.steps, torch, stream)
+    dt64 = time_solves(p64, f, u64, args.steps, args.warmup, torch, stream)
     print(f"# fp64 plain: {dt64 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
-    dt0 = time_solves(p0, f, u0, args.steps, args.warmup, torch)
+    dt0 = time_solves(p0, f, u0, args.steps, args.warmup, torch, stream)
     print(f"# fp32 no dc: {dt0 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
 
     a32, a64, a0 = u32.cpu().numpy(), u64.cpu().numpy(), u0.cpu().numpy()

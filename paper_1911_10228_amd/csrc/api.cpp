@@ -68,7 +68,7 @@ lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int
   lgf::Plan* p = nullptr;
   std::string err;
   hipError_t e = lgf::plan_build(blocks, levels, n, N_b, interp_order, o.precision == LGF_FP32_REFINE,
-                                 o.dc_iters, o.hbm_budget, &p, &err);
+                                 o.dc_iters, o.hbm_budget, &p, &err, false, o.autotune != 0);
   if (e != hipSuccess) {
     if (!err.empty()) std::fprintf(stderr, "lgf_plan: %s\n", err.c_str());
     return from_hip(e);
@@ -106,7 +106,7 @@ lgf_status lgf_plan_check(const int32_t* blocks, const int32_t* levels, int64_t 
 lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream) {
   if (!p || !f || !u) return LGF_EINVAL;
   std::vector<lgf::Member> m{{p->p, f, u}};
-  return from_hip(lgf::solve_members(m, (hipStream_t)stream));
+  return from_hip(lgf::solve_members_graph(m, (hipStream_t)stream));
 }
 
 lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* const* u, int32_t n,
@@ -119,7 +119,7 @@ lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* 
     if (!seen.insert(p[i]->p).second) return LGF_EINVAL;
     m.push_back({p[i]->p, f[i], u[i]});
   }
-  return from_hip(lgf::solve_members(m, (hipStream_t)stream));
+  return from_hip(lgf::solve_members_graph(m, (hipStream_t)stream));
 }
 
 lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out) {

@@ -128,12 +128,11 @@ __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
   const WorkSet& ws = sets.s[set];
   const CombineItem<T>& it = ((const CombineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
   const double sc = it.scale;
-  double* dd = it.dst_d ? it.dst_d : (it.dst_t ? nullptr : ws.out + it.dst_out);
+  double* dd = it.dst_d ? it.dst_d : ws.out + it.dst_out;
   for (int i = threadIdx.x; i < N3; i += kOpThreads) {
     double v = it.v ? sc * double(it.v[i]) : 0.0;
-    if (it.base) v += double(it.base[i]);
-    if (dd) dd[i] = v;
-    else it.dst_t[i] = T(v);
+    if (it.base) v += it.base[i];
+    dd[i] = v;
   }
 }
 
@@ -192,17 +191,17 @@ __device__ __forceinline__ T refine_point(const T* __restrict__ pw, const double
   return s;
 }
 
-template <int NB, typename T>
+template <int NB>
 __global__ __launch_bounds__(kOpThreads) void refine_kernel(SetTable sets) {
   constexpr int N3 = NB * NB * NB;
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
-  const RefineItem<T>& it = ((const RefineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const RefineItem& it = ((const RefineItem*)ws.items)[blockIdx.x - ws.wg_begin];
   const double* __restrict__ w3 = ws.w;
   const int cx = it.octant & 1, cy = (it.octant >> 1) & 1, cz = (it.octant >> 2) & 1;
   for (int i = threadIdx.x; i < N3; i += kOpThreads) {
     const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
-    it.jw[i] = refine_point<NB>(it.parent_w, w3, cx * NB + x, cy * NB + y, cz * NB + z);
+    it.jw[i] = refine_point<NB, double>(it.parent_w, w3, cx * NB + x, cy * NB + y, cz * NB + z);
   }
 }
 
@@ -217,58 +216,75 @@ __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
   for (int i = threadIdx.x; i < N3; i += kOpThreads) {
     const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
-    const T centre = it.jw[i];
-    T sum = T(0);
+    const double centre = it.jw[i];
+    double sum = 0.0;
 #pragma unroll
     for (int face = 0; face < 6; ++face) {
       const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
       int q[3] = {p[0], p[1], p[2]};
       q[ax] += sg;
-      T v;
+      double v;
       if (q[ax] >= 0 && q[ax] < NB) {
         v = it.jw[(q[2] * NB + q[1]) * NB + q[0]];
       } else if (it.nbr[face]) {
         q[ax] = sg > 0 ? 0 : NB - 1;
         v = it.nbr[face][(q[2] * NB + q[1]) * NB + q[0]];
       } else {
-        v = refine_point<NB>(it.parent_w, w3, c[0] * NB + (ax == 0 ? q[0] : p[0]),
-                             c[1] * NB + (ax == 1 ? q[1] : p[1]), c[2] * NB + (ax == 2 ? q[2] : p[2]));
+        v = refine_point<NB, double>(it.parent_w, w3, c[0] * NB + (ax == 0 ? q[0] : p[0]),
+                                     c[1] * NB + (ax == 1 ? q[1] : p[1]), c[2] * NB + (ax == 2 ? q[2] : p[2]));
       }
       sum += v;
     }
-    const double lap = double(sum) - 6.0 * double(centre);
+    const double lap = sum - 6.0 * centre;
     it.g[i] = T(f[i] - it.inv_h2 * lap);
   }
 }
 
+// r = f - h^-2 (sum of 6 neighbours - 6 u) on cells whose neighbours all exist; the block and
+// its one-cell halo (from the face-adjacent same-level blocks) are staged in LDS.
 template <int NB>
 __global__ __launch_bounds__(kOpThreads) void residual_kernel(SetTable sets) {
-  constexpr int N3 = NB * NB * NB;
+  constexpr int N3 = NB * NB * NB, E = NB + 2;
+  __shared__ double ext[E * E * E];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const ResidualItem& it = ((const ResidualItem*)ws.items)[blockIdx.x - ws.wg_begin];
+  if (!it.leaf) {
+    for (int i = threadIdx.x; i < N3; i += kOpThreads) it.r[i] = 0.0;
+    return;
+  }
   const double* __restrict__ f = ws.in + it.off;
   const double* __restrict__ u = ws.out + it.off;
   for (int i = threadIdx.x; i < N3; i += kOpThreads) {
-    if (!it.leaf) { it.r[i] = 0.0; continue; }
-    const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
-    double sum = 0.0;
-    bool ok = true;
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    ext[((z + 1) * E + y + 1) * E + x + 1] = u[i];
+  }
+  int missing = 0;
 #pragma unroll
-    for (int face = 0; face < 6; ++face) {
-      const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
-      int q[3] = {p[0], p[1], p[2]};
-      q[ax] += sg;
-      if (q[ax] >= 0 && q[ax] < NB) {
-        sum += u[(q[2] * NB + q[1]) * NB + q[0]];
-      } else if (it.nbr_off[face] >= 0) {
-        q[ax] = sg > 0 ? 0 : NB - 1;
-        sum += ws.out[it.nbr_off[face] + (q[2] * NB + q[1]) * NB + q[0]];
-      } else {
-        ok = false;
-      }
+  for (int face = 0; face < 6; ++face) {
+    if (it.nbr_off[face] < 0) { missing |= 1 << face; continue; }
+    const double* nb = ws.out + it.nbr_off[face];
+    const int ax = face >> 1, hi = face & 1;
+    for (int j = threadIdx.x; j < NB * NB; j += kOpThreads) {
+      const int a = j % NB, b = j / NB;
+      int p[3], q[3];                      // p: cell in the neighbour, q: halo cell in ext
+      const int src = hi ? 0 : NB - 1, dst = hi ? NB + 1 : 0;
+      if (ax == 0) { p[0] = src; p[1] = a; p[2] = b; q[0] = dst; q[1] = a + 1; q[2] = b + 1; }
+      else if (ax == 1) { p[0] = a; p[1] = src; p[2] = b; q[0] = a + 1; q[1] = dst; q[2] = b + 1; }
+      else { p[0] = a; p[1] = b; p[2] = src; q[0] = a + 1; q[1] = b + 1; q[2] = dst; }
+      ext[(q[2] * E + q[1]) * E + q[0]] = nb[(p[2] * NB + p[1]) * NB + p[0]];
     }
-    it.r[i] = ok ? f[i] - it.inv_h2 * (sum - 6.0 * u[i]) : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    const bool edge = ((missing & 1) && x == 0) || ((missing & 2) && x == NB - 1) ||
+                      ((missing & 4) && y == 0) || ((missing & 8) && y == NB - 1) ||
+                      ((missing & 16) && z == 0) || ((missing & 32) && z == NB - 1);
+    const int c = ((z + 1) * E + y + 1) * E + x + 1;
+    const double lap = ext[c - 1] + ext[c + 1] + ext[c - E] + ext[c + E] + ext[c - E * E] +
+                       ext[c + E * E] - 6.0 * ext[c];
+    it.r[i] = edge ? 0.0 : f[i] - it.inv_h2 * lap;
   }
 }
 
@@ -311,8 +327,8 @@ template <typename T> hipError_t launch_convert(int nb, SetTable& t, hipStream_t
 hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st) {
   LGF_LAUNCH_SIMPLE(coarsen_kernel<NB>)
 }
-template <typename T> hipError_t launch_refine(int nb, SetTable& t, hipStream_t st) {
-  LGF_LAUNCH_SIMPLE(refine_kernel<NB, T>)
+hipError_t launch_refine(int nb, SetTable& t, hipStream_t st) {
+  LGF_LAUNCH_SIMPLE(refine_kernel<NB>)
 }
 template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st) {
   LGF_LAUNCH_SIMPLE(correct_kernel<NB, T>)
@@ -336,7 +352,6 @@ template hipError_t launch_interp<float, double>(int, SetTable&, hipStream_t);
 #define LGF_INST(T)                                                       \
   template hipError_t launch_combine<T>(int, SetTable&, hipStream_t);     \
   template hipError_t launch_convert<T>(int, SetTable&, hipStream_t);     \
-  template hipError_t launch_refine<T>(int, SetTable&, hipStream_t);      \
   template hipError_t launch_correct<T>(int, SetTable&, hipStream_t);
 LGF_INST(float)
 LGF_INST(double)

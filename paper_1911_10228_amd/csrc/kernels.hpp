@@ -79,11 +79,10 @@ template <typename TC, typename TP> struct InterpItem {
 // Fields that come from the solve pass's input / output are addressed by offsets into
 // WorkSet::in / WorkSet::out; plan-owned buffers by pointers.
 template <typename T> struct CombineItem {
-  double* dst_d;         // double destination (plan buffer), or
-  T* dst_t;              // T destination (plan buffer), or, if both null,
+  double* dst_d;         // plan buffer destination, or, if null,
   int64_t dst_out;       // offset into WorkSet::out
   const T* v;            // level field (nullptr: zero)
-  const T* base;         // added field (nullptr: zero)
+  const double* base;    // added field (nullptr: zero)
   double scale;          // dst = base + scale * v
 };
 template <typename T> struct ConvertItem {
@@ -96,19 +95,22 @@ struct CoarsenItem {
   const double* child[8];
   int64_t child_in[8];   // used where child[c] is null: WorkSet::in + child_in[c]
 };
-template <typename T> struct RefineItem {
-  T* jw;                 // child block values of J^{l-1} w^{l-1}
-  const T* parent_w;     // parent's leaf-only field
+// The interpolated coarse field and the leaf-only field stay in FP64 in both precisions: the
+// correction takes their 7-point Laplacian scaled by h^-2, which would turn FP32 rounding of the
+// stored values into a source error that the next convolution spreads over the whole level.
+struct RefineItem {
+  double* jw;            // child block values of J^{l-1} w^{l-1}
+  const double* parent_w;  // parent's leaf-only field
   int32_t octant;
   int32_t pad;
 };
 template <typename T> struct CorrectItem {
-  T* g;                  // corrected source g = f - h^-2 L(Jw)
+  T* g;                  // corrected source g = f - h^-2 L(Jw), rounded to T
   const double* f;       // (coarsened) level source, or nullptr: WorkSet::in + f_in
   int64_t f_in;
-  const T* jw;           // own Jw
-  const T* nbr[6];       // neighbour blocks' Jw (-x,+x,-y,+y,-z,+z), nullptr: ghost from parent
-  const T* parent_w;     // parent field for ghost values
+  const double* jw;      // own Jw
+  const double* nbr[6];  // neighbour blocks' Jw (-x,+x,-y,+y,-z,+z), nullptr: ghost from parent
+  const double* parent_w;  // parent field for ghost values
   int32_t octant;
   int32_t pad;
   double inv_h2;
@@ -136,13 +138,15 @@ hipError_t launch_kernel_spectra(int nb, int nspec, const int32_t* d_sd, const d
 // The launcher fills wg_begin from the counts and returns the number of workgroups used.
 template <typename T> hipError_t launch_fft_fwd(int nb, SetTable& t, hipStream_t st);
 template <typename T> hipError_t launch_fft_inv(int nb, SetTable& t, hipStream_t st);
-template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st);
+template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st, int mode = 0);
+constexpr int kMacModes32[3] = {1, 2, 4};   // candidate launch shapes for the autotuner
+constexpr int kMacModes64[3] = {1, 2, 6};
 template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
 template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
 template <typename T> hipError_t launch_combine(int nb, SetTable& t, hipStream_t st);
 template <typename T> hipError_t launch_convert(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st);
-template <typename T> hipError_t launch_refine(int nb, SetTable& t, hipStream_t st);   // ws.w = W3
+hipError_t launch_refine(int nb, SetTable& t, hipStream_t st);                          // ws.w = W3
 template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st);  // ws.w = W3
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);

@@ -227,10 +227,10 @@ hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
 
 }  // namespace
 
-// Launch shape: LGF_MAC_MODE = row | pair | tile | split overrides the default (rows per
-// wavefront 1, 2 or 4; split: FP64 source rows over 6 wavefronts).  Default: FP32 one row per
-// wavefront with the kernel spectra in LDS and 16 wavefronts per workgroup; FP64 one row per
-// wavefront with the kernel spectra prefetched from memory.
+// Launch shape (mode): 1 row, 2 pair, 4 tile = rows per wavefront; 6 split = FP64 source rows
+// over 6 wavefronts; 0 = default (one row per wavefront; FP32 with the kernel spectra in LDS and
+// 16 wavefronts per workgroup, FP64 with the kernel spectra prefetched from memory).  The plan's
+// autotuner picks the mode per step; LGF_MAC_MODE = row | pair | tile | split overrides it.
 int mac_mode_override() {
   static const int m = [] {
     const char* e = std::getenv("LGF_MAC_MODE");
@@ -244,11 +244,11 @@ int mac_mode_override() {
   return m;
 }
 
-template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st) {
+template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st, int mode) {
   const int P = 2 * nb;
   const int S = P * P * (nb + 1);          // multiple of 64 for nb in {8, 16}
   if (S % 64) return hipErrorInvalidValue;
-  const int mode = mac_mode_override();
+  if (const int o = mac_mode_override()) mode = o;
   if constexpr (sizeof(T) == 4) {
     if (mode == 4) return launch_tiles<T, 16, 4, true>(S, t, st);
     if (mode == 2) return launch_tiles<T, 16, 2, true>(S, t, st);
@@ -260,7 +260,7 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st)
   }
 }
 
-template hipError_t launch_mac<float>(int, SetTable&, hipStream_t);
-template hipError_t launch_mac<double>(int, SetTable&, hipStream_t);
+template hipError_t launch_mac<float>(int, SetTable&, hipStream_t, int);
+template hipError_t launch_mac<double>(int, SetTable&, hipStream_t, int);
 
 }  // namespace lgf

@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <set>
 #include <tuple>
@@ -468,11 +470,9 @@ bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int co
       }
       case K_COMBINE: {
         const auto& it = ((const CombineItem<double>*)items)[i];
-        if (it.dst_d && !in_ranges(p, it.dst_d, N3 * 8)) return bad("combine dst", i);
-        if (it.dst_t && !in_ranges(p, it.dst_t, N3 * es)) return bad("combine dst", i);
-        if (!it.dst_d && !it.dst_t && !off_ok(it.dst_out)) return bad("combine out offset", i);
+        if (it.dst_d ? !in_ranges(p, it.dst_d, N3 * 8) : !off_ok(it.dst_out)) return bad("combine dst", i);
         if (it.v && !in_ranges(p, it.v, N3 * es)) return bad("combine v", i);
-        if (it.base && !in_ranges(p, it.base, N3 * es)) return bad("combine base", i);
+        if (it.base && !in_ranges(p, it.base, N3 * 8)) return bad("combine base", i);
         break;
       }
       case K_CONVERT: {
@@ -489,17 +489,17 @@ bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int co
         break;
       }
       case K_REFINE: {
-        const auto& it = ((const RefineItem<double>*)items)[i];
-        if (!in_ranges(p, it.jw, N3 * es) || !in_ranges(p, it.parent_w, N3 * es)) return bad("refine", i);
+        const auto& it = ((const RefineItem*)items)[i];
+        if (!in_ranges(p, it.jw, N3 * 8) || !in_ranges(p, it.parent_w, N3 * 8)) return bad("refine", i);
         break;
       }
       case K_CORRECT: {
         const auto& it = ((const CorrectItem<double>*)items)[i];
-        if (!in_ranges(p, it.g, N3 * es) || !in_ranges(p, it.jw, N3 * es) || !in_ranges(p, it.parent_w, N3 * es))
+        if (!in_ranges(p, it.g, N3 * es) || !in_ranges(p, it.jw, N3 * 8) || !in_ranges(p, it.parent_w, N3 * 8))
           return bad("correct", i);
         if (it.f ? !in_ranges(p, it.f, N3 * 8) : !off_ok(it.f_in)) return bad("correct f", i);
         for (int f = 0; f < 6; ++f)
-          if (it.nbr[f] && !in_ranges(p, it.nbr[f], N3 * es)) return bad("correct neighbour", i);
+          if (it.nbr[f] && !in_ranges(p, it.nbr[f], N3 * 8)) return bad("correct neighbour", i);
         break;
       }
       case K_RESIDUAL: {
@@ -600,16 +600,17 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   if (LR > 1) {
     LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
     p->fe = (double*)tmp;
-    LGF_HIP_CHECK(ar.alloc(&p->jw, n * N3 * es(tyb)));
-    LGF_HIP_CHECK(ar.alloc(&p->w, n * N3 * es(tyb)));
+    LGF_HIP_CHECK(ar.alloc(&p->jw, n * N3 * sizeof(double)));
+    LGF_HIP_CHECK(ar.alloc(&p->w, n * N3 * sizeof(double)));
   }
   uint8_t *srcA[2], *fhatA[2], *uhatA[2], *vA[2];
   for (int ty = 0; ty < 2; ++ty) {
     void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
     LGF_HIP_CHECK(ar.alloc(&a, nsrc[ty] * N3 * es(ty)));
-    // one extra all-zero spectrum (slot nsrc[ty]) stands in for absent sources in MAC tiles
+    // one extra all-zero spectrum (slot nsrc[ty]) stands in for absent sources in MAC tiles;
+    // the whole arena starts zeroed (plan time, outside any captured graph)
     LGF_HIP_CHECK(ar.alloc(&b, (nsrc[ty] + 1) * S * 2 * es(ty)));
-    if (!p->dry) LGF_HIP_CHECK(hipMemset((uint8_t*)b + nsrc[ty] * S * 2 * es(ty), 0, S * 2 * es(ty)));
+    if (!p->dry) LGF_HIP_CHECK(hipMemset(b, 0, (nsrc[ty] + 1) * S * 2 * es(ty)));
     LGF_HIP_CHECK(ar.alloc(&c, ntgt[ty] * S * 2 * es(ty)));
     LGF_HIP_CHECK(ar.alloc(&d, ntgt[ty] * N3 * es(ty)));
     srcA[ty] = (uint8_t*)a; fhatA[ty] = (uint8_t*)b; uhatA[ty] = (uint8_t*)c; vA[ty] = (uint8_t*)d;
@@ -638,8 +639,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   auto FH = [&](int ty, int64_t slot) { return (cpx<D>*)(fhatA[ty] + slot * S * 2 * es(ty)); };
   auto UH = [&](int ty, int64_t slot) { return (cpx<D>*)(uhatA[ty] + slot * S * 2 * es(ty)); };
   auto V = [&](int ty, int64_t slot) { return (D*)(vA[ty] + slot * N3 * es(ty)); };
-  auto JW = [&](int64_t blk) { return (D*)((uint8_t*)p->jw + blk * N3 * es(tyb)); };
-  auto WW = [&](int64_t blk) { return (D*)((uint8_t*)p->w + blk * N3 * es(tyb)); };
+  auto JW = [&](int64_t blk) { return (double*)p->jw + blk * N3; };
+  auto WW = [&](int64_t blk) { return (double*)p->w + blk * N3; };
 
   HostItems hi;
   std::vector<PendingStep> steps, rsteps;
@@ -678,12 +679,12 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       }
       push(steps, l, 1, 0, K_CONVERT, tyb, hi.add(it), it.size(), nullptr);
     } else {
-      std::vector<RefineItem<D>> rit;
+      std::vector<RefineItem> rit;
       std::vector<CorrectItem<D>> cit;
       for (int i : ids[l]) {
         const I3 c = coords[i];
         const int par = cmap[l - 1].at(parent_of(c));
-        RefineItem<D> r{};
+        RefineItem r{};
         r.jw = JW(i);
         r.parent_w = WW(par);
         r.octant = octant_of(c);
@@ -702,7 +703,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         q.inv_h2 = 1.0 / (h * h);
         cit.push_back(q);
       }
-      push(steps, l, 1, 0, K_REFINE, tyb, hi.add(rit), rit.size(), p->d_w3);
+      push(steps, l, 1, 0, K_REFINE, TY_F64, hi.add(rit), rit.size(), p->d_w3);
       push(steps, l, 1, 1, K_CORRECT, tyb, hi.add(cit), cit.size(), p->d_w3);
     }
     const int K = (int)chT[l].lv.size();
@@ -814,7 +815,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       cmb.push_back(c);
       if (!leaf[i]) {
         CombineItem<D> q{};
-        q.dst_t = WW(i);
+        q.dst_d = WW(i);
         const int ta = chA[l].lv[0].tgt_slot[a];
         q.v = ta >= 0 ? V(tyb, ta) : nullptr;
         q.base = l > 0 ? JW(i) : nullptr;
@@ -858,7 +859,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   p->d_items = d_items;
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
     for (const PendingStep& s : in)
-      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work});
+      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work, 0});
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
@@ -873,8 +874,11 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 
 }  // namespace
 
+hipError_t plan_autotune(Plan* p, hipStream_t st);
+
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
-                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err, bool dry) {
+                      bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err, bool dry,
+                      bool autotune) {
   Plan* p = new Plan();
   p->nb = nb;
   p->n_i = n_i;
@@ -897,6 +901,7 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
   }
   p->LR = LR;
   e = build_plan(p, coords, lev, budget, err);
+  if (e == hipSuccess && autotune && !dry) e = plan_autotune(p, p->ctx->stream);
   if (e != hipSuccess) {
     plan_free(p);
     return e;
@@ -907,6 +912,7 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
 
 void plan_free(Plan* p) {
   if (!p) return;
+  if (!p->dry) graph_forget(p);
   if (!p->dry)
     for (void* a : p->allocs) (void)hipFree(a);
   delete p;
@@ -916,14 +922,14 @@ void plan_free(Plan* p) {
 namespace {
 
 template <typename T>
-hipError_t launch_kind(int kind, int nb, SetTable& t, hipStream_t st) {
+hipError_t launch_kind(int kind, int nb, SetTable& t, hipStream_t st, int mode) {
   switch (kind) {
     case K_CONVERT: return launch_convert<T>(nb, t, st);
-    case K_REFINE: return launch_refine<T>(nb, t, st);
+    case K_REFINE: return launch_refine(nb, t, st);
     case K_CORRECT: return launch_correct<T>(nb, t, st);
     case K_ANTERP: return launch_anterp<T, T>(nb, t, st);
     case K_FWD: return launch_fft_fwd<T>(nb, t, st);
-    case K_MAC: return launch_mac<T>(nb, t, st);
+    case K_MAC: return launch_mac<T>(nb, t, st, mode);
     case K_INV: return launch_fft_inv<T>(nb, t, st);
     case K_INTERP: return launch_interp<T, T>(nb, t, st);
     case K_COMBINE: return launch_combine<T>(nb, t, st);
@@ -933,16 +939,16 @@ hipError_t launch_kind(int kind, int nb, SetTable& t, hipStream_t st) {
   }
 }
 
-hipError_t launch_typed(int kind, int ty, int nb, SetTable& t, hipStream_t st) {
-  if (ty == 0) return launch_kind<float>(kind, nb, t, st);
-  if (ty == 1) return launch_kind<double>(kind, nb, t, st);
+hipError_t launch_typed(int kind, int ty, int nb, SetTable& t, hipStream_t st, int mode = 0) {
+  if (ty == 0) return launch_kind<float>(kind, nb, t, st, mode);
+  if (ty == 1) return launch_kind<double>(kind, nb, t, st, mode);
   if (kind == K_ANTERP) return launch_anterp<float, double>(nb, t, st);
   if (kind == K_INTERP) return launch_interp<float, double>(nb, t, st);
   return hipErrorInvalidValue;
 }
 
 struct Ref {
-  int l, phase, sub, kind, nb, ty;
+  int l, phase, sub, kind, nb, ty, mode;
   int member;
   const Step* step;
   bool operator<(const Ref& o) const {
@@ -952,6 +958,7 @@ struct Ref {
     if (kind != o.kind) return kind < o.kind;
     if (nb != o.nb) return nb < o.nb;
     if (ty != o.ty) return ty < o.ty;
+    if (mode != o.mode) return mode < o.mode;
     return member < o.member;
   }
 };
@@ -996,7 +1003,7 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
   for (size_t i = 0; i < m.size(); ++i) {
     const std::vector<Step>& sv = residual ? m[i].p->residual : m[i].p->pass;
     for (const Step& s : sv)
-      refs.push_back({s.l, s.phase, s.sub, s.kind, m[i].p->nb, s.ty, (int)i, &s});
+      refs.push_back({s.l, s.phase, s.sub, s.kind, m[i].p->nb, s.ty, s.mode, (int)i, &s});
   }
   std::sort(refs.begin(), refs.end());
   size_t a = 0;
@@ -1007,7 +1014,7 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
     t.pad = 0;
     while (b < refs.size() && t.n < kMaxSets && refs[b].l == refs[a].l && refs[b].phase == refs[a].phase &&
            refs[b].sub == refs[a].sub && refs[b].kind == refs[a].kind && refs[b].nb == refs[a].nb &&
-           refs[b].ty == refs[a].ty) {
+           refs[b].ty == refs[a].ty && refs[b].mode == refs[a].mode) {
       const Member& mm = m[refs[b].member];
       WorkSet& ws = t.s[t.n++];
       ws.items = refs[b].step->items;
@@ -1031,7 +1038,7 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
       LGF_HIP_CHECK(hipEventCreate(&rec.b));
       LGF_HIP_CHECK(hipEventRecord(rec.a, st));
     }
-    hipError_t e = launch_typed(refs[a].kind, refs[a].ty, refs[a].nb, t, st);
+    hipError_t e = launch_typed(refs[a].kind, refs[a].ty, refs[a].nb, t, st, refs[a].mode);
     if (e != hipSuccess) return e;
     if (prof) {
       LGF_HIP_CHECK(hipEventRecord(rec.b, st));
@@ -1061,6 +1068,153 @@ hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
       LGF_HIP_CHECK(launch_axpy(x.out, x.p->e, x.p->nblocks * N3, st));
     }
   }
+  return hipSuccess;
+}
+
+// ----------------------------------------------------------------------------- graphs
+namespace {
+struct GraphKey {
+  std::vector<std::tuple<Plan*, const double*, double*>> m;
+  bool operator<(const GraphKey& o) const { return m < o.m; }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+constexpr size_t kMaxGraphs = 64;
+
+bool graphs_enabled() {
+  static const bool on = std::getenv("LGF_NO_GRAPH") == nullptr;
+  return on;
+}
+}  // namespace
+
+void graph_forget(Plan* p) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    bool hit = false;
+    for (auto& t : it->first.m) hit |= std::get<0>(t) == p;
+    if (hit) {
+      (void)hipGraphExecDestroy(it->second);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st) {
+  bool prof;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof = g_prof_on;
+  }
+  if (!st || prof || !graphs_enabled()) return solve_members(m, st);
+  GraphKey key;
+  for (const Member& x : m) key.m.emplace_back(x.p, x.in, x.out);
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) return hipGraphLaunch(it->second, st);
+  }
+  LGF_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  hipError_t e = solve_members(m, st);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(st, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  LGF_HIP_CHECK(e2);
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  LGF_HIP_CHECK(e);
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(g_graphs.begin()->second);
+      g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs[key] = ex;
+  }
+  return hipGraphLaunch(ex, st);
+}
+
+// ----------------------------------------------------------------------------- autotuner
+// Chooses the MAC launch shape of every MAC step of a plan by timing each candidate on the
+// plan's own work items (3 repetitions, median), remembering the choice per (N_b, element type,
+// tile count) for the process and in the file named by LGF_TUNE_CACHE (one "nb ty tiles mode"
+// line per entry).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int64_t, 3>, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("LGF_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  long long a, b, c;
+  int mode;
+  while (std::fscanf(f, "%lld %lld %lld %d", &a, &b, &c, &mode) == 4) g_tune[{a, b, c}] = mode;
+  std::fclose(f);
+}
+void tune_store(const std::array<int64_t, 3>& k, int mode) {
+  g_tune[k] = mode;
+  const char* path = std::getenv("LGF_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%lld %lld %lld %d\n", (long long)k[0], (long long)k[1], (long long)k[2], mode);
+  std::fclose(f);
+}
+}  // namespace
+
+hipError_t plan_autotune(Plan* p, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load();
+  hipEvent_t a, b;
+  LGF_HIP_CHECK(hipEventCreate(&a));
+  LGF_HIP_CHECK(hipEventCreate(&b));
+  for (std::vector<Step>* list : {&p->pass}) {
+    for (Step& s : *list) {
+      if (s.kind != K_MAC) continue;
+      const std::array<int64_t, 3> key{p->nb, s.ty, s.count};
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        s.mode = it->second;
+        continue;
+      }
+      const int* cand = s.ty == 0 ? kMacModes32 : kMacModes64;
+      float best = 1e30f;
+      int best_mode = 0;
+      for (int c = 0; c < 3; ++c) {
+        float t[3];
+        for (int rep = 0; rep < 3; ++rep) {
+          SetTable tab;
+          tab.n = 1;
+          tab.pad = 0;
+          tab.s[0] = WorkSet{s.items, 0, s.count, 0, nullptr, nullptr, s.w};
+          LGF_HIP_CHECK(hipEventRecord(a, st));
+          LGF_HIP_CHECK(launch_typed(K_MAC, s.ty, p->nb, tab, st, cand[c]));
+          LGF_HIP_CHECK(hipEventRecord(b, st));
+          LGF_HIP_CHECK(hipEventSynchronize(b));
+          LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
+        }
+        std::sort(t, t + 3);
+        if (t[1] < best) {
+          best = t[1];
+          best_mode = cand[c];
+        }
+      }
+      s.mode = best_mode;
+      tune_store(key, best_mode);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   return hipSuccess;
 }
 

@@ -51,6 +51,7 @@ struct Step {
   int32_t count;
   const double* w;                     // weight table for the kernel (or nullptr)
   int64_t work;                        // MAC: block interactions in the step (for flop counts)
+  int mode;                            // MAC launch shape chosen by the autotuner (0: default)
 };
 
 // Optional launch timing: when enabled, every launch is bracketed by HIP events on its stream
@@ -77,8 +78,8 @@ struct Plan {
   std::vector<void*> allocs;
   int64_t bytes = 0;
   double* fe = nullptr;                // coarsened source (multi-level)
-  void* jw = nullptr;                  // T [n][N3]
-  void* w = nullptr;                   // T [n][N3]
+  void* jw = nullptr;                  // FP64 [n][N3]: interpolated coarse field J w
+  void* w = nullptr;                   // FP64 [n][N3]: leaf-only field of non-leaf blocks
   void* src = nullptr;                 // T [nsrc][N3]
   void* fhat = nullptr;                // cpx<T> [nsrc][S]
   void* uhat = nullptr;                // cpx<T> [ntgt][S]
@@ -95,7 +96,7 @@ struct Plan {
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
                       bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err,
-                      bool dry = false);
+                      bool dry = false, bool autotune = false);
 void plan_free(Plan* p);
 
 struct Member {
@@ -107,5 +108,9 @@ struct Member {
 hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st);
 // Full solve of several plans (pass, then defect-correction iterations), shared launches.
 hipError_t solve_members(const std::vector<Member>& m, hipStream_t st);
+// Same, replayed from a captured hipGraph when the same (plan, in, out) set was solved before on
+// a non-default stream (launch overhead of a solve's ~30-80 kernels paid once).
+hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st);
+void graph_forget(Plan* p);
 
 }  // namespace lgf

@@ -7,7 +7,7 @@ FP32 + defect correction within 1e-6; the LGF table within 1e-14 relative; integ
 import numpy as np
 import pytest
 
-from oracle import direct, fmm, lgf as olgf, multires
+from oracle import dc as dc_oracle, direct, fmm, lgf as olgf, multires
 from paper_1911_10228_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -125,13 +125,17 @@ def test_single_block(lgf):
 
 
 def test_uniform_fp32_defect_correction(lgf):
+    """FP32 without DC is compared with the FP64 FLGF oracle; with K DC iterations it is compared
+    with the oracle's DC of the same K (FP64 inner solves), which isolates precision: DC moves the
+    answer towards the lattice solution L u = f by the FMM truncation error."""
     L = workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=6, seed=3, interp_order=8)
     ref = fmm.flgf(L.blocks, L.f, L.n_b, 8)
-    errs = []
-    for dc in (0, 1, 2):
-        u, _ = gpu_solve(lgf, L, precision=1, dc=dc)
-        errs.append(rel_linf(u, ref))
-    assert max(errs) <= 1e-6, errs
+    u, _ = gpu_solve(lgf, L, precision=1, dc=0)
+    assert rel_linf(u, ref) <= 1e-6
+    its = dc_oracle.solve_dc(L.blocks, L.levels, L.f, L.n_b, 8, iters=2, dtype=np.float64)
+    for k in (1, 2):
+        u, _ = gpu_solve(lgf, L, precision=1, dc=k)
+        assert rel_linf(u, its[k]) <= 1e-6
 
 
 # ----------------------------------------------------------------------------- multi-resolution
@@ -167,8 +171,11 @@ def test_multires_fp64(lgf, make):
 def test_multires_fp32_defect_correction(lgf):
     L = three_level()
     ref = multires.solve(L.blocks, L.levels, L.f, L.n_b, L.interp_order)
-    u, _ = gpu_solve(lgf, L, precision=1, dc=2)
+    u, _ = gpu_solve(lgf, L, precision=1, dc=0)
     assert rel_linf(u, ref) <= 1e-6
+    its = dc_oracle.solve_dc(L.blocks, L.levels, L.f, L.n_b, L.interp_order, iters=2, dtype=np.float64)
+    u, _ = gpu_solve(lgf, L, precision=1, dc=2)
+    assert rel_linf(u, its[2]) <= 1e-6
 
 
 # ----------------------------------------------------------------------------- batching

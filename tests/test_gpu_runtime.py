@@ -1,0 +1,127 @@
+"""Runtime features on the GPU: captured-graph replays, the launch-shape autotuner, batched solves
+and the continuous-batching server.  Every result is compared with an eager single solve of the
+same plan (bitwise where the arithmetic is identical) and with the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import dc as dc_oracle, fmm, multires
+from paper_1911_10228_amd import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lgf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_10228_amd import lgf as m
+    m.init()
+    return m
+
+
+def field(L):
+    return torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
+
+
+def eager(lgf, plan, f):
+    """Solve on the legacy default stream (never captured into a graph)."""
+    u = torch.zeros_like(f)
+    lgf.load().lgf_solve(plan.handle, lgf._ptr(f), lgf._ptr(u), None)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def small_cases():
+    return [workloads.uniform_mixture(nblk=5, n_b=8, n_gauss=4, seed=21, interp_order=6),
+            workloads.uniform_mixture(nblk=3, n_b=16, n_gauss=3, seed=22, interp_order=8)]
+
+
+@pytest.mark.parametrize("precision,dc", [(0, 0), (1, 1)])
+def test_graph_replays_equal_eager(lgf, precision, dc):
+    L = small_cases()[0]
+    p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, precision, dc)
+    f = field(L)
+    ref = eager(lgf, p, f)
+    s = torch.cuda.Stream()
+    u = torch.zeros_like(f)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            u.zero_()                      # a fill kernel, not a memset, between replays
+            p.solve(f, u, stream=s)
+        s.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum()   # the program's own eager work
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref), f"replay {rep} differs"
+        del junk
+
+
+def test_autotuned_plan_matches(lgf):
+    for L in small_cases():
+        ref = fmm.flgf(L.blocks, L.f, L.n_b, L.interp_order)
+        for precision, tol in ((0, 1e-12), (1, 1e-6)):
+            p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, precision, 0)
+            a = eager(lgf, p, field(L))
+            opt = lgf.Options(precision, 0, 1, 0, 0)
+            import ctypes as C
+            h = C.c_void_p()
+            b = np.ascontiguousarray(L.blocks, dtype=np.int32)
+            lv = np.ascontiguousarray(L.levels, dtype=np.int32)
+            lgf._check(lgf.load().lgf_plan(b.ctypes.data, lv.ctypes.data, len(b), L.n_b,
+                                           L.interp_order, C.byref(opt), C.byref(h)), "lgf_plan")
+            q = lgf.Plan.__new__(lgf.Plan)
+            q._h, q.n_b, q.nblocks, q.precision = h, L.n_b, len(b), precision
+            c = eager(lgf, q, field(L))
+            assert np.abs(c - ref).max() <= tol * np.abs(ref).max()
+            assert np.abs(c - a).max() <= tol * np.abs(ref).max()
+            q.close()
+
+
+def test_server_results_equal_alone(lgf):
+    Ls = small_cases() + [workloads.uniform_gaussian()]
+    plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, 1, 1) for L in Ls]
+    fs = [field(L) for L in Ls]
+    alone = [eager(lgf, p, f) for p, f in zip(plans, fs)]
+    srv = lgf.Server(hbm_budget=0, stream=torch.cuda.Stream())
+    outs, ids = [], []
+    for rep in range(3):                      # the same plan arrives again while in flight
+        for p, f in zip(plans, fs):
+            u = torch.zeros_like(f)
+            outs.append(u)
+            ids.append(srv.submit(p, f, u))
+    srv.wait_all()
+    st = srv.stats()
+    assert st["completed"] == len(ids) and st["p99_us"] >= st["p50_us"] > 0
+    for k, u in enumerate(outs):
+        assert srv.poll(ids[k])
+        assert np.array_equal(u.cpu().numpy(), alone[k % len(plans)])
+    srv.close()
+
+
+def test_server_budget_admission(lgf):
+    Ls = small_cases()
+    plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, 0, 0) for L in Ls]
+    budget = min(p.info()["workspace_bytes"] for p in plans)   # only one plan fits at a time
+    fs = [field(L) for L in Ls]
+    srv = lgf.Server(hbm_budget=budget, stream=torch.cuda.Stream())
+    us = [torch.zeros_like(f) for f in fs]
+    ids = [srv.submit(p, f, u) for p, f, u in zip(plans, fs, us)]
+    srv.wait_all()
+    for p, f, u in zip(plans, fs, us):
+        assert np.array_equal(u.cpu().numpy(), eager(lgf, p, f))
+    srv.close()
+
+
+def test_multires_torus_reduced_matches_oracle(lgf):
+    L = workloads.torus(nblk=4, n_b=8, n_levels=3, interp_order=6)
+    p = lgf.Plan(L.blocks, L.levels, L.n_b, 6, 0, 0)
+    u = eager(lgf, p, field(L))
+    ref = multires.solve(L.blocks, L.levels, L.f, L.n_b, 6)
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+    p32 = lgf.Plan(L.blocks, L.levels, L.n_b, 6, 1, 0)
+    u32 = eager(lgf, p32, field(L))
+    assert np.abs(u32 - ref).max() <= 1e-6 * np.abs(ref).max()
+    its = dc_oracle.solve_dc(L.blocks, L.levels, L.f, L.n_b, 6, iters=1, dtype=np.float64)
+    p32 = lgf.Plan(L.blocks, L.levels, L.n_b, 6, 1, 1)
+    u32 = eager(lgf, p32, field(L))
+    assert np.abs(u32 - its[1]).max() <= 1e-6 * np.abs(its[1]).max()
