@@ -26,6 +26,21 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
 
 
+def measured_traffic(name, source):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_uniform8_nb16.md")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1911_10228_amd", "csrc", source), "rb").read()).hexdigest()
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 6 and parts[0] == "traffic" and parts[1] == name and parts[5] == sha:
+            return float(parts[2])
+    return None
+
+
 def spectrum_size(n_b):
     P = 2 * n_b
     return P * P * (n_b + 1)
@@ -91,7 +106,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dc", type=int, default=1, help="defect-correction iterations of the FP32 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every kernel directly (no captured-graph replays), for profilers")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 512 MiB device-to-device copy 3 times (counter calibration)")
     args = ap.parse_args()
+    if args.no_graph:
+        os.environ["LGF_NO_GRAPH"] = "1"
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
               "not part of this build", file=sys.stderr)
@@ -140,8 +170,9 @@ def main():
     dom = kern[0]
     if dom.get("unit") == "flop":
         peak = PEAK["fp32_vector_tflops"] if dom["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
+        traffic = measured_traffic("mac_fp32_nb16", "mac.hip") if dom["precision"] == "fp32" else None
         roof = {"bound": "alu", "achieved": round(dom["rate"], 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(dom["rate"] / peak, 4), "traffic": None,
+                "frac": round(dom["rate"] / peak, 4), "traffic": traffic,
                 "kernel": f"spectral MAC ({dom['precision']}, n_b={dom['n_b']})",
                 "avg_launch_us": round(dom["avg_us"], 2)}
     elif dom.get("unit") == "byte":
