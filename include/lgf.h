@@ -56,11 +56,20 @@ typedef enum {
                            repeated dc_iters times (defect correction) */
 } lgf_precision;
 
+/* How the base octree level of every refinement level is convolved.  Both give the same result
+ * up to rounding: every base-level interaction of a block (its near list N(B) and influence list
+ * I(B), Sec. 2.1) has its source among the children of the 27 neighbours of the block's parent.
+ *   LGF_BASE_SUPER: one zero-padded convolution per parent super-block (2 N_b cells per side,
+ *                   FFT size 4 N_b) against the 27 neighbouring super-blocks (default);
+ *   LGF_BASE_BLOCK: one zero-padded convolution per block (FFT size 2 N_b) against the up to 216
+ *                   blocks of its lists, as the paper describes. */
+typedef enum { LGF_BASE_SUPER = 0, LGF_BASE_BLOCK = 1 } lgf_base_level;
+
 typedef struct {
   int32_t precision;     /* lgf_precision */
   int32_t dc_iters;      /* defect-correction iterations for LGF_FP32_REFINE (0..8) */
-  int32_t autotune;      /* reserved for launch-shape selection; 0 = defaults */
-  int32_t reserved;
+  int32_t autotune;      /* 1: time the launch shapes of the far-field MAC steps at plan time */
+  int32_t base_level;    /* lgf_base_level */
   uint64_t hbm_budget;   /* bytes the plan may allocate; 0 = unlimited */
 } lgf_options;
 
@@ -75,6 +84,10 @@ typedef struct {
   int64_t mac_rows;
   int64_t workspace_bytes;    /* device bytes owned by the plan */
   int64_t spectra;            /* distinct kernel spectra referenced */
+  int64_t super_forward;      /* forward super-block FFTs per solve pass (LGF_BASE_SUPER) */
+  int64_t super_inverse;      /* inverse super-block FFTs per solve pass */
+  int64_t near_rows;          /* rows of 8 target super-blocks in the base-level MAC */
+  int64_t near_pairs;         /* (target, source) super-block pairs in the base-level MAC */
 } lgf_plan_info;
 
 /* Builds the FP64 LGF table on the current device (Sec. 2: quadrature of eq. GL_B for
@@ -112,7 +125,9 @@ const char* lgf_status_string(lgf_status s);
  * lgf_green_table: copies the dense table cube [101][101][101] (entries for sorted
  *   a >= b >= c with a^2+b^2+c^2 <= 100^2 are valid) to the device array out.
  * lgf_kernel_spectrum: FP64 half spectrum [2N_b][2N_b][N_b+1] (kx fastest) of the zero-padded
- *   kernel block G(s (d N_b + r)) to the device array out (complex as interleaved doubles). */
+ *   kernel block G(s (d N_b + r)), |d| <= 3, s a power of two, to the device array out (complex
+ *   as interleaved doubles).  s = 0 selects the base-level super-block kernels instead: block
+ *   side B = 2 N_b, G(d B + r) for |d| <= 1, half spectrum [2B][2B][B+1]. */
 lgf_status lgf_green_eval(const int32_t* n, int64_t m, double* out, lgf_stream_t stream);
 lgf_status lgf_green_table(double* out, lgf_stream_t stream);
 lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, int32_t dz,

@@ -64,11 +64,13 @@ lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int
   if (opt) o = *opt;
   if (o.precision != LGF_FP64_PLAIN && o.precision != LGF_FP32_REFINE) return LGF_EINVAL;
   if (o.dc_iters < 0 || o.dc_iters > 8) return LGF_EINVAL;
+  if (o.base_level != LGF_BASE_SUPER && o.base_level != LGF_BASE_BLOCK) return LGF_EINVAL;
   if (!validate_layout(blocks, levels, n)) return LGF_ELAYOUT;
   lgf::Plan* p = nullptr;
   std::string err;
   hipError_t e = lgf::plan_build(blocks, levels, n, N_b, interp_order, o.precision == LGF_FP32_REFINE,
-                                 o.dc_iters, o.hbm_budget, &p, &err, false, o.autotune != 0);
+                                 o.dc_iters, o.hbm_budget, &p, &err, false, o.autotune != 0,
+                                 o.base_level == LGF_BASE_SUPER);
   if (e != hipSuccess) {
     if (!err.empty()) std::fprintf(stderr, "lgf_plan: %s\n", err.c_str());
     return from_hip(e);
@@ -86,11 +88,13 @@ lgf_status lgf_plan_check(const int32_t* blocks, const int32_t* levels, int64_t 
   if (opt) o = *opt;
   if (o.precision != LGF_FP64_PLAIN && o.precision != LGF_FP32_REFINE) return LGF_EINVAL;
   if (o.dc_iters < 0 || o.dc_iters > 8) return LGF_EINVAL;
+  if (o.base_level != LGF_BASE_SUPER && o.base_level != LGF_BASE_BLOCK) return LGF_EINVAL;
   if (!validate_layout(blocks, levels, n)) return LGF_ELAYOUT;
   lgf::Plan* p = nullptr;
   std::string err;
   hipError_t e = lgf::plan_build(blocks, levels, n, N_b, interp_order, o.precision == LGF_FP32_REFINE,
-                                 o.dc_iters, o.hbm_budget, &p, &err, /*dry=*/true);
+                                 o.dc_iters, o.hbm_budget, &p, &err, /*dry=*/true, false,
+                                 o.base_level == LGF_BASE_SUPER);
   if (e != hipSuccess) {
     if (!err.empty()) std::fprintf(stderr, "lgf_plan_check: %s\n", err.c_str());
     return e == hipErrorOutOfMemory ? LGF_ENOMEM : LGF_EINVAL;
@@ -135,6 +139,10 @@ lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out) {
   out->mac_rows = q->n_rows;
   out->workspace_bytes = q->bytes;
   out->spectra = q->n_spectra;
+  out->super_forward = q->n_sup_fwd;
+  out->super_inverse = q->n_sup_inv;
+  out->near_rows = q->n_near_rows;
+  out->near_pairs = q->near_pairs;
   return LGF_OK;
 }
 
@@ -177,8 +185,9 @@ lgf_status lgf_green_table(double* out, lgf_stream_t stream) {
 
 lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, int32_t dz, double* out,
                                lgf_stream_t stream) {
-  if (!out || (N_b != 8 && N_b != 16) || s < 1 || (s & (s - 1)) || dx < -3 || dx > 3 || dy < -3 ||
-      dy > 3 || dz < -3 || dz > 3)
+  const int R = s == 0 ? 1 : 3;
+  if (!out || (N_b != 8 && N_b != 16) || s < 0 || (s & (s - 1)) || dx < -R || dx > R || dy < -R ||
+      dy > R || dz < -R || dz > R)
     return LGF_EINVAL;
   lgf::DeviceCtx* c = nullptr;
   hipError_t e = lgf::device_ctx(&c);
@@ -186,8 +195,9 @@ lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, i
   const lgf::SpecSet* ss = nullptr;
   e = lgf::spectra_for(c, N_b, s, &ss);
   if (e != hipSuccess) return from_hip(e);
-  const size_t S = (size_t)(2 * N_b) * (2 * N_b) * (N_b + 1);
-  const int idx = (dz + 3) * 49 + (dy + 3) * 7 + (dx + 3);
+  const size_t S = (size_t)ss->spec;
+  const int W = 2 * R + 1;
+  const int idx = ((dz + R) * W + (dy + R)) * W + (dx + R);
   return from_hip(hipMemcpyAsync(out, ss->d64 + idx * S, S * sizeof(lgf::c64), hipMemcpyDeviceToDevice,
                                  (hipStream_t)stream));
 }

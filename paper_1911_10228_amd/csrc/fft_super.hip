@@ -1,0 +1,206 @@
+// Zero-padded FFTs of base-level super-blocks.
+//
+// On the base octree level every target's interaction region (its near field N(B) plus its
+// influence list I(B), Sec. 2.1) is exactly the set of children of its parent's 27 neighbours.
+// The base-level interaction of all 8 children of a parent is therefore one block convolution of
+// the parent-sized super-block (B2 = 2 N_b cells per side, zero-padded to P = 2 B2) with its 27
+// neighbouring super-blocks, against the base-lattice kernel.  These kernels transform a
+// super-block assembled from (up to) eight child blocks, and scatter the inverse transform's
+// cropped output back to the children.
+//
+// Each direction takes two passes through a global intermediate plane stack
+// T[z][ky][kx] (z < B2, ky < P, kx <= B2): the (x, y) pass transforms one z-plane per lane group,
+// the z pass one (kx, ky) line per lane.  Every length-P line has only its first B2 entries
+// nonzero (forward) or needed (inverse), so each is two length-B2 transforms.
+#include "kernels.hpp"
+
+namespace lgf {
+
+namespace {
+
+template <int B2> struct SupShape {
+  static constexpr int P = 2 * B2;
+  static constexpr int H = B2 + 1;               // kx in [0, B2]
+  static constexpr int NB = B2 / 2;              // child block side
+  static constexpr int PLANE = P * H;            // complex entries per intermediate plane
+  static constexpr int S = P * P * H;
+};
+
+// child element (x, y, z) of a super-block, children indexed by octant cx + 2 cy + 4 cz
+template <int NB, typename T>
+__device__ __forceinline__ T child_value(const T* const* ch, int x, int y, int z) {
+  const int oc = (x >= NB) + 2 * (y >= NB) + 4 * (z >= NB);
+  const T* c = ch[oc];
+  if (!c) return T(0);
+  const int lx = x & (NB - 1), ly = y & (NB - 1), lz = z & (NB - 1);
+  return c[(lz * NB + ly) * NB + lx];
+}
+
+// forward (x, y) pass: one workgroup per (super-block, z-plane); lanes own x-lines, then y-lines
+// T: transform and spectrum type, TC: element type of the child blocks
+template <int B2, typename T, typename TC>
+__global__ __launch_bounds__(64) void sup_fwd_xy(SetTable sets) {
+  using Sh = SupShape<B2>;
+  constexpr int P = Sh::P, H = Sh::H, NB = Sh::NB;
+  __shared__ cpx<T> pl[B2 * H];                 // [y][kx] after the x pass
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const SuperFwdItem<T>& it = ((const SuperFwdItem<T>*)ws.items)[local / B2];
+  const TC* const* ch = (const TC* const*)it.child;
+  const int z = (int)(local % B2);
+  const int tid = threadIdx.x;
+  for (int y = tid; y < B2; y += 64) {
+    T xr[B2], xi[B2], Xr[P], Xi[P];
+#pragma unroll
+    for (int x = 0; x < B2; ++x) { xr[x] = T(child_value<NB>(ch, x, y, z)); xi[x] = T(0); }
+    fwd_padded<B2>(xr, xi, Xr, Xi);
+#pragma unroll
+    for (int k = 0; k < H; ++k) pl[y * H + k] = {Xr[k], Xi[k]};
+  }
+  __syncthreads();
+  cpx<T>* out = it.tmp + (int64_t)z * Sh::PLANE;
+  for (int kx = tid; kx < H; kx += 64) {
+    T yr[B2], yi[B2], Yr[P], Yi[P];
+#pragma unroll
+    for (int y = 0; y < B2; ++y) { yr[y] = pl[y * H + kx].x; yi[y] = pl[y * H + kx].y; }
+    fwd_padded<B2>(yr, yi, Yr, Yi);
+#pragma unroll
+    for (int ky = 0; ky < P; ++ky) out[ky * H + kx] = {Yr[ky], Yi[ky]};
+  }
+}
+
+// forward z pass: one lane per (kx, ky) line
+template <int B2, typename T>
+__global__ __launch_bounds__(256) void sup_fwd_z(SetTable sets) {
+  using Sh = SupShape<B2>;
+  constexpr int P = Sh::P, B = B2;
+  constexpr int LINES = Sh::PLANE;
+  constexpr int WG_PER_ITEM = (LINES + 255) / 256;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const SuperFwdItem<T>& it = ((const SuperFwdItem<T>*)ws.items)[local / WG_PER_ITEM];
+  const int line = (int)(local % WG_PER_ITEM) * 256 + threadIdx.x;
+  if (line >= LINES) return;
+  const cpx<T>* in = it.tmp + line;
+  T zr[B], zi[B], Zr[P], Zi[P];
+#pragma unroll
+  for (int z = 0; z < B; ++z) { const cpx<T> v = in[(int64_t)z * LINES]; zr[z] = v.x; zi[z] = v.y; }
+  fwd_padded<B>(zr, zi, Zr, Zi);
+  cpx<T>* out = it.dst + line;
+#pragma unroll
+  for (int kz = 0; kz < P; ++kz) out[(int64_t)kz * LINES] = {Zr[kz], Zi[kz]};
+}
+
+// inverse z pass: one lane per (kx, ky) line, keep z < B2
+template <int B2, typename T>
+__global__ __launch_bounds__(256) void sup_inv_z(SetTable sets) {
+  using Sh = SupShape<B2>;
+  constexpr int P = Sh::P, B = B2;
+  constexpr int LINES = Sh::PLANE;
+  constexpr int WG_PER_ITEM = (LINES + 255) / 256;
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const SuperInvItem<T>& it = ((const SuperInvItem<T>*)ws.items)[local / WG_PER_ITEM];
+  const int line = (int)(local % WG_PER_ITEM) * 256 + threadIdx.x;
+  if (line >= LINES) return;
+  const cpx<T>* in = it.src + line;
+  T Zr[P], Zi[P], zr[B], zi[B];
+#pragma unroll
+  for (int kz = 0; kz < P; ++kz) { const cpx<T> v = in[(int64_t)kz * LINES]; Zr[kz] = v.x; Zi[kz] = v.y; }
+  inv_cropped<B>(Zr, Zi, zr, zi);
+  cpx<T>* out = it.tmp + line;
+#pragma unroll
+  for (int z = 0; z < B; ++z) out[(int64_t)z * LINES] = {zr[z], zi[z]};
+}
+
+// inverse (y, x) pass: one workgroup per (super-block, z-plane); crop, scale by 1/P^3 and write
+// the children's cells
+template <int B2, typename T, typename TC>
+__global__ __launch_bounds__(64) void sup_inv_yx(SetTable sets) {
+  using Sh = SupShape<B2>;
+  constexpr int P = Sh::P, H = Sh::H, NB = Sh::NB;
+  __shared__ cpx<T> pl[B2 * H];                 // [y][kx] after the y pass
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const SuperInvItem<T>& it = ((const SuperInvItem<T>*)ws.items)[local / B2];
+  const int z = (int)(local % B2);
+  const int tid = threadIdx.x;
+  const cpx<T>* in = it.tmp + (int64_t)z * Sh::PLANE;
+  for (int kx = tid; kx < H; kx += 64) {
+    T Yr[P], Yi[P], yr[B2], yi[B2];
+#pragma unroll
+    for (int ky = 0; ky < P; ++ky) { const cpx<T> v = in[ky * H + kx]; Yr[ky] = v.x; Yi[ky] = v.y; }
+    inv_cropped<B2>(Yr, Yi, yr, yi);
+#pragma unroll
+    for (int y = 0; y < B2; ++y) pl[y * H + kx] = {yr[y], yi[y]};
+  }
+  __syncthreads();
+  const T inv = T(1.0 / (double(P) * P * P));
+  const int cz = z / NB, lz = z % NB;
+  for (int y = tid; y < B2; y += 64) {
+    T Xr[P], Xi[P], xr[B2], xi[B2];
+#pragma unroll
+    for (int k = 0; k < H; ++k) { Xr[k] = pl[y * H + k].x; Xi[k] = pl[y * H + k].y; }
+#pragma unroll
+    for (int k = 1; k < B2; ++k) { Xr[P - k] = Xr[k]; Xi[P - k] = -Xi[k]; }
+    inv_cropped<B2>(Xr, Xi, xr, xi);
+    const int cy = y / NB, ly = y % NB;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      TC* c = (TC*)it.child[half + 2 * cy + 4 * cz];
+      if (!c) continue;
+      TC* row = c + (lz * NB + ly) * NB;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) row[x] = TC(xr[half * NB + x] * inv);
+    }
+  }
+}
+
+template <int B2, typename T, typename TC> hipError_t fwd_b2(SetTable& t, hipStream_t st) {
+  using Sh = SupShape<B2>;
+  const int64_t wg1 = assign_wg(t, B2);
+  if (wg1 == 0) return hipSuccess;
+  sup_fwd_xy<B2, T, TC><<<(unsigned)wg1, 64, 0, st>>>(t);
+  LGF_HIP_CHECK(hipGetLastError());
+  const int64_t wg2 = assign_wg(t, (Sh::PLANE + 255) / 256);
+  sup_fwd_z<B2, T><<<(unsigned)wg2, 256, 0, st>>>(t);
+  return hipGetLastError();
+}
+
+template <int B2, typename T, typename TC> hipError_t inv_b2(SetTable& t, hipStream_t st) {
+  using Sh = SupShape<B2>;
+  const int64_t wg1 = assign_wg(t, (Sh::PLANE + 255) / 256);
+  if (wg1 == 0) return hipSuccess;
+  sup_inv_z<B2, T><<<(unsigned)wg1, 256, 0, st>>>(t);
+  LGF_HIP_CHECK(hipGetLastError());
+  const int64_t wg2 = assign_wg(t, B2);
+  sup_inv_yx<B2, T, TC><<<(unsigned)wg2, 64, 0, st>>>(t);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// nb is the child block side; the super-block side is 2 nb.  T: transform type, TC: child type.
+template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st) {
+  if (nb == 16) return fwd_b2<32, T, TC>(t, st);
+  if (nb == 8) return fwd_b2<16, T, TC>(t, st);
+  return hipErrorInvalidValue;
+}
+template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st) {
+  if (nb == 16) return inv_b2<32, T, TC>(t, st);
+  if (nb == 8) return inv_b2<16, T, TC>(t, st);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_super_fwd<float, float>(int, SetTable&, hipStream_t);
+template hipError_t launch_super_fwd<double, double>(int, SetTable&, hipStream_t);
+template hipError_t launch_super_fwd<double, float>(int, SetTable&, hipStream_t);
+template hipError_t launch_super_inv<float, float>(int, SetTable&, hipStream_t);
+template hipError_t launch_super_inv<double, double>(int, SetTable&, hipStream_t);
+template hipError_t launch_super_inv<double, float>(int, SetTable&, hipStream_t);
+
+}  // namespace lgf

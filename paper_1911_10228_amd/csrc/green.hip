@@ -178,6 +178,54 @@ __global__ void full_fft_z(const c64* __restrict__ tmp, c64* __restrict__ out64,
   }
 }
 
+// The same three passes for long lines: one workgroup of P lanes per line, lane k forms output k
+// as a direct DFT from the line staged in LDS, with twiddles e^{-2 pi i m / P} from sincospi.
+// PASS 0: real x-lines -> tmp[spec][z][y][kx]; PASS 1: y-lines of tmp in place; PASS 2: z-lines
+// of tmp -> out[spec][kz][ky][kx].
+template <int P, int PASS>
+__global__ __launch_bounds__(P) void full_dft_lds(const double* __restrict__ in_real,
+                                                  const c64* in_c, c64* out, c32* out32,
+                                                  int nspec) {
+  constexpr int H = P / 2 + 1;
+  __shared__ double lr[P], li[P], wr[P], wi[P];
+  const int64_t line = blockIdx.x;
+  const int k = threadIdx.x;
+  {
+    double s, c;
+    sincospi(-2.0 * k / P, &s, &c);
+    wr[k] = c;
+    wi[k] = s;
+  }
+  int64_t base, stride, obase, ostride;
+  if (PASS == 0) {                     // line = (spec, z, y)
+    base = line * P; stride = 1; obase = line * H; ostride = 1;
+  } else if (PASS == 1) {              // line = (spec, z, kx)
+    const int kx = line % H;
+    base = (line / H) * P * H + kx; stride = H; obase = base; ostride = H;
+  } else {                             // line = (spec, ky, kx)
+    const int64_t spec = line / (P * H);
+    base = spec * P * P * H + line % (P * H); stride = (int64_t)P * H; obase = base; ostride = stride;
+  }
+  if (PASS == 0) {
+    lr[k] = in_real[base + k];
+    li[k] = 0.0;
+  } else {
+    const c64 v = in_c[base + k * stride];
+    lr[k] = v.x;
+    li[k] = v.y;
+  }
+  __syncthreads();
+  double sr = 0.0, si = 0.0;
+  for (int j = 0; j < P; ++j) {
+    const int m = (j * k) & (P - 1);
+    sr += lr[j] * wr[m] - li[j] * wi[m];
+    si += lr[j] * wi[m] + li[j] * wr[m];
+  }
+  if (PASS == 0 && k >= H) return;
+  out[obase + k * ostride] = {sr, si};
+  if (PASS == 2 && out32) out32[obase + k * ostride] = {float(sr), float(si)};
+}
+
 }  // namespace
 
 int quad_nodes() { return kQuadNodes; }
@@ -216,6 +264,11 @@ hipError_t launch_kernel_spectra(int nb, int nspec, const int32_t* d_sd, const d
     full_fft_x<16><<<(unsigned)((lx + 63) / 64), 64, 0, st>>>(d_real, d_tmp, nspec);
     full_fft_y<16><<<(unsigned)((ly + 63) / 64), 64, 0, st>>>(d_tmp, nspec);
     full_fft_z<16><<<(unsigned)((ly + 63) / 64), 64, 0, st>>>(d_tmp, d_out64, d_out32, nspec);
+  } else if (P == 64) {
+    // too long a line for one lane's registers: one workgroup per line, DFT through LDS
+    full_dft_lds<64, 0><<<(unsigned)lx, 64, 0, st>>>(d_real, nullptr, d_tmp, nullptr, nspec);
+    full_dft_lds<64, 1><<<(unsigned)ly, 64, 0, st>>>(nullptr, d_tmp, d_tmp, nullptr, nspec);
+    full_dft_lds<64, 2><<<(unsigned)ly, 64, 0, st>>>(nullptr, d_tmp, d_out64, d_out32, nspec);
   } else {
     return hipErrorInvalidValue;
   }

@@ -64,6 +64,34 @@ template <typename T> struct MacTile {
   cpx<T>* uhat;                        // target spectra arena (slot * S)
   const cpx<T>* const* kptr;           // 343 kernel spectra of the tile's level, (dz+3)*49+(dy+3)*7+dx+3
 };
+// Base-level super-blocks (the 2x2x2 children of one parent, side B2 = 2 N_b, FFT size P = 2 B2)
+template <typename T> struct SuperFwdItem {
+  const T* child[8];     // child source blocks, octant cx + 2 cy + 4 cz (nullptr: zero)
+  cpx<T>* tmp;           // intermediate planes [B2][P][B2+1]
+  cpx<T>* dst;           // super-block half spectrum [P][P][B2+1]
+};
+template <typename T> struct SuperInvItem {
+  const cpx<T>* src;     // super-block half spectrum
+  cpx<T>* tmp;           // intermediate planes
+  T* child[8];           // child field blocks receiving the cropped IFFT / P^3 (nullptr: skip)
+};
+constexpr int kNearSlots = kMacL + 2;     // source x slots of a near row: x0 - 1 .. x0 + W
+// A near row: up to W (4 or 8) super-block targets along x starting at x0 = W wx; each interacts
+// with the 27 super-blocks at offsets |D|_inf <= 1 through the exact base-lattice kernel.  The
+// non-empty source rows (dy, dz) are listed first, padded with all-zero rows to a multiple of 3.
+template <typename T> struct NearRow {
+  int32_t tgt[kMacL];                  // target super slots (-1: none), first W used
+  int32_t src[9][kNearSlots];          // source super slots of listed row i at x0 - 1 + q, q < W + 2
+                                       // (the zero slot where absent)
+  uint64_t pj_code;                    // listed row i is source row (dz+1)*3+(dy+1) =
+                                       // bits [4 i, 4 i + 4) (one scalar word: no per-row loads)
+  int32_t ngroups;                     // listed rows / 3
+  int32_t pad;
+  const cpx<T>* fhat;                  // super source spectra arena (slot * S)
+  cpx<T>* uhat;                        // super target spectra arena
+  const c64* const* kptr;              // 27 FP64 kernel spectra, index (dz+1)*9+(dy+1)*3+dx+1
+};
+
 // TC: element type of the child level, TP: of the parent level (they differ where an FP32
 // base level meets FP64 coarse levels).
 template <typename TC, typename TP> struct AnterpItem {
@@ -150,6 +178,9 @@ hipError_t launch_refine(int nb, SetTable& t, hipStream_t st);                  
 template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st);  // ws.w = W3
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);
+template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st);
+template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st);
+template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int width);
 
 // number of workgroups each item of a kernel needs (for set-table bookkeeping)
 inline int64_t assign_wg(SetTable& t, int64_t per_item_num, int64_t per_item_den = 1) {

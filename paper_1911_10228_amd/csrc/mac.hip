@@ -263,4 +263,125 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
 template hipError_t launch_mac<float>(int, SetTable&, hipStream_t, int);
 template hipError_t launch_mac<double>(int, SetTable&, hipStream_t, int);
 
+// ============================================================================= near (super) MAC
+// U_P[k] = sum over the 27 super-blocks Q with |P - Q|_inf <= 1 of K_{P-Q}[k] F_Q[k].
+// One wavefront owns a row of W target super-blocks along x and 64 frequencies.  The source rows
+// (dy, dz) that hold sources come in groups of 3; a group's 3 (W + 2) source spectra are loaded
+// together while the previous group is applied (3 kernel offsets along x each, kernels from LDS:
+// 27 kernels x 64 frequencies).  The products are formed and summed in FP64 from FP64 kernel
+// spectra whatever the storage type T of the super-block spectra: the FP64 multiply-add rate
+// equals the unpacked FP32 rate, and the FP64 sum keeps the rounding of the largest
+// (low-frequency) terms out of the smooth part of the result.
+namespace {
+
+template <typename T, int NS>
+__device__ __forceinline__ void load_group(cpx<T> (&f)[3][NS], const NearRow<T>* row, int g,
+                                           gptr<T> F, int S, int k) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) f[r][s] = gload<T>(F, (int64_t)row->src[3 * g + r][s] * S + k);
+}
+
+template <typename T, int W, int NS>
+__device__ __forceinline__ void apply_group(cpx<double> (&acc)[W], const cpx<T> (&f)[3][NS],
+                                            uint64_t code, int g, const cpx<double>* kl, int lane) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int pj = (int)((code >> (4 * (3 * g + r))) & 15u);
+    cpx<double> fd[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) fd[s] = {double(f[r][s].x), double(f[r][s].y)};
+#pragma unroll
+    for (int dxi = 0; dxi < 3; ++dxi) {
+      const cpx<double> kv = kl[(pj * 3 + dxi) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < W; ++i) cmac(acc[i], kv, fd[i - dxi + 2]);   // src x = x0 + i - dx
+    }
+  }
+}
+
+template <typename T, int W, int NG>
+__device__ __forceinline__ void near_groups(cpx<double> (&acc)[W], const NearRow<T>* row,
+                                            uint64_t code, gptr<T> F, int S, int k,
+                                            const cpx<double>* kl, int lane) {
+  constexpr int NS = W + 2;
+  cpx<T> fa[3][NS], fb[3][NS];
+  load_group<T, NS>(fa, row, 0, F, S, k);
+  if constexpr (NG > 1) load_group<T, NS>(fb, row, 1, F, S, k);
+  apply_group<T, W, NS>(acc, fa, code, 0, kl, lane);
+  if constexpr (NG > 2) load_group<T, NS>(fa, row, 2, F, S, k);
+  if constexpr (NG > 1) apply_group<T, W, NS>(acc, fb, code, 1, kl, lane);
+  if constexpr (NG > 2) apply_group<T, W, NS>(acc, fa, code, 2, kl, lane);
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
+  constexpr int NS = W + 2;
+  __shared__ cpx<double> kl[27 * 64];
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;       // wg_begin is a multiple of 8
+  const int ngroups = (ws.count + 3) / 4;
+  const int xcd = (int)(local & 7);
+  const int64_t j = local >> 3;
+  const int chunk = (int)(j / ngroups) * 8 + xcd;
+  const int grp = (int)(j % ngroups);
+  if (chunk * 64 >= S) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int k = chunk * 64 + lane;
+  const NearRow<T>* rows = (const NearRow<T>*)ws.items;
+  const int ri = grp * 4 + wave;
+  const bool active = ri < ws.count;
+  const NearRow<T>* row = rows + (active ? ri : grp * 4);
+  const cptr64 kp = (cptr64)row->kptr;
+  for (int h = wave; h < 27; h += 4) kl[h * 64 + lane] = gload<double>((gptr<double>)kp[h], k);
+  __syncthreads();
+  if (!active) return;
+
+  gptr<T> F = (gptr<T>)row->fhat;
+  cpx<double> acc[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) acc[i] = {0.0, 0.0};
+  const int ng = row->ngroups;
+  const uint64_t code = row->pj_code;
+  // straight-line code per group count, so that every wait for a group's loads leaves the next
+  // group's loads in flight (the vector memory counter retires in order)
+  if (ng == 3) near_groups<T, W, 3>(acc, row, code, F, S, k, kl, lane);
+  else if (ng == 2) near_groups<T, W, 2>(acc, row, code, F, S, k, kl, lane);
+  else if (ng == 1) near_groups<T, W, 1>(acc, row, code, F, S, k, kl, lane);
+  gmut<T> U = (gmut<T>)row->uhat;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const int t = row->tgt[i];
+    if (t >= 0) {
+      U[2 * ((int64_t)t * S + k)] = T(acc[i].x);
+      U[2 * ((int64_t)t * S + k) + 1] = T(acc[i].y);
+    }
+  }
+}
+
+}  // namespace
+
+// width: targets per row (4 or 8), chosen by the planner
+template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int width) {
+  const int B2 = 2 * nb, P = 2 * B2;
+  const int S = P * P * (B2 + 1);
+  if (S % 64) return hipErrorInvalidValue;
+  const int chunks8 = (S / 64 + 7) / 8;
+  int64_t wg = 0;
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (int64_t)((t.s[i].count + 3) / 4) * chunks8 * 8;
+  }
+  if (wg == 0) return hipSuccess;
+  if (width == 4) near_mac_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else if (width == 8) near_mac_kernel<T, 8><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template hipError_t launch_near_mac<float>(int, SetTable&, hipStream_t, int);
+template hipError_t launch_near_mac<double>(int, SetTable&, hipStream_t, int);
+
 }  // namespace lgf

@@ -258,28 +258,37 @@ struct Arena {
   }
 };
 
+// spectra count and size of a kernel set (s == 0: the 27 super-block neighbour spectra)
+inline int spec_count(int s) { return s == 0 ? 27 : 343; }
+inline int64_t spec_size(int nb, int s) {
+  const int64_t b = s == 0 ? 2 * nb : nb;
+  return (2 * b) * (2 * b) * (b + 1);
+}
+
 // kernel spectra of (nb, s) for a plan: the shared cache, or fake ranges in a dry build
 hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
+  const int cnt = spec_count(s);
+  const size_t S = (size_t)spec_size(nb, s);
   if (!p->dry) {
     LGF_HIP_CHECK(spectra_for(p->ctx, nb, s, out));
-    const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
-    p->ranges.push_back({(uintptr_t)(*out)->d64, 343 * S * sizeof(c64)});
-    p->ranges.push_back({(uintptr_t)(*out)->d32, 343 * S * sizeof(c32)});
-    p->ranges.push_back({(uintptr_t)(*out)->kp64, 343 * sizeof(void*)});
-    p->ranges.push_back({(uintptr_t)(*out)->kp32, 343 * sizeof(void*)});
+    p->ranges.push_back({(uintptr_t)(*out)->d64, cnt * S * sizeof(c64)});
+    p->ranges.push_back({(uintptr_t)(*out)->d32, cnt * S * sizeof(c32)});
+    p->ranges.push_back({(uintptr_t)(*out)->kp64, cnt * sizeof(void*)});
+    p->ranges.push_back({(uintptr_t)(*out)->kp32, cnt * sizeof(void*)});
     return hipSuccess;
   }
   auto key = std::make_pair(nb, s);
   auto it = p->dry_spectra.find(key);
   if (it == p->dry_spectra.end()) {
-    const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
     SpecSet ss;
     ss.nb = nb;
     ss.s = s;
-    ss.d64 = (c64*)fake_alloc(p, 343 * S * sizeof(c64));
-    ss.d32 = (c32*)fake_alloc(p, 343 * S * sizeof(c32));
-    ss.kp64 = (const c64**)fake_alloc(p, 343 * sizeof(void*));
-    ss.kp32 = (const c32**)fake_alloc(p, 343 * sizeof(void*));
+    ss.count = cnt;
+    ss.spec = (int64_t)S;
+    ss.d64 = (c64*)fake_alloc(p, cnt * S * sizeof(c64));
+    ss.d32 = (c32*)fake_alloc(p, cnt * S * sizeof(c32));
+    ss.kp64 = (const c64**)fake_alloc(p, cnt * sizeof(void*));
+    ss.kp32 = (const c32**)fake_alloc(p, cnt * sizeof(void*));
     it = p->dry_spectra.emplace(key, ss).first;
   }
   *out = &it->second;
@@ -346,42 +355,47 @@ hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out) {
     *out = &it->second;
     return hipSuccess;
   }
-  const int P = 2 * nb, H = nb + 1;
+  // s == 0: kernels of super-blocks of 2 nb cells between neighbours on the base lattice
+  const int cnt = spec_count(s), R = s == 0 ? 1 : 3;
+  const int bf = s == 0 ? 2 * nb : nb, sf = s == 0 ? 1 : s;
+  const int P = 2 * bf, H = bf + 1;
   const size_t S = (size_t)P * P * H, P3 = (size_t)P * P * P;
   std::vector<int32_t> sd;
-  for (int dz = -3; dz <= 3; ++dz)
-    for (int dy = -3; dy <= 3; ++dy)
-      for (int dx = -3; dx <= 3; ++dx) {
-        sd.push_back(s); sd.push_back(dx); sd.push_back(dy); sd.push_back(dz);
+  for (int dz = -R; dz <= R; ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        sd.push_back(sf); sd.push_back(dx); sd.push_back(dy); sd.push_back(dz);
       }
   SpecSet ss;
   ss.nb = nb;
   ss.s = s;
+  ss.count = cnt;
+  ss.spec = (int64_t)S;
   int32_t* d_sd = nullptr;
   double* d_real = nullptr;
   c64* d_tmp = nullptr;
   LGF_HIP_CHECK(hipMalloc(&d_sd, sd.size() * sizeof(int32_t)));
-  LGF_HIP_CHECK(hipMalloc(&d_real, 343 * P3 * sizeof(double)));
-  LGF_HIP_CHECK(hipMalloc(&d_tmp, 343 * (size_t)P * P * H * sizeof(c64)));
-  LGF_HIP_CHECK(hipMalloc(&ss.d64, 343 * S * sizeof(c64)));
-  LGF_HIP_CHECK(hipMalloc(&ss.d32, 343 * S * sizeof(c32)));
-  LGF_HIP_CHECK(hipMalloc(&ss.kp64, 343 * sizeof(void*)));
-  LGF_HIP_CHECK(hipMalloc(&ss.kp32, 343 * sizeof(void*)));
+  LGF_HIP_CHECK(hipMalloc(&d_real, cnt * P3 * sizeof(double)));
+  LGF_HIP_CHECK(hipMalloc(&d_tmp, cnt * S * sizeof(c64)));
+  LGF_HIP_CHECK(hipMalloc(&ss.d64, cnt * S * sizeof(c64)));
+  LGF_HIP_CHECK(hipMalloc(&ss.d32, cnt * S * sizeof(c32)));
+  LGF_HIP_CHECK(hipMalloc(&ss.kp64, cnt * sizeof(void*)));
+  LGF_HIP_CHECK(hipMalloc(&ss.kp32, cnt * sizeof(void*)));
   LGF_HIP_CHECK(hipMemcpyAsync(d_sd, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                ctx->stream));
-  LGF_HIP_CHECK(launch_kernel_spectra(nb, 343, d_sd, ctx->cube, d_real, d_tmp, ss.d64, ss.d32, ctx->stream));
-  std::vector<const void*> p64(343), p32(343);
-  for (int i = 0; i < 343; ++i) {
+  LGF_HIP_CHECK(launch_kernel_spectra(bf, cnt, d_sd, ctx->cube, d_real, d_tmp, ss.d64, ss.d32, ctx->stream));
+  std::vector<const void*> p64(cnt), p32(cnt);
+  for (int i = 0; i < cnt; ++i) {
     p64[i] = ss.d64 + i * S;
     p32[i] = ss.d32 + i * S;
   }
-  LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp64, p64.data(), 343 * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
-  LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp32, p32.data(), 343 * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp64, p64.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp32, p32.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
   LGF_HIP_CHECK(hipStreamSynchronize(ctx->stream));
   (void)hipFree(d_sd);
   (void)hipFree(d_real);
   (void)hipFree(d_tmp);
-  ctx->bytes += (int64_t)(343 * S * (sizeof(c64) + sizeof(c32)));
+  ctx->bytes += (int64_t)(cnt * S * (sizeof(c64) + sizeof(c32)));
   auto res = ctx->spectra.emplace(key, ss);
   *out = &res.first->second;
   return hipSuccess;
@@ -406,6 +420,7 @@ struct PendingStep {
   int32_t count;
   const double* w;
   int64_t work;
+  int mode;
 };
 
 // ----------------------------------------------------------------------------- item validation
@@ -416,11 +431,20 @@ bool in_ranges(const Plan* p, const void* ptr, size_t len) {
   return false;
 }
 
+struct SlotCounts {
+  int64_t nsrc[2], ntgt[2];            // block spectra slots per element type (source: + zero slot)
+  int64_t nsup_src[2], nsup_tgt[2];    // super-block spectra slots
+};
+
 bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int count, int64_t n,
-                   const int64_t nsrc[2], const int64_t ntgt[2], std::string* err) {
+                   const SlotCounts& sc, std::string* err) {
   const int nb = p->nb;
   const size_t N3 = (size_t)nb * nb * nb;
   const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
+  const size_t S2 = (size_t)spec_size(nb, 0);
+  const size_t TMP2 = (size_t)(2 * nb) * (4 * nb) * (2 * nb + 1);    // intermediate z-plane stack
+  const int64_t* nsrc = sc.nsrc;
+  const int64_t* ntgt = sc.ntgt;
   const size_t es = ty == 0 ? 4 : 8, esc = ty == 1 ? 8 : 4, esp = ty == 0 ? 4 : 8;  // MIX: child 4, parent 8
   const int64_t nmax = n * (int64_t)N3;
   auto bad = [&](const char* what, int i) {
@@ -509,6 +533,36 @@ bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int co
           if (it.nbr_off[f] != -1 && !off_ok(it.nbr_off[f])) return bad("residual neighbour", i);
         break;
       }
+      case K_SUP_FWD: {
+        const auto& it = ((const SuperFwdItem<double>*)items)[i];
+        if (!in_ranges(p, it.dst, 2 * S2 * es) || !in_ranges(p, it.tmp, 2 * TMP2 * es)) return bad("super fwd", i);
+        for (int c = 0; c < 8; ++c)
+          if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("super fwd child", i);
+        break;
+      }
+      case K_SUP_INV: {
+        const auto& it = ((const SuperInvItem<double>*)items)[i];
+        if (!in_ranges(p, it.src, 2 * S2 * es) || !in_ranges(p, it.tmp, 2 * TMP2 * es)) return bad("super inv", i);
+        for (int c = 0; c < 8; ++c)
+          if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("super inv child", i);
+        break;
+      }
+      case K_NEAR_MAC: {
+        const auto& it = ((const NearRow<double>*)items)[i];
+        const int t = ty == 0 ? 0 : 1;
+        if (it.ngroups < 0 || it.ngroups > 3) return bad("near row groups", i);
+        for (int j = 0; j < 9; ++j) {
+          if (((it.pj_code >> (4 * j)) & 15u) > 8) return bad("near source row index", i);
+          for (int q = 0; q < kNearSlots; ++q)
+            if (it.src[j][q] < 0 || it.src[j][q] > sc.nsup_src[t]) return bad("near source slot", i);
+        }
+        for (int q = 0; q < kMacL; ++q)
+          if (it.tgt[q] < -1 || it.tgt[q] >= sc.nsup_tgt[t]) return bad("near target slot", i);
+        if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
+        if (sc.nsup_tgt[t] && !in_ranges(p, it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
+        if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
+        break;
+      }
       default:
         return bad("unknown kind", i);
     }
@@ -595,6 +649,65 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     p->Kmax = std::max(p->Kmax, (int)chT[l].lv.size());
   }
 
+  // Base level as parent super-blocks (Sec. 2.1: a block's N(B) and I(B) together are the
+  // children of its parent's 27 neighbours): per (refinement level, channel) the target
+  // super-blocks are the parents of blocks with base-level interactions, the source super-blocks
+  // their neighbours that hold source children.  A source super-block spectrum is computed once
+  // for each distinct set of source children (channels T and A share it where they agree).
+  struct SupTgt { I3 c; int slot; int child[8]; };
+  struct SupInst { int l, ch; std::vector<SupTgt> tg; I3Map sslot; int64_t pairs = 0; };
+  std::vector<SupInst> sup;
+  std::map<std::array<int, 8>, int> sup_src_of;          // child source slots -> super slot
+  std::vector<std::array<int, 8>> sup_src_children;
+  std::vector<int> sup_src_level;
+  int64_t nsup_src = 0, nsup_tgt = 0;
+  if (p->super_base) {
+    for (int l = 0; l < LR; ++l)
+      for (int ch = 0; ch < 2; ++ch) {
+        if (ch == 1 && !hasA[l]) continue;
+        const OctLevel& L0 = (ch == 0 ? chT[l] : chA[l]).lv[0];
+        std::unordered_map<I3, std::array<int, 8>, I3Hash> smap, tmap;
+        const std::array<int, 8> none{-1, -1, -1, -1, -1, -1, -1, -1};
+        for (size_t i = 0; i < L0.nodes.size(); ++i) {
+          const I3 par = parent_of(L0.nodes[i]);
+          const int oc = octant_of(L0.nodes[i]);
+          if (L0.is_src[i]) smap.emplace(par, none).first->second[oc] = L0.src_slot[i];
+          if (L0.has_ifft[i]) tmap.emplace(par, none).first->second[oc] = (int)i;
+        }
+        std::vector<I3> keys;
+        for (const auto& kv : tmap) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end());
+        SupInst si;
+        si.l = l;
+        si.ch = ch;
+        for (const I3& T : keys) {
+          SupTgt t;
+          t.c = T;
+          t.slot = (int)nsup_tgt++;
+          const std::array<int, 8>& kids = tmap.at(T);
+          for (int oc = 0; oc < 8; ++oc) t.child[oc] = kids[oc];
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                const I3 S{T.x - dx, T.y - dy, T.z - dz};
+                auto it = smap.find(S);
+                if (it == smap.end()) continue;
+                ++si.pairs;
+                if (si.sslot.count(S)) continue;
+                auto q = sup_src_of.find(it->second);
+                if (q == sup_src_of.end()) {
+                  q = sup_src_of.emplace(it->second, (int)nsup_src++).first;
+                  sup_src_children.push_back(it->second);
+                  sup_src_level.push_back(l);
+                }
+                si.sslot[S] = q->second;
+              }
+          si.tg.push_back(t);
+        }
+        sup.push_back(std::move(si));
+      }
+  }
+
   // arenas
   void* tmp = nullptr;
   if (LR > 1) {
@@ -614,6 +727,21 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     LGF_HIP_CHECK(ar.alloc(&c, ntgt[ty] * S * 2 * es(ty)));
     LGF_HIP_CHECK(ar.alloc(&d, ntgt[ty] * N3 * es(ty)));
     srcA[ty] = (uint8_t*)a; fhatA[ty] = (uint8_t*)b; uhatA[ty] = (uint8_t*)c; vA[ty] = (uint8_t*)d;
+  }
+  const int64_t S2 = spec_size(nb, 0);
+  // Super-block spectra: the base level's type on single-level layouts; FP64 spectra of FP32
+  // blocks (TY_MIX) where the layout has refinement.  Defect correction forms its residual only
+  // where all six neighbours are stored, so it cannot remove FP32 spectral error at refinement
+  // interfaces: a block-smooth error there stays, and the correction spreads it (by 3-4x in
+  // L-inf on the torus layouts), while on a single level only the outer boundary is excluded.
+  const int tys = (p->fp32 && LR > 1) ? TY_MIX : tyb;
+  const int64_t ess = tys == TY_F32 ? 4 : 8;
+  if (p->super_base) {
+    void* b = nullptr;
+    LGF_HIP_CHECK(ar.alloc(&b, (nsup_src + 1) * S2 * 2 * ess));    // last slot: zero spectrum
+    if (!p->dry) LGF_HIP_CHECK(hipMemset(b, 0, (nsup_src + 1) * S2 * 2 * ess));
+    p->sfhat = b;
+    LGF_HIP_CHECK(ar.alloc(&p->suhat, nsup_tgt * S2 * 2 * ess));
   }
   p->src = srcA[tyb];
   p->fhat = fhatA[tyb];
@@ -639,14 +767,16 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   auto FH = [&](int ty, int64_t slot) { return (cpx<D>*)(fhatA[ty] + slot * S * 2 * es(ty)); };
   auto UH = [&](int ty, int64_t slot) { return (cpx<D>*)(uhatA[ty] + slot * S * 2 * es(ty)); };
   auto V = [&](int ty, int64_t slot) { return (D*)(vA[ty] + slot * N3 * es(ty)); };
+  auto SFH = [&](int64_t slot) { return (cpx<D>*)((uint8_t*)p->sfhat + slot * S2 * 2 * ess); };
+  auto SUH = [&](int64_t slot) { return (cpx<D>*)((uint8_t*)p->suhat + slot * S2 * 2 * ess); };
   auto JW = [&](int64_t blk) { return (double*)p->jw + blk * N3; };
   auto WW = [&](int64_t blk) { return (double*)p->w + blk * N3; };
 
   HostItems hi;
   std::vector<PendingStep> steps, rsteps;
   auto push = [&](std::vector<PendingStep>& dst, int l, int phase, int sub, int kind, int ty, size_t off,
-                  size_t count, const double* wt, int64_t work = 0) {
-    if (count) dst.push_back({l, phase, sub, kind, ty, off, (int32_t)count, wt, work});
+                  size_t count, const double* wt, int64_t work = 0, int mode = 0) {
+    if (count) dst.push_back({l, phase, sub, kind, ty, off, (int32_t)count, wt, work, mode});
   };
 
   // coarsening (before level 0), bottom-up over levels
@@ -739,12 +869,13 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       for (size_t k = 0; k < F.lv.size(); ++k) {
         OctLevel& L = F.lv[k];
         const int ty = ty_of((int)k);
+        const bool blockwise = !(k == 0 && p->super_base);
         for (size_t i = 0; i < L.nodes.size(); ++i) {
-          if (L.referenced[i] && !fwd_done[ty][L.src_slot[i]]) {
+          if (blockwise && L.referenced[i] && !fwd_done[ty][L.src_slot[i]]) {
             fwd_done[ty][L.src_slot[i]] = 1;
             fwd[ty].push_back({SRC(ty, L.src_slot[i]), FH(ty, L.src_slot[i])});
           }
-          if (L.has_ifft[i]) inv[ty].push_back({UH(ty, L.tgt_slot[i]), V(ty, L.tgt_slot[i])});
+          if (blockwise && L.has_ifft[i]) inv[ty].push_back({UH(ty, L.tgt_slot[i]), V(ty, L.tgt_slot[i])});
           if (k + 1 < F.lv.size() && L.has_val[i] && F.lv[k + 1].has_val[L.parent[i]]) {
             InterpItem<D, D> q{};
             q.child = V(ty, L.tgt_slot[i]);
@@ -756,6 +887,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         }
       }
       for (const TileDesc& rd : F.rows) {
+        if (rd.k == 0 && p->super_base) continue;
         const SpecSet* ss = nullptr;
         LGF_HIP_CHECK(plan_spectra(p, nb, 1 << rd.k, &ss));
         OctLevel& L = F.lv[rd.k];
@@ -793,6 +925,96 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     for (int k = 0; k < K; ++k) {
       p->n_rows += (int64_t)rows[k].size();
       push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k]);
+    }
+    if (p->super_base) {
+      // super-block transforms and rows of this refinement level (phases of the block FFTs/MAC)
+      std::vector<SuperFwdItem<D>> sf;
+      for (int64_t q = 0; q < nsup_src; ++q) {
+        if (sup_src_level[q] != l) continue;
+        SuperFwdItem<D> it{};
+        for (int oc = 0; oc < 8; ++oc) {
+          const int sl = sup_src_children[q][oc];
+          it.child[oc] = sl >= 0 ? SRC(tyb, sl) : nullptr;
+        }
+        it.dst = SFH(q);
+        it.tmp = it.dst;                 // the z pass transforms the plane stack in place
+        sf.push_back(it);
+      }
+      const SpecSet* ns = nullptr;
+      LGF_HIP_CHECK(plan_spectra(p, nb, 0, &ns));
+      // rows of W targets along x; W in {4, 8} by a cost model of the kernel's executed work per
+      // non-empty source row (3 W complex multiply-adds, W + 2 spectrum loads)
+      auto build_rows = [&](int W, std::vector<NearRow<D>>* out) {
+        double cost = 0.0;
+        for (const SupInst& si : sup) {
+          if (si.l != l) continue;
+          std::map<I3, size_t> row_of;
+          size_t first = out ? out->size() : 0;
+          std::vector<NearRow<D>> local;
+          std::vector<NearRow<D>>& dst = out ? *out : local;
+          for (const SupTgt& t : si.tg) {
+            const int wx = floordiv(t.c.x, W);
+            const I3 key{wx, t.c.y, t.c.z};
+            auto it = row_of.find(key);
+            if (it == row_of.end()) {
+              NearRow<D> r{};
+              for (int i = 0; i < kMacL; ++i) r.tgt[i] = -1;
+              int nl = 0;                  // listed (non-empty) source rows
+              for (int pj = 0; pj < 9; ++pj) {
+                const int dz = pj / 3 - 1, dy = pj % 3 - 1;
+                int slots[kNearSlots];
+                bool any = false;
+                for (int q = 0; q < kNearSlots; ++q) {
+                  auto sit = q < W + 2 ? si.sslot.find({wx * W - 1 + q, t.c.y - dy, t.c.z - dz}) : si.sslot.end();
+                  slots[q] = sit != si.sslot.end() ? sit->second : (int)nsup_src;
+                  any |= sit != si.sslot.end();
+                }
+                if (!any) continue;
+                for (int q = 0; q < kNearSlots; ++q) r.src[nl][q] = slots[q];
+                r.pj_code |= (uint64_t)pj << (4 * nl++);
+              }
+              for (int q = nl; q < 9; ++q)         // padding rows read the zero spectrum
+                for (int x = 0; x < kNearSlots; ++x) r.src[q][x] = (int)nsup_src;
+              r.ngroups = (nl + 2) / 3;
+              r.fhat = SFH(0);
+              r.uhat = SUH(0);
+              r.kptr = ns->kp64;
+              it = row_of.emplace(key, dst.size()).first;
+              dst.push_back(r);
+            }
+            dst[it->second].tgt[t.c.x - wx * W] = t.slot;
+          }
+          for (size_t q = first; q < dst.size(); ++q)
+            cost += 3.0 * dst[q].ngroups * (12.0 * W + 4.0 * (W + 2));
+        }
+        return cost;
+      };
+      // FP64 storage holds two groups of 10 spectra per lane only at W = 4
+      const int width = (tys != TY_F32 || build_rows(4, nullptr) <= build_rows(8, nullptr)) ? 4 : 8;
+      std::vector<NearRow<D>> nr;
+      build_rows(width, &nr);
+      std::vector<SuperInvItem<D>> si_items;
+      int64_t pairs = 0;
+      for (const SupInst& si : sup) {
+        if (si.l != l) continue;
+        pairs += si.pairs;
+        const OctLevel& L0 = (si.ch == 0 ? chT[l] : chA[l]).lv[0];
+        for (const SupTgt& t : si.tg) {
+          SuperInvItem<D> v{};
+          v.src = SUH(t.slot);
+          v.tmp = SUH(t.slot);             // the z pass transforms the spectrum in place
+          for (int oc = 0; oc < 8; ++oc)
+            v.child[oc] = t.child[oc] >= 0 ? V(tyb, L0.tgt_slot[t.child[oc]]) : nullptr;
+          si_items.push_back(v);
+        }
+      }
+      p->n_sup_fwd += (int64_t)sf.size();
+      p->n_sup_inv += (int64_t)si_items.size();
+      p->n_near_rows += (int64_t)nr.size();
+      p->near_pairs += pairs;
+      push(steps, l, 3, 0, K_SUP_FWD, tys, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size());
+      push(steps, l, 4, 0, K_NEAR_MAC, tys, hi.add(nr), nr.size(), nullptr, pairs, width);
+      push(steps, l, 5, 0, K_SUP_INV, tys, hi.add(si_items), si_items.size(), nullptr, (int64_t)si_items.size());
     }
     for (int k = 1; k < K; ++k) {
       const int ty = (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
@@ -846,10 +1068,12 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 
   // every item must stay inside the plan's device ranges before anything is launched
   {
-    const int64_t nsrc_[2] = {nsrc[0], nsrc[1]}, ntgt_[2] = {ntgt[0], ntgt[1]};
+    SlotCounts sc{{nsrc[0], nsrc[1]}, {ntgt[0], ntgt[1]}, {0, 0}, {0, 0}};
+    sc.nsup_src[tys == TY_F32 ? 0 : 1] = nsup_src;
+    sc.nsup_tgt[tys == TY_F32 ? 0 : 1] = nsup_tgt;
     for (const auto* list : {&steps, &rsteps})
       for (const PendingStep& st : *list)
-        if (!validate_step(p, st.kind, st.ty, hi.buf.data() + st.off, st.count, n, nsrc_, ntgt_, err))
+        if (!validate_step(p, st.kind, st.ty, hi.buf.data() + st.off, st.count, n, sc, err))
           return hipErrorInvalidValue;
   }
   void* d_items = nullptr;
@@ -859,7 +1083,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   p->d_items = d_items;
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
     for (const PendingStep& s : in)
-      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work, 0});
+      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work, s.mode});
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
@@ -867,7 +1091,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   for (int l = 0; l < LR; ++l)
     for (const TileDesc& rd : chT[l].rows) used.insert(rd.k);
   p->n_spectra = 0;
-  for (int k : used) p->n_spectra += k == 0 ? 343 : 316;
+  for (int k : used) p->n_spectra += k == 0 ? (p->super_base ? 27 : 343) : 316;
   (void)err;
   return hipSuccess;
 }
@@ -878,8 +1102,9 @@ hipError_t plan_autotune(Plan* p, hipStream_t st);
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
                       bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err, bool dry,
-                      bool autotune) {
+                      bool autotune, bool super_base) {
   Plan* p = new Plan();
+  p->super_base = super_base;
   p->nb = nb;
   p->n_i = n_i;
   p->fp32 = fp32;
@@ -935,6 +1160,9 @@ hipError_t launch_kind(int kind, int nb, SetTable& t, hipStream_t st, int mode) 
     case K_COMBINE: return launch_combine<T>(nb, t, st);
     case K_COARSEN: return launch_coarsen(nb, t, st);
     case K_RESIDUAL: return launch_residual(nb, t, st);
+    case K_SUP_FWD: return launch_super_fwd<T, T>(nb, t, st);
+    case K_NEAR_MAC: return launch_near_mac<T>(nb, t, st, mode);
+    case K_SUP_INV: return launch_super_inv<T, T>(nb, t, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -944,6 +1172,10 @@ hipError_t launch_typed(int kind, int ty, int nb, SetTable& t, hipStream_t st, i
   if (ty == 1) return launch_kind<double>(kind, nb, t, st, mode);
   if (kind == K_ANTERP) return launch_anterp<float, double>(nb, t, st);
   if (kind == K_INTERP) return launch_interp<float, double>(nb, t, st);
+  // FP64 super-block spectra of FP32 child blocks
+  if (kind == K_SUP_FWD) return launch_super_fwd<double, float>(nb, t, st);
+  if (kind == K_SUP_INV) return launch_super_inv<double, float>(nb, t, st);
+  if (kind == K_NEAR_MAC) return launch_near_mac<double>(nb, t, st, mode);
   return hipErrorInvalidValue;
 }
 

@@ -16,11 +16,16 @@
 namespace lgf {
 
 // ----------------------------------------------------------------------------- device context
+// Kernel spectra of one block size and level scale.  s >= 1: the 343 offsets |d| <= 3 of blocks of
+// nb cells at lattice scale s, index (dz+3)*49+(dy+3)*7+(dx+3).  s == 0: the 27 neighbour offsets
+// |d| <= 1 of base-level super-blocks of 2 nb cells, index (dz+1)*9+(dy+1)*3+(dx+1).
 struct SpecSet {
   int nb = 0, s = 0;
-  c64* d64 = nullptr;                  // 343 spectra, index (dz+3)*49+(dy+3)*7+(dx+3)
+  int count = 0;                       // 343 or 27
+  int64_t spec = 0;                    // complex entries per spectrum
+  c64* d64 = nullptr;
   c32* d32 = nullptr;
-  const c64** kp64 = nullptr;          // device arrays of 343 pointers
+  const c64** kp64 = nullptr;          // device arrays of count pointers
   const c32** kp32 = nullptr;
 };
 
@@ -40,7 +45,7 @@ hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out);
 // ----------------------------------------------------------------------------- steps
 enum StepKind : int {
   K_COARSEN = 0, K_CONVERT, K_REFINE, K_CORRECT, K_ANTERP, K_FWD, K_MAC, K_INV, K_INTERP,
-  K_COMBINE, K_RESIDUAL, K_COUNT
+  K_COMBINE, K_RESIDUAL, K_SUP_FWD, K_NEAR_MAC, K_SUP_INV, K_COUNT
 };
 
 struct Step {
@@ -63,6 +68,7 @@ hipError_t profile_collect(std::vector<ProfileEntry>* out);
 struct Plan {
   int nb = 0, n_i = 0, LR = 0, Kmax = 0;
   bool fp32 = false;
+  bool super_base = true;              // base level as parent super-blocks (false: per block)
   bool dry = false;                    // host-only build: fake addresses, no device calls
   std::vector<std::pair<uintptr_t, size_t>> ranges;   // every device range items may touch
   uintptr_t next_fake = 0;
@@ -84,6 +90,8 @@ struct Plan {
   void* fhat = nullptr;                // cpx<T> [nsrc][S]
   void* uhat = nullptr;                // cpx<T> [ntgt][S]
   void* v = nullptr;                   // T [ntgt][N3]
+  void* sfhat = nullptr;               // cpx<T> [nsup_src + 1][S2]: super-block source spectra
+  void* suhat = nullptr;               // cpx<T> [nsup_tgt][S2]: super-block target spectra
   double* r = nullptr;                 // DC residual [n][N3]
   double* e = nullptr;                 // DC correction [n][N3]
   double* d_w = nullptr;               // Lagrange matrix [2 nb][nb]
@@ -92,11 +100,12 @@ struct Plan {
 
   // statistics
   int64_t interactions = 0, n_fwd = 0, n_inv = 0, n_rows = 0, n_spectra = 0;
+  int64_t n_sup_fwd = 0, n_sup_inv = 0, n_near_rows = 0, near_pairs = 0;
 };
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
                       bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err,
-                      bool dry = false, bool autotune = false);
+                      bool dry = false, bool autotune = false, bool super_base = true);
 void plan_free(Plan* p);
 
 struct Member {

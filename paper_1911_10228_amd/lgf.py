@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "liblgf.so")
 
 LGF_FP64_PLAIN = 0
 LGF_FP32_REFINE = 1
+LGF_BASE_SUPER = 0
+LGF_BASE_BLOCK = 1
 
 EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
@@ -31,14 +33,16 @@ class LgfError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dc_iters", C.c_int32), ("autotune", C.c_int32),
-                ("reserved", C.c_int32), ("hbm_budget", C.c_uint64)]
+                ("base_level", C.c_int32), ("hbm_budget", C.c_uint64)]
 
 
 class PlanInfo(C.Structure):
     _fields_ = [("blocks", C.c_int64), ("unknowns", C.c_int64), ("refinement_levels", C.c_int32),
                 ("max_octree_levels", C.c_int32), ("interactions", C.c_int64),
                 ("fft_forward", C.c_int64), ("fft_inverse", C.c_int64), ("mac_rows", C.c_int64),
-                ("workspace_bytes", C.c_int64), ("spectra", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("spectra", C.c_int64),
+                ("super_forward", C.c_int64), ("super_inverse", C.c_int64),
+                ("near_rows", C.c_int64), ("near_pairs", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,12 +118,13 @@ class Plan:
     """A planned solve for a block layout (see include/lgf.h for the conventions)."""
 
     def __init__(self, blocks, levels, n_b: int, interp_order: int,
-                 precision: int = LGF_FP64_PLAIN, dc_iters: int = 0, hbm_budget: int = 0):
+                 precision: int = LGF_FP64_PLAIN, dc_iters: int = 0, hbm_budget: int = 0,
+                 base_level: int = 0, autotune: int = 0):
         lib = load()
         b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
         lv = np.ascontiguousarray(np.zeros(len(b), np.int32) if levels is None
                                   else np.asarray(levels, dtype=np.int32).reshape(-1))
-        opt = Options(precision, dc_iters, 0, 0, hbm_budget)
+        opt = Options(precision, dc_iters, autotune, base_level, hbm_budget)
         h = C.c_void_p()
         _check(lib.lgf_plan(b.ctypes.data, lv.ctypes.data, len(b), n_b, interp_order,
                             C.byref(opt), C.byref(h)), "lgf_plan")
@@ -162,12 +167,12 @@ class Plan:
 
 
 def plan_check(blocks, levels, n_b: int, interp_order: int, precision: int = LGF_FP64_PLAIN,
-               dc_iters: int = 0) -> dict:
+               dc_iters: int = 0, base_level: int = 0) -> dict:
     """Host-only plan build with validation of every kernel work item (no GPU needed)."""
     b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
     lv = np.ascontiguousarray(np.zeros(len(b), np.int32) if levels is None
                               else np.asarray(levels, dtype=np.int32).reshape(-1))
-    opt = Options(precision, dc_iters, 0, 0, 0)
+    opt = Options(precision, dc_iters, 0, base_level, 0)
     inf = PlanInfo()
     _check(load().lgf_plan_check(b.ctypes.data, lv.ctypes.data, len(b), n_b, interp_order,
                                  C.byref(opt), C.byref(inf)), "lgf_plan_check")
@@ -198,7 +203,8 @@ def green_table(out_dev, stream=None):
 
 def kernel_spectrum(n_b, s, d, out_dev, stream=None):
     """FP64 half spectrum [2N_b, 2N_b, N_b+1] complex of G(s (d N_b + r)) into out (float64
-    CUDA tensor [2N_b, 2N_b, N_b+1, 2])."""
+    CUDA tensor [2N_b, 2N_b, N_b+1, 2]).  s = 0: the base-level super-block kernel of block
+    side B = 2 N_b, G(d B + r) with |d| <= 1, into a tensor [2B, 2B, B+1, 2]."""
     _check(load().lgf_kernel_spectrum(n_b, s, int(d[0]), int(d[1]), int(d[2]), _ptr(out_dev),
                                       _stream(stream)), "lgf_kernel_spectrum")
 
@@ -210,7 +216,7 @@ class ProfileEntry(C.Structure):
 
 
 KIND_NAMES = ["coarsen", "convert", "refine", "correct", "anterp", "fft_fwd", "mac", "fft_inv",
-              "interp", "combine", "residual"]
+              "interp", "combine", "residual", "super_fwd", "near_mac", "super_inv"]
 
 
 def profile(enable: bool):

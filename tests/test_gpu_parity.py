@@ -28,8 +28,9 @@ def rel_linf(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def gpu_solve(lgf, L, precision=0, dc=0, order=None, plan=None):
-    p = plan or lgf.Plan(L.blocks, L.levels, L.n_b, order or L.interp_order, precision, dc)
+def gpu_solve(lgf, L, precision=0, dc=0, order=None, plan=None, base_level=0):
+    p = plan or lgf.Plan(L.blocks, L.levels, L.n_b, order or L.interp_order, precision, dc,
+                         base_level=base_level)
     f = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
     u = torch.zeros_like(f)
     p.solve(f, u)
@@ -81,6 +82,20 @@ def test_kernel_spectra_match_oracle(lgf, n_b, s, d):
     assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("n_b,d", [(8, (0, 0, 0)), (8, (1, -1, 0)), (16, (-1, 1, 1)), (16, (0, 0, 1))])
+def test_super_block_kernel_spectra_match_oracle(lgf, n_b, d):
+    """Base-level super-block kernels: blocks of 2 N_b cells on the base lattice (FFT size 4 N_b,
+    transformed by the long-line DFT path for N_b = 16)."""
+    B = 2 * n_b
+    out = torch.zeros((2 * B, 2 * B, B + 1, 2), dtype=torch.float64, device="cuda")
+    lgf.kernel_spectrum(n_b, 0, d, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    got = got[..., 0] + 1j * got[..., 1]
+    ref = np.fft.rfftn(fmm.kernel_block(B, 1, d))
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
 # ----------------------------------------------------------------------------- uniform FLGF
 def test_uniform_gaussian_fp64_matches_oracle_and_brute_force(lgf):
     L = workloads.uniform_gaussian()
@@ -92,17 +107,19 @@ def test_uniform_gaussian_fp64_matches_oracle_and_brute_force(lgf):
     assert p.info()["interactions"] == 64
 
 
+@pytest.mark.parametrize("base_level", [0, 1])
 @pytest.mark.parametrize("nblk,n_b,order", [(6, 8, 4), (5, 8, 8), (3, 16, 6)])
-def test_uniform_multilevel_fp64(lgf, nblk, n_b, order):
+def test_uniform_multilevel_fp64(lgf, nblk, n_b, order, base_level):
     L = workloads.uniform_mixture(nblk=nblk, n_b=n_b, n_gauss=5, seed=nblk + n_b)
-    u, p = gpu_solve(lgf, L, order=order)
+    u, p = gpu_solve(lgf, L, order=order, base_level=base_level)
     ref = fmm.flgf(L.blocks, L.f, L.n_b, order)
     assert rel_linf(u, ref) <= 1e-12
     counts = fmm.count_interactions(L.blocks)
     assert p.info()["interactions"] == sum(a + b for _, a, b in counts)
 
 
-def test_sparse_negative_ragged_layout_fp64(lgf):
+@pytest.mark.parametrize("base_level", [0, 1])
+def test_sparse_negative_ragged_layout_fp64(lgf, base_level):
     rng = np.random.default_rng(11)
     blocks = np.unique(rng.integers(-9, 7, size=(70, 3)), axis=0).astype(np.int32)
     n_b = 8
@@ -111,7 +128,7 @@ def test_sparse_negative_ragged_layout_fp64(lgf):
     f = workloads.gaussian_mixture(pos, [(-10, 5, 0), (20, -30, 10)], [3.0, 2.0], [1.0, -0.5])
     f = f + 0.01 * rng.normal(size=f.shape)
     L = workloads.Layout(blocks, levels, n_b, f, 6)
-    u, _ = gpu_solve(lgf, L)
+    u, _ = gpu_solve(lgf, L, base_level=base_level)
     ref = fmm.flgf(blocks, f, n_b, 6)
     assert rel_linf(u, ref) <= 1e-12
 
@@ -124,17 +141,18 @@ def test_single_block(lgf):
     assert rel_linf(u, ref) <= 1e-12
 
 
-def test_uniform_fp32_defect_correction(lgf):
+@pytest.mark.parametrize("base_level", [0, 1])
+def test_uniform_fp32_defect_correction(lgf, base_level):
     """FP32 without DC is compared with the FP64 FLGF oracle; with K DC iterations it is compared
     with the oracle's DC of the same K (FP64 inner solves), which isolates precision: DC moves the
     answer towards the lattice solution L u = f by the FMM truncation error."""
     L = workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=6, seed=3, interp_order=8)
     ref = fmm.flgf(L.blocks, L.f, L.n_b, 8)
-    u, _ = gpu_solve(lgf, L, precision=1, dc=0)
+    u, _ = gpu_solve(lgf, L, precision=1, dc=0, base_level=base_level)
     assert rel_linf(u, ref) <= 1e-6
     its = dc_oracle.solve_dc(L.blocks, L.levels, L.f, L.n_b, 8, iters=2, dtype=np.float64)
     for k in (1, 2):
-        u, _ = gpu_solve(lgf, L, precision=1, dc=k)
+        u, _ = gpu_solve(lgf, L, precision=1, dc=k, base_level=base_level)
         assert rel_linf(u, its[k]) <= 1e-6
 
 
@@ -160,10 +178,11 @@ def three_level(n_b=8):
     return workloads.Layout(blocks, levels, n_b, f, 6)
 
 
+@pytest.mark.parametrize("base_level", [0, 1])
 @pytest.mark.parametrize("make", [lambda: two_level(8), three_level])
-def test_multires_fp64(lgf, make):
+def test_multires_fp64(lgf, make, base_level):
     L = make()
-    u, _ = gpu_solve(lgf, L)
+    u, _ = gpu_solve(lgf, L, base_level=base_level)
     ref = multires.solve(L.blocks, L.levels, L.f, L.n_b, L.interp_order)
     assert rel_linf(u, ref) <= 1e-12
 

@@ -99,3 +99,73 @@ def test_torus_layout_validates():
     L = workloads.torus(nblk=4, n_b=8, n_levels=3)
     info = lgf.plan_check(L.blocks, L.levels, L.n_b, 6, 1, 1)
     assert info["refinement_levels"] == 3
+
+
+def super_counts(blocks, levels):
+    """Base-level super-block bookkeeping written out from the block lists: per refinement level
+    and channel, the target super-blocks are the parents of target blocks that have a source
+    block among the children of their parent's 27 neighbours; each pairs with every such
+    neighbour that holds a source child.  A source super-block transform is shared where two
+    channels have the same source children."""
+    blocks = np.asarray(blocks)
+    levels = np.asarray(levels)
+    have = {(int(l),) + tuple(int(v) for v in b) for b, l in zip(blocks, levels)}
+    leaf = [(int(l) + 1,) + tuple(int(v) for v in 2 * b) not in have for b, l in zip(blocks, levels)]
+    n_tgt = pairs = 0
+    src_sets = set()
+    for l in range(int(levels.max()) + 1):
+        ids = [i for i in range(len(blocks)) if levels[i] == l]
+        chans = [([True] * len(ids), [True] * len(ids))]
+        if not all(leaf[i] for i in ids):
+            chans.append(([leaf[i] for i in ids], [not leaf[i] for i in ids]))
+        for is_src, is_tgt in chans:
+            kids = {}
+            for a, i in enumerate(ids):
+                if is_src[a]:
+                    b = tuple(int(v) for v in blocks[i])
+                    kids.setdefault(tuple(v // 2 for v in b), set()).add(b)
+            nbrs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+            tgts = set()
+            for a, i in enumerate(ids):
+                if not is_tgt[a]:
+                    continue
+                T = tuple(int(v) // 2 for v in blocks[i])
+                if any(tuple(t - d for t, d in zip(T, D)) in kids for D in nbrs):
+                    tgts.add(T)
+            n_tgt += len(tgts)
+            for T in tgts:
+                for D in nbrs:
+                    S = tuple(t - d for t, d in zip(T, D))
+                    if S in kids:
+                        pairs += 1
+                        src_sets.add((l, frozenset(kids[S])))
+    return n_tgt, pairs, len(src_sets)
+
+
+@pytest.mark.parametrize("case", ["box6x8", "slab", "sparse_neg", "multi0", "multi1", "torus"])
+def test_super_block_bookkeeping(case):
+    if case.startswith("multi"):
+        blocks, levels, n_b = multi_layouts()[int(case[-1])]
+        n_i = 6
+    elif case == "torus":
+        L = workloads.torus(nblk=4, n_b=8, n_levels=3)
+        blocks, levels, n_b, n_i = L.blocks, L.levels, L.n_b, 6
+    else:
+        L = LAYOUTS[case]()
+        blocks, n_b, n_i = L.blocks, L.n_b, L.interp_order
+        levels = L.levels if L.levels is not None else np.zeros(len(blocks), np.int32)
+    n_tgt, pairs, n_src = super_counts(blocks, levels)
+    for precision in (0, 1):
+        sup = lgf.plan_check(blocks, levels, n_b, n_i, precision, 1, base_level=lgf.LGF_BASE_SUPER)
+        blk = lgf.plan_check(blocks, levels, n_b, n_i, precision, 1, base_level=lgf.LGF_BASE_BLOCK)
+        assert (sup["super_inverse"], sup["near_pairs"], sup["super_forward"]) == (n_tgt, pairs, n_src)
+        assert sup["interactions"] == blk["interactions"]
+        assert blk["super_forward"] == blk["near_rows"] == 0
+        # the per-block base transforms are the ones the super-blocks replace
+        assert sup["fft_forward"] < blk["fft_forward"] and sup["fft_inverse"] < blk["fft_inverse"]
+
+
+def test_base_level_option_rejects_unknown():
+    L = workloads.uniform_gaussian()
+    with pytest.raises(lgf.LgfError):
+        lgf.plan_check(L.blocks, None, L.n_b, L.interp_order, 0, 0, base_level=2)
