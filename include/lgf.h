@@ -153,10 +153,15 @@ lgf_status lgf_profile(int32_t enable);
 lgf_status lgf_profile_read(lgf_profile_entry* out, int32_t cap, int32_t* n);
 
 /* Serving: continuous batching of solve requests under an HBM budget.
- * submit enqueues (plan, f, u); requests are admitted while the plans' workspace fits the budget
- * and advanced one refinement-level phase per step, all admitted requests sharing launches.
- * A background thread steps the server; poll reports completion (1) or not (0).
- * Latency = completion - submission, reported as p50/p99 over completed requests. */
+ * submit enqueues (plan, f, u) and returns at once; the caller keeps f and u alive until the
+ * request completes.  A launcher thread forms a batch from the queued requests whose plans fit
+ * the budget next to the batches already on the GPU (a plan runs in one batch at a time: its
+ * workspace is shared) and enqueues the batch as one multi-plan solve (lgf_solve_batch: every
+ * kernel step of all members in shared launches) on the server's stream, while earlier batches
+ * still run; requests arriving meanwhile form the next batch.  A completion thread retires
+ * batches in order.  poll reports completion (1) or not (0).
+ * Latency = completion - submission, reported as p50/p99 over completed requests; points_per_s
+ * = unknowns completed / (last completion - first submission). */
 lgf_status lgf_server_create(uint64_t hbm_budget, lgf_stream_t stream, lgf_server_t* out);
 lgf_status lgf_server_submit(lgf_server_t s, lgf_plan_t p, const double* f, double* u, int64_t* req_id);
 lgf_status lgf_server_poll(lgf_server_t s, int64_t req_id, int32_t* done);

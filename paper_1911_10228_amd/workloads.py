@@ -20,7 +20,9 @@ streamfunction has an analytic Laplacian; there is no public dataset):
                            Gaussian-core torus (major radius L/4, core 0.03 L, random tilt);
 * ``batch``              - 64 independent layouts, block counts log-uniform in [8, 512],
                            n_b in {8, 16}, 0..2 refinement levels, Gaussian mixtures;
-* ``arrivals``           - Poisson arrival times and sizes for the serving stream.
+* ``arrivals``           - Poisson arrival times and sizes for the serving stream;
+* ``request_pool``       - layouts of log-uniform size (4096 .. 16.7M base unknowns, n_b in
+                           {8, 16}, 1..3 levels) that serving requests draw from.
 """
 from __future__ import annotations
 
@@ -65,6 +67,34 @@ def gaussian_mixture(pos: np.ndarray, centres, sigmas, amps) -> np.ndarray:
     return out
 
 
+class Mixture:
+    """Sum of isotropic Gaussians a exp(-|p - c|^2 / (2 s^2)) evaluated block by block from its
+    separable 1-D factors; a Gaussian's contribution to a block is dropped where it stays below
+    1e-30 |a| over the whole block."""
+
+    def __init__(self, centres, sigmas, amps):
+        self.centres = np.asarray(centres, np.float64).reshape(-1, 3)
+        self.sigmas = np.asarray(sigmas, np.float64).reshape(-1)
+        self.amps = np.asarray(amps, np.float64).reshape(-1)
+
+    def __call__(self, blocks, levels, n_b):
+        blocks = np.asarray(blocks, np.float64).reshape(-1, 3)
+        h = 2.0 ** (-np.asarray(levels, np.float64).reshape(-1))
+        j = np.arange(n_b, dtype=np.float64)
+        # positions along each axis: [n, 3, n_b]
+        pos = ((blocks[:, :, None] * n_b + j[None, None, :]) + 0.5) * h[:, None, None] - 0.5
+        out = np.zeros((len(blocks), n_b, n_b, n_b))
+        for c, sg, a in zip(self.centres, self.sigmas, self.amps):
+            e = np.exp(-((pos - c[None, :, None]) ** 2) / (2.0 * sg * sg))     # [n, 3, n_b]
+            m = e.max(axis=2)
+            keep = np.nonzero(m[:, 0] * m[:, 1] * m[:, 2] >= 1e-30)[0]
+            if len(keep) == 0:
+                continue
+            ek = e[keep]
+            out[keep] += a * (ek[:, 2, :, None, None] * ek[:, 1, None, :, None]) * ek[:, 0, None, None, :]
+        return out
+
+
 def box_blocks(nx: int, ny: int, nz: int, origin=(0, 0, 0)) -> np.ndarray:
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     b = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1) + np.asarray(origin)
@@ -91,8 +121,7 @@ def uniform_mixture(nblk: int = 8, n_b: int = 16, n_gauss: int = 16, seed: int =
     centres = rng.uniform(L / 4, 3 * L / 4, size=(n_gauss, 3))
     sigmas = rng.uniform(1.5, 4.0, size=n_gauss)
     amps = rng.normal(size=n_gauss)
-    pos = cell_centres(blocks, levels, n_b)
-    f = gaussian_mixture(pos, centres, sigmas, amps)
+    f = Mixture(centres, sigmas, amps)(blocks, levels, n_b)
     return Layout(blocks, levels, n_b, f, interp_order,
                   f"uniform {nblk}^3 blocks of {n_b}^3, {n_gauss} Gaussians",
                   meta=dict(centres=centres, sigmas=sigmas, amps=amps))
@@ -102,11 +131,12 @@ def refine_by_criterion(base_blocks: np.ndarray, n_b: int, n_levels: int, source
                         alpha: float = 1.0 / 32) -> tuple[np.ndarray, np.ndarray]:
     """Refinement criterion of eq. ref_crit, read as: a level-l block is refined (all 8
     children created) iff max over its cells of |source| exceeds alpha^(L_R-1-l) times the
-    maximum of |source| over all level-l cells, with L_R = n_levels."""
+    maximum of |source| over all level-l cells, with L_R = n_levels.  ``source(blocks, levels,
+    n_b)`` returns the cell values [n, n_b, n_b, n_b]."""
     blocks = [np.asarray(base_blocks, np.int64)]
     for l in range(n_levels - 1):
         cur = blocks[l]
-        vals = np.abs(source(cell_centres(cur, np.full(len(cur), l), n_b)))
+        vals = np.abs(source(cur, np.full(len(cur), l), n_b))
         bmax = vals.reshape(len(cur), -1).max(axis=1)
         thr = alpha ** (n_levels - 1 - l) * bmax.max()
         ref = cur[bmax > thr]
@@ -146,14 +176,14 @@ def torus(seed: int = 3, n_b: int = 16, nblk: int = 8, n_levels: int = 3,
     axis = v / np.linalg.norm(v)
     centre = np.full(3, L / 2 - 0.5)
     R, sigma = 0.25 * L, 0.03 * L
-    src = lambda p: torus_source(p, centre, axis, R, sigma)[0]
+    src = lambda b, lv, nb: torus_source(cell_centres(b, lv, nb), centre, axis, R, sigma)[0]
     blocks, levels = refine_by_criterion(box_blocks(nblk, nblk, nblk), n_b, n_levels, src, alpha)
     pos = cell_centres(blocks, levels, n_b)
     if manufactured:
         f = torus_laplacian(pos, centre, axis, R, sigma)
         exact = torus_source(pos, centre, axis, R, sigma)[0]
     else:
-        f = src(pos)
+        f = torus_source(pos, centre, axis, R, sigma)[0]
         exact = None
     return Layout(blocks, levels, n_b, f, interp_order,
                   f"torus {nblk}^3 base blocks of {n_b}^3, {n_levels} levels", exact,
@@ -188,9 +218,9 @@ def batch(seed: int = 4, count: int = 64, min_blocks: int = 8, max_blocks: int =
         centres = rng.uniform(ext / 4, 3 * ext / 4, size=(ng, 3)) - 0.5
         sigmas = rng.uniform(1.5, 4.0, size=ng)
         amps = rng.normal(size=ng)
-        srcf = lambda p, c_=centres, s_=sigmas, a_=amps: gaussian_mixture(p, c_, s_, a_)
+        srcf = Mixture(centres, sigmas, amps)
         blocks, levels = refine_by_criterion(box_blocks(a, b, c), n_b, nl, srcf)
-        f = srcf(cell_centres(blocks, levels, n_b))
+        f = srcf(blocks, levels, n_b)
         order = 8                      # the most nodes a block of 8 cells holds
         out.append(Layout(blocks, levels, n_b, f, order,
                           f"batch[{i}] {a}x{b}x{c} blocks of {n_b}^3, {nl} levels"))
@@ -204,3 +234,31 @@ def arrivals(seed: int = 5, count: int = 1000, rate_hz: float = 100.0,
     gaps = rng.exponential(1.0 / rate_hz, size=count)
     sizes = np.exp(rng.uniform(math.log(min_unknowns), math.log(max_unknowns), size=count))
     return np.cumsum(gaps), sizes.astype(np.int64)
+
+
+def sized_layout(unknowns: int, rng, max_levels: int = 3) -> Layout:
+    """A layout of about ``unknowns`` base-level unknowns: n_b in {8, 16} (16 only from 16^3
+    upward), the most cubic box of base blocks (at most 16^3 blocks of 16^3 or 32^3 of 8^3),
+    1..max_levels refinement levels by the refinement criterion, a Gaussian-mixture source."""
+    n_b = int(rng.choice((8, 16))) if unknowns >= 16 ** 3 else 8
+    B = int(min(max(1, round(unknowns / n_b ** 3)), (4096 if n_b == 16 else 32768)))
+    a, b, c = most_cubic_box(B)
+    nl = int(rng.integers(1, max_levels + 1))
+    ng = int(rng.integers(1, 17))
+    ext = np.array([a, b, c]) * n_b
+    centres = rng.uniform(ext / 4, 3 * ext / 4, size=(ng, 3)) - 0.5
+    sigmas = rng.uniform(1.5, 4.0, size=ng)
+    amps = rng.normal(size=ng)
+    srcf = Mixture(centres, sigmas, amps)
+    blocks, levels = refine_by_criterion(box_blocks(a, b, c), n_b, nl, srcf)
+    f = srcf(blocks, levels, n_b)
+    return Layout(blocks, levels, n_b, f, 8, f"{a}x{b}x{c} blocks of {n_b}^3, {nl} levels")
+
+
+def request_pool(seed: int = 5, count: int = 24, min_unknowns: int = 4096,
+                 max_unknowns: int = 16777216) -> list[Layout]:
+    """The distinct layouts a serving stream draws from (sizes log-uniform): a service keeps
+    one plan per layout resident and requests name a layout and bring a source."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(min_unknowns), math.log(max_unknowns), size=count))
+    return [sized_layout(int(u), rng) for u in sizes]
