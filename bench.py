@@ -8,7 +8,9 @@ residual + FP32 re-solve + FP64 update of defect correction) with f and u reside
 
 Headline value: FP32 FFT/MAC on the base octree level (FP64 on the coarse far-field levels)
 with one FP64 defect-correction iteration.  The FP64 plain solve of the same plan shape is timed
-beside it.  Prints one JSON line.
+beside it, and so are, as extra fields of the same JSON line: the multi-resolution torus layout
+(15.5M stored unknowns), 64 independent layouts in one batched solve, and a Poisson-arrival
+request stream through the server (p50/p99 latency).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -89,6 +91,76 @@ def profiled(lgf, plan, f, u, steps, torch, stream):
     return lgf.profile_read()
 
 
+def bench_torus(lgf, workloads, torch, stream, steps, warmup, dc):
+    """Multi-resolution solve of the torus layout (8^3 base blocks of 16^3, two refinement
+    levels): grid points (all stored unknowns) per second, FP32 + DC and FP64 plain."""
+    L = workloads.torus()
+    f = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
+    out = {"layout": f"{L.name}, {len(L.blocks)} blocks", "unknowns": L.unknowns}
+    res = {}
+    for name, prec, k in (("fp32_dc", lgf.LGF_FP32_REFINE, dc), ("fp64_plain", lgf.LGF_FP64_PLAIN, 0)):
+        p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, prec, k)
+        u = torch.zeros_like(f)
+        dt = time_solves(p, f, u, steps, warmup, torch, stream)
+        res[name] = u.cpu().numpy()
+        out[name] = {"value": L.unknowns / dt, "ms_per_step": dt * 1e3}
+        p.close()
+    out["fp32_dc"]["diff_vs_fp64_plain"] = float(np.abs(res["fp32_dc"] - res["fp64_plain"]).max()
+                                                 / np.abs(res["fp64_plain"]).max())
+    return out
+
+
+def bench_batch(lgf, workloads, torch, stream, steps, warmup, dc):
+    """64 independent layouts in one batched solve (shared launches, captured graph replays),
+    FP32 + DC with autotuned MAC launch shapes: aggregate grid points per second."""
+    Ls = workloads.batch()
+    plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, dc, autotune=1)
+             for L in Ls]
+    fs = [torch.from_numpy(np.ascontiguousarray(L.f)).cuda() for L in Ls]
+    us = [torch.zeros_like(f) for f in fs]
+    for _ in range(warmup):
+        lgf.solve_batch(plans, fs, us, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lgf.solve_batch(plans, fs, us, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    total = sum(L.unknowns for L in Ls)
+    for p in plans:
+        p.close()
+    return {"solves": len(Ls), "unknowns": total, "value": total / dt, "ms_per_batch": dt * 1e3}
+
+
+def bench_serving(lgf, workloads, torch, capacity_pts, dc, count=400):
+    """Poisson-arrival request stream through the continuous-batching server: requests draw a
+    layout from a pool of 24 (4096 .. 16.7M unknowns, log-uniform) and bring a source; the rate
+    offers 0.7 of the measured batched capacity; latency = completion - arrival."""
+    pool = workloads.request_pool(count=24)
+    plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, dc) for L in pool]
+    fs = [torch.from_numpy(np.ascontiguousarray(L.f)).cuda() for L in pool]
+    mean_pts = float(np.mean([L.unknowns for L in pool]))
+    rate = 0.7 * capacity_pts / mean_pts
+    times, _ = workloads.arrivals(seed=5, count=count, rate_hz=rate)
+    which = np.random.default_rng(5).integers(0, len(pool), size=count)
+    us = [torch.zeros_like(f) for f in fs]
+    budget = 200 << 30
+    srv = lgf.Server(hbm_budget=budget, stream=torch.cuda.Stream())
+    t0 = time.perf_counter()
+    for t, k in zip(times, which):
+        while time.perf_counter() - t0 < t:
+            pass
+        srv.submit(plans[k], fs[k], us[k])
+    srv.wait_all()
+    st = srv.stats()
+    srv.close()
+    for p in plans:
+        p.close()
+    return {"requests": count, "rate_hz": rate, "hbm_budget_bytes": budget, "p50_ms": st["p50_us"] / 1e3,
+            "p99_ms": st["p99_us"] / 1e3, "value": st["points_per_s"], "unit": "grid points/s",
+            "pool": "24 layouts, 4096..16.7M unknowns log-uniform, n_b 8/16, 1..3 levels"}
+
+
 def cpu_baseline(n_b=16, nblk=8, order=8):
     """The FP64 oracle, single-threaded, on a bounded sample of the same workload recipe."""
     from threadpoolctl import threadpool_limits
@@ -111,6 +183,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dc", type=int, default=1, help="defect-correction iterations of the FP32 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the torus, 64-layout batch and serving measurements")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every kernel directly (no captured-graph replays), for profilers")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -223,6 +297,13 @@ def main():
         "err_vs_fp64": err32,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()} for e in kern],
     }
+    if not args.no_extra:
+        out["multires_torus"] = bench_torus(lgf, workloads, torch, stream, max(args.steps // 4, 3), 1, args.dc)
+        print(f"# torus: {out['multires_torus']}", file=sys.stderr, flush=True)
+        out["batch64"] = bench_batch(lgf, workloads, torch, stream, max(args.steps // 4, 3), 1, args.dc)
+        print(f"# batch64: {out['batch64']}", file=sys.stderr, flush=True)
+        out["serving"] = bench_serving(lgf, workloads, torch, out["batch64"]["value"], args.dc)
+        print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
