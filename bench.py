@@ -81,7 +81,8 @@ def time_solves(plan, f, u, steps, warmup, torch, stream):
 
 
 def profiled(lgf, plan, f, u, steps, torch, stream):
-    """Per-kernel HIP-event times over `steps` solves (direct launches: events bracket each)."""
+    """Per-kernel HIP-event times over `steps` solves (direct launches on one stream: events
+    bracket each kernel running alone)."""
     lgf.profile_read()
     lgf.profile(True)
     for _ in range(steps):
@@ -187,11 +188,16 @@ def main():
                     help="skip the torus, 64-layout batch and serving measurements")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every kernel directly (no captured-graph replays), for profilers")
+    ap.add_argument("--serial", action="store_true",
+                    help="one stream per solve (no base-level/far-field overlap), so that a "
+                         "profiler's kernel durations are those of kernels running alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (counter calibration)")
     args = ap.parse_args()
     if args.no_graph:
         os.environ["LGF_NO_GRAPH"] = "1"
+    if args.serial:
+        os.environ["LGF_NO_FORK"] = "1"
     if args.copy_calibration:
         import torch
         a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)

@@ -1230,6 +1230,59 @@ hipError_t profile_collect(std::vector<ProfileEntry>* out) {
   return hipSuccess;
 }
 
+// Within a refinement level the base-level super-block path (forward super-block FFTs, near MAC,
+// inverse) and the far field (anterpolation, coarse-level FFTs and MACs, interpolation down to
+// level 1) depend only on the level's sources and meet at the interpolation into the base
+// level.  The far-field kernels are small and latency-bound, so the base path runs on a second
+// stream beside them: fork after the level's sources are formed, join before the base-level
+// interpolation.  Chains: 0 before the fork, 1 base path (second stream), 2 far field, 3 after.
+namespace {
+int chain_of(const Ref& r) {
+  if (r.phase <= 1) return 0;
+  if (r.kind == K_SUP_FWD || r.kind == K_NEAR_MAC || r.kind == K_SUP_INV) return 1;
+  if (r.phase >= 7 || (r.kind == K_INTERP && r.sub == 100)) return 3;
+  return 2;
+}
+
+// one second stream per (thread, device), default priority, and a reusable event pool
+struct ForkRes {
+  std::map<int, hipStream_t> aux;
+  std::vector<hipEvent_t> ev;
+};
+thread_local ForkRes t_fork;
+
+hipError_t fork_stream(hipStream_t* out) {
+  int dev = 0;
+  LGF_HIP_CHECK(hipGetDevice(&dev));
+  auto it = t_fork.aux.find(dev);
+  if (it == t_fork.aux.end()) {
+    hipStream_t s = nullptr;
+    LGF_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    it = t_fork.aux.emplace(dev, s).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+hipError_t fork_event(size_t i, hipEvent_t* out) {
+  while (t_fork.ev.size() <= i) {
+    hipEvent_t e = nullptr;
+    LGF_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    t_fork.ev.push_back(e);
+  }
+  *out = t_fork.ev[i];
+  return hipSuccess;
+}
+
+// dst waits for all work enqueued on src so far
+hipError_t stream_after(hipStream_t dst, hipStream_t src, size_t ev_index) {
+  hipEvent_t e = nullptr;
+  LGF_HIP_CHECK(fork_event(ev_index, &e));
+  LGF_HIP_CHECK(hipEventRecord(e, src));
+  return hipStreamWaitEvent(dst, e, 0);
+}
+}  // namespace
+
 hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st) {
   std::vector<Ref> refs;
   for (size_t i = 0; i < m.size(); ++i) {
@@ -1238,6 +1291,22 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
       refs.push_back({s.l, s.phase, s.sub, s.kind, m[i].p->nb, s.ty, s.mode, (int)i, &s});
   }
   std::sort(refs.begin(), refs.end());
+  bool prof;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof = g_prof_on;
+  }
+  // per-launch timing (and LGF_NO_FORK) keeps one stream, so that kernel times are not shared
+  static const bool no_fork = std::getenv("LGF_NO_FORK") != nullptr;
+  std::set<int> base_chain;                      // levels with a base-level super-block path
+  if (!prof && !no_fork)
+    for (const Ref& r : refs)
+      if (chain_of(r) == 1) base_chain.insert(r.l);
+  hipStream_t aux = nullptr;
+  if (!base_chain.empty()) LGF_HIP_CHECK(fork_stream(&aux));
+  bool forked = false;
+  int fork_l = -1;
+  size_t nev = 0;
   size_t a = 0;
   while (a < refs.size()) {
     size_t b = a;
@@ -1258,27 +1327,34 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
       ws.w = refs[b].step->w;
       ++b;
     }
-    bool prof;
-    {
-      std::lock_guard<std::mutex> lk(g_prof_mu);
-      prof = g_prof_on;
+    const int c = chain_of(refs[a]), l = refs[a].l;
+    if (forked && (l != fork_l || c == 0 || c == 3)) {
+      LGF_HIP_CHECK(stream_after(st, aux, nev++));          // join
+      forked = false;
     }
+    if (!forked && (c == 1 || c == 2) && base_chain.count(l)) {
+      LGF_HIP_CHECK(stream_after(aux, st, nev++));          // fork
+      forked = true;
+      fork_l = l;
+    }
+    hipStream_t ls = (forked && c == 1) ? aux : st;
     ProfRec rec{refs[a].kind, refs[a].ty, refs[a].nb, 0, nullptr, nullptr};
     if (prof) {
       for (size_t q = a; q < b; ++q) rec.work += refs[q].step->work;
       LGF_HIP_CHECK(hipEventCreate(&rec.a));
       LGF_HIP_CHECK(hipEventCreate(&rec.b));
-      LGF_HIP_CHECK(hipEventRecord(rec.a, st));
+      LGF_HIP_CHECK(hipEventRecord(rec.a, ls));
     }
-    hipError_t e = launch_typed(refs[a].kind, refs[a].ty, refs[a].nb, t, st, refs[a].mode);
+    hipError_t e = launch_typed(refs[a].kind, refs[a].ty, refs[a].nb, t, ls, refs[a].mode);
     if (e != hipSuccess) return e;
     if (prof) {
-      LGF_HIP_CHECK(hipEventRecord(rec.b, st));
+      LGF_HIP_CHECK(hipEventRecord(rec.b, ls));
       std::lock_guard<std::mutex> lk(g_prof_mu);
       g_prof.push_back(rec);
     }
     a = b;
   }
+  if (forked) LGF_HIP_CHECK(stream_after(st, aux, nev++));
   return hipSuccess;
 }
 
