@@ -92,6 +92,22 @@ template <typename T> struct NearRow {
   const c64* const* kptr;              // 27 FP64 kernel spectra, index (dz+1)*9+(dy+1)*3+dx+1
 };
 
+// A near tile: 2 x 2 rows (y0 + ry, z0 + rz), row r = ry + 2 rz, of up to 4 targets along x at
+// x0 = 4 wx.  The 4 x 4 source rows (y0 - 1 + qy, z0 - 1 + qz), q = qy + 4 qz, cover the 27
+// neighbours of every target of the tile; a workgroup stages them in LDS once per frequency
+// chunk.
+constexpr int kTileW = 4;                 // targets per tile row
+template <typename T> struct NearTile {
+  int32_t tgt[4][kMacL];               // target super slots (-1: none), first kTileW used
+  int32_t src[16 * (kTileW + 2)];      // source super slot of row q at x0 - 1 + s: [q * 6 + s]
+                                       // (the zero slot where absent)
+  uint32_t src_mask;                   // bit q: source row q holds a source
+  uint32_t row_mask;                   // bit r: row r holds a target
+  const cpx<T>* fhat;
+  cpx<T>* uhat;
+  const c64* const* kptr;              // 27 FP64 kernel spectra, index (dz+1)*9+(dy+1)*3+dx+1
+};
+
 // TC: element type of the child level, TP: of the parent level (they differ where an FP32
 // base level meets FP64 coarse levels).
 template <typename TC, typename TP> struct AnterpItem {
@@ -180,7 +196,9 @@ hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st);
-template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int width);
+// mode: W (4 or 8) for NearRow items; kNearTiled + 4 for NearTile items
+constexpr int kNearTiled = 16;
+template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode);
 
 // number of workgroups each item of a kernel needs (for set-table bookkeeping)
 inline int64_t assign_wg(SetTable& t, int64_t per_item_num, int64_t per_item_den = 1) {

@@ -361,22 +361,108 @@ __global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
   }
 }
 
+// Tiled form: one workgroup of 4 wavefronts per (tile, frequency chunk); the 16 source rows of
+// the tile ((W + 2) spectra each, 64 frequencies) and the 27 kernels are staged in LDS with all
+// loads of a wavefront in flight together, then each wavefront applies its row's 9 source rows
+// from LDS.  Compared with one wavefront per row loading its own 9 source rows, this reads each
+// source spectrum chunk from L2 once per tile instead of up to 4 times.
+template <typename T, int W>
+__global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
+  static_assert(W == kTileW, "tile rows hold kTileW targets");
+  constexpr int NS = W + 2;
+  constexpr int NE = 16 * NS;                      // staged spectra per tile
+  constexpr int PER_WAVE = (NE + 3) / 4;
+  __shared__ cpx<T> fl[NE * 64];
+  __shared__ cpx<double> kl[27 * 64];
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;       // wg_begin is a multiple of 8
+  const int ntiles = ws.count;
+  const int xcd = (int)(local & 7);
+  const int64_t j = local >> 3;
+  const int chunk = (int)(j / ntiles) * 8 + xcd;
+  const int ti = (int)(j % ntiles);
+  if (chunk * 64 >= S) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int k = chunk * 64 + lane;
+  const NearTile<T>* tile = (const NearTile<T>*)ws.items + ti;
+  gptr<T> F = (gptr<T>)tile->fhat;
+  const uint32_t smask = tile->src_mask;
+  {
+    // each wavefront stages a contiguous run of entries: one wide scalar load of their slots,
+    // then all vector loads back to back (absent sources read the zero spectrum)
+    static_assert(NE % 4 == 0, "tile entries split evenly over 4 wavefronts");
+    const int32_t* sl = tile->src + wave * PER_WAVE;
+    cpx<T> v[PER_WAVE];
+#pragma unroll
+    for (int e = 0; e < PER_WAVE; ++e) v[e] = gload<T>(F, (int64_t)sl[e] * S + k);
+    const cptr64 kp = (cptr64)tile->kptr;
+    cpx<double> kv[7];
+#pragma unroll
+    for (int e = 0; e < 7; ++e) kv[e] = gload<double>((gptr<double>)kp[min(wave * 7 + e, 26)], k);
+#pragma unroll
+    for (int e = 0; e < PER_WAVE; ++e) fl[(wave * PER_WAVE + e) * 64 + lane] = v[e];
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+      const int h = wave * 7 + e;
+      if (h < 27) kl[h * 64 + lane] = kv[e];
+    }
+  }
+  __syncthreads();
+  const int r = wave;
+  if (!((tile->row_mask >> r) & 1u)) return;
+  const int ry = r & 1, rz = r >> 1;
+  cpx<double> acc[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) acc[i] = {0.0, 0.0};
+#pragma unroll
+  for (int pj = 0; pj < 9; ++pj) {
+    const int dz = pj / 3 - 1, dy = pj % 3 - 1;
+    const int q = (ry + 1 - dy) + 4 * (rz + 1 - dz);
+    if (!((smask >> q) & 1u)) continue;
+    cpx<double> fd[NS];
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const cpx<T> f = fl[(q * NS + s2) * 64 + lane];
+      fd[s2] = {double(f.x), double(f.y)};
+    }
+#pragma unroll
+    for (int dxi = 0; dxi < 3; ++dxi) {
+      const cpx<double> kk = kl[(pj * 3 + dxi) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < W; ++i) cmac(acc[i], kk, fd[i - dxi + 2]);   // src x = x0 + i - dx
+    }
+  }
+  gmut<T> U = (gmut<T>)tile->uhat;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const int t = tile->tgt[r][i];
+    if (t >= 0) {
+      U[2 * ((int64_t)t * S + k)] = T(acc[i].x);
+      U[2 * ((int64_t)t * S + k) + 1] = T(acc[i].y);
+    }
+  }
+}
+
 }  // namespace
 
-// width: targets per row (4 or 8), chosen by the planner
-template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int width) {
+// mode: targets per row W (4 or 8) with NearRow items, or kNearTiled + W with NearTile items;
+// chosen by the planner
+template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode) {
   const int B2 = 2 * nb, P = 2 * B2;
   const int S = P * P * (B2 + 1);
   if (S % 64) return hipErrorInvalidValue;
   const int chunks8 = (S / 64 + 7) / 8;
+  const bool tiled = mode > kNearTiled;
   int64_t wg = 0;
   for (int i = 0; i < t.n; ++i) {
     t.s[i].wg_begin = wg;
-    wg += (int64_t)((t.s[i].count + 3) / 4) * chunks8 * 8;
+    wg += (int64_t)(tiled ? t.s[i].count : (t.s[i].count + 3) / 4) * chunks8 * 8;
   }
   if (wg == 0) return hipSuccess;
-  if (width == 4) near_mac_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
-  else if (width == 8) near_mac_kernel<T, 8><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  if (mode == 4) near_mac_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else if (mode == 8) near_mac_kernel<T, 8><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else if (mode == kNearTiled + 4) near_tile_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -436,7 +436,7 @@ struct SlotCounts {
   int64_t nsup_src[2], nsup_tgt[2];    // super-block spectra slots
 };
 
-bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int count, int64_t n,
+bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* items, int count, int64_t n,
                    const SlotCounts& sc, std::string* err) {
   const int nb = p->nb;
   const size_t N3 = (size_t)nb * nb * nb;
@@ -548,8 +548,22 @@ bool validate_step(const Plan* p, int kind, int ty, const uint8_t* items, int co
         break;
       }
       case K_NEAR_MAC: {
-        const auto& it = ((const NearRow<double>*)items)[i];
         const int t = ty == 0 ? 0 : 1;
+        if (mode > kNearTiled) {
+          if (mode != kNearTiled + 4) return bad("near tile width", i);
+          const auto& it = ((const NearTile<double>*)items)[i];
+          for (int j = 0; j < 16 * (kTileW + 2); ++j)
+            if (it.src[j] < 0 || it.src[j] > sc.nsup_src[t]) return bad("near tile source slot", i);
+          for (int r = 0; r < 4; ++r)
+            for (int q = 0; q < kMacL; ++q)
+              if (it.tgt[r][q] < -1 || it.tgt[r][q] >= sc.nsup_tgt[t]) return bad("near tile target slot", i);
+          if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
+          if (sc.nsup_tgt[t] && !in_ranges(p, it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
+          if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
+          break;
+        }
+        if (mode != 4 && mode != 8) return bad("near row width", i);
+        const auto& it = ((const NearRow<double>*)items)[i];
         if (it.ngroups < 0 || it.ngroups > 3) return bad("near row groups", i);
         for (int j = 0; j < 9; ++j) {
           if (((it.pj_code >> (4 * j)) & 15u) > 8) return bad("near source row index", i);
@@ -992,7 +1006,43 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       // FP64 storage holds two groups of 10 spectra per lane only at W = 4
       const int width = (tys != TY_F32 || build_rows(4, nullptr) <= build_rows(8, nullptr)) ? 4 : 8;
       std::vector<NearRow<D>> nr;
-      build_rows(width, &nr);
+      std::vector<NearTile<D>> nt;
+      const bool tiled = tys == TY_F32;       // FP32 storage: 2 x 2 rows of 4 share staged sources
+      if (tiled) {
+        for (const SupInst& si : sup) {
+          if (si.l != l) continue;
+          std::map<I3, size_t> tile_of;
+          for (const SupTgt& t : si.tg) {
+            const int wx = floordiv(t.c.x, kTileW), ty2 = floordiv(t.c.y, 2), tz2 = floordiv(t.c.z, 2);
+            const I3 key{wx, ty2, tz2};
+            auto it = tile_of.find(key);
+            if (it == tile_of.end()) {
+              NearTile<D> q{};
+              for (int r = 0; r < 4; ++r)
+                for (int i = 0; i < kMacL; ++i) q.tgt[r][i] = -1;
+              q.src_mask = 0;
+              q.row_mask = 0;
+              for (int qz = 0; qz < 4; ++qz)
+                for (int qy = 0; qy < 4; ++qy)
+                  for (int x = 0; x < kTileW + 2; ++x) {
+                    auto sit = si.sslot.find({wx * kTileW - 1 + x, 2 * ty2 - 1 + qy, 2 * tz2 - 1 + qz});
+                    q.src[(qy + 4 * qz) * (kTileW + 2) + x] = sit != si.sslot.end() ? sit->second : (int)nsup_src;
+                    if (sit != si.sslot.end()) q.src_mask |= 1u << (qy + 4 * qz);
+                  }
+              q.fhat = SFH(0);
+              q.uhat = SUH(0);
+              q.kptr = ns->kp64;
+              it = tile_of.emplace(key, nt.size()).first;
+              nt.push_back(q);
+            }
+            const int r = (t.c.y - 2 * ty2) + 2 * (t.c.z - 2 * tz2);
+            nt[it->second].tgt[r][t.c.x - wx * kTileW] = t.slot;
+            nt[it->second].row_mask |= 1u << r;
+          }
+        }
+      } else {
+        build_rows(width, &nr);
+      }
       std::vector<SuperInvItem<D>> si_items;
       int64_t pairs = 0;
       for (const SupInst& si : sup) {
@@ -1010,10 +1060,13 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       }
       p->n_sup_fwd += (int64_t)sf.size();
       p->n_sup_inv += (int64_t)si_items.size();
-      p->n_near_rows += (int64_t)nr.size();
+      p->n_near_rows += (int64_t)(tiled ? 4 * nt.size() : nr.size());
       p->near_pairs += pairs;
       push(steps, l, 3, 0, K_SUP_FWD, tys, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size());
-      push(steps, l, 4, 0, K_NEAR_MAC, tys, hi.add(nr), nr.size(), nullptr, pairs, width);
+      if (tiled)
+        push(steps, l, 4, 0, K_NEAR_MAC, tys, hi.add(nt), nt.size(), nullptr, pairs, kNearTiled + 4);
+      else
+        push(steps, l, 4, 0, K_NEAR_MAC, tys, hi.add(nr), nr.size(), nullptr, pairs, width);
       push(steps, l, 5, 0, K_SUP_INV, tys, hi.add(si_items), si_items.size(), nullptr, (int64_t)si_items.size());
     }
     for (int k = 1; k < K; ++k) {
@@ -1073,7 +1126,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     sc.nsup_tgt[tys == TY_F32 ? 0 : 1] = nsup_tgt;
     for (const auto* list : {&steps, &rsteps})
       for (const PendingStep& st : *list)
-        if (!validate_step(p, st.kind, st.ty, hi.buf.data() + st.off, st.count, n, sc, err))
+        if (!validate_step(p, st.kind, st.ty, st.mode, hi.buf.data() + st.off, st.count, n, sc, err))
           return hipErrorInvalidValue;
   }
   void* d_items = nullptr;
