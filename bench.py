@@ -48,23 +48,27 @@ def spectrum_size(n_b):
     return P * P * (n_b + 1)
 
 
-def algorithmic(entry, n_b):
-    """(amount, unit, bound) per launch-summed entry.  MACs: 8 flops per complex multiply-add,
-    S of them per (target, source) pair (work = pairs).  Transforms: compulsory HBM bytes per
-    item (work = items): the block or the 8 child blocks of a super-block, and the half
-    spectrum (2 S reals)."""
+def algorithmic(entry, n_b, info):
+    """Algorithmic work of one profiled entry (summed over its launches): (flops, flop peak in
+    TFLOP/s, compulsory HBM bytes), None where not defined.  MACs: 8 flops per complex
+    multiply-add, S per (target, source) pair (work = pairs); the near MAC computes in FP64
+    whatever the storage type and reads each source spectrum and the 27 FP64 kernels once and
+    writes each target spectrum once.  Transforms: per item (work = items) the block or the 8
+    child blocks of a super-block, and the half spectrum (2 S reals)."""
     es = 4 if entry["precision"] == "fp32" else 8
     S, S2 = spectrum_size(n_b), spectrum_size(2 * n_b)
     N3 = n_b ** 3
     k = entry["kernel"]
+    peak = PEAK["fp32_vector_tflops"] if entry["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
     if k == "mac":
-        return 8.0 * S * entry["work"], "flop", "alu"
+        return 8.0 * S * entry["work"], peak, None
     if k == "near_mac":
-        return 8.0 * S2 * entry["work"], "flop", "alu"
+        per_launch = (info["super_forward"] + info["super_inverse"]) * 2 * S2 * es + 27 * S2 * 16
+        return 8.0 * S2 * entry["work"], PEAK["fp64_vector_tflops"], per_launch * entry["launches"]
     if k in ("fft_fwd", "fft_inv"):
-        return float(entry["work"]) * (N3 * es + 2 * S * es), "byte", "hbm"
+        return None, None, float(entry["work"]) * (N3 * es + 2 * S * es)
     if k in ("super_fwd", "super_inv"):
-        return float(entry["work"]) * (8 * N3 * es + 2 * S2 * es), "byte", "hbm"
+        return None, None, float(entry["work"]) * (8 * N3 * es + 2 * S2 * es)
     return None, None, None
 
 
@@ -248,15 +252,18 @@ def main():
     err0 = float(np.abs(a0 - a64).max() / np.abs(a64).max())
     errb = float(np.abs(ub.cpu().numpy() - a64).max() / np.abs(a64).max())
 
-    # dominant kernel of the headline form
+    # dominant kernel of the headline form (per-launch event times of kernels running alone);
+    # its roofline is the larger of the HBM time of its compulsory bytes and the ALU time of its
+    # flops, over the measured time
     kern = []
     for e in prof:
-        amt, unit, bound = algorithmic(e, L.n_b)
+        flops, fpeak, nbytes = algorithmic(e, L.n_b, info)
         e = dict(e, avg_us=1e3 * e["ms"] / max(e["launches"], 1))
-        if amt is not None:
-            rate = amt / (e["ms"] * 1e-3)
-            e.update(algorithmic=amt / e["launches"], unit=unit, bound=bound,
-                     rate=rate / (1e12 if unit == "flop" else 1e9))
+        t = e["ms"] * 1e-3
+        if flops is not None:
+            e.update(flops_per_launch=flops / e["launches"], tflops=flops / t / 1e12, flop_peak=fpeak)
+        if nbytes is not None:
+            e.update(bytes_per_launch=nbytes / e["launches"], gbs=nbytes / t / 1e9)
         kern.append(e)
     kern.sort(key=lambda e: -e["ms"])
     dom = kern[0]
@@ -264,20 +271,21 @@ def main():
     src = {"mac": "mac.hip", "near_mac": "mac.hip", "fft_fwd": "fft_blocks.hip", "fft_inv": "fft_blocks.hip",
            "super_fwd": "fft_super.hip", "super_inv": "fft_super.hip"}.get(dom["kernel"])
     traffic = measured_traffic(tag, src) if src else None
-    if dom.get("unit") == "flop":
-        peak = PEAK["fp32_vector_tflops"] if dom["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
-        roof = {"bound": "alu", "achieved": round(dom["rate"], 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(dom["rate"] / peak, 4), "traffic": traffic,
-                "kernel": f"{dom['kernel']} ({dom['precision']}, n_b={dom['n_b']})",
-                "avg_launch_us": round(dom["avg_us"], 2)}
-    elif dom.get("unit") == "byte":
-        roof = {"bound": "hbm", "achieved": round(dom["rate"], 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                "frac": round(dom["rate"] / PEAK["hbm_gbs"], 4), "traffic": traffic,
-                "kernel": f"{dom['kernel']} ({dom['precision']}, n_b={dom['n_b']})",
-                "avg_launch_us": round(dom["avg_us"], 2)}
-    else:
+    t_hbm = dom["bytes_per_launch"] / (PEAK["hbm_gbs"] * 1e9) if "bytes_per_launch" in dom else 0.0
+    t_alu = dom["flops_per_launch"] / (dom["flop_peak"] * 1e12) if "flops_per_launch" in dom else 0.0
+    name = f"{dom['kernel']} ({dom['precision']} storage, n_b={dom['n_b']})"
+    if t_hbm == 0.0 and t_alu == 0.0:
         roof = {"bound": "hbm", "achieved": None, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": None,
-                "traffic": None, "kernel": dom["kernel"]}
+                "traffic": traffic, "kernel": name}
+    elif t_hbm >= t_alu:
+        roof = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                "frac": round(dom["gbs"] / PEAK["hbm_gbs"], 4), "traffic": traffic, "kernel": name,
+                "avg_launch_us": round(dom["avg_us"], 2),
+                "alu": {"achieved_tflops": round(dom.get("tflops", 0.0), 3), "peak": dom.get("flop_peak")}}
+    else:
+        roof = {"bound": "alu", "achieved": round(dom["tflops"], 3), "peak": dom["flop_peak"], "unit": "TFLOP/s",
+                "frac": round(dom["tflops"] / dom["flop_peak"], 4), "traffic": traffic, "kernel": name,
+                "avg_launch_us": round(dom["avg_us"], 2)}
 
     out = {
         "metric": "grid points/s per Poisson solve (FP32+refine; FP64 plain beside it)",
