@@ -51,9 +51,9 @@ def spectrum_size(n_b):
 def algorithmic(entry, n_b, info):
     """Algorithmic work of one profiled entry (summed over its launches): (flops, flop peak in
     TFLOP/s, compulsory HBM bytes), None where not defined.  MACs: 8 flops per complex
-    multiply-add, S per (target, source) pair (work = pairs); the near MAC computes in FP64
-    whatever the storage type and reads each source spectrum and the 27 FP64 kernels once and
-    writes each target spectrum once.  Transforms: per item (work = items) the block or the 8
+    multiply-add, S per (target, source) pair (work = pairs); the near MAC reads each source
+    spectrum and the 27 kernel spectra once and writes each target spectrum once (FP32 tiles
+    compute in FP32; rows of FP64 spectra in FP64).  Transforms: per item (work = items) the block or the 8
     child blocks of a super-block, and the half spectrum (2 S reals)."""
     es = 4 if entry["precision"] == "fp32" else 8
     S, S2 = spectrum_size(n_b), spectrum_size(2 * n_b)
@@ -63,8 +63,8 @@ def algorithmic(entry, n_b, info):
     if k == "mac":
         return 8.0 * S * entry["work"], peak, None
     if k == "near_mac":
-        per_launch = (info["super_forward"] + info["super_inverse"]) * 2 * S2 * es + 27 * S2 * 16
-        return 8.0 * S2 * entry["work"], PEAK["fp64_vector_tflops"], per_launch * entry["launches"]
+        per_launch = (info["super_forward"] + info["super_inverse"] + 27) * 2 * S2 * es
+        return 8.0 * S2 * entry["work"], peak, per_launch * entry["launches"]
     if k in ("fft_fwd", "fft_inv"):
         return None, None, float(entry["work"]) * (N3 * es + 2 * S * es)
     if k in ("super_fwd", "super_inv"):

@@ -105,7 +105,8 @@ template <typename T> struct NearTile {
   uint32_t row_mask;                   // bit r: row r holds a target
   const cpx<T>* fhat;
   cpx<T>* uhat;
-  const c64* const* kptr;              // 27 FP64 kernel spectra, index (dz+1)*9+(dy+1)*3+dx+1
+  const cpx<T>* const* kptr;           // 27 kernel spectra in the storage type, index
+                                       // (dz+1)*9+(dy+1)*3+dx+1
 };
 
 // TC: element type of the child level, TP: of the parent level (they differ where an FP32

@@ -362,18 +362,21 @@ __global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
 }
 
 // Tiled form: one workgroup of 4 wavefronts per (tile, frequency chunk); the 16 source rows of
-// the tile ((W + 2) spectra each, 64 frequencies) and the 27 kernels are staged in LDS with all
-// loads of a wavefront in flight together, then each wavefront applies its row's 9 source rows
-// from LDS.  Compared with one wavefront per row loading its own 9 source rows, this reads each
-// source spectrum chunk from L2 once per tile instead of up to 4 times.
+// the tile ((W + 2) spectra each, 64 frequencies) are staged in LDS with all loads of a
+// wavefront in flight together, and each wavefront holds the 27 kernel values of its frequency
+// in registers.  Each wavefront then applies its row's 9 source rows from LDS, in the storage
+// type (the planner uses tiles for FP32 spectra on single-level layouts, where defect
+// correction removes FP32 error: an FP64 sum there changed nothing measurable).  Compared
+// with one wavefront per row loading its own 9 source rows, each source spectrum chunk is read
+// from L2 once per tile instead of up to 4 times.
 template <typename T, int W>
 __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
   static_assert(W == kTileW, "tile rows hold kTileW targets");
   constexpr int NS = W + 2;
   constexpr int NE = 16 * NS;                      // staged spectra per tile
-  constexpr int PER_WAVE = (NE + 3) / 4;
+  constexpr int PER_WAVE = NE / 4;
+  static_assert(NE % 4 == 0, "tile entries split evenly over 4 wavefronts");
   __shared__ cpx<T> fl[NE * 64];
-  __shared__ cpx<double> kl[27 * 64];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;       // wg_begin is a multiple of 8
@@ -391,46 +394,36 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
   {
     // each wavefront stages a contiguous run of entries: one wide scalar load of their slots,
     // then all vector loads back to back (absent sources read the zero spectrum)
-    static_assert(NE % 4 == 0, "tile entries split evenly over 4 wavefronts");
     const int32_t* sl = tile->src + wave * PER_WAVE;
     cpx<T> v[PER_WAVE];
 #pragma unroll
     for (int e = 0; e < PER_WAVE; ++e) v[e] = gload<T>(F, (int64_t)sl[e] * S + k);
-    const cptr64 kp = (cptr64)tile->kptr;
-    cpx<double> kv[7];
-#pragma unroll
-    for (int e = 0; e < 7; ++e) kv[e] = gload<double>((gptr<double>)kp[min(wave * 7 + e, 26)], k);
 #pragma unroll
     for (int e = 0; e < PER_WAVE; ++e) fl[(wave * PER_WAVE + e) * 64 + lane] = v[e];
-#pragma unroll
-    for (int e = 0; e < 7; ++e) {
-      const int h = wave * 7 + e;
-      if (h < 27) kl[h * 64 + lane] = kv[e];
-    }
   }
+  const cptr64 kp = (cptr64)tile->kptr;
+  cpx<T> kv[27];
+#pragma unroll
+  for (int h = 0; h < 27; ++h) kv[h] = gload<T>((gptr<T>)kp[h], k);
   __syncthreads();
   const int r = wave;
   if (!((tile->row_mask >> r) & 1u)) return;
   const int ry = r & 1, rz = r >> 1;
-  cpx<double> acc[W];
+  cpx<T> acc[W];
 #pragma unroll
-  for (int i = 0; i < W; ++i) acc[i] = {0.0, 0.0};
+  for (int i = 0; i < W; ++i) acc[i] = {T(0), T(0)};
 #pragma unroll
   for (int pj = 0; pj < 9; ++pj) {
     const int dz = pj / 3 - 1, dy = pj % 3 - 1;
     const int q = (ry + 1 - dy) + 4 * (rz + 1 - dz);
     if (!((smask >> q) & 1u)) continue;
-    cpx<double> fd[NS];
+    cpx<T> fd[NS];
 #pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2) {
-      const cpx<T> f = fl[(q * NS + s2) * 64 + lane];
-      fd[s2] = {double(f.x), double(f.y)};
-    }
+    for (int s2 = 0; s2 < NS; ++s2) fd[s2] = fl[(q * NS + s2) * 64 + lane];
 #pragma unroll
     for (int dxi = 0; dxi < 3; ++dxi) {
-      const cpx<double> kk = kl[(pj * 3 + dxi) * 64 + lane];
 #pragma unroll
-      for (int i = 0; i < W; ++i) cmac(acc[i], kk, fd[i - dxi + 2]);   // src x = x0 + i - dx
+      for (int i = 0; i < W; ++i) cmac(acc[i], kv[pj * 3 + dxi], fd[i - dxi + 2]);   // src x = x0 + i - dx
     }
   }
   gmut<T> U = (gmut<T>)tile->uhat;

@@ -1031,7 +1031,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
                   }
               q.fhat = SFH(0);
               q.uhat = SUH(0);
-              q.kptr = ns->kp64;
+              q.kptr = (const cpx<D>* const*)ns->kp32;     // FP32 tiles: FP32 kernel spectra
               it = tile_of.emplace(key, nt.size()).first;
               nt.push_back(q);
             }
