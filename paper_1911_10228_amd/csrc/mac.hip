@@ -139,14 +139,16 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
     load_src<T>(fs, tile->src[pj], F, S, k);
     if constexpr (!KLDS) load_k<T, ROWS>(ks, kp, r0, pj / 6, pj % 6, k);
     for (;;) {
-      const int pn = todo ? __builtin_ctzll(todo) : -1;
+      // the next source row's loads are issued unconditionally (the last iteration reloads the
+      // current row), so every iteration issues the same loads and the waits for the current
+      // row leave the next row's loads in flight (the vector memory counter retires in order)
+      const bool more = todo != 0;
+      const int pn = more ? __builtin_ctzll(todo) : pj;
+      todo &= todo - 1;
       cpx<T> fn[kMacSlots];
       cpx<T> kn[KLDS ? 1 : ROWS][7];
-      if (pn >= 0) {
-        todo &= todo - 1;
-        load_src<T>(fn, tile->src[pn], F, S, k);
-        if constexpr (!KLDS) load_k<T, ROWS>(kn, kp, r0, pn / 6, pn % 6, k);
-      }
+      load_src<T>(fn, tile->src[pn], F, S, k);
+      if constexpr (!KLDS) load_k<T, ROWS>(kn, kp, r0, pn / 6, pn % 6, k);
       const int jz = pj / 6, jy = pj % 6;
 #pragma unroll
       for (int q = 0; q < ROWS; ++q) {
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
           mac_row<T>(acc[q], fs, r, jz, jy, base, [&](int dxi) { return ks[q][dxi]; });
         }
       }
-      if (pn < 0) break;
+      if (!more) break;
 #pragma unroll
       for (int s = 0; s < kMacSlots; ++s) fs[s] = fn[s];
       if constexpr (!KLDS) {
