@@ -193,7 +193,7 @@ lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, i
   hipError_t e = lgf::device_ctx(&c);
   if (e != hipSuccess) return from_hip(e);
   const lgf::SpecSet* ss = nullptr;
-  e = lgf::spectra_for(c, N_b, s, &ss);
+  e = lgf::spectra_for(c, N_b, s == 0 ? -1 : s, &ss);      // s = 0: base-level super-blocks
   if (e != hipSuccess) return from_hip(e);
   const size_t S = (size_t)ss->spec;
   const int W = 2 * R + 1;

@@ -259,9 +259,10 @@ struct Arena {
 };
 
 // spectra count and size of a kernel set (s == 0: the 27 super-block neighbour spectra)
-inline int spec_count(int s) { return s == 0 ? 27 : 343; }
+// s >= 1: block kernels at scale s; s <= -1: super-block kernels at scale -s
+inline int spec_count(int s) { return s < 0 ? 27 : 343; }
 inline int64_t spec_size(int nb, int s) {
-  const int64_t b = s == 0 ? 2 * nb : nb;
+  const int64_t b = s < 0 ? 2 * nb : nb;
   return (2 * b) * (2 * b) * (b + 1);
 }
 
@@ -275,6 +276,7 @@ hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
     p->ranges.push_back({(uintptr_t)(*out)->d32, cnt * S * sizeof(c32)});
     p->ranges.push_back({(uintptr_t)(*out)->kp64, cnt * sizeof(void*)});
     p->ranges.push_back({(uintptr_t)(*out)->kp32, cnt * sizeof(void*)});
+    if ((*out)->near64) p->ranges.push_back({(uintptr_t)(*out)->near64, 27 * sizeof(void*)});
     return hipSuccess;
   }
   auto key = std::make_pair(nb, s);
@@ -289,6 +291,7 @@ hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
     ss.d32 = (c32*)fake_alloc(p, cnt * S * sizeof(c32));
     ss.kp64 = (const c64**)fake_alloc(p, cnt * sizeof(void*));
     ss.kp32 = (const c32**)fake_alloc(p, cnt * sizeof(void*));
+    if (s > 0) ss.near64 = (const c64**)fake_alloc(p, 27 * sizeof(void*));
     it = p->dry_spectra.emplace(key, ss).first;
   }
   *out = &it->second;
@@ -355,9 +358,9 @@ hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out) {
     *out = &it->second;
     return hipSuccess;
   }
-  // s == 0: kernels of super-blocks of 2 nb cells between neighbours on the base lattice
-  const int cnt = spec_count(s), R = s == 0 ? 1 : 3;
-  const int bf = s == 0 ? 2 * nb : nb, sf = s == 0 ? 1 : s;
+  // s <= -1: kernels between neighbouring super-blocks of 2 nb cells at scale -s
+  const int cnt = spec_count(s), R = s < 0 ? 1 : 3;
+  const int bf = s < 0 ? 2 * nb : nb, sf = s < 0 ? -s : s;
   const int P = 2 * bf, H = bf + 1;
   const size_t S = (size_t)P * P * H, P3 = (size_t)P * P * P;
   std::vector<int32_t> sd;
@@ -384,13 +387,21 @@ hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out) {
   LGF_HIP_CHECK(hipMemcpyAsync(d_sd, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                ctx->stream));
   LGF_HIP_CHECK(launch_kernel_spectra(bf, cnt, d_sd, ctx->cube, d_real, d_tmp, ss.d64, ss.d32, ctx->stream));
-  std::vector<const void*> p64(cnt), p32(cnt);
+  std::vector<const void*> p64(cnt), p32(cnt), pn(27);
   for (int i = 0; i < cnt; ++i) {
     p64[i] = ss.d64 + i * S;
     p32[i] = ss.d32 + i * S;
   }
   LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp64, p64.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
   LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp32, p32.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  if (s > 0) {                         // the 27 near offsets of a block set
+    LGF_HIP_CHECK(hipMalloc(&ss.near64, 27 * sizeof(void*)));
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx)
+          pn[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1] = p64[(dz + 3) * 49 + (dy + 3) * 7 + dx + 3];
+    LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.near64, pn.data(), 27 * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  }
   LGF_HIP_CHECK(hipStreamSynchronize(ctx->stream));
   (void)hipFree(d_sd);
   (void)hipFree(d_real);
@@ -421,6 +432,7 @@ struct PendingStep {
   const double* w;
   int64_t work;
   int mode;
+  int chain;
 };
 
 // ----------------------------------------------------------------------------- item validation
@@ -441,7 +453,7 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
   const int nb = p->nb;
   const size_t N3 = (size_t)nb * nb * nb;
   const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
-  const size_t S2 = (size_t)spec_size(nb, 0);
+  const size_t S2 = (size_t)spec_size(nb, -1);
   const size_t TMP2 = (size_t)(2 * nb) * (4 * nb) * (2 * nb + 1);    // intermediate z-plane stack
   const int64_t* nsrc = sc.nsrc;
   const int64_t* ntgt = sc.ntgt;
@@ -463,6 +475,7 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       case K_INV: {
         const auto& it = ((const FftInvItem<double>*)items)[i];
         if (!in_ranges(p, it.src, 2 * S * es) || !in_ranges(p, it.dst, N3 * es)) return bad("fft_inv", i);
+        if (it.mode < -1 || it.mode > 1) return bad("fft_inv mode", i);
         break;
       }
       case K_MAC: {
@@ -549,6 +562,24 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_NEAR_MAC: {
         const int t = ty == 0 ? 0 : 1;
+        if (mode > kNearBlock) {             // rows over block spectra (coarse near part)
+          const int w = mode - kNearBlock;
+          if (w != 4 && w != 8) return bad("near block row width", i);
+          const auto& it = ((const NearRow<double>*)items)[i];
+          if (it.ngroups < 0 || it.ngroups > 3) return bad("near row groups", i);
+          for (int j = 0; j < 9; ++j) {
+            if (((it.pj_code >> (4 * j)) & 15u) > 8) return bad("near source row index", i);
+            for (int q = 0; q < kNearSlots; ++q)
+              if (it.src[j][q] < 0 || it.src[j][q] > nsrc[t]) return bad("near block source slot", i);
+          }
+          for (int q = 0; q < kMacL; ++q)
+            if (it.tgt[q] < -1 || it.tgt[q] >= ntgt[t]) return bad("near block target slot", i);
+          if (!in_ranges(p, it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("near block source arena", i);
+          if (ntgt[t] && !in_ranges(p, it.uhat, ntgt[t] * 2 * S * es)) return bad("near block target arena", i);
+          if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near block kernel table", i);
+          if (i > 0 && it.kptr != ((const NearRow<double>*)items)[0].kptr) return bad("near kernel table mix", i);
+          break;
+        }
         if (mode > kNearTiled) {
           if (mode != kNearTiled + 4) return bad("near tile width", i);
           const auto& it = ((const NearTile<double>*)items)[i];
@@ -663,62 +694,96 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     p->Kmax = std::max(p->Kmax, (int)chT[l].lv.size());
   }
 
-  // Base level as parent super-blocks (Sec. 2.1: a block's N(B) and I(B) together are the
-  // children of its parent's 27 neighbours): per (refinement level, channel) the target
-  // super-blocks are the parents of blocks with base-level interactions, the source super-blocks
-  // their neighbours that hold source children.  A source super-block spectrum is computed once
-  // for each distinct set of source children (channels T and A share it where they agree).
+  // Super-blocks (Sec. 2.1: a block's near list N(B) and influence list I(B) together are the
+  // children of the 27 neighbours of its parent).  Base octree level: the whole level
+  // interaction is one zero-padded convolution per parent super-block against its 27
+  // neighbours.  Coarse octree levels: the same super-block convolution covers N(B) + I(B); the
+  // near part, which finer levels account for, is computed block by block over the 27
+  // neighbours and subtracted.  Per (refinement level, channel, octree level): target
+  // super-blocks are the parents of blocks with interactions, source super-blocks their
+  // neighbours holding source children.  A source super-block spectrum is computed once per
+  // distinct set of source children of one element type (channels T and A share it where their
+  // children agree).  Spectra arenas: 0 = FP32, 1 = FP64.
   struct SupTgt { I3 c; int slot; int child[8]; };
-  struct SupInst { int l, ch; std::vector<SupTgt> tg; I3Map sslot; int64_t pairs = 0; };
+  struct SupInst { int l, ch, k, a; std::vector<SupTgt> tg; I3Map sslot; int64_t pairs = 0; };
+  struct SupSrc { int l, k; std::array<int, 8> children; };
   std::vector<SupInst> sup;
-  std::map<std::array<int, 8>, int> sup_src_of;          // child source slots -> super slot
-  std::vector<std::array<int, 8>> sup_src_children;
-  std::vector<int> sup_src_level;
-  int64_t nsup_src = 0, nsup_tgt = 0;
+  std::map<std::pair<int, std::array<int, 8>>, int> sup_src_of;   // (arena, child slots) -> slot
+  std::vector<SupSrc> sup_src[2];                                  // per arena, by slot
+  int64_t nsup_src[2] = {0, 0}, nsup_tgt[2] = {0, 0};
+  // Super-block spectra of the base level: the base level's type on single-level layouts; FP64
+  // spectra of FP32 blocks (TY_MIX) where the layout has refinement.  Defect correction forms
+  // its residual only where all six neighbours are stored, so it cannot remove FP32 spectral
+  // error at refinement interfaces: a block-smooth error there stays, and the correction spreads
+  // it (by 3-4x in L-inf on the torus layouts), while on a single level only the outer boundary
+  // is excluded.  Coarse octree levels are FP64 throughout.
+  const int tys = (p->fp32 && LR > 1) ? TY_MIX : tyb;
+  auto arena_of = [&](int k) { return (k == 0 && tys == TY_F32) ? 0 : 1; };
+  auto sup_ty = [&](int k) { return k == 0 ? tys : TY_F64; };
+  // per (refinement level, channel, octree level >= 1): sources of the subtracted near part
+  std::map<std::array<int, 3>, I3Map> near_src;
   if (p->super_base) {
     for (int l = 0; l < LR; ++l)
       for (int ch = 0; ch < 2; ++ch) {
         if (ch == 1 && !hasA[l]) continue;
-        const OctLevel& L0 = (ch == 0 ? chT[l] : chA[l]).lv[0];
-        std::unordered_map<I3, std::array<int, 8>, I3Hash> smap, tmap;
-        const std::array<int, 8> none{-1, -1, -1, -1, -1, -1, -1, -1};
-        for (size_t i = 0; i < L0.nodes.size(); ++i) {
-          const I3 par = parent_of(L0.nodes[i]);
-          const int oc = octant_of(L0.nodes[i]);
-          if (L0.is_src[i]) smap.emplace(par, none).first->second[oc] = L0.src_slot[i];
-          if (L0.has_ifft[i]) tmap.emplace(par, none).first->second[oc] = (int)i;
-        }
-        std::vector<I3> keys;
-        for (const auto& kv : tmap) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end());
-        SupInst si;
-        si.l = l;
-        si.ch = ch;
-        for (const I3& T : keys) {
-          SupTgt t;
-          t.c = T;
-          t.slot = (int)nsup_tgt++;
-          const std::array<int, 8>& kids = tmap.at(T);
-          for (int oc = 0; oc < 8; ++oc) t.child[oc] = kids[oc];
-          for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-              for (int dx = -1; dx <= 1; ++dx) {
-                const I3 S{T.x - dx, T.y - dy, T.z - dz};
-                auto it = smap.find(S);
-                if (it == smap.end()) continue;
-                ++si.pairs;
-                if (si.sslot.count(S)) continue;
-                auto q = sup_src_of.find(it->second);
-                if (q == sup_src_of.end()) {
-                  q = sup_src_of.emplace(it->second, (int)nsup_src++).first;
-                  sup_src_children.push_back(it->second);
-                  sup_src_level.push_back(l);
+        const Fmm& F = ch == 0 ? chT[l] : chA[l];
+        for (int k = 0; k < (int)F.lv.size(); ++k) {
+          const OctLevel& L = F.lv[k];
+          const int a = arena_of(k);
+          // base level: every source block is stored; coarse levels: anterpolated sources
+          auto is_source = [&](size_t i) { return k == 0 ? (bool)L.is_src[i] : (bool)L.need_src[i]; };
+          std::unordered_map<I3, std::array<int, 8>, I3Hash> smap, tmap;
+          const std::array<int, 8> none{-1, -1, -1, -1, -1, -1, -1, -1};
+          bool any_tgt = false;
+          for (size_t i = 0; i < L.nodes.size(); ++i) {
+            const I3 par = parent_of(L.nodes[i]);
+            const int oc = octant_of(L.nodes[i]);
+            if (is_source(i)) smap.emplace(par, none).first->second[oc] = L.src_slot[i];
+            if (L.has_ifft[i]) {
+              tmap.emplace(par, none).first->second[oc] = (int)i;
+              any_tgt = true;
+            }
+          }
+          if (!any_tgt) continue;
+          if (k > 0) {
+            I3Map& ns = near_src[{l, ch, k}];
+            for (size_t i = 0; i < L.nodes.size(); ++i)
+              if (is_source(i)) ns[L.nodes[i]] = L.src_slot[i];
+          }
+          std::vector<I3> keys;
+          for (const auto& kv : tmap) keys.push_back(kv.first);
+          std::sort(keys.begin(), keys.end());
+          SupInst si;
+          si.l = l;
+          si.ch = ch;
+          si.k = k;
+          si.a = a;
+          for (const I3& T : keys) {
+            SupTgt t;
+            t.c = T;
+            t.slot = (int)nsup_tgt[a]++;
+            const std::array<int, 8>& kids = tmap.at(T);
+            for (int oc = 0; oc < 8; ++oc) t.child[oc] = kids[oc];
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                  const I3 Sx{T.x - dx, T.y - dy, T.z - dz};
+                  auto it = smap.find(Sx);
+                  if (it == smap.end()) continue;
+                  ++si.pairs;
+                  if (si.sslot.count(Sx)) continue;
+                  const auto key = std::make_pair(a, it->second);
+                  auto q = sup_src_of.find(key);
+                  if (q == sup_src_of.end()) {
+                    q = sup_src_of.emplace(key, (int)nsup_src[a]++).first;
+                    sup_src[a].push_back({l, k, it->second});
+                  }
+                  si.sslot[Sx] = q->second;
                 }
-                si.sslot[S] = q->second;
-              }
-          si.tg.push_back(t);
+            si.tg.push_back(t);
+          }
+          sup.push_back(std::move(si));
         }
-        sup.push_back(std::move(si));
       }
   }
 
@@ -742,21 +807,21 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     LGF_HIP_CHECK(ar.alloc(&d, ntgt[ty] * N3 * es(ty)));
     srcA[ty] = (uint8_t*)a; fhatA[ty] = (uint8_t*)b; uhatA[ty] = (uint8_t*)c; vA[ty] = (uint8_t*)d;
   }
-  const int64_t S2 = spec_size(nb, 0);
-  // Super-block spectra: the base level's type on single-level layouts; FP64 spectra of FP32
-  // blocks (TY_MIX) where the layout has refinement.  Defect correction forms its residual only
-  // where all six neighbours are stored, so it cannot remove FP32 spectral error at refinement
-  // interfaces: a block-smooth error there stays, and the correction spreads it (by 3-4x in
-  // L-inf on the torus layouts), while on a single level only the outer boundary is excluded.
-  const int tys = (p->fp32 && LR > 1) ? TY_MIX : tyb;
-  const int64_t ess = tys == TY_F32 ? 4 : 8;
-  if (p->super_base) {
-    void* b = nullptr;
-    LGF_HIP_CHECK(ar.alloc(&b, (nsup_src + 1) * S2 * 2 * ess));    // last slot: zero spectrum
-    if (!p->dry) LGF_HIP_CHECK(hipMemset(b, 0, (nsup_src + 1) * S2 * 2 * ess));
-    p->sfhat = b;
-    LGF_HIP_CHECK(ar.alloc(&p->suhat, nsup_tgt * S2 * 2 * ess));
+  const int64_t S2 = spec_size(nb, -1);
+  uint8_t* sfhA[2] = {nullptr, nullptr};
+  uint8_t* suhA[2] = {nullptr, nullptr};
+  for (int a = 0; a < 2; ++a) {
+    if (!nsup_tgt[a]) continue;
+    const int64_t ea = a == 0 ? 4 : 8;
+    void *b = nullptr, *c = nullptr;
+    LGF_HIP_CHECK(ar.alloc(&b, (nsup_src[a] + 1) * S2 * 2 * ea));   // last slot: zero spectrum
+    if (!p->dry) LGF_HIP_CHECK(hipMemset(b, 0, (nsup_src[a] + 1) * S2 * 2 * ea));
+    LGF_HIP_CHECK(ar.alloc(&c, nsup_tgt[a] * S2 * 2 * ea));
+    sfhA[a] = (uint8_t*)b;
+    suhA[a] = (uint8_t*)c;
   }
+  p->sfhat = sfhA[arena_of(0)];
+  p->suhat = suhA[arena_of(0)];
   p->src = srcA[tyb];
   p->fhat = fhatA[tyb];
   p->uhat = uhatA[tyb];
@@ -781,16 +846,90 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   auto FH = [&](int ty, int64_t slot) { return (cpx<D>*)(fhatA[ty] + slot * S * 2 * es(ty)); };
   auto UH = [&](int ty, int64_t slot) { return (cpx<D>*)(uhatA[ty] + slot * S * 2 * es(ty)); };
   auto V = [&](int ty, int64_t slot) { return (D*)(vA[ty] + slot * N3 * es(ty)); };
-  auto SFH = [&](int64_t slot) { return (cpx<D>*)((uint8_t*)p->sfhat + slot * S2 * 2 * ess); };
-  auto SUH = [&](int64_t slot) { return (cpx<D>*)((uint8_t*)p->suhat + slot * S2 * 2 * ess); };
+  auto SFH = [&](int a, int64_t slot) { return (cpx<D>*)(sfhA[a] + slot * S2 * 2 * (a == 0 ? 4 : 8)); };
+  auto SUH = [&](int a, int64_t slot) { return (cpx<D>*)(suhA[a] + slot * S2 * 2 * (a == 0 ? 4 : 8)); };
+  // Near rows: W targets along x at x0 = W wx, their 27 neighbours' spectra in groups of 3
+  // non-empty source rows (zero slot where absent).  All rows of one call share fhat/uhat/kptr.
+  auto make_rows = [&](const std::vector<std::pair<I3, int>>& tg, const I3Map& srcs, int zero, int W,
+                       const cpx<D>* fhat, cpx<D>* uhat, const c64* const* kptr,
+                       std::vector<NearRow<D>>& out) {
+    std::map<I3, size_t> row_of;
+    for (const auto& t : tg) {
+      const int wx = floordiv(t.first.x, W);
+      const I3 key{wx, t.first.y, t.first.z};
+      auto it = row_of.find(key);
+      if (it == row_of.end()) {
+        NearRow<D> r{};
+        for (int i = 0; i < kMacL; ++i) r.tgt[i] = -1;
+        int nl = 0;                      // listed (non-empty) source rows
+        for (int pj = 0; pj < 9; ++pj) {
+          const int dz = pj / 3 - 1, dy = pj % 3 - 1;
+          int slots[kNearSlots];
+          bool any = false;
+          for (int q = 0; q < kNearSlots; ++q) {
+            auto sit = q < W + 2 ? srcs.find({wx * W - 1 + q, t.first.y - dy, t.first.z - dz}) : srcs.end();
+            slots[q] = sit != srcs.end() ? sit->second : zero;
+            any |= sit != srcs.end();
+          }
+          if (!any) continue;
+          for (int q = 0; q < kNearSlots; ++q) r.src[nl][q] = slots[q];
+          r.pj_code |= (uint64_t)pj << (4 * nl++);
+        }
+        for (int q = nl; q < 9; ++q)     // padding rows read the zero spectrum
+          for (int x = 0; x < kNearSlots; ++x) r.src[q][x] = zero;
+        r.ngroups = (nl + 2) / 3;
+        r.fhat = fhat;
+        r.uhat = uhat;
+        r.kptr = kptr;
+        it = row_of.emplace(key, out.size()).first;
+        out.push_back(r);
+      }
+      out[it->second].tgt[t.first.x - wx * W] = t.second;
+    }
+  };
+  // Near tiles: 2 x 2 rows of kTileW targets sharing their 4 x 4 source rows (staged in LDS)
+  auto make_tiles = [&](const std::vector<std::pair<I3, int>>& tg, const I3Map& srcs, int zero,
+                        const cpx<D>* fhat, cpx<D>* uhat, const cpx<D>* const* kptr,
+                        std::vector<NearTile<D>>& out) {
+    std::map<I3, size_t> tile_of;
+    for (const auto& t : tg) {
+      const int wx = floordiv(t.first.x, kTileW), ty2 = floordiv(t.first.y, 2), tz2 = floordiv(t.first.z, 2);
+      const I3 key{wx, ty2, tz2};
+      auto it = tile_of.find(key);
+      if (it == tile_of.end()) {
+        NearTile<D> q{};
+        for (int r = 0; r < 4; ++r)
+          for (int i = 0; i < kMacL; ++i) q.tgt[r][i] = -1;
+        for (int qz = 0; qz < 4; ++qz)
+          for (int qy = 0; qy < 4; ++qy)
+            for (int x = 0; x < kTileW + 2; ++x) {
+              auto sit = srcs.find({wx * kTileW - 1 + x, 2 * ty2 - 1 + qy, 2 * tz2 - 1 + qz});
+              q.src[(qy + 4 * qz) * (kTileW + 2) + x] = sit != srcs.end() ? sit->second : zero;
+              if (sit != srcs.end()) q.src_mask |= 1u << (qy + 4 * qz);
+            }
+        q.fhat = fhat;
+        q.uhat = uhat;
+        q.kptr = kptr;
+        it = tile_of.emplace(key, out.size()).first;
+        out.push_back(q);
+      }
+      const int r = (t.first.y - 2 * ty2) + 2 * (t.first.z - 2 * tz2);
+      out[it->second].tgt[r][t.first.x - wx * kTileW] = t.second;
+      out[it->second].row_mask |= 1u << r;
+    }
+  };
   auto JW = [&](int64_t blk) { return (double*)p->jw + blk * N3; };
   auto WW = [&](int64_t blk) { return (double*)p->w + blk * N3; };
 
   HostItems hi;
   std::vector<PendingStep> steps, rsteps;
+  // chain: 0 before the level's fork, 1 base-level super-block path, 2 far field, 3 after the
+  // join (see run_steps); -1 derives it from the phase
   auto push = [&](std::vector<PendingStep>& dst, int l, int phase, int sub, int kind, int ty, size_t off,
-                  size_t count, const double* wt, int64_t work = 0, int mode = 0) {
-    if (count) dst.push_back({l, phase, sub, kind, ty, off, (int32_t)count, wt, work, mode});
+                  size_t count, const double* wt, int64_t work = 0, int mode = 0, int chain = -1) {
+    if (chain < 0)
+      chain = phase <= 1 ? 0 : (phase >= 7 || (kind == K_INTERP && sub == 100)) ? 3 : 2;
+    if (count) dst.push_back({l, phase, sub, kind, ty, off, (int32_t)count, wt, work, mode, chain});
   };
 
   // coarsening (before level 0), bottom-up over levels
@@ -883,7 +1022,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       for (size_t k = 0; k < F.lv.size(); ++k) {
         OctLevel& L = F.lv[k];
         const int ty = ty_of((int)k);
-        const bool blockwise = !(k == 0 && p->super_base);
+        const bool blockwise = !p->super_base;
         for (size_t i = 0; i < L.nodes.size(); ++i) {
           if (blockwise && L.referenced[i] && !fwd_done[ty][L.src_slot[i]]) {
             fwd_done[ty][L.src_slot[i]] = 1;
@@ -901,7 +1040,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         }
       }
       for (const TileDesc& rd : F.rows) {
-        if (rd.k == 0 && p->super_base) continue;
+        if (p->super_base) continue;
         const SpecSet* ss = nullptr;
         LGF_HIP_CHECK(plan_spectra(p, nb, 1 << rd.k, &ss));
         OctLevel& L = F.lv[rd.k];
@@ -941,133 +1080,104 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k]);
     }
     if (p->super_base) {
-      // super-block transforms and rows of this refinement level (phases of the block FFTs/MAC)
-      std::vector<SuperFwdItem<D>> sf;
-      for (int64_t q = 0; q < nsup_src; ++q) {
-        if (sup_src_level[q] != l) continue;
-        SuperFwdItem<D> it{};
-        for (int oc = 0; oc < 8; ++oc) {
-          const int sl = sup_src_children[q][oc];
-          it.child[oc] = sl >= 0 ? SRC(tyb, sl) : nullptr;
-        }
-        it.dst = SFH(q);
-        it.tmp = it.dst;                 // the z pass transforms the plane stack in place
-        sf.push_back(it);
-      }
-      const SpecSet* ns = nullptr;
-      LGF_HIP_CHECK(plan_spectra(p, nb, 0, &ns));
-      // rows of W targets along x; W in {4, 8} by a cost model of the kernel's executed work per
-      // non-empty source row (3 W complex multiply-adds, W + 2 spectrum loads)
-      auto build_rows = [&](int W, std::vector<NearRow<D>>* out) {
-        double cost = 0.0;
-        for (const SupInst& si : sup) {
-          if (si.l != l) continue;
-          std::map<I3, size_t> row_of;
-          size_t first = out ? out->size() : 0;
-          std::vector<NearRow<D>> local;
-          std::vector<NearRow<D>>& dst = out ? *out : local;
-          for (const SupTgt& t : si.tg) {
-            const int wx = floordiv(t.c.x, W);
-            const I3 key{wx, t.c.y, t.c.z};
-            auto it = row_of.find(key);
-            if (it == row_of.end()) {
-              NearRow<D> r{};
-              for (int i = 0; i < kMacL; ++i) r.tgt[i] = -1;
-              int nl = 0;                  // listed (non-empty) source rows
-              for (int pj = 0; pj < 9; ++pj) {
-                const int dz = pj / 3 - 1, dy = pj % 3 - 1;
-                int slots[kNearSlots];
-                bool any = false;
-                for (int q = 0; q < kNearSlots; ++q) {
-                  auto sit = q < W + 2 ? si.sslot.find({wx * W - 1 + q, t.c.y - dy, t.c.z - dz}) : si.sslot.end();
-                  slots[q] = sit != si.sslot.end() ? sit->second : (int)nsup_src;
-                  any |= sit != si.sslot.end();
-                }
-                if (!any) continue;
-                for (int q = 0; q < kNearSlots; ++q) r.src[nl][q] = slots[q];
-                r.pj_code |= (uint64_t)pj << (4 * nl++);
-              }
-              for (int q = nl; q < 9; ++q)         // padding rows read the zero spectrum
-                for (int x = 0; x < kNearSlots; ++x) r.src[q][x] = (int)nsup_src;
-              r.ngroups = (nl + 2) / 3;
-              r.fhat = SFH(0);
-              r.uhat = SUH(0);
-              r.kptr = ns->kp64;
-              it = row_of.emplace(key, dst.size()).first;
-              dst.push_back(r);
-            }
-            dst[it->second].tgt[t.c.x - wx * W] = t.slot;
+      // Per octree level k (one kernel set per step): super-block transforms, near rows and
+      // inverse transforms; at k >= 1 also the near part on the block grid, subtracted from the
+      // super-block result by the block inverse transforms after every super-block inverse.
+      std::vector<FftFwdItem<D>> nfwd;
+      std::vector<FftInvItem<D>> ninv;
+      std::vector<char> nfwd_done(nsrc[TY_F64], 0);
+      for (int k = 0; k < K; ++k) {
+        const int a = arena_of(k), sty = sup_ty(k);
+        const int chain = k == 0 ? 1 : 2;
+        std::vector<SuperFwdItem<D>> sf;
+        for (size_t q = 0; q < sup_src[a].size(); ++q) {
+          const SupSrc& ss = sup_src[a][q];
+          if (ss.l != l || ss.k != k) continue;
+          SuperFwdItem<D> it{};
+          for (int oc = 0; oc < 8; ++oc) {
+            const int sl = ss.children[oc];
+            it.child[oc] = sl >= 0 ? SRC(ty_of(k), sl) : nullptr;
           }
-          for (size_t q = first; q < dst.size(); ++q)
-            cost += 3.0 * dst[q].ngroups * (12.0 * W + 4.0 * (W + 2));
+          it.dst = SFH(a, (int64_t)q);
+          it.tmp = it.dst;                 // the z pass transforms the plane stack in place
+          sf.push_back(it);
         }
-        return cost;
-      };
-      // FP64 storage holds two groups of 10 spectra per lane only at W = 4
-      const int width = (tys != TY_F32 || build_rows(4, nullptr) <= build_rows(8, nullptr)) ? 4 : 8;
-      std::vector<NearRow<D>> nr;
-      std::vector<NearTile<D>> nt;
-      const bool tiled = tys == TY_F32;       // FP32 storage: 2 x 2 rows of 4 share staged sources
-      if (tiled) {
+        const SpecSet* ns = nullptr;
+        LGF_HIP_CHECK(plan_spectra(p, nb, -(1 << k), &ns));     // super-block kernels, scale 2^k
+        std::vector<NearRow<D>> nr;
+        std::vector<NearTile<D>> nt;
+        std::vector<SuperInvItem<D>> si_items;
+        int64_t pairs = 0;
+        const bool tiled = sty == TY_F32;      // FP32 storage: 2 x 2 rows of 4 share staged sources
         for (const SupInst& si : sup) {
-          if (si.l != l) continue;
-          std::map<I3, size_t> tile_of;
+          if (si.l != l || si.k != k) continue;
+          pairs += si.pairs;
+          std::vector<std::pair<I3, int>> tg;
+          for (const SupTgt& t : si.tg) tg.push_back({t.c, t.slot});
+          if (tiled)
+            make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0),
+                       (const cpx<D>* const*)ns->kp32, nt);
+          else
+            make_rows(tg, si.sslot, (int)nsup_src[a], 4, SFH(a, 0), SUH(a, 0), ns->kp64, nr);
+          const OctLevel& L = (si.ch == 0 ? chT[l] : chA[l]).lv[k];
           for (const SupTgt& t : si.tg) {
-            const int wx = floordiv(t.c.x, kTileW), ty2 = floordiv(t.c.y, 2), tz2 = floordiv(t.c.z, 2);
-            const I3 key{wx, ty2, tz2};
-            auto it = tile_of.find(key);
-            if (it == tile_of.end()) {
-              NearTile<D> q{};
-              for (int r = 0; r < 4; ++r)
-                for (int i = 0; i < kMacL; ++i) q.tgt[r][i] = -1;
-              q.src_mask = 0;
-              q.row_mask = 0;
-              for (int qz = 0; qz < 4; ++qz)
-                for (int qy = 0; qy < 4; ++qy)
-                  for (int x = 0; x < kTileW + 2; ++x) {
-                    auto sit = si.sslot.find({wx * kTileW - 1 + x, 2 * ty2 - 1 + qy, 2 * tz2 - 1 + qz});
-                    q.src[(qy + 4 * qz) * (kTileW + 2) + x] = sit != si.sslot.end() ? sit->second : (int)nsup_src;
-                    if (sit != si.sslot.end()) q.src_mask |= 1u << (qy + 4 * qz);
+            SuperInvItem<D> v{};
+            v.src = SUH(a, t.slot);
+            v.tmp = SUH(a, t.slot);          // the z pass transforms the spectrum in place
+            for (int oc = 0; oc < 8; ++oc)
+              v.child[oc] = t.child[oc] >= 0 ? V(ty_of(k), L.tgt_slot[t.child[oc]]) : nullptr;
+            si_items.push_back(v);
+          }
+        }
+        p->n_sup_fwd += (int64_t)sf.size();
+        p->n_sup_inv += (int64_t)si_items.size();
+        p->n_near_rows += (int64_t)(tiled ? 4 * nt.size() : nr.size());
+        p->near_pairs += pairs;
+        push(steps, l, 3, k, K_SUP_FWD, sty, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size(), 0, chain);
+        if (tiled)
+          push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt), nt.size(), nullptr, pairs, kNearTiled + 4, chain);
+        else
+          push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
+        push(steps, l, 5, k, K_SUP_INV, sty, hi.add(si_items), si_items.size(), nullptr,
+             (int64_t)si_items.size(), 0, chain);
+        if (k == 0) continue;
+        // near part on the block grid at scale 2^k: rows of target blocks, 27 neighbours each
+        const SpecSet* bs = nullptr;
+        LGF_HIP_CHECK(plan_spectra(p, nb, 1 << k, &bs));
+        std::vector<NearRow<D>> br;
+        int64_t bpairs = 0;
+        for (int ch = 0; ch < 2; ++ch) {
+          auto nit = near_src.find({l, ch, k});
+          if (nit == near_src.end()) continue;
+          const I3Map& srcs = nit->second;
+          const OctLevel& L = (ch == 0 ? chT[l] : chA[l]).lv[k];
+          std::vector<std::pair<I3, int>> tg;
+          for (size_t i = 0; i < L.nodes.size(); ++i) {
+            if (!L.has_ifft[i]) continue;
+            tg.push_back({L.nodes[i], L.tgt_slot[i]});
+            ninv.push_back({UH(TY_F64, L.tgt_slot[i]), V(TY_F64, L.tgt_slot[i]), -1, 0});
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                  auto sit = srcs.find({L.nodes[i].x - dx, L.nodes[i].y - dy, L.nodes[i].z - dz});
+                  if (sit == srcs.end()) continue;
+                  ++bpairs;
+                  if (!nfwd_done[sit->second]) {
+                    nfwd_done[sit->second] = 1;
+                    nfwd.push_back({SRC(TY_F64, sit->second), FH(TY_F64, sit->second)});
                   }
-              q.fhat = SFH(0);
-              q.uhat = SUH(0);
-              q.kptr = (const cpx<D>* const*)ns->kp32;     // FP32 tiles: FP32 kernel spectra
-              it = tile_of.emplace(key, nt.size()).first;
-              nt.push_back(q);
-            }
-            const int r = (t.c.y - 2 * ty2) + 2 * (t.c.z - 2 * tz2);
-            nt[it->second].tgt[r][t.c.x - wx * kTileW] = t.slot;
-            nt[it->second].row_mask |= 1u << r;
+                }
           }
+          make_rows(tg, srcs, (int)nsrc[TY_F64], 4, FH(TY_F64, 0), UH(TY_F64, 0), bs->near64, br);
         }
-      } else {
-        build_rows(width, &nr);
+        p->n_near_rows += (int64_t)br.size();
+        push(steps, l, 4, k, K_NEAR_MAC, TY_F64, hi.add(br), br.size(), nullptr, bpairs, kNearBlock + 4, 2);
       }
-      std::vector<SuperInvItem<D>> si_items;
-      int64_t pairs = 0;
-      for (const SupInst& si : sup) {
-        if (si.l != l) continue;
-        pairs += si.pairs;
-        const OctLevel& L0 = (si.ch == 0 ? chT[l] : chA[l]).lv[0];
-        for (const SupTgt& t : si.tg) {
-          SuperInvItem<D> v{};
-          v.src = SUH(t.slot);
-          v.tmp = SUH(t.slot);             // the z pass transforms the spectrum in place
-          for (int oc = 0; oc < 8; ++oc)
-            v.child[oc] = t.child[oc] >= 0 ? V(tyb, L0.tgt_slot[t.child[oc]]) : nullptr;
-          si_items.push_back(v);
-        }
-      }
-      p->n_sup_fwd += (int64_t)sf.size();
-      p->n_sup_inv += (int64_t)si_items.size();
-      p->n_near_rows += (int64_t)(tiled ? 4 * nt.size() : nr.size());
-      p->near_pairs += pairs;
-      push(steps, l, 3, 0, K_SUP_FWD, tys, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size());
-      if (tiled)
-        push(steps, l, 4, 0, K_NEAR_MAC, tys, hi.add(nt), nt.size(), nullptr, pairs, kNearTiled + 4);
-      else
-        push(steps, l, 4, 0, K_NEAR_MAC, tys, hi.add(nr), nr.size(), nullptr, pairs, width);
-      push(steps, l, 5, 0, K_SUP_INV, tys, hi.add(si_items), si_items.size(), nullptr, (int64_t)si_items.size());
+      p->n_fwd += (int64_t)nfwd.size();
+      p->n_inv += (int64_t)ninv.size();
+      push(steps, l, 3, 0, K_FWD, TY_F64, hi.add(nfwd), nfwd.size(), nullptr, (int64_t)nfwd.size(), 0, 2);
+      // after every super-block inverse (subs 0 .. K-1) of this level
+      push(steps, l, 5, 50, K_INV, TY_F64, hi.add(ninv), ninv.size(), nullptr, (int64_t)ninv.size(), 0, 2);
     }
     for (int k = 1; k < K; ++k) {
       const int ty = (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
@@ -1121,9 +1231,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 
   // every item must stay inside the plan's device ranges before anything is launched
   {
-    SlotCounts sc{{nsrc[0], nsrc[1]}, {ntgt[0], ntgt[1]}, {0, 0}, {0, 0}};
-    sc.nsup_src[tys == TY_F32 ? 0 : 1] = nsup_src;
-    sc.nsup_tgt[tys == TY_F32 ? 0 : 1] = nsup_tgt;
+    SlotCounts sc{{nsrc[0], nsrc[1]}, {ntgt[0], ntgt[1]}, {nsup_src[0], nsup_src[1]},
+                  {nsup_tgt[0], nsup_tgt[1]}};
     for (const auto* list : {&steps, &rsteps})
       for (const PendingStep& st : *list)
         if (!validate_step(p, st.kind, st.ty, st.mode, hi.buf.data() + st.off, st.count, n, sc, err))
@@ -1136,15 +1245,18 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   p->d_items = d_items;
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
     for (const PendingStep& s : in)
-      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work, s.mode});
+      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work,
+                     s.mode, s.chain});
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
   std::set<int> used;
   for (int l = 0; l < LR; ++l)
     for (const TileDesc& rd : chT[l].rows) used.insert(rd.k);
+  // spectra referenced: per octree level with interactions, the 27 super-block kernels (plus the
+  // 27 near block kernels at coarse levels), or the block kernels of the lists
   p->n_spectra = 0;
-  for (int k : used) p->n_spectra += k == 0 ? (p->super_base ? 27 : 343) : 316;
+  for (int k : used) p->n_spectra += p->super_base ? (k == 0 ? 27 : 54) : (k == 0 ? 343 : 316);
   (void)err;
   return hipSuccess;
 }
@@ -1290,12 +1402,7 @@ hipError_t profile_collect(std::vector<ProfileEntry>* out) {
 // stream beside them: fork after the level's sources are formed, join before the base-level
 // interpolation.  Chains: 0 before the fork, 1 base path (second stream), 2 far field, 3 after.
 namespace {
-int chain_of(const Ref& r) {
-  if (r.phase <= 1) return 0;
-  if (r.kind == K_SUP_FWD || r.kind == K_NEAR_MAC || r.kind == K_SUP_INV) return 1;
-  if (r.phase >= 7 || (r.kind == K_INTERP && r.sub == 100)) return 3;
-  return 2;
-}
+int chain_of(const Ref& r) { return r.step->chain; }
 
 // one second stream per (thread, device), default priority, and a reusable event pool
 struct ForkRes {

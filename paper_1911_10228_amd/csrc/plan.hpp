@@ -17,8 +17,8 @@ namespace lgf {
 
 // ----------------------------------------------------------------------------- device context
 // Kernel spectra of one block size and level scale.  s >= 1: the 343 offsets |d| <= 3 of blocks of
-// nb cells at lattice scale s, index (dz+3)*49+(dy+3)*7+(dx+3).  s == 0: the 27 neighbour offsets
-// |d| <= 1 of base-level super-blocks of 2 nb cells, index (dz+1)*9+(dy+1)*3+(dx+1).
+// nb cells at lattice scale s, index (dz+3)*49+(dy+3)*7+(dx+3).  s <= -1: the 27 neighbour
+// offsets |d| <= 1 of super-blocks of 2 nb cells at scale -s, index (dz+1)*9+(dy+1)*3+(dx+1).
 struct SpecSet {
   int nb = 0, s = 0;
   int count = 0;                       // 343 or 27
@@ -27,6 +27,7 @@ struct SpecSet {
   c32* d32 = nullptr;
   const c64** kp64 = nullptr;          // device arrays of count pointers
   const c32** kp32 = nullptr;
+  const c64** near64 = nullptr;        // block sets: the 27 offsets |d| <= 1, index (dz+1)*9+(dy+1)*3+dx+1
 };
 
 struct DeviceCtx {
@@ -57,6 +58,8 @@ struct Step {
   const double* w;                     // weight table for the kernel (or nullptr)
   int64_t work;                        // MAC: block interactions in the step (for flop counts)
   int mode;                            // MAC launch shape chosen by the autotuner (0: default)
+  int chain;                           // 0 before the level's fork, 1 base super-block path,
+                                       // 2 far field, 3 after the join
 };
 
 // Optional launch timing: when enabled, every launch is bracketed by HIP events on its stream

@@ -102,43 +102,72 @@ def test_torus_layout_validates():
 
 
 def super_counts(blocks, levels):
-    """Base-level super-block bookkeeping written out from the block lists: per refinement level
-    and channel, the target super-blocks are the parents of target blocks that have a source
-    block among the children of their parent's 27 neighbours; each pairs with every such
-    neighbour that holds a source child.  A source super-block transform is shared where two
-    channels have the same source children."""
+    """Super-block bookkeeping written out from the octree lists (oracle.tree): per refinement
+    level, channel and octree level k, the target super-blocks are the parents of target nodes
+    with interactions (N(B) + I(B) at the base level, I(B) above), each pairs with every
+    neighbouring super-block holding a source child; the source children are the source blocks
+    at the base level and, above it, the nodes whose anterpolated source is formed (referenced
+    by an influence list, or below such a node).  A source super-block transform is shared where
+    the two channels have the same base-level source children."""
+    from oracle import tree
     blocks = np.asarray(blocks)
     levels = np.asarray(levels)
     have = {(int(l),) + tuple(int(v) for v in b) for b, l in zip(blocks, levels)}
-    leaf = [(int(l) + 1,) + tuple(int(v) for v in 2 * b) not in have for b, l in zip(blocks, levels)]
+    leaf = np.array([(int(l) + 1,) + tuple(int(v) for v in 2 * b) not in have
+                     for b, l in zip(blocks, levels)])
+    nbrs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
     n_tgt = pairs = 0
     src_sets = set()
     for l in range(int(levels.max()) + 1):
-        ids = [i for i in range(len(blocks)) if levels[i] == l]
-        chans = [([True] * len(ids), [True] * len(ids))]
-        if not all(leaf[i] for i in ids):
-            chans.append(([leaf[i] for i in ids], [not leaf[i] for i in ids]))
-        for is_src, is_tgt in chans:
-            kids = {}
-            for a, i in enumerate(ids):
-                if is_src[a]:
-                    b = tuple(int(v) for v in blocks[i])
+        ids = np.nonzero(levels == l)[0]
+        tl = tree.build_levels(blocks[ids])
+        chans = [(np.ones(len(ids), bool), np.ones(len(ids), bool))]
+        if not leaf[ids].all():
+            chans.append((leaf[ids].copy(), ~leaf[ids]))
+        for ch, (src0, tgt0) in enumerate(chans):
+            # flags per octree level
+            srcs, tgts = [src0], [tgt0]
+            pars = []
+            for k in range(len(tl) - 1):
+                pidx = tree.index_of(tl[k + 1])
+                par = np.array([pidx[tuple(int(v) for v in q)] for q in tree.parent_of(tl[k])])
+                pars.append(par)
+                s2 = np.zeros(len(tl[k + 1]), bool)
+                t2 = np.zeros(len(tl[k + 1]), bool)
+                s2[par[srcs[k]]] = True
+                t2[par[tgts[k]]] = True
+                srcs.append(s2)
+                tgts.append(t2)
+            has_ifft, referenced = [], []
+            for k, nodes in enumerate(tl):
+                h = np.zeros(len(nodes), bool)
+                r = np.zeros(len(nodes), bool)
+                for t, s_ in tree.interactions(nodes, base=(k == 0)):
+                    if tgts[k][t] and srcs[k][s_]:
+                        h[t] = True
+                        r[s_] = True
+                has_ifft.append(h)
+                referenced.append(r)
+            need = [None] * len(tl)
+            for k in range(len(tl) - 1, -1, -1):
+                up = need[k + 1][pars[k]] if k + 1 < len(tl) else np.zeros(len(tl[k]), bool)
+                need[k] = srcs[k] & (referenced[k] | up)
+            for k, nodes in enumerate(tl):
+                use = srcs[k] if k == 0 else need[k]
+                kids = {}
+                for i in np.nonzero(use)[0]:
+                    b = tuple(int(v) for v in nodes[i])
                     kids.setdefault(tuple(v // 2 for v in b), set()).add(b)
-            nbrs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-            tgts = set()
-            for a, i in enumerate(ids):
-                if not is_tgt[a]:
-                    continue
-                T = tuple(int(v) // 2 for v in blocks[i])
-                if any(tuple(t - d for t, d in zip(T, D)) in kids for D in nbrs):
-                    tgts.add(T)
-            n_tgt += len(tgts)
-            for T in tgts:
-                for D in nbrs:
-                    S = tuple(t - d for t, d in zip(T, D))
-                    if S in kids:
-                        pairs += 1
-                        src_sets.add((l, frozenset(kids[S])))
+                tsup = {tuple(int(v) // 2 for v in nodes[i]) for i in np.nonzero(has_ifft[k])[0]}
+                n_tgt += len(tsup)
+                for T in tsup:
+                    for D in nbrs:
+                        S = tuple(t - d for t, d in zip(T, D))
+                        if S in kids:
+                            pairs += 1
+                            # base sources are shared by the channels; above, each channel
+                            # anterpolates its own
+                            src_sets.add((l, k, ch if k > 0 else -1, frozenset(kids[S])))
     return n_tgt, pairs, len(src_sets)
 
 
