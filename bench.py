@@ -104,7 +104,7 @@ def bench_torus(lgf, workloads, torch, stream, steps, warmup, dc):
     out = {"layout": f"{L.name}, {len(L.blocks)} blocks", "unknowns": L.unknowns}
     res = {}
     for name, prec, k in (("fp32_dc", lgf.LGF_FP32_REFINE, dc), ("fp64_plain", lgf.LGF_FP64_PLAIN, 0)):
-        p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, prec, k)
+        p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, prec, k, autotune=1)
         u = torch.zeros_like(f)
         dt = time_solves(p, f, u, steps, warmup, torch, stream)
         res[name] = u.cpu().numpy()
@@ -225,9 +225,10 @@ def main():
     u32 = torch.zeros_like(f)
     u64 = torch.zeros_like(f)
     u0 = torch.zeros_like(f)
-    p32 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, args.dc)
-    p64 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP64_PLAIN, 0)
-    p0 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, 0)
+    # launch shapes chosen by the plan-time autotuner
+    p32 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, args.dc, autotune=1)
+    p64 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP64_PLAIN, 0, autotune=1)
+    p0 = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, lgf.LGF_FP32_REFINE, 0, autotune=1)
     info = p32.info()
     print(f"# plan: {info}", file=sys.stderr, flush=True)
 

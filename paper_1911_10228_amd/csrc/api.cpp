@@ -93,7 +93,7 @@ lgf_status lgf_plan_check(const int32_t* blocks, const int32_t* levels, int64_t 
   lgf::Plan* p = nullptr;
   std::string err;
   hipError_t e = lgf::plan_build(blocks, levels, n, N_b, interp_order, o.precision == LGF_FP32_REFINE,
-                                 o.dc_iters, o.hbm_budget, &p, &err, /*dry=*/true, false,
+                                 o.dc_iters, o.hbm_budget, &p, &err, /*dry=*/true, o.autotune != 0,
                                  o.base_level == LGF_BASE_SUPER);
   if (e != hipSuccess) {
     if (!err.empty()) std::fprintf(stderr, "lgf_plan_check: %s\n", err.c_str());

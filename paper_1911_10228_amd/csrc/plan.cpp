@@ -922,7 +922,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   auto WW = [&](int64_t blk) { return (double*)p->w + blk * N3; };
 
   HostItems hi;
-  std::vector<PendingStep> steps, rsteps;
+  std::vector<PendingStep> steps, rsteps, alt_steps;
+  std::vector<size_t> alt_of;                    // primary step index of each alternative
   // chain: 0 before the level's fork, 1 base-level super-block path, 2 far field, 3 after the
   // join (see run_steps); -1 derives it from the phase
   auto push = [&](std::vector<PendingStep>& dst, int l, int phase, int sub, int kind, int ty, size_t off,
@@ -1134,10 +1135,27 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         p->n_near_rows += (int64_t)(tiled ? 4 * nt.size() : nr.size());
         p->near_pairs += pairs;
         push(steps, l, 3, k, K_SUP_FWD, sty, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size(), 0, chain);
+        const size_t primary = steps.size();
         if (tiled)
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt), nt.size(), nullptr, pairs, kNearTiled + 4, chain);
         else
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
+        if (p->tune && steps.size() > primary) {
+          // the other launch shapes for the autotuner: rows of 4 or 8 targets (FP32 also tiles)
+          for (int shape : {4, 8}) {
+            if (!tiled && shape == 4) continue;
+            std::vector<NearRow<D>> alt_rows;
+            for (const SupInst& si : sup) {
+              if (si.l != l || si.k != k) continue;
+              std::vector<std::pair<I3, int>> tg;
+              for (const SupTgt& t : si.tg) tg.push_back({t.c, t.slot});
+              make_rows(tg, si.sslot, (int)nsup_src[a], shape, SFH(a, 0), SUH(a, 0), ns->kp64, alt_rows);
+            }
+            push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(alt_rows), alt_rows.size(), nullptr, pairs, shape,
+                 chain);
+            alt_of.push_back(primary);
+          }
+        }
         push(steps, l, 5, k, K_SUP_INV, sty, hi.add(si_items), si_items.size(), nullptr,
              (int64_t)si_items.size(), 0, chain);
         if (k == 0) continue;
@@ -1233,7 +1251,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   {
     SlotCounts sc{{nsrc[0], nsrc[1]}, {ntgt[0], ntgt[1]}, {nsup_src[0], nsup_src[1]},
                   {nsup_tgt[0], nsup_tgt[1]}};
-    for (const auto* list : {&steps, &rsteps})
+    for (const auto* list : {&steps, &rsteps, &alt_steps})
       for (const PendingStep& st : *list)
         if (!validate_step(p, st.kind, st.ty, st.mode, hi.buf.data() + st.off, st.count, n, sc, err))
           return hipErrorInvalidValue;
@@ -1250,6 +1268,11 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
+  {
+    std::vector<Step> alts;
+    fin(alt_steps, alts);
+    for (size_t i = 0; i < alts.size(); ++i) p->alt.push_back({alt_of[i], alts[i]});
+  }
   std::set<int> used;
   for (int l = 0; l < LR; ++l)
     for (const TileDesc& rd : chT[l].rows) used.insert(rd.k);
@@ -1270,6 +1293,7 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
                       bool autotune, bool super_base) {
   Plan* p = new Plan();
   p->super_base = super_base;
+  p->tune = autotune;
   p->nb = nb;
   p->n_i = n_i;
   p->fp32 = fp32;
@@ -1608,10 +1632,12 @@ hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st) {
 }
 
 // ----------------------------------------------------------------------------- autotuner
-// Chooses the MAC launch shape of every MAC step of a plan by timing each candidate on the
-// plan's own work items (3 repetitions, median), remembering the choice per (N_b, element type,
-// tile count) for the process and in the file named by LGF_TUNE_CACHE (one "nb ty tiles mode"
-// line per entry).
+// Chooses the launch shape of every MAC step of a plan by timing each candidate on the plan's
+// own work items (3 repetitions, median): the tile MAC's shapes (rows per wavefront, source-row
+// split) and the near MAC's (rows of 4 or 8 targets, 2 x 2-row tiles; the planner builds each
+// shape's items).  The choice is remembered per (N_b, element type, tile count or pair count)
+// for the process and in the file named by LGF_TUNE_CACHE (one "nb key count mode" line per
+// entry).
 namespace {
 std::mutex g_tune_mu;
 std::map<std::array<int64_t, 3>, int> g_tune;
@@ -1680,6 +1706,45 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
       s.mode = best_mode;
       tune_store(key, best_mode);
     }
+  }
+  // near MAC: the planner built the other launch shapes with their own items; time each
+  // (median of 3) and keep the fastest in the pass
+  std::map<size_t, std::vector<Step>> groups;
+  for (const auto& pa : p->alt) groups[pa.first].push_back(pa.second);
+  for (auto& g : groups) {
+    Step& prim = p->pass[g.first];
+    std::vector<Step> cands{prim};
+    for (const Step& x : g.second) cands.push_back(x);
+    const std::array<int64_t, 3> key{p->nb, 1000 + prim.ty, prim.work};
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      for (const Step& c : cands)
+        if (c.mode == it->second) prim = c;
+      continue;
+    }
+    float best = 1e30f;
+    size_t best_i = 0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      float t[3];
+      for (int rep = 0; rep < 3; ++rep) {
+        SetTable tab;
+        tab.n = 1;
+        tab.pad = 0;
+        tab.s[0] = WorkSet{cands[c].items, 0, cands[c].count, 0, nullptr, nullptr, cands[c].w};
+        LGF_HIP_CHECK(hipEventRecord(a, st));
+        LGF_HIP_CHECK(launch_typed(cands[c].kind, cands[c].ty, p->nb, tab, st, cands[c].mode));
+        LGF_HIP_CHECK(hipEventRecord(b, st));
+        LGF_HIP_CHECK(hipEventSynchronize(b));
+        LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
+      }
+      std::sort(t, t + 3);
+      if (t[1] < best) {
+        best = t[1];
+        best_i = c;
+      }
+    }
+    prim = cands[best_i];
+    tune_store(key, prim.mode);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

@@ -80,7 +80,10 @@ struct Plan {
   int64_t nblocks = 0;
   DeviceCtx* ctx = nullptr;
 
+  bool tune = false;                   // build launch-shape alternatives for the autotuner
   std::vector<Step> pass;              // one solve pass: input field -> output field
+  // alternatives of a pass step (index into pass) with another launch shape and its own items
+  std::vector<std::pair<size_t, Step>> alt;
   std::vector<Step> residual;          // r = f - L u (FP32 refine only)
 
   // owned device memory

@@ -167,12 +167,13 @@ class Plan:
 
 
 def plan_check(blocks, levels, n_b: int, interp_order: int, precision: int = LGF_FP64_PLAIN,
-               dc_iters: int = 0, base_level: int = 0) -> dict:
-    """Host-only plan build with validation of every kernel work item (no GPU needed)."""
+               dc_iters: int = 0, base_level: int = 0, autotune: int = 0) -> dict:
+    """Host-only plan build with validation of every kernel work item, including the launch-shape
+    alternatives the autotuner would time (no GPU needed)."""
     b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
     lv = np.ascontiguousarray(np.zeros(len(b), np.int32) if levels is None
                               else np.asarray(levels, dtype=np.int32).reshape(-1))
-    opt = Options(precision, dc_iters, 0, base_level, 0)
+    opt = Options(precision, dc_iters, autotune, base_level, 0)
     inf = PlanInfo()
     _check(load().lgf_plan_check(b.ctypes.data, lv.ctypes.data, len(b), n_b, interp_order,
                                  C.byref(opt), C.byref(inf)), "lgf_plan_check")

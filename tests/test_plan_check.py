@@ -54,11 +54,11 @@ LAYOUTS = {
 
 
 @pytest.mark.parametrize("name", sorted(LAYOUTS))
-@pytest.mark.parametrize("precision,dc", [(0, 0), (1, 0), (1, 2)])
-def test_uniform_layouts_validate_and_count(name, precision, dc):
+@pytest.mark.parametrize("precision,dc,tune", [(0, 0, 0), (1, 0, 1), (1, 2, 0), (0, 0, 1)])
+def test_uniform_layouts_validate_and_count(name, precision, dc, tune):
     L = LAYOUTS[name]()
     levels = L.levels if L.levels is not None else np.zeros(len(L.blocks), np.int32)
-    info = lgf.plan_check(L.blocks, levels, L.n_b, L.interp_order, precision, dc)
+    info = lgf.plan_check(L.blocks, levels, L.n_b, L.interp_order, precision, dc, autotune=tune)
     counts = fmm.count_interactions(L.blocks)
     assert info["interactions"] == sum(a + b for _, a, b in counts)
     assert info["blocks"] == len(L.blocks)
@@ -97,8 +97,9 @@ def test_batch_generator_layouts_validate():
 
 def test_torus_layout_validates():
     L = workloads.torus(nblk=4, n_b=8, n_levels=3)
-    info = lgf.plan_check(L.blocks, L.levels, L.n_b, 6, 1, 1)
-    assert info["refinement_levels"] == 3
+    for precision in (0, 1):
+        info = lgf.plan_check(L.blocks, L.levels, L.n_b, 6, precision, 1, autotune=1)
+        assert info["refinement_levels"] == 3
 
 
 def super_counts(blocks, levels):
