@@ -154,16 +154,9 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_inv_kernel(SetTable sets
 #pragma unroll
     for (int k = 1; k < NB; ++k) { Xr[P - k] = Xr[k]; Xi[P - k] = -Xi[k]; }
     inv_cropped<NB>(Xr, Xi, xr, xi);
-    const FftInvItem<T>& item = items[first + bb];
-    T* dst = item.dst + (zz * NB + y) * NB;
-    if (item.mode == 0) {
+    T* dst = items[first + bb].dst + (zz * NB + y) * NB;
 #pragma unroll
-      for (int x = 0; x < NB; ++x) dst[x] = xr[x] * inv;
-    } else {
-      const T sg = item.mode > 0 ? inv : -inv;
-#pragma unroll
-      for (int x = 0; x < NB; ++x) dst[x] += xr[x] * sg;
-    }
+    for (int x = 0; x < NB; ++x) dst[x] = xr[x] * inv;
   }
 }
 

@@ -48,9 +48,7 @@ template <typename T> struct FftFwdItem {
 };
 template <typename T> struct FftInvItem {
   const cpx<T>* src;     // half spectrum
-  T* dst;                // n_b^3 real block: dst = IFFT / P^3 (mode 0), dst += (1), dst -= (-1)
-  int32_t mode;
-  int32_t pad;
+  T* dst;                // n_b^3 real block, receives IFFT / P^3
 };
 // A MAC tile: the 2x2 sibling rows y in {2py, 2py+1}, z in {2pz, 2pz+1} of an x window of 8
 // blocks starting at x0 = 8 wx.  Siblings share their parent's neighbours, so all four rows draw
@@ -199,10 +197,8 @@ hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st);
-// mode: W (4 or 8) for NearRow items of super-block spectra; kNearTiled + 4 for NearTile items;
-// kNearBlock + W for NearRow items of block spectra (the near part at coarse octree levels)
+// mode: W (4 or 8) for NearRow items; kNearTiled + 4 for NearTile items
 constexpr int kNearTiled = 16;
-constexpr int kNearBlock = 64;
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode);
 
 // number of workgroups each item of a kernel needs (for set-table bookkeeping)

@@ -441,13 +441,11 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
 
 }  // namespace
 
-// mode: targets per row W (4 or 8) with NearRow items, kNearTiled + 4 with NearTile items, plus
-// kNearBlock for rows over block spectra; chosen by the planner.  All rows of a work set share
-// one kernel table (a workgroup stages the kernels of its first row for all its rows).
+// mode: targets per row W (4 or 8) with NearRow items, kNearTiled + 4 with NearTile items;
+// chosen by the planner.  All rows of a work set share one kernel table (the wavefronts of a
+// workgroup stage the kernels for all its rows).
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode) {
-  const bool block = mode > kNearBlock;    // block spectra (P = 2 nb) instead of super-blocks
-  if (block) mode -= kNearBlock;
-  const int B2 = block ? nb : 2 * nb, P = 2 * B2;
+  const int B2 = 2 * nb, P = 2 * B2;
   const int S = P * P * (B2 + 1);
   if (S % 64) return hipErrorInvalidValue;
   const int chunks8 = (S / 64 + 7) / 8;

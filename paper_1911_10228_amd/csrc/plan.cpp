@@ -276,7 +276,6 @@ hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
     p->ranges.push_back({(uintptr_t)(*out)->d32, cnt * S * sizeof(c32)});
     p->ranges.push_back({(uintptr_t)(*out)->kp64, cnt * sizeof(void*)});
     p->ranges.push_back({(uintptr_t)(*out)->kp32, cnt * sizeof(void*)});
-    if ((*out)->near64) p->ranges.push_back({(uintptr_t)(*out)->near64, 27 * sizeof(void*)});
     return hipSuccess;
   }
   auto key = std::make_pair(nb, s);
@@ -291,7 +290,6 @@ hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
     ss.d32 = (c32*)fake_alloc(p, cnt * S * sizeof(c32));
     ss.kp64 = (const c64**)fake_alloc(p, cnt * sizeof(void*));
     ss.kp32 = (const c32**)fake_alloc(p, cnt * sizeof(void*));
-    if (s > 0) ss.near64 = (const c64**)fake_alloc(p, 27 * sizeof(void*));
     it = p->dry_spectra.emplace(key, ss).first;
   }
   *out = &it->second;
@@ -387,21 +385,13 @@ hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out) {
   LGF_HIP_CHECK(hipMemcpyAsync(d_sd, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                ctx->stream));
   LGF_HIP_CHECK(launch_kernel_spectra(bf, cnt, d_sd, ctx->cube, d_real, d_tmp, ss.d64, ss.d32, ctx->stream));
-  std::vector<const void*> p64(cnt), p32(cnt), pn(27);
+  std::vector<const void*> p64(cnt), p32(cnt);
   for (int i = 0; i < cnt; ++i) {
     p64[i] = ss.d64 + i * S;
     p32[i] = ss.d32 + i * S;
   }
   LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp64, p64.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
   LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp32, p32.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
-  if (s > 0) {                         // the 27 near offsets of a block set
-    LGF_HIP_CHECK(hipMalloc(&ss.near64, 27 * sizeof(void*)));
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx)
-          pn[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1] = p64[(dz + 3) * 49 + (dy + 3) * 7 + dx + 3];
-    LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.near64, pn.data(), 27 * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
-  }
   LGF_HIP_CHECK(hipStreamSynchronize(ctx->stream));
   (void)hipFree(d_sd);
   (void)hipFree(d_real);
@@ -475,7 +465,6 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       case K_INV: {
         const auto& it = ((const FftInvItem<double>*)items)[i];
         if (!in_ranges(p, it.src, 2 * S * es) || !in_ranges(p, it.dst, N3 * es)) return bad("fft_inv", i);
-        if (it.mode < -1 || it.mode > 1) return bad("fft_inv mode", i);
         break;
       }
       case K_MAC: {
@@ -562,24 +551,6 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_NEAR_MAC: {
         const int t = ty == 0 ? 0 : 1;
-        if (mode > kNearBlock) {             // rows over block spectra (coarse near part)
-          const int w = mode - kNearBlock;
-          if (w != 4 && w != 8) return bad("near block row width", i);
-          const auto& it = ((const NearRow<double>*)items)[i];
-          if (it.ngroups < 0 || it.ngroups > 3) return bad("near row groups", i);
-          for (int j = 0; j < 9; ++j) {
-            if (((it.pj_code >> (4 * j)) & 15u) > 8) return bad("near source row index", i);
-            for (int q = 0; q < kNearSlots; ++q)
-              if (it.src[j][q] < 0 || it.src[j][q] > nsrc[t]) return bad("near block source slot", i);
-          }
-          for (int q = 0; q < kMacL; ++q)
-            if (it.tgt[q] < -1 || it.tgt[q] >= ntgt[t]) return bad("near block target slot", i);
-          if (!in_ranges(p, it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("near block source arena", i);
-          if (ntgt[t] && !in_ranges(p, it.uhat, ntgt[t] * 2 * S * es)) return bad("near block target arena", i);
-          if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near block kernel table", i);
-          if (i > 0 && it.kptr != ((const NearRow<double>*)items)[0].kptr) return bad("near kernel table mix", i);
-          break;
-        }
         if (mode > kNearTiled) {
           if (mode != kNearTiled + 4) return bad("near tile width", i);
           const auto& it = ((const NearTile<double>*)items)[i];
@@ -694,16 +665,16 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     p->Kmax = std::max(p->Kmax, (int)chT[l].lv.size());
   }
 
-  // Super-blocks (Sec. 2.1: a block's near list N(B) and influence list I(B) together are the
-  // children of the 27 neighbours of its parent).  Base octree level: the whole level
-  // interaction is one zero-padded convolution per parent super-block against its 27
-  // neighbours.  Coarse octree levels: the same super-block convolution covers N(B) + I(B); the
-  // near part, which finer levels account for, is computed block by block over the 27
-  // neighbours and subtracted.  Per (refinement level, channel, octree level): target
-  // super-blocks are the parents of blocks with interactions, source super-blocks their
-  // neighbours holding source children.  A source super-block spectrum is computed once per
-  // distinct set of source children of one element type (channels T and A share it where their
-  // children agree).  Spectra arenas: 0 = FP32, 1 = FP64.
+  // Base level as parent super-blocks (Sec. 2.1: a block's near list N(B) and influence list
+  // I(B) together are the children of the 27 neighbours of its parent): per (refinement level,
+  // channel) the whole base-level interaction is one zero-padded convolution per parent
+  // super-block against its 27 neighbours.  Target super-blocks are the parents of blocks with
+  // base-level interactions, source super-blocks their neighbours holding source children.  A
+  // source super-block spectrum is computed once per distinct set of source children (channels
+  // T and A share it where they agree).  Spectra arenas: 0 = FP32, 1 = FP64.  (The coarse
+  // octree levels keep the block-wise influence lists: there a super-block convolution would
+  // cover N(B) as well, which would have to be subtracted, and at their sizes the extra
+  // transforms cost more than the tile MAC they replace.)
   struct SupTgt { I3 c; int slot; int child[8]; };
   struct SupInst { int l, ch, k, a; std::vector<SupTgt> tg; I3Map sslot; int64_t pairs = 0; };
   struct SupSrc { int l, k; std::array<int, 8> children; };
@@ -716,22 +687,19 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   // its residual only where all six neighbours are stored, so it cannot remove FP32 spectral
   // error at refinement interfaces: a block-smooth error there stays, and the correction spreads
   // it (by 3-4x in L-inf on the torus layouts), while on a single level only the outer boundary
-  // is excluded.  Coarse octree levels are FP64 throughout.
+  // is excluded.
   const int tys = (p->fp32 && LR > 1) ? TY_MIX : tyb;
   auto arena_of = [&](int k) { return (k == 0 && tys == TY_F32) ? 0 : 1; };
   auto sup_ty = [&](int k) { return k == 0 ? tys : TY_F64; };
-  // per (refinement level, channel, octree level >= 1): sources of the subtracted near part
-  std::map<std::array<int, 3>, I3Map> near_src;
   if (p->super_base) {
     for (int l = 0; l < LR; ++l)
       for (int ch = 0; ch < 2; ++ch) {
         if (ch == 1 && !hasA[l]) continue;
         const Fmm& F = ch == 0 ? chT[l] : chA[l];
-        for (int k = 0; k < (int)F.lv.size(); ++k) {
+        for (int k = 0; k < 1; ++k) {
           const OctLevel& L = F.lv[k];
           const int a = arena_of(k);
-          // base level: every source block is stored; coarse levels: anterpolated sources
-          auto is_source = [&](size_t i) { return k == 0 ? (bool)L.is_src[i] : (bool)L.need_src[i]; };
+          auto is_source = [&](size_t i) { return (bool)L.is_src[i]; };
           std::unordered_map<I3, std::array<int, 8>, I3Hash> smap, tmap;
           const std::array<int, 8> none{-1, -1, -1, -1, -1, -1, -1, -1};
           bool any_tgt = false;
@@ -745,11 +713,6 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
             }
           }
           if (!any_tgt) continue;
-          if (k > 0) {
-            I3Map& ns = near_src[{l, ch, k}];
-            for (size_t i = 0; i < L.nodes.size(); ++i)
-              if (is_source(i)) ns[L.nodes[i]] = L.src_slot[i];
-          }
           std::vector<I3> keys;
           for (const auto& kv : tmap) keys.push_back(kv.first);
           std::sort(keys.begin(), keys.end());
@@ -1023,7 +986,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       for (size_t k = 0; k < F.lv.size(); ++k) {
         OctLevel& L = F.lv[k];
         const int ty = ty_of((int)k);
-        const bool blockwise = !p->super_base;
+        const bool blockwise = !(k == 0 && p->super_base);
         for (size_t i = 0; i < L.nodes.size(); ++i) {
           if (blockwise && L.referenced[i] && !fwd_done[ty][L.src_slot[i]]) {
             fwd_done[ty][L.src_slot[i]] = 1;
@@ -1041,7 +1004,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         }
       }
       for (const TileDesc& rd : F.rows) {
-        if (p->super_base) continue;
+        if (rd.k == 0 && p->super_base) continue;
         const SpecSet* ss = nullptr;
         LGF_HIP_CHECK(plan_spectra(p, nb, 1 << rd.k, &ss));
         OctLevel& L = F.lv[rd.k];
@@ -1081,13 +1044,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k]);
     }
     if (p->super_base) {
-      // Per octree level k (one kernel set per step): super-block transforms, near rows and
-      // inverse transforms; at k >= 1 also the near part on the block grid, subtracted from the
-      // super-block result by the block inverse transforms after every super-block inverse.
-      std::vector<FftFwdItem<D>> nfwd;
-      std::vector<FftInvItem<D>> ninv;
-      std::vector<char> nfwd_done(nsrc[TY_F64], 0);
-      for (int k = 0; k < K; ++k) {
+      // super-block transforms, near rows and inverse transforms of the base octree level
+      for (int k = 0; k < 1; ++k) {
         const int a = arena_of(k), sty = sup_ty(k);
         const int chain = k == 0 ? 1 : 2;
         std::vector<SuperFwdItem<D>> sf;
@@ -1158,44 +1116,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         }
         push(steps, l, 5, k, K_SUP_INV, sty, hi.add(si_items), si_items.size(), nullptr,
              (int64_t)si_items.size(), 0, chain);
-        if (k == 0) continue;
-        // near part on the block grid at scale 2^k: rows of target blocks, 27 neighbours each
-        const SpecSet* bs = nullptr;
-        LGF_HIP_CHECK(plan_spectra(p, nb, 1 << k, &bs));
-        std::vector<NearRow<D>> br;
-        int64_t bpairs = 0;
-        for (int ch = 0; ch < 2; ++ch) {
-          auto nit = near_src.find({l, ch, k});
-          if (nit == near_src.end()) continue;
-          const I3Map& srcs = nit->second;
-          const OctLevel& L = (ch == 0 ? chT[l] : chA[l]).lv[k];
-          std::vector<std::pair<I3, int>> tg;
-          for (size_t i = 0; i < L.nodes.size(); ++i) {
-            if (!L.has_ifft[i]) continue;
-            tg.push_back({L.nodes[i], L.tgt_slot[i]});
-            ninv.push_back({UH(TY_F64, L.tgt_slot[i]), V(TY_F64, L.tgt_slot[i]), -1, 0});
-            for (int dz = -1; dz <= 1; ++dz)
-              for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                  auto sit = srcs.find({L.nodes[i].x - dx, L.nodes[i].y - dy, L.nodes[i].z - dz});
-                  if (sit == srcs.end()) continue;
-                  ++bpairs;
-                  if (!nfwd_done[sit->second]) {
-                    nfwd_done[sit->second] = 1;
-                    nfwd.push_back({SRC(TY_F64, sit->second), FH(TY_F64, sit->second)});
-                  }
-                }
-          }
-          make_rows(tg, srcs, (int)nsrc[TY_F64], 4, FH(TY_F64, 0), UH(TY_F64, 0), bs->near64, br);
-        }
-        p->n_near_rows += (int64_t)br.size();
-        push(steps, l, 4, k, K_NEAR_MAC, TY_F64, hi.add(br), br.size(), nullptr, bpairs, kNearBlock + 4, 2);
       }
-      p->n_fwd += (int64_t)nfwd.size();
-      p->n_inv += (int64_t)ninv.size();
-      push(steps, l, 3, 0, K_FWD, TY_F64, hi.add(nfwd), nfwd.size(), nullptr, (int64_t)nfwd.size(), 0, 2);
-      // after every super-block inverse (subs 0 .. K-1) of this level
-      push(steps, l, 5, 50, K_INV, TY_F64, hi.add(ninv), ninv.size(), nullptr, (int64_t)ninv.size(), 0, 2);
     }
     for (int k = 1; k < K; ++k) {
       const int ty = (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
@@ -1276,10 +1197,10 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   std::set<int> used;
   for (int l = 0; l < LR; ++l)
     for (const TileDesc& rd : chT[l].rows) used.insert(rd.k);
-  // spectra referenced: per octree level with interactions, the 27 super-block kernels (plus the
-  // 27 near block kernels at coarse levels), or the block kernels of the lists
+  // spectra referenced: per octree level with interactions, the 27 super-block kernels at the
+  // base level, or the block kernels of the lists
   p->n_spectra = 0;
-  for (int k : used) p->n_spectra += p->super_base ? (k == 0 ? 27 : 54) : (k == 0 ? 343 : 316);
+  for (int k : used) p->n_spectra += k == 0 ? (p->super_base ? 27 : 343) : 316;
   (void)err;
   return hipSuccess;
 }

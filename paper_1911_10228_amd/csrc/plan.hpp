@@ -27,7 +27,6 @@ struct SpecSet {
   c32* d32 = nullptr;
   const c64** kp64 = nullptr;          // device arrays of count pointers
   const c32** kp32 = nullptr;
-  const c64** near64 = nullptr;        // block sets: the 27 offsets |d| <= 1, index (dz+1)*9+(dy+1)*3+dx+1
 };
 
 struct DeviceCtx {

@@ -103,13 +103,11 @@ def test_torus_layout_validates():
 
 
 def super_counts(blocks, levels):
-    """Super-block bookkeeping written out from the octree lists (oracle.tree): per refinement
-    level, channel and octree level k, the target super-blocks are the parents of target nodes
-    with interactions (N(B) + I(B) at the base level, I(B) above), each pairs with every
-    neighbouring super-block holding a source child; the source children are the source blocks
-    at the base level and, above it, the nodes whose anterpolated source is formed (referenced
-    by an influence list, or below such a node).  A source super-block transform is shared where
-    the two channels have the same base-level source children."""
+    """Base-level super-block bookkeeping written out from the octree lists (oracle.tree): per
+    refinement level and channel, the target super-blocks are the parents of target blocks with
+    base-level interactions (N(B) + I(B)); each pairs with every neighbouring super-block holding
+    a source block.  A source super-block transform is shared where the two channels have the
+    same source children."""
     from oracle import tree
     blocks = np.asarray(blocks)
     levels = np.asarray(levels)
@@ -154,7 +152,9 @@ def super_counts(blocks, levels):
                 up = need[k + 1][pars[k]] if k + 1 < len(tl) else np.zeros(len(tl[k]), bool)
                 need[k] = srcs[k] & (referenced[k] | up)
             for k, nodes in enumerate(tl):
-                use = srcs[k] if k == 0 else need[k]
+                if k > 0:                      # coarse levels keep the block-wise lists
+                    continue
+                use = srcs[k]
                 kids = {}
                 for i in np.nonzero(use)[0]:
                     b = tuple(int(v) for v in nodes[i])
