@@ -103,6 +103,8 @@ template <typename T> struct NearTile {
                                        // (the zero slot where absent)
   uint32_t src_mask;                   // bit q: source row q holds a source
   uint32_t row_mask;                   // bit r: row r holds a target
+  int32_t zero;                        // the zero slot (not loaded: staged as zeros)
+  int32_t pad;
   const cpx<T>* fhat;
   cpx<T>* uhat;
   const cpx<T>* const* kptr;           // 27 kernel spectra in the storage type, index

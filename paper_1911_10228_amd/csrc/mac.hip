@@ -393,24 +393,36 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
   const NearTile<T>* tile = (const NearTile<T>*)ws.items + ti;
   gptr<T> F = (gptr<T>)tile->fhat;
   const uint32_t smask = tile->src_mask;
+  const int r = wave;
+  const int ry = r & 1, rz = r >> 1;
+  const bool has_row = (tile->row_mask >> r) & 1u;
   {
     // each wavefront stages a contiguous run of entries: one wide scalar load of their slots,
-    // then all vector loads back to back (absent sources read the zero spectrum)
+    // then the vector loads back to back; absent sources (the zero slot) are staged as zeros
+    // without a load
+    static_assert(PER_WAVE <= 64, "one slot per lane");
     const int32_t* sl = tile->src + wave * PER_WAVE;
+    const int zero = tile->zero;
+    // one vector load of the wavefront's slot list, then each slot broadcast from its lane
+    // (scalar loads inside the branches below would each wait for their own round trip)
+    const int myslot = lane < PER_WAVE ? sl[lane] : zero;
     cpx<T> v[PER_WAVE];
 #pragma unroll
-    for (int e = 0; e < PER_WAVE; ++e) v[e] = gload<T>(F, (int64_t)sl[e] * S + k);
+    for (int e = 0; e < PER_WAVE; ++e) {
+      const int slot = __builtin_amdgcn_readlane(myslot, e);
+      v[e] = slot != zero ? gload<T>(F, (int64_t)slot * S + k) : cpx<T>{T(0), T(0)};
+    }
 #pragma unroll
     for (int e = 0; e < PER_WAVE; ++e) fl[(wave * PER_WAVE + e) * 64 + lane] = v[e];
   }
+  // the 27 kernel values of this lane's frequency (unconditional: the scalar loads of the
+  // pointer table then batch)
   const cptr64 kp = (cptr64)tile->kptr;
   cpx<T> kv[27];
 #pragma unroll
   for (int h = 0; h < 27; ++h) kv[h] = gload<T>((gptr<T>)kp[h], k);
   __syncthreads();
-  const int r = wave;
-  if (!((tile->row_mask >> r) & 1u)) return;
-  const int ry = r & 1, rz = r >> 1;
+  if (!has_row) return;
   cpx<T> acc[W];
 #pragma unroll
   for (int i = 0; i < W; ++i) acc[i] = {T(0), T(0)};

@@ -870,6 +870,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
               q.src[(qy + 4 * qz) * (kTileW + 2) + x] = sit != srcs.end() ? sit->second : zero;
               if (sit != srcs.end()) q.src_mask |= 1u << (qy + 4 * qz);
             }
+        q.zero = zero;
         q.fhat = fhat;
         q.uhat = uhat;
         q.kptr = kptr;
