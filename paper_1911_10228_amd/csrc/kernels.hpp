@@ -9,6 +9,7 @@ namespace lgf {
 constexpr int kTableKmax = 100;           // table holds |n_i| <= 100 (n.n <= 100^2)
 constexpr int kMacL = 8;                  // target blocks per MAC row (x run, starts even)
 constexpr int kMacSlots = kMacL + 6;      // source x slots per (dy, dz) pair
+constexpr int kMacHalfRows = 32;          // MAC mode bit: tiles of rows of kMacL / 2 targets
 
 // ----------------------------------------------------------------------------- Green function
 // Paper's policy: table for n.n <= 100^2, A_G^3 up to 600^2, A_G^2 beyond.
@@ -50,9 +51,11 @@ template <typename T> struct FftInvItem {
   const cpx<T>* src;     // half spectrum
   T* dst;                // n_b^3 real block, receives IFFT / P^3
 };
-// A MAC tile: the 2x2 sibling rows y in {2py, 2py+1}, z in {2pz, 2pz+1} of an x window of 8
-// blocks starting at x0 = 8 wx.  Siblings share their parent's neighbours, so all four rows draw
-// from the same 6x6 source rows y' = 2py-2+jy, z' = 2pz-2+jz (jy, jz in 0..5).
+// A MAC tile: the 2x2 sibling rows y in {2py, 2py+1}, z in {2pz, 2pz+1} of an x window of W
+// blocks (8, or 4 with the kMacHalfRows launch bit) starting at x0 = W wx.  Siblings share their
+// parent's neighbours, so all four rows draw from the same 6x6 source rows y' = 2py-2+jy,
+// z' = 2pz-2+jz (jy, jz in 0..5).  With W = 4 only the first 4 targets and 10 source slots of a
+// row are used (the rest are -1 / the zero spectrum).
 template <typename T> struct MacTile {
   int32_t tgt[4][kMacL];               // target slots of row r = ry + 2 rz, x = x0 + i (-1: none)
   int32_t src[36][kMacSlots];          // source slots of source row jz*6+jy, x' = x0 - 3 + s

@@ -5,11 +5,11 @@
 // d = t - src with c_i - 3 <= d_i <= c_i + 2 (c = parity of t); on coarse levels the near region
 // |d|_inf <= 1 is excluded, on the base level it is included.
 //
-// Work unit: a tile of 2x2 sibling target rows (8 targets along x each) and 64 consecutive
-// frequencies (one per lane).  Siblings share their parent's neighbours, so the four rows draw
-// from the same 36 source rows.  A wavefront accumulates ROWS of the tile's rows (1, 2 or 4):
-// for each source row it holds the 14 source spectra of the x window in registers and reuses
-// them against the 7 kernel offsets along x and its rows.  The next source row's spectra (and,
+// Work unit: a tile of 2x2 sibling target rows (W = 8 targets along x each, or 4 on levels only a
+// few blocks wide) and 64 consecutive frequencies (one per lane).  Siblings share their parent's
+// neighbours, so the four rows draw from the same 36 source rows.  A wavefront accumulates ROWS
+// of the tile's rows (1, 2 or 4): for each source row it holds the W + 6 source spectra of the x
+// window in registers and reuses them against the 7 kernel offsets along x and its rows.  The next source row's spectra (and,
 // without LDS staging, its kernel spectra) are loaded before the current row's arithmetic, so a
 // single wait per source row covers the memory latency.  In FP32 the kernel spectra of the
 // level are staged in LDS for the workgroup's 64 frequencies; only offsets d >= 0
@@ -35,11 +35,11 @@ template <typename T> __device__ __forceinline__ cpx<T> gload(gptr<T> base, int6
 }
 
 // absent sources point at the arena's all-zero spectrum, so every load is unconditional
-template <typename T>
-__device__ __forceinline__ void load_src(cpx<T> (&fs)[kMacSlots], const int32_t* __restrict__ sr,
+template <typename T, int NS>
+__device__ __forceinline__ void load_src(cpx<T> (&fs)[NS], const int32_t* __restrict__ sr,
                                          gptr<T> F, int S, int k) {
 #pragma unroll
-  for (int s = 0; s < kMacSlots; ++s) fs[s] = gload<T>(F, (int64_t)sr[s] * S + k);
+  for (int s = 0; s < NS; ++s) fs[s] = gload<T>(F, (int64_t)sr[s] * S + k);
 }
 
 __device__ __forceinline__ int kindex(int r, int jz, int jy, int dxi) {
@@ -58,9 +58,9 @@ __device__ __forceinline__ void load_k(cpx<T> (&ks)[ROWS][7], cptr64 kp, int r0,
     }
 }
 
-// accumulate one source row (jz, jy) into target row r with kernel values kv(dxi)
-template <typename T, typename KF>
-__device__ __forceinline__ void mac_row(cpx<T> (&acc)[kMacL], const cpx<T> (&fs)[kMacSlots], int r, int jz,
+// accumulate one source row (jz, jy) into target row r (XW targets) with kernel values kv(dxi)
+template <typename T, int XW, typename KF>
+__device__ __forceinline__ void mac_row(cpx<T> (&acc)[XW], const cpx<T> (&fs)[XW + 6], int r, int jz,
                                         int jy, bool base, KF&& kv) {
   const int ry = r & 1, rz = r >> 1;
   const int dz = rz + 2 - jz, dy = ry + 2 - jy;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void mac_row(cpx<T> (&acc)[kMacL], const cpx<T> (&fs)
     if (!base && near_zy && dx >= -1 && dx <= 1) continue;
     const cpx<T> kk = kv(dxi);
 #pragma unroll
-    for (int i = 0; i < kMacL; ++i) {
+    for (int i = 0; i < XW; ++i) {
       const int c = i & 1;
       if (dx < c - 3 || dx > c + 2) continue;
       cmac(acc[i], kk, fs[i - dx + 3]);
@@ -81,10 +81,12 @@ __device__ __forceinline__ void mac_row(cpx<T> (&acc)[kMacL], const cpx<T> (&fs)
 
 // SPLIT = 6: the six waves of a workgroup share one (tile, row group) and take one source-row
 // plane jz each; their partial sums are added in a fixed order through LDS (for small levels).
-template <typename T, int WAVES, int ROWS, bool KLDS, int SPLIT>
+// XW = 8 or 4 targets per row (the tiles' x window; rows of 4 for levels only a few blocks wide).
+template <typename T, int WAVES, int ROWS, bool KLDS, int SPLIT, int XW>
 __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int S) {
+  constexpr int NS = XW + 6;
   __shared__ cpx<T> klds[KLDS ? kHalfK * 64 : 1];
-  __shared__ cpx<T> red[SPLIT > 1 ? (SPLIT - 1) * ROWS * kMacL * 64 : 1];
+  __shared__ cpx<T> red[SPLIT > 1 ? (SPLIT - 1) * ROWS * XW * 64 : 1];
   constexpr int UPT = 4 / ROWS;                  // units (row groups) per tile
   constexpr int UPW = WAVES / SPLIT;             // units per workgroup
   const int set = find_set(sets, blockIdx.x);
@@ -125,18 +127,18 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
   if constexpr (SPLIT > 1) todo &= 0x3Full << (6 * part);
   gptr<T> F = (gptr<T>)tile->fhat;
 
-  cpx<T> acc[ROWS][kMacL];
+  cpx<T> acc[ROWS][XW];
 #pragma unroll
   for (int q = 0; q < ROWS; ++q)
 #pragma unroll
-    for (int i = 0; i < kMacL; ++i) acc[q][i] = {T(0), T(0)};
+    for (int i = 0; i < XW; ++i) acc[q][i] = {T(0), T(0)};
 
   if (todo) {
     int pj = __builtin_ctzll(todo);
     todo &= todo - 1;
-    cpx<T> fs[kMacSlots];
+    cpx<T> fs[NS];
     cpx<T> ks[KLDS ? 1 : ROWS][7];
-    load_src<T>(fs, tile->src[pj], F, S, k);
+    load_src<T, NS>(fs, tile->src[pj], F, S, k);
     if constexpr (!KLDS) load_k<T, ROWS>(ks, kp, r0, pj / 6, pj % 6, k);
     for (;;) {
       // the next source row's loads are issued unconditionally (the last iteration reloads the
@@ -145,9 +147,9 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
       const bool more = todo != 0;
       const int pn = more ? __builtin_ctzll(todo) : pj;
       todo &= todo - 1;
-      cpx<T> fn[kMacSlots];
+      cpx<T> fn[NS];
       cpx<T> kn[KLDS ? 1 : ROWS][7];
-      load_src<T>(fn, tile->src[pn], F, S, k);
+      load_src<T, NS>(fn, tile->src[pn], F, S, k);
       if constexpr (!KLDS) load_k<T, ROWS>(kn, kp, r0, pn / 6, pn % 6, k);
       const int jz = pj / 6, jy = pj % 6;
 #pragma unroll
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
         if (!((mymask >> q) & 1)) continue;
         const int r = r0 + q;
         if constexpr (KLDS) {
-          mac_row<T>(acc[q], fs, r, jz, jy, base, [&](int dxi) {
+          mac_row<T, XW>(acc[q], fs, r, jz, jy, base, [&](int dxi) {
             const int idx = kindex(r, jz, jy, dxi);
             const bool mirror = idx >= kHalfK;
             cpx<T> kv = klds[(mirror ? 342 - idx : idx) * 64 + lane];
@@ -163,12 +165,12 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
             return kv;
           });
         } else {
-          mac_row<T>(acc[q], fs, r, jz, jy, base, [&](int dxi) { return ks[q][dxi]; });
+          mac_row<T, XW>(acc[q], fs, r, jz, jy, base, [&](int dxi) { return ks[q][dxi]; });
         }
       }
       if (!more) break;
 #pragma unroll
-      for (int s = 0; s < kMacSlots; ++s) fs[s] = fn[s];
+      for (int s = 0; s < NS; ++s) fs[s] = fn[s];
       if constexpr (!KLDS) {
 #pragma unroll
         for (int q = 0; q < ROWS; ++q)
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
 #pragma unroll
       for (int q = 0; q < ROWS; ++q)
 #pragma unroll
-        for (int i = 0; i < kMacL; ++i) red[(((part - 1) * ROWS + q) * kMacL + i) * 64 + lane] = acc[q][i];
+        for (int i = 0; i < XW; ++i) red[(((part - 1) * ROWS + q) * XW + i) * 64 + lane] = acc[q][i];
     }
     __syncthreads();
     if (part > 0) return;
@@ -193,8 +195,8 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
 #pragma unroll
       for (int q = 0; q < ROWS; ++q)
 #pragma unroll
-        for (int i = 0; i < kMacL; ++i) {
-          const cpx<T> v = red[(((p - 1) * ROWS + q) * kMacL + i) * 64 + lane];
+        for (int i = 0; i < XW; ++i) {
+          const cpx<T> v = red[(((p - 1) * ROWS + q) * XW + i) * 64 + lane];
           acc[q][i].x += v.x;
           acc[q][i].y += v.y;
         }
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
 #pragma unroll
   for (int q = 0; q < ROWS; ++q)
 #pragma unroll
-    for (int i = 0; i < kMacL; ++i) {
+    for (int i = 0; i < XW; ++i) {
       const int t = tile->tgt[r0 + q][i];
       if (t >= 0) {
         U[2 * ((int64_t)t * S + k)] = acc[q][i].x;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
     }
 }
 
-template <typename T, int WAVES, int ROWS, bool KLDS, int SPLIT = 1>
+template <typename T, int WAVES, int ROWS, bool KLDS, int SPLIT = 1, int XW = kMacL>
 hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
   constexpr int UPT = 4 / ROWS, UPW = WAVES / SPLIT;
   static_assert(UPW >= 1 && WAVES % SPLIT == 0, "shape");
@@ -223,7 +225,7 @@ hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
     wg += (int64_t)((t.s[i].count * UPT + UPW - 1) / UPW) * chunks8 * 8;
   }
   if (wg == 0) return hipSuccess;
-  mac_tile_kernel<T, WAVES, ROWS, KLDS, SPLIT><<<(unsigned)wg, 64 * WAVES, 0, st>>>(t, S);
+  mac_tile_kernel<T, WAVES, ROWS, KLDS, SPLIT, XW><<<(unsigned)wg, 64 * WAVES, 0, st>>>(t, S);
   return hipGetLastError();
 }
 
@@ -231,8 +233,9 @@ hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
 
 // Launch shape (mode): 1 row, 2 pair, 4 tile = rows per wavefront; 6 split = FP64 source rows
 // over 6 wavefronts; 0 = default (one row per wavefront; FP32 with the kernel spectra in LDS and
-// 16 wavefronts per workgroup, FP64 with the kernel spectra prefetched from memory).  The plan's
-// autotuner picks the mode per step; LGF_MAC_MODE = row | pair | tile | split overrides it.
+// 16 wavefronts per workgroup, FP64 with the kernel spectra prefetched from memory).  Bit
+// kMacHalfRows marks tiles whose rows hold 4 targets (set by the planner with the items).  The
+// plan's autotuner picks the shape per step; LGF_MAC_MODE = row | pair | tile | split overrides it.
 int mac_mode_override() {
   static const int m = [] {
     const char* e = std::getenv("LGF_MAC_MODE");
@@ -250,7 +253,20 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
   const int P = 2 * nb;
   const int S = P * P * (nb + 1);          // multiple of 64 for nb in {8, 16}
   if (S % 64) return hipErrorInvalidValue;
+  const bool half = mode & kMacHalfRows;
+  mode &= kMacHalfRows - 1;
   if (const int o = mac_mode_override()) mode = o;
+  if (half) {
+    if constexpr (sizeof(T) == 4) {
+      if (mode == 4) return launch_tiles<T, 16, 4, true, 1, 4>(S, t, st);
+      if (mode == 2) return launch_tiles<T, 16, 2, true, 1, 4>(S, t, st);
+      return launch_tiles<T, 16, 1, true, 1, 4>(S, t, st);
+    } else {
+      if (mode == 2) return launch_tiles<T, 4, 2, false, 1, 4>(S, t, st);
+      if (mode == 6) return launch_tiles<T, 6, 1, false, 6, 4>(S, t, st);
+      return launch_tiles<T, 4, 1, false, 1, 4>(S, t, st);
+    }
+  }
   if constexpr (sizeof(T) == 4) {
     if (mode == 4) return launch_tiles<T, 16, 4, true>(S, t, st);
     if (mode == 2) return launch_tiles<T, 16, 2, true>(S, t, st);

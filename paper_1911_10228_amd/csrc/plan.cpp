@@ -103,6 +103,7 @@ struct OctLevel {
 
 struct TileDesc {
   int k;
+  int W;                               // targets per row: 8 or 4
   I3 key;                              // (x window, y pair, z pair)
   int tgt_node[4][kMacL];
   int src_node[36][kMacSlots];
@@ -168,7 +169,7 @@ void fmm_build(const std::vector<I3>& base, const std::vector<char>& src, const 
     L.has_ifft.assign(n, 0);
     L.referenced.assign(n, 0);
     const bool base_level = (k == 0);
-    std::map<I3, TileDesc> rows;
+    std::map<I3, TileDesc> rows8, rows4;
     for (size_t t = 0; t < n; ++t) {
       if (!L.is_tgt[t]) continue;
       const I3 a = L.nodes[t];
@@ -188,29 +189,37 @@ void fmm_build(const std::vector<I3>& base, const std::vector<char>& src, const 
       L.has_ifft[t] = 1;
       F.interactions += cnt;
       F.level_interactions[k] += cnt;
-      const int wx = floordiv(a.x, kMacL), py = floordiv2(a.y), pz = floordiv2(a.z);
-      const I3 key{wx, py, pz};
-      auto rit = rows.find(key);
-      if (rit == rows.end()) {
-        TileDesc r;
-        r.k = k;
-        r.key = key;
-        for (int q = 0; q < 4; ++q)
-          for (int i = 0; i < kMacL; ++i) r.tgt_node[q][i] = -1;
-        r.mask = 0;
-        for (int jz = 0; jz < 6; ++jz)
-          for (int jy = 0; jy < 6; ++jy)
-            for (int q = 0; q < kMacSlots; ++q) {
-              auto it = L.index.find({wx * kMacL - 3 + q, 2 * py - 2 + jy, 2 * pz - 2 + jz});
-              const int id = (it != L.index.end() && L.is_src[it->second]) ? it->second : -1;
-              r.src_node[jz * 6 + jy][q] = id;
-              if (id >= 0) r.mask |= 1ull << (jz * 6 + jy);
-            }
-        rit = rows.emplace(key, r).first;
+      // tiles of rows of 8 and of 4 targets (the planner picks one width per level)
+      for (int wi = 0; wi < 2; ++wi) {
+        const int W = wi == 0 ? kMacL : kMacL / 2;
+        const int wx = floordiv(a.x, W), py = floordiv2(a.y), pz = floordiv2(a.z);
+        const I3 key{wx, py, pz};
+        auto& rows = wi == 0 ? rows8 : rows4;
+        auto rit = rows.find(key);
+        if (rit == rows.end()) {
+          TileDesc r;
+          r.k = k;
+          r.W = W;
+          r.key = key;
+          for (int q = 0; q < 4; ++q)
+            for (int i = 0; i < kMacL; ++i) r.tgt_node[q][i] = -1;
+          r.mask = 0;
+          for (int jz = 0; jz < 6; ++jz)
+            for (int jy = 0; jy < 6; ++jy)
+              for (int q = 0; q < kMacSlots; ++q) {
+                auto it = q < W + 6 ? L.index.find({wx * W - 3 + q, 2 * py - 2 + jy, 2 * pz - 2 + jz})
+                                    : L.index.end();
+                const int id = (it != L.index.end() && L.is_src[it->second]) ? it->second : -1;
+                r.src_node[jz * 6 + jy][q] = id;
+                if (id >= 0) r.mask |= 1ull << (jz * 6 + jy);
+              }
+          rit = rows.emplace(key, r).first;
+        }
+        rit->second.tgt_node[(a.y - 2 * py) + 2 * (a.z - 2 * pz)][a.x - wx * W] = (int)t;
       }
-      rit->second.tgt_node[(a.y - 2 * py) + 2 * (a.z - 2 * pz)][a.x - wx * kMacL] = (int)t;
     }
-    for (auto& kv : rows) F.rows.push_back(kv.second);
+    for (auto& kv : rows8) F.rows.push_back(kv.second);
+    for (auto& kv : rows4) F.rows.push_back(kv.second);
   }
   // values: top-down; source needs: top-down from referenced
   for (int k = K - 1; k >= 0; --k) {
@@ -473,9 +482,11 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
         for (int j = 0; j < 36; ++j)
           for (int q = 0; q < kMacSlots; ++q)
             if (it.src[j][q] < 0 || it.src[j][q] > nsrc[t]) return bad("mac source slot", i);
+        const int w = (mode & kMacHalfRows) ? kMacL / 2 : kMacL;
         for (int r = 0; r < 4; ++r)
           for (int q = 0; q < kMacL; ++q)
-            if (it.tgt[r][q] < -1 || it.tgt[r][q] >= ntgt[t]) return bad("mac target slot", i);
+            if (it.tgt[r][q] < -1 || it.tgt[r][q] >= ntgt[t] || (q >= w && it.tgt[r][q] != -1))
+              return bad("mac target slot", i);
         if (!in_ranges(p, it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("mac source arena", i);
         if (ntgt[t] && !in_ranges(p, it.uhat, ntgt[t] * 2 * S * es)) return bad("mac target arena", i);
         if (!in_ranges(p, it.kptr, 343 * sizeof(void*))) return bad("mac kernel table", i);
@@ -961,6 +972,30 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     std::vector<FftInvItem<D>> inv[2];
     std::vector<std::vector<MacTile<D>>> rows(K);      // per octree level (one kernel set each)
     std::vector<int64_t> work(K, 0);
+    // row width of each octree level's tiles: 4 targets where rows of 8 would be mostly empty
+    // (levels a few blocks wide).  Cost per wavefront and source row: the W + 6 source and 7
+    // kernel spectra it loads plus its W target accumulations.
+    std::vector<int> wsel(K, kMacL);
+    {
+      std::vector<double> cost[2] = {std::vector<double>(K, 0.0), std::vector<double>(K, 0.0)};
+      for (int ch = 0; ch < 2; ++ch) {
+        if (ch == 1 && !hasA[l]) continue;
+        for (const TileDesc& rd : (ch == 0 ? chT[l] : chA[l]).rows) {
+          int active = 0;
+          for (int q = 0; q < 4; ++q)
+            for (int i = 0; i < rd.W; ++i)
+              if (rd.tgt_node[q][i] >= 0) {
+                ++active;
+                break;
+              }
+          cost[rd.W == kMacL ? 0 : 1][rd.k] +=
+              (double)active * __builtin_popcountll(rd.mask) * (2 * rd.W + 13);
+        }
+      }
+      for (int k = 0; k < K; ++k)
+        if (cost[1][k] < cost[0][k]) wsel[k] = kMacL / 2;
+    }
+    std::vector<std::vector<MacTile<D>>> alt_mac(K);   // the other width, for the autotuner
     std::vector<char> fwd_done[2] = {std::vector<char>(nsrc[0], 0), std::vector<char>(nsrc[1], 0)};
     for (int ch = 0; ch < 2; ++ch) {
       if (ch == 1 && !hasA[l]) continue;
@@ -1006,6 +1041,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       }
       for (const TileDesc& rd : F.rows) {
         if (rd.k == 0 && p->super_base) continue;
+        if (rd.W != wsel[rd.k] && !p->tune) continue;
         const SpecSet* ss = nullptr;
         LGF_HIP_CHECK(plan_spectra(p, nb, 1 << rd.k, &ss));
         OctLevel& L = F.lv[rd.k];
@@ -1031,7 +1067,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         m.fhat = FH(ty, 0);
         m.uhat = UH(ty, 0);
         m.kptr = ty == TY_F32 ? (const cpx<D>* const*)ss->kp32 : (const cpx<D>* const*)ss->kp64;
-        rows[rd.k].push_back(m);
+        (rd.W == wsel[rd.k] ? rows : alt_mac)[rd.k].push_back(m);
       }
     }
     for (int ty = 0; ty < 2; ++ty) {
@@ -1042,7 +1078,14 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     }
     for (int k = 0; k < K; ++k) {
       p->n_rows += (int64_t)rows[k].size();
-      push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k]);
+      const int half = wsel[k] == kMacL ? 0 : kMacHalfRows;
+      const size_t primary = steps.size();
+      push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k], half);
+      if (steps.size() > primary && !alt_mac[k].empty()) {
+        push(alt_steps, l, 4, k, K_MAC, ty_of(k), hi.add(alt_mac[k]), alt_mac[k].size(), nullptr, work[k],
+             kMacHalfRows - half);
+        alt_of.push_back(primary);
+      }
     }
     if (p->super_base) {
       // super-block transforms, near rows and inverse transforms of the base octree level
@@ -1597,10 +1640,11 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
   for (std::vector<Step>* list : {&p->pass}) {
     for (Step& s : *list) {
       if (s.kind != K_MAC) continue;
-      const std::array<int64_t, 3> key{p->nb, s.ty, s.count};
+      const int half = s.mode & kMacHalfRows;
+      const std::array<int64_t, 3> key{p->nb, s.ty + (half ? 10 : 0), s.count};
       auto it = g_tune.find(key);
       if (it != g_tune.end()) {
-        s.mode = it->second;
+        s.mode = it->second | half;
         continue;
       }
       const int* cand = s.ty == 0 ? kMacModes32 : kMacModes64;
@@ -1614,7 +1658,7 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
           tab.pad = 0;
           tab.s[0] = WorkSet{s.items, 0, s.count, 0, nullptr, nullptr, s.w};
           LGF_HIP_CHECK(hipEventRecord(a, st));
-          LGF_HIP_CHECK(launch_typed(K_MAC, s.ty, p->nb, tab, st, cand[c]));
+          LGF_HIP_CHECK(launch_typed(K_MAC, s.ty, p->nb, tab, st, cand[c] | half));
           LGF_HIP_CHECK(hipEventRecord(b, st));
           LGF_HIP_CHECK(hipEventSynchronize(b));
           LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
@@ -1625,7 +1669,7 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
           best_mode = cand[c];
         }
       }
-      s.mode = best_mode;
+      s.mode = best_mode | half;
       tune_store(key, best_mode);
     }
   }
@@ -1637,7 +1681,7 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
     Step& prim = p->pass[g.first];
     std::vector<Step> cands{prim};
     for (const Step& x : g.second) cands.push_back(x);
-    const std::array<int64_t, 3> key{p->nb, 1000 + prim.ty, prim.work};
+    const std::array<int64_t, 3> key{p->nb, (prim.kind == K_MAC ? 2000 : 1000) + prim.ty, prim.work};
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
       for (const Step& c : cands)
