@@ -285,12 +285,16 @@ template hipError_t launch_mac<double>(int, SetTable&, hipStream_t, int);
 // U_P[k] = sum over the 27 super-blocks Q with |P - Q|_inf <= 1 of K_{P-Q}[k] F_Q[k].
 // One wavefront owns a row of W target super-blocks along x and 64 frequencies.  The source rows
 // (dy, dz) that hold sources come in groups of 3; a group's 3 (W + 2) source spectra are loaded
-// together while the previous group is applied (3 kernel offsets along x each, kernels from LDS:
-// 27 kernels x 64 frequencies).  The products are formed and summed in FP64 from FP64 kernel
+// together while the previous group is applied (3 kernel offsets along x each, kernels from LDS).
+// Kernel offsets are numbered h = 9 (dz + 1) + 3 (dy + 1) + dx + 1; only h <= 13 is read: the
+// zero-padded kernel block is real and G is even in every coordinate (the unused middle plane is
+// zero on both sides), so K_{-d}[k] = conj(K_d[k]), i.e. K_h = conj(K_{26-h}).  The products are formed and summed in FP64 from FP64 kernel
 // spectra whatever the storage type T of the super-block spectra: the FP64 multiply-add rate
 // equals the unpacked FP32 rate, and the FP64 sum keeps the rounding of the largest
 // (low-frequency) terms out of the smooth part of the result.
 namespace {
+
+constexpr int kNearHalfK = 14;   // kernel offsets h = 0..13 (the centre and one of each +-d pair)
 
 template <typename T, int NS>
 __device__ __forceinline__ void load_group(cpx<T> (&f)[3][NS], const NearRow<T>* row, int g,
@@ -312,7 +316,9 @@ __device__ __forceinline__ void apply_group(cpx<double> (&acc)[W], const cpx<T> 
     for (int s = 0; s < NS; ++s) fd[s] = {double(f[r][s].x), double(f[r][s].y)};
 #pragma unroll
     for (int dxi = 0; dxi < 3; ++dxi) {
-      const cpx<double> kv = kl[(pj * 3 + dxi) * 64 + lane];
+      const int h = pj * 3 + dxi;
+      cpx<double> kv = kl[(h < kNearHalfK ? h : 26 - h) * 64 + lane];
+      if (h >= kNearHalfK) kv.y = -kv.y;
 #pragma unroll
       for (int i = 0; i < W; ++i) cmac(acc[i], kv, fd[i - dxi + 2]);   // src x = x0 + i - dx
     }
@@ -336,7 +342,7 @@ __device__ __forceinline__ void near_groups(cpx<double> (&acc)[W], const NearRow
 template <typename T, int W>
 __global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
   constexpr int NS = W + 2;
-  __shared__ cpx<double> kl[27 * 64];
+  __shared__ cpx<double> kl[kNearHalfK * 64];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;       // wg_begin is a multiple of 8
@@ -353,7 +359,7 @@ __global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
   const bool active = ri < ws.count;
   const NearRow<T>* row = rows + (active ? ri : grp * 4);
   const cptr64 kp = (cptr64)row->kptr;
-  for (int h = wave; h < 27; h += 4) kl[h * 64 + lane] = gload<double>((gptr<double>)kp[h], k);
+  for (int h = wave; h < kNearHalfK; h += 4) kl[h * 64 + lane] = gload<double>((gptr<double>)kp[h], k);
   __syncthreads();
   if (!active) return;
 
@@ -381,8 +387,8 @@ __global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
 
 // Tiled form: one workgroup of 4 wavefronts per (tile, frequency chunk); the 16 source rows of
 // the tile ((W + 2) spectra each, 64 frequencies) are staged in LDS with all loads of a
-// wavefront in flight together, and each wavefront holds the 27 kernel values of its frequency
-// in registers.  Each wavefront then applies its row's 9 source rows from LDS, in the storage
+// wavefront in flight together, and each wavefront holds the 14 kernel values h <= 13 of its
+// frequency in registers (the others are their conjugates).  Each wavefront then applies its row's 9 source rows from LDS, in the storage
 // type (the planner uses tiles for FP32 spectra on single-level layouts, where defect
 // correction removes FP32 error: an FP64 sum there changed nothing measurable).  Compared
 // with one wavefront per row loading its own 9 source rows, each source spectrum chunk is read
@@ -431,12 +437,12 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
 #pragma unroll
     for (int e = 0; e < PER_WAVE; ++e) fl[(wave * PER_WAVE + e) * 64 + lane] = v[e];
   }
-  // the 27 kernel values of this lane's frequency (unconditional: the scalar loads of the
+  // the kernel values h <= 13 of this lane's frequency (unconditional: the scalar loads of the
   // pointer table then batch)
   const cptr64 kp = (cptr64)tile->kptr;
-  cpx<T> kv[27];
+  cpx<T> kv[kNearHalfK];
 #pragma unroll
-  for (int h = 0; h < 27; ++h) kv[h] = gload<T>((gptr<T>)kp[h], k);
+  for (int h = 0; h < kNearHalfK; ++h) kv[h] = gload<T>((gptr<T>)kp[h], k);
   __syncthreads();
   if (!has_row) return;
   cpx<T> acc[W];
@@ -452,8 +458,10 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
     for (int s2 = 0; s2 < NS; ++s2) fd[s2] = fl[(q * NS + s2) * 64 + lane];
 #pragma unroll
     for (int dxi = 0; dxi < 3; ++dxi) {
+      const int h = pj * 3 + dxi;
+      const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
 #pragma unroll
-      for (int i = 0; i < W; ++i) cmac(acc[i], kv[pj * 3 + dxi], fd[i - dxi + 2]);   // src x = x0 + i - dx
+      for (int i = 0; i < W; ++i) cmac(acc[i], kk, fd[i - dxi + 2]);   // src x = x0 + i - dx
     }
   }
   gmut<T> U = (gmut<T>)tile->uhat;

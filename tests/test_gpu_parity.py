@@ -96,6 +96,22 @@ def test_super_block_kernel_spectra_match_oracle(lgf, n_b, d):
     assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
 
 
+def test_super_block_kernel_spectra_conjugate_pairs(lgf):
+    """The near MAC reads the kernels h <= 13 and conjugates them for -d."""
+    n_b = 8
+    B = 2 * n_b
+    spec = {}
+    for d in [(1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1)]:
+        out = torch.zeros((2 * B, 2 * B, B + 1, 2), dtype=torch.float64, device="cuda")
+        lgf.kernel_spectrum(n_b, 0, d, out)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        spec[d] = o[..., 0] + 1j * o[..., 1]
+    for d in [(1, 0, -1), (0, 1, 1)]:
+        m = tuple(-x for x in d)
+        assert np.abs(spec[m] - np.conj(spec[d])).max() <= 1e-14 * np.abs(spec[d]).max()
+
+
 # ----------------------------------------------------------------------------- uniform FLGF
 def test_uniform_gaussian_fp64_matches_oracle_and_brute_force(lgf):
     L = workloads.uniform_gaussian()

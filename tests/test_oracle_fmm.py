@@ -86,6 +86,16 @@ def test_block_conv_fft_equals_direct(s, d):
     assert np.abs(a - b).max() <= 1e-15 * np.abs(f).sum()
 
 
+@pytest.mark.parametrize("b,s,d", [(4, 1, (1, 0, -1)), (8, 2, (2, -3, 1)), (8, 1, (1, 1, 1))])
+def test_kernel_spectrum_of_opposite_offset_is_conjugate(b, s, d):
+    """The zero-padded kernel block is real and G is even in every coordinate (Sec. 2, the LGF
+    depends on |n_x|, |n_y|, |n_z| only), so the spectrum for -d is the conjugate of the one
+    for d; the GPU MACs read only one of each pair."""
+    kp = np.fft.rfftn(fmm.kernel_block(b, s, d))
+    km = np.fft.rfftn(fmm.kernel_block(b, s, tuple(-x for x in d)))
+    assert np.abs(km - np.conj(kp)).max() <= 1e-14 * np.abs(kp).max()
+
+
 # ---------------------------------------------------------------- whole FLGF
 def test_uniform_gaussian_equals_brute_force():
     """2^3 blocks are all mutual neighbours: the FLGF uses only the exact kernel and equals
