@@ -16,6 +16,12 @@ namespace {
 
 constexpr int kOpThreads = 256;
 
+// Block kernels give each thread the cells i = tid + j kOpThreads, j < N3 / kOpThreads, and
+// load all of a thread's values into registers before the first store: the block pointers are
+// generic, so the compiler may not move a load past an earlier store, and a load-store loop
+// would wait one memory round trip per cell.
+template <int NB> constexpr int per_thread() { return NB * NB * NB / kOpThreads; }
+
 
 // child += (Wz (x) Wy (x) Wx) parent for octant c; W is [2 NB][NB] row-major (FP64).
 // Arithmetic in the parent's type TP, stored in the child's type TC.
@@ -31,7 +37,19 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
   const InterpItem<TC, TP>& it = ((const InterpItem<TC, TP>*)ws.items)[blockIdx.x - ws.wg_begin];
   const double* __restrict__ W = ws.w;
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) b0[i] = it.parent[i];
+  constexpr int PT = per_thread<NB>();
+  {
+    TP pv[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) pv[j] = it.parent[threadIdx.x + j * kOpThreads];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) b0[threadIdx.x + j * kOpThreads] = pv[j];
+  }
+  TC cv[PT];
+  if (it.accumulate) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) cv[j] = it.child[threadIdx.x + j * kOpThreads];
+  }
   for (int i = threadIdx.x; i < 3 * NB * NB; i += kOpThreads) {
     const int d = i / (NB * NB), r = (i / NB) % NB, m = i % NB;
     w[d][r][m] = T(W[(c[d] * NB + r) * NB + m]);
@@ -53,13 +71,20 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
     b0[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {       // z
+  TC* const child = it.child;
+  const bool accumulate = it.accumulate;
+  TC out[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {                              // z
+    const int i = threadIdx.x + j * kOpThreads;
     const int XY = i % (NB * NB), Z = i / (NB * NB);
     T s = 0;
 #pragma unroll
     for (int z = 0; z < NB; ++z) s += w[2][Z][z] * b0[z * NB * NB + XY];
-    it.child[i] = TC(it.accumulate ? T(it.child[i]) + s : s);
+    out[j] = TC(accumulate ? T(cv[j]) + s : s);
   }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) child[threadIdx.x + j * kOpThreads] = out[j];
 }
 
 // parent = sum_c (Wz (x) Wy (x) Wx)^T child_c, arithmetic in the parent's type TP.
@@ -129,11 +154,16 @@ __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
   const CombineItem<T>& it = ((const CombineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
   const double sc = it.scale;
   double* dd = it.dst_d ? it.dst_d : ws.out + it.dst_out;
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
-    double v = it.v ? sc * double(it.v[i]) : 0.0;
-    if (it.base) v += it.base[i];
-    dd[i] = v;
+  constexpr int PT = per_thread<NB>();
+  double v[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) v[j] = it.v ? sc * double(it.v[threadIdx.x + j * kOpThreads]) : 0.0;
+  if (it.base) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) v[j] += it.base[threadIdx.x + j * kOpThreads];
   }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) dd[threadIdx.x + j * kOpThreads] = v[j];
 }
 
 template <int NB, typename T>
@@ -143,7 +173,13 @@ __global__ __launch_bounds__(kOpThreads) void convert_kernel(SetTable sets) {
   const WorkSet& ws = sets.s[set];
   const ConvertItem<T>& it = ((const ConvertItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
   const double* src = it.src ? it.src : ws.in + it.src_in;
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) it.dst[i] = T(src[i]);
+  constexpr int PT = per_thread<NB>();
+  double v[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) v[j] = src[threadIdx.x + j * kOpThreads];
+  T* const dst = it.dst;
+#pragma unroll
+  for (int j = 0; j < PT; ++j) dst[threadIdx.x + j * kOpThreads] = T(v[j]);
 }
 
 template <int NB>
@@ -152,19 +188,29 @@ __global__ __launch_bounds__(kOpThreads) void coarsen_kernel(SetTable sets) {
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const CoarsenItem& it = ((const CoarsenItem*)ws.items)[blockIdx.x - ws.wg_begin];
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
-    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
-    const int oc = (x / HB) + 2 * (y / HB) + 4 * (z / HB);
-    const double* ch = it.child[oc] ? it.child[oc] : ws.in + it.child_in[oc];
-    const int fx = 2 * (x % HB), fy = 2 * (y % HB), fz = 2 * (z % HB);
-    double s = 0.0;
+  constexpr int PT = per_thread<NB>(), G = PT < 8 ? PT : 8;   // groups of G cells (registers)
+  double* const dst = it.dst;
+#pragma unroll 1
+  for (int j0 = 0; j0 < PT; j0 += G) {
+    double out[G];
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = jj, i = threadIdx.x + (j0 + jj) * kOpThreads;
+      const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+      const int oc = (x / HB) + 2 * (y / HB) + 4 * (z / HB);
+      const double* ch = it.child[oc] ? it.child[oc] : ws.in + it.child_in[oc];
+      const int fx = 2 * (x % HB), fy = 2 * (y % HB), fz = 2 * (z % HB);
+      double s = 0.0;
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
+      for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) s += ch[((fz + dz) * NB + fy + dy) * NB + fx + dx];
-    it.dst[i] = 0.125 * s;
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) s += ch[((fz + dz) * NB + fy + dy) * NB + fx + dx];
+      out[j] = 0.125 * s;
+    }
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) dst[threadIdx.x + (j0 + jj) * kOpThreads] = out[jj];
   }
 }
 
@@ -199,10 +245,17 @@ __global__ __launch_bounds__(kOpThreads) void refine_kernel(SetTable sets) {
   const RefineItem& it = ((const RefineItem*)ws.items)[blockIdx.x - ws.wg_begin];
   const double* __restrict__ w3 = ws.w;
   const int cx = it.octant & 1, cy = (it.octant >> 1) & 1, cz = (it.octant >> 2) & 1;
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+  constexpr int PT = per_thread<NB>();
+  double out[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int i = threadIdx.x + j * kOpThreads;
     const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
-    it.jw[i] = refine_point<NB, double>(it.parent_w, w3, cx * NB + x, cy * NB + y, cz * NB + z);
+    out[j] = refine_point<NB, double>(it.parent_w, w3, cx * NB + x, cy * NB + y, cz * NB + z);
   }
+  double* const jw = it.jw;
+#pragma unroll
+  for (int j = 0; j < PT; ++j) jw[threadIdx.x + j * kOpThreads] = out[j];
 }
 
 template <int NB, typename T>
@@ -214,29 +267,39 @@ __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
   const double* __restrict__ w3 = ws.w;
   const double* __restrict__ f = it.f ? it.f : ws.in + it.f_in;
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
-    const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
-    const double centre = it.jw[i];
-    double sum = 0.0;
+  constexpr int PT = per_thread<NB>(), G = 2;   // groups of G cells (registers)
+  T* const g = it.g;
+#pragma unroll 1
+  for (int j0 = 0; j0 < PT; j0 += G) {
+    T out[G];
 #pragma unroll
-    for (int face = 0; face < 6; ++face) {
-      const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
-      int q[3] = {p[0], p[1], p[2]};
-      q[ax] += sg;
-      double v;
-      if (q[ax] >= 0 && q[ax] < NB) {
-        v = it.jw[(q[2] * NB + q[1]) * NB + q[0]];
-      } else if (it.nbr[face]) {
-        q[ax] = sg > 0 ? 0 : NB - 1;
-        v = it.nbr[face][(q[2] * NB + q[1]) * NB + q[0]];
-      } else {
-        v = refine_point<NB, double>(it.parent_w, w3, c[0] * NB + (ax == 0 ? q[0] : p[0]),
-                                     c[1] * NB + (ax == 1 ? q[1] : p[1]), c[2] * NB + (ax == 2 ? q[2] : p[2]));
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = jj, i = threadIdx.x + (j0 + jj) * kOpThreads;
+      const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
+      const double centre = it.jw[i];
+      double sum = 0.0;
+#pragma unroll
+      for (int face = 0; face < 6; ++face) {
+        const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
+        int q[3] = {p[0], p[1], p[2]};
+        q[ax] += sg;
+        double v;
+        if (q[ax] >= 0 && q[ax] < NB) {
+          v = it.jw[(q[2] * NB + q[1]) * NB + q[0]];
+        } else if (it.nbr[face]) {
+          q[ax] = sg > 0 ? 0 : NB - 1;
+          v = it.nbr[face][(q[2] * NB + q[1]) * NB + q[0]];
+        } else {
+          v = refine_point<NB, double>(it.parent_w, w3, c[0] * NB + (ax == 0 ? q[0] : p[0]),
+                                       c[1] * NB + (ax == 1 ? q[1] : p[1]), c[2] * NB + (ax == 2 ? q[2] : p[2]));
+        }
+        sum += v;
       }
-      sum += v;
+      const double lap = sum - 6.0 * centre;
+      out[j] = T(f[i] - it.inv_h2 * lap);
     }
-    const double lap = sum - 6.0 * centre;
-    it.g[i] = T(f[i] - it.inv_h2 * lap);
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) g[threadIdx.x + (j0 + jj) * kOpThreads] = out[jj];
   }
 }
 
@@ -249,34 +312,59 @@ __global__ __launch_bounds__(kOpThreads) void residual_kernel(SetTable sets) {
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const ResidualItem& it = ((const ResidualItem*)ws.items)[blockIdx.x - ws.wg_begin];
+  constexpr int PT = per_thread<NB>();
   if (!it.leaf) {
-    for (int i = threadIdx.x; i < N3; i += kOpThreads) it.r[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < PT; ++j) it.r[threadIdx.x + j * kOpThreads] = 0.0;
     return;
   }
   const double* __restrict__ f = ws.in + it.off;
   const double* __restrict__ u = ws.out + it.off;
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
-    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
-    ext[((z + 1) * E + y + 1) * E + x + 1] = u[i];
-  }
+  double fv[PT], uv[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) fv[j] = f[threadIdx.x + j * kOpThreads];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) uv[j] = u[threadIdx.x + j * kOpThreads];
+  // halo cells: face-adjacent neighbour cells, (NB^2 per face) spread over the threads
+  constexpr int HP = (6 * NB * NB + kOpThreads - 1) / kOpThreads;
+  double hv[HP];
+  int hq[HP];
   int missing = 0;
 #pragma unroll
-  for (int face = 0; face < 6; ++face) {
-    if (it.nbr_off[face] < 0) { missing |= 1 << face; continue; }
+  for (int face = 0; face < 6; ++face)
+    if (it.nbr_off[face] < 0) missing |= 1 << face;
+#pragma unroll
+  for (int h = 0; h < HP; ++h) {
+    const int jj = threadIdx.x + h * kOpThreads;
+    hq[h] = -1;
+    if (jj >= 6 * NB * NB) continue;
+    const int face = jj / (NB * NB), j = jj % (NB * NB);
+    if ((missing >> face) & 1) continue;
     const double* nb = ws.out + it.nbr_off[face];
     const int ax = face >> 1, hi = face & 1;
-    for (int j = threadIdx.x; j < NB * NB; j += kOpThreads) {
-      const int a = j % NB, b = j / NB;
-      int p[3], q[3];                      // p: cell in the neighbour, q: halo cell in ext
-      const int src = hi ? 0 : NB - 1, dst = hi ? NB + 1 : 0;
-      if (ax == 0) { p[0] = src; p[1] = a; p[2] = b; q[0] = dst; q[1] = a + 1; q[2] = b + 1; }
-      else if (ax == 1) { p[0] = a; p[1] = src; p[2] = b; q[0] = a + 1; q[1] = dst; q[2] = b + 1; }
-      else { p[0] = a; p[1] = b; p[2] = src; q[0] = a + 1; q[1] = b + 1; q[2] = dst; }
-      ext[(q[2] * E + q[1]) * E + q[0]] = nb[(p[2] * NB + p[1]) * NB + p[0]];
-    }
+    const int a = j % NB, b = j / NB;
+    int p[3], q[3];                      // p: cell in the neighbour, q: halo cell in ext
+    const int src = hi ? 0 : NB - 1, dst = hi ? NB + 1 : 0;
+    if (ax == 0) { p[0] = src; p[1] = a; p[2] = b; q[0] = dst; q[1] = a + 1; q[2] = b + 1; }
+    else if (ax == 1) { p[0] = a; p[1] = src; p[2] = b; q[0] = a + 1; q[1] = dst; q[2] = b + 1; }
+    else { p[0] = a; p[1] = b; p[2] = src; q[0] = a + 1; q[1] = b + 1; q[2] = dst; }
+    hq[h] = (q[2] * E + q[1]) * E + q[0];
+    hv[h] = nb[(p[2] * NB + p[1]) * NB + p[0]];
   }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int i = threadIdx.x + j * kOpThreads;
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    ext[((z + 1) * E + y + 1) * E + x + 1] = uv[j];
+  }
+#pragma unroll
+  for (int h = 0; h < HP; ++h)
+    if (hq[h] >= 0) ext[hq[h]] = hv[h];
   __syncthreads();
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {
+  double out[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int i = threadIdx.x + j * kOpThreads;
     const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
     const bool edge = ((missing & 1) && x == 0) || ((missing & 2) && x == NB - 1) ||
                       ((missing & 4) && y == 0) || ((missing & 8) && y == NB - 1) ||
@@ -284,8 +372,11 @@ __global__ __launch_bounds__(kOpThreads) void residual_kernel(SetTable sets) {
     const int c = ((z + 1) * E + y + 1) * E + x + 1;
     const double lap = ext[c - 1] + ext[c + 1] + ext[c - E] + ext[c + E] + ext[c - E * E] +
                        ext[c + E * E] - 6.0 * ext[c];
-    it.r[i] = edge ? 0.0 : f[i] - it.inv_h2 * lap;
+    out[j] = edge ? 0.0 : fv[j] - it.inv_h2 * lap;
   }
+  double* const r = it.r;
+#pragma unroll
+  for (int j = 0; j < PT; ++j) r[threadIdx.x + j * kOpThreads] = out[j];
 }
 
 __global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
