@@ -237,70 +237,146 @@ __device__ __forceinline__ T refine_point(const T* __restrict__ pw, const double
   return s;
 }
 
+// Jw on a child block: the quadratic is separable, so it is applied along x, then y, then z
+// through LDS over the parent cells the octant's stencils touch (R = NB/2 + 2 per axis, from
+// the first child cell's stencil start; the planner checks that every stencil of the octant
+// lies inside that range).
 template <int NB>
 __global__ __launch_bounds__(kOpThreads) void refine_kernel(SetTable sets) {
-  constexpr int N3 = NB * NB * NB;
+  constexpr int R = NB / 2 + 2, PT = per_thread<NB>();
+  constexpr int R3 = R * R * R, PL = R3 > R * NB * NB ? R3 : R * NB * NB;
+  __shared__ double pl[PL];              // parent region [z][y][x], then the y pass [z][y][X]
+  __shared__ double t1[R * R * NB];      // x pass [z][y][X]
+  __shared__ double tab[3][NB][4];       // per axis and child index: stencil start - base, w0..w2
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const RefineItem& it = ((const RefineItem*)ws.items)[blockIdx.x - ws.wg_begin];
   const double* __restrict__ w3 = ws.w;
-  const int cx = it.octant & 1, cy = (it.octant >> 1) & 1, cz = (it.octant >> 2) & 1;
-  constexpr int PT = per_thread<NB>();
+  const double* __restrict__ pw = it.parent_w;
+  const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
+  // table row of child index j along axis d: w3[4 (c_d NB + j + 1) ...]
+  const int b0 = (int)w3[4 * (c[0] * NB + 1)], b1 = (int)w3[4 * (c[1] * NB + 1)],
+            b2 = (int)w3[4 * (c[2] * NB + 1)];
+  if (threadIdx.x < 3 * NB) {
+    const int d = threadIdx.x / NB, j = threadIdx.x % NB;
+    const double* r = w3 + 4 * (c[d] * NB + j + 1);
+    const int base = d == 0 ? b0 : d == 1 ? b1 : b2;
+    tab[d][j][0] = r[0] - base;
+    tab[d][j][1] = r[1];
+    tab[d][j][2] = r[2];
+    tab[d][j][3] = r[3];
+  }
+  {
+    constexpr int RP = (R3 + kOpThreads - 1) / kOpThreads;
+    double v[RP];
+#pragma unroll
+    for (int h = 0; h < RP; ++h) {
+      const int i = threadIdx.x + h * kOpThreads;
+      const int x = b0 + i % R, y = b1 + (i / R) % R, z = b2 + i / (R * R);
+      v[h] = (i < R3 && x < NB && y < NB && z < NB) ? pw[(z * NB + y) * NB + x] : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < RP; ++h)
+      if (threadIdx.x + h * kOpThreads < R3) pl[threadIdx.x + h * kOpThreads] = v[h];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R * R * NB; i += kOpThreads) {        // x
+    const int X = i % NB, zy = i / NB;
+    const int lo = (int)tab[0][X][0];
+    const double* row = pl + zy * R + lo;
+    t1[i] = tab[0][X][1] * row[0] + tab[0][X][2] * row[1] + tab[0][X][3] * row[2];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R * NB * NB; i += kOpThreads) {       // y
+    const int X = i % NB, Y = (i / NB) % NB, z = i / (NB * NB);
+    const int lo = (int)tab[1][Y][0];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s += tab[1][Y][1 + k] * t1[(z * R + lo + k) * NB + X];
+    pl[i] = s;
+  }
+  __syncthreads();
   double out[PT];
 #pragma unroll
-  for (int j = 0; j < PT; ++j) {
+  for (int j = 0; j < PT; ++j) {                                       // z
     const int i = threadIdx.x + j * kOpThreads;
-    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
-    out[j] = refine_point<NB, double>(it.parent_w, w3, cx * NB + x, cy * NB + y, cz * NB + z);
+    const int XY = i % (NB * NB), Z = i / (NB * NB);
+    const int lo = (int)tab[2][Z][0];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s += tab[2][Z][1 + k] * pl[(lo + k) * NB * NB + XY];
+    out[j] = s;
   }
   double* const jw = it.jw;
 #pragma unroll
   for (int j = 0; j < PT; ++j) jw[threadIdx.x + j * kOpThreads] = out[j];
 }
 
+// g = f - h^-2 L(Jw): the block's Jw and its one-cell halo are staged in LDS; a halo cell is the
+// face-adjacent neighbour block's Jw where that block exists, else the parent's quadratic
+// extended one child cell outward (each halo cell computed by one thread).
 template <int NB, typename T>
 __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
-  constexpr int N3 = NB * NB * NB;
+  constexpr int E = NB + 2, PT = per_thread<NB>();
+  __shared__ double ext[E * E * E];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const CorrectItem<T>& it = ((const CorrectItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
   const double* __restrict__ w3 = ws.w;
   const double* __restrict__ f = it.f ? it.f : ws.in + it.f_in;
+  const double* __restrict__ jw = it.jw;
+  const double* __restrict__ pw = it.parent_w;
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
-  constexpr int PT = per_thread<NB>(), G = 2;   // groups of G cells (registers)
-  T* const g = it.g;
+  double fv[PT], jv[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) fv[j] = f[threadIdx.x + j * kOpThreads];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) jv[j] = jw[threadIdx.x + j * kOpThreads];
+  // halo cells (6 NB^2) spread over the threads
+  constexpr int HP = (6 * NB * NB + kOpThreads - 1) / kOpThreads;
 #pragma unroll 1
-  for (int j0 = 0; j0 < PT; j0 += G) {
-    T out[G];
-#pragma unroll
-    for (int jj = 0; jj < G; ++jj) {
-      const int j = jj, i = threadIdx.x + (j0 + jj) * kOpThreads;
-      const int p[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
-      const double centre = it.jw[i];
-      double sum = 0.0;
-#pragma unroll
-      for (int face = 0; face < 6; ++face) {
-        const int ax = face >> 1, sg = (face & 1) ? 1 : -1;
-        int q[3] = {p[0], p[1], p[2]};
-        q[ax] += sg;
-        double v;
-        if (q[ax] >= 0 && q[ax] < NB) {
-          v = it.jw[(q[2] * NB + q[1]) * NB + q[0]];
-        } else if (it.nbr[face]) {
-          q[ax] = sg > 0 ? 0 : NB - 1;
-          v = it.nbr[face][(q[2] * NB + q[1]) * NB + q[0]];
-        } else {
-          v = refine_point<NB, double>(it.parent_w, w3, c[0] * NB + (ax == 0 ? q[0] : p[0]),
-                                       c[1] * NB + (ax == 1 ? q[1] : p[1]), c[2] * NB + (ax == 2 ? q[2] : p[2]));
-        }
-        sum += v;
-      }
-      const double lap = sum - 6.0 * centre;
-      out[j] = T(f[i] - it.inv_h2 * lap);
+  for (int h = 0; h < HP; ++h) {
+    const int jj = threadIdx.x + h * kOpThreads;
+    if (jj >= 6 * NB * NB) break;
+    const int face = jj / (NB * NB), j = jj % (NB * NB);
+    const int ax = face >> 1, hi = face & 1;
+    const int a = j % NB, b = j / NB;
+    int q[3];                              // halo cell in the block's coordinates (-1 or NB on ax)
+    const int o = hi ? NB : -1;
+    if (ax == 0) { q[0] = o; q[1] = a; q[2] = b; }
+    else if (ax == 1) { q[0] = a; q[1] = o; q[2] = b; }
+    else { q[0] = a; q[1] = b; q[2] = o; }
+    double v;
+    if (const double* nb = it.nbr[face]) {
+      int p[3] = {q[0], q[1], q[2]};
+      p[ax] = hi ? 0 : NB - 1;
+      v = nb[(p[2] * NB + p[1]) * NB + p[0]];
+    } else {
+      v = refine_point<NB, double>(pw, w3, c[0] * NB + q[0], c[1] * NB + q[1], c[2] * NB + q[2]);
     }
-#pragma unroll
-    for (int jj = 0; jj < G; ++jj) g[threadIdx.x + (j0 + jj) * kOpThreads] = out[jj];
+    ext[((q[2] + 1) * E + q[1] + 1) * E + q[0] + 1] = v;
   }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int i = threadIdx.x + j * kOpThreads;
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    ext[((z + 1) * E + y + 1) * E + x + 1] = jv[j];
+  }
+  __syncthreads();
+  const double inv_h2 = it.inv_h2;
+  T out[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int i = threadIdx.x + j * kOpThreads;
+    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+    const int cc = ((z + 1) * E + y + 1) * E + x + 1;
+    const double lap = ext[cc - 1] + ext[cc + 1] + ext[cc - E] + ext[cc + E] + ext[cc - E * E] +
+                       ext[cc + E * E] - 6.0 * ext[cc];
+    out[j] = T(fv[j] - inv_h2 * lap);
+  }
+  T* const g = it.g;
+#pragma unroll
+  for (int j = 0; j < PT; ++j) g[threadIdx.x + j * kOpThreads] = out[j];
 }
 
 // r = f - h^-2 (sum of 6 neighbours - 6 u) on cells whose neighbours all exist; the block and

@@ -808,6 +808,16 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   }
   {
     const std::vector<double> W = lagrange_matrix(nb, p->n_i), W3 = refine_table(nb);
+    // the refinement kernel stages nb/2 + 2 parent cells per axis from the stencil start of
+    // the octant's first child cell
+    for (int c = 0; c < 2; ++c)
+      for (int j = 0; j < nb; ++j) {
+        const int lo = (int)W3[4 * (c * nb + j + 1)], base = (int)W3[4 * (c * nb + 1)];
+        if (lo < base || lo - base + 3 > nb / 2 + 2) {
+          if (err) *err = "internal: refinement stencil outside the staged parent region";
+          return hipErrorInvalidValue;
+        }
+      }
     LGF_HIP_CHECK(ar.alloc(&tmp, W.size() * sizeof(double)));
     p->d_w = (double*)tmp;
     if (!p->dry) LGF_HIP_CHECK(hipMemcpy(p->d_w, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
