@@ -1612,7 +1612,7 @@ hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st) {
 // split) and the near MAC's (rows of 4 or 8 targets, 2 x 2-row tiles; the planner builds each
 // shape's items).  The choice is remembered per (N_b, element type, tile count or pair count)
 // for the process and in the file named by LGF_TUNE_CACHE (one "nb key count mode" line per
-// entry).
+// entry).  LGF_TUNE_VERBOSE prints every candidate's time on stderr.
 namespace {
 std::mutex g_tune_mu;
 std::map<std::array<int64_t, 3>, int> g_tune;
@@ -1644,6 +1644,7 @@ void tune_store(const std::array<int64_t, 3>& k, int mode) {
 hipError_t plan_autotune(Plan* p, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load();
+  static const bool verbose = std::getenv("LGF_TUNE_VERBOSE") != nullptr;   // candidate times on stderr
   hipEvent_t a, b;
   LGF_HIP_CHECK(hipEventCreate(&a));
   LGF_HIP_CHECK(hipEventCreate(&b));
@@ -1674,6 +1675,9 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
           LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
         }
         std::sort(t, t + 3);
+        if (verbose)
+          std::fprintf(stderr, "[lgf tune] mac ty %d count %d mode %d: %.1f us\n", s.ty, s.count, cand[c] | half,
+                       1e3f * t[1]);
         if (c == 0 || t[1] < 0.95f * best) {    // the first candidate is the default shape
           best = t[1];
           best_mode = cand[c];
@@ -1714,6 +1718,9 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
         LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
       }
       std::sort(t, t + 3);
+      if (verbose)
+        std::fprintf(stderr, "[lgf tune] kind %d ty %d work %lld mode %d: %.1f us\n", cands[c].kind, cands[c].ty,
+                     (long long)cands[c].work, cands[c].mode, 1e3f * t[1]);
       // an alternative replaces the planner's shape only when clearly faster (5%), so that
       // near ties do not flip from run to run
       if (c == 0 || t[1] < 0.95f * best) {
