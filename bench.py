@@ -48,20 +48,24 @@ def spectrum_size(n_b):
     return P * P * (n_b + 1)
 
 
-def algorithmic(entry, n_b, info):
-    """Algorithmic work of one profiled entry (summed over its launches): (flops, flop peak in
-    TFLOP/s, compulsory HBM bytes), None where not defined.  MACs: 8 flops per complex
-    multiply-add, S per (target, source) pair (work = pairs); the near MAC reads each source
-    spectrum and the 27 kernel spectra once and writes each target spectrum once (FP32 tiles
-    compute in FP32; rows of FP64 spectra in FP64).  Transforms: per item (work = items) the block or the 8
-    child blocks of a super-block, and the half spectrum (2 S reals)."""
+def algorithmic(entry, n_b, info, passes):
+    """Algorithmic work of one profiled entry (summed over its launches, `passes` solve passes):
+    (flops, flop peak in TFLOP/s, compulsory HBM bytes), None where not defined.  MACs: 8 flops
+    per complex multiply-add, S per (target, source) pair (work = pairs); a MAC reads each source
+    spectrum and each kernel spectrum of its level once and writes each target spectrum once
+    (near MAC: the super-block spectra and the 27 super-block kernels; coarse MAC: the block
+    spectra of the coarse levels and their 316 kernels per level).  FP32 tiles compute in FP32;
+    FP64 spectra in FP64.  Transforms: per item (work = items) the block or the 8 child blocks
+    of a super-block, and the half spectrum (2 S reals)."""
     es = 4 if entry["precision"] == "fp32" else 8
     S, S2 = spectrum_size(n_b), spectrum_size(2 * n_b)
     N3 = n_b ** 3
     k = entry["kernel"]
     peak = PEAK["fp32_vector_tflops"] if entry["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
     if k == "mac":
-        return 8.0 * S * entry["work"], peak, None
+        coarse_kernels = info["spectra"] - (27 if info["super_forward"] else 343)
+        per_pass = (info["fft_forward"] + info["fft_inverse"] + coarse_kernels) * 2 * S * es
+        return 8.0 * S * entry["work"], peak, per_pass * passes
     if k == "near_mac":
         per_launch = (info["super_forward"] + info["super_inverse"] + 27) * 2 * S2 * es
         return 8.0 * S2 * entry["work"], peak, per_launch * entry["launches"]
@@ -258,7 +262,7 @@ def main():
     # flops, over the measured time
     kern = []
     for e in prof:
-        flops, fpeak, nbytes = algorithmic(e, L.n_b, info)
+        flops, fpeak, nbytes = algorithmic(e, L.n_b, info, args.steps * (1 + args.dc))
         e = dict(e, avg_us=1e3 * e["ms"] / max(e["launches"], 1))
         t = e["ms"] * 1e-3
         if flops is not None:

@@ -129,6 +129,13 @@ const char* lgf_status_string(lgf_status s);
  *   as interleaved doubles).  s = 0 selects the base-level super-block kernels instead: block
  *   side B = 2 N_b, G(d B + r) for |d| <= 1, half spectrum [2B][2B][B+1]. */
 lgf_status lgf_green_eval(const int32_t* n, int64_t m, double* out, lgf_stream_t stream);
+/* lgf_plan_set_mac_shape: forces the launch shape of the tile spectral MAC steps of p (coarse
+ *   octree levels; also the base level with LGF_BASE_BLOCK) whose element type has it: shape 1
+ *   one target row per wavefront, 2 two rows, 4 the tile's four rows (FP32 steps), 6 source rows
+ *   split over 6 wavefronts (FP64 steps), 8 the tile's rows on 4 wavefronts sharing each source
+ *   row through LDS (FP64 steps); 0 restores the planner's and autotuner's choice.  So that every
+ *   shape can be checked; results agree up to rounding order.  LGF_EINVAL for another value. */
+lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape);
 lgf_status lgf_green_table(double* out, lgf_stream_t stream);
 lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, int32_t dz,
                                double* out, lgf_stream_t stream);

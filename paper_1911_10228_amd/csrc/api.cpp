@@ -146,6 +146,12 @@ lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out) {
   return LGF_OK;
 }
 
+lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape) {
+  if (!p) return LGF_EINVAL;
+  const hipError_t e = lgf::plan_set_mac_shape(p->p, shape);
+  return e == hipErrorInvalidValue ? LGF_EINVAL : from_hip(e);
+}
+
 lgf_status lgf_plan_destroy(lgf_plan_t p) {
   if (!p) return LGF_EINVAL;
   lgf::plan_free(p->p);

@@ -90,11 +90,15 @@ struct WorkSet {
   const void* items;   // device array of per-kernel item structs
   int64_t wg_begin;    // first workgroup of this set
   int32_t count;       // number of items
-  int32_t aux;         // kernel-specific
+  int32_t aux;         // flags: kAuxAccumulate
   const double* in;    // the solve pass's input field (items address it by offset)
   double* out;         // the solve pass's output field
   const double* w;     // the plan's 1-D weight table of this kernel
 };
+
+// WorkSet::aux: the combine adds into the output field instead of writing it (the pass is a
+// defect-correction re-solve whose result updates u)
+constexpr int32_t kAuxAccumulate = 1;
 
 struct SetTable {
   int32_t n;

@@ -6,7 +6,8 @@
 //     correction g = f - L^l(J^l w^l) (Sec. 3, Algorithm 2, step 2b, reading: the operator acts
 //     on the interpolated field); neighbour values come from the adjacent same-level block, or,
 //     where there is none, from the parent's quadratic extended one child cell outward;
-//   * FP64 residual r = f - L^l u of defect correction and the update u += e.
+//   * FP64 residual r = f - L^l u of defect correction (the update u += e is the correction
+//     pass's combine in accumulate mode).
 // The 1-D weight tables are computed on the host in FP64.
 #include "kernels.hpp"
 
@@ -161,6 +162,10 @@ __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
   if (it.base) {
 #pragma unroll
     for (int j = 0; j < PT; ++j) v[j] += it.base[threadIdx.x + j * kOpThreads];
+  }
+  if (!it.dst_d && (ws.aux & kAuxAccumulate)) {       // defect-correction update of u
+#pragma unroll
+    for (int j = 0; j < PT; ++j) v[j] += dd[threadIdx.x + j * kOpThreads];
   }
 #pragma unroll
   for (int j = 0; j < PT; ++j) dd[threadIdx.x + j * kOpThreads] = v[j];
@@ -379,87 +384,96 @@ __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
   for (int j = 0; j < PT; ++j) g[threadIdx.x + j * kOpThreads] = out[j];
 }
 
-// r = f - h^-2 (sum of 6 neighbours - 6 u) on cells whose neighbours all exist; the block and
-// its one-cell halo (from the face-adjacent same-level blocks) are staged in LDS.
+// r = f - h^-2 (sum of 6 neighbours - 6 u) on cells whose neighbours all exist.  One workgroup
+// per (block, z-slab of NB / kResidualSlabs planes) and one thread per (x, y) column: the slab
+// and its one-cell halo (from the block itself or the face-adjacent same-level blocks) are
+// staged in LDS.  Writes r in FP64 and/or its FP32 rounding (null pointers skip).
 template <int NB>
-__global__ __launch_bounds__(kOpThreads) void residual_kernel(SetTable sets) {
-  constexpr int N3 = NB * NB * NB, E = NB + 2;
-  __shared__ double ext[E * E * E];
+__global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
+  constexpr int SZ = NB / kResidualSlabs, E = NB + 2, N2 = NB * NB;
+  __shared__ double ext[(SZ + 2) * E * E];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
-  const ResidualItem& it = ((const ResidualItem*)ws.items)[blockIdx.x - ws.wg_begin];
-  constexpr int PT = per_thread<NB>();
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const ResidualItem& it = ((const ResidualItem*)ws.items)[local / kResidualSlabs];
+  const int z0 = (int)(local % kResidualSlabs) * SZ;
+  double* const r = it.r;
+  float* const conv = it.conv;
+  if (!r && !conv) return;
+  const int t = threadIdx.x, x = t % NB, y = t / NB;
   if (!it.leaf) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j) it.r[threadIdx.x + j * kOpThreads] = 0.0;
+    for (int j = 0; j < SZ; ++j) {
+      const int i = (z0 + j) * N2 + t;
+      if (r) r[i] = 0.0;
+      if (conv) conv[i] = 0.0f;
+    }
     return;
   }
   const double* __restrict__ f = ws.in + it.off;
   const double* __restrict__ u = ws.out + it.off;
-  double fv[PT], uv[PT];
-#pragma unroll
-  for (int j = 0; j < PT; ++j) fv[j] = f[threadIdx.x + j * kOpThreads];
-#pragma unroll
-  for (int j = 0; j < PT; ++j) uv[j] = u[threadIdx.x + j * kOpThreads];
-  // halo cells: face-adjacent neighbour cells, (NB^2 per face) spread over the threads
-  constexpr int HP = (6 * NB * NB + kOpThreads - 1) / kOpThreads;
-  double hv[HP];
-  int hq[HP];
   int missing = 0;
 #pragma unroll
   for (int face = 0; face < 6; ++face)
     if (it.nbr_off[face] < 0) missing |= 1 << face;
+  // own planes z0 - 1 .. z0 + SZ (the outer two from the z neighbours at the block faces)
+  double fv[SZ], uv[SZ + 2];
+#pragma unroll
+  for (int j = 0; j < SZ; ++j) fv[j] = f[(z0 + j) * N2 + t];
+#pragma unroll
+  for (int j = 0; j < SZ + 2; ++j) {
+    const int z = z0 - 1 + j;
+    uv[j] = 0.0;
+    if (z >= 0 && z < NB) uv[j] = u[z * N2 + t];
+    else if (z < 0 && !(missing & 16)) uv[j] = ws.out[it.nbr_off[4] + (NB - 1) * N2 + t];
+    else if (z >= NB && !(missing & 32)) uv[j] = ws.out[it.nbr_off[5] + t];
+  }
+  // x and y faces of the slab's planes: 4 faces x NB x SZ cells over the threads
+  constexpr int HP = (4 * NB * SZ + N2 - 1) / N2;
+  double hv[HP];
+  int hq[HP];
 #pragma unroll
   for (int h = 0; h < HP; ++h) {
-    const int jj = threadIdx.x + h * kOpThreads;
+    const int jj = t + h * N2;
     hq[h] = -1;
-    if (jj >= 6 * NB * NB) continue;
-    const int face = jj / (NB * NB), j = jj % (NB * NB);
+    if (jj >= 4 * NB * SZ) continue;
+    const int face = jj / (NB * SZ), rem = jj % (NB * SZ), a = rem % NB, zz = rem / NB;
     if ((missing >> face) & 1) continue;
     const double* nb = ws.out + it.nbr_off[face];
     const int ax = face >> 1, hi = face & 1;
-    const int a = j % NB, b = j / NB;
-    int p[3], q[3];                      // p: cell in the neighbour, q: halo cell in ext
     const int src = hi ? 0 : NB - 1, dst = hi ? NB + 1 : 0;
-    if (ax == 0) { p[0] = src; p[1] = a; p[2] = b; q[0] = dst; q[1] = a + 1; q[2] = b + 1; }
-    else if (ax == 1) { p[0] = a; p[1] = src; p[2] = b; q[0] = a + 1; q[1] = dst; q[2] = b + 1; }
-    else { p[0] = a; p[1] = b; p[2] = src; q[0] = a + 1; q[1] = b + 1; q[2] = dst; }
-    hq[h] = (q[2] * E + q[1]) * E + q[0];
-    hv[h] = nb[(p[2] * NB + p[1]) * NB + p[0]];
+    int px, py, qx, qy;                   // cell in the neighbour, halo cell in ext
+    if (ax == 0) { px = src; py = a; qx = dst; qy = a + 1; }
+    else { px = a; py = src; qx = a + 1; qy = dst; }
+    hq[h] = ((zz + 1) * E + qy) * E + qx;
+    hv[h] = nb[(z0 + zz) * N2 + py * NB + px];
   }
 #pragma unroll
-  for (int j = 0; j < PT; ++j) {
-    const int i = threadIdx.x + j * kOpThreads;
-    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
-    ext[((z + 1) * E + y + 1) * E + x + 1] = uv[j];
-  }
+  for (int j = 0; j < SZ + 2; ++j) ext[(j * E + y + 1) * E + x + 1] = uv[j];
 #pragma unroll
   for (int h = 0; h < HP; ++h)
     if (hq[h] >= 0) ext[hq[h]] = hv[h];
   __syncthreads();
-  double out[PT];
+  const double inv_h2 = it.inv_h2;
+  double out[SZ];
 #pragma unroll
-  for (int j = 0; j < PT; ++j) {
-    const int i = threadIdx.x + j * kOpThreads;
-    const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
+  for (int j = 0; j < SZ; ++j) {
+    const int z = z0 + j;
     const bool edge = ((missing & 1) && x == 0) || ((missing & 2) && x == NB - 1) ||
                       ((missing & 4) && y == 0) || ((missing & 8) && y == NB - 1) ||
                       ((missing & 16) && z == 0) || ((missing & 32) && z == NB - 1);
-    const int c = ((z + 1) * E + y + 1) * E + x + 1;
+    const int c = ((j + 1) * E + y + 1) * E + x + 1;
     const double lap = ext[c - 1] + ext[c + 1] + ext[c - E] + ext[c + E] + ext[c - E * E] +
                        ext[c + E * E] - 6.0 * ext[c];
-    out[j] = edge ? 0.0 : fv[j] - it.inv_h2 * lap;
+    out[j] = edge ? 0.0 : fv[j] - inv_h2 * lap;
   }
-  double* const r = it.r;
 #pragma unroll
-  for (int j = 0; j < PT; ++j) r[threadIdx.x + j * kOpThreads] = out[j];
+  for (int j = 0; j < SZ; ++j) {
+    const int i = (z0 + j) * N2 + t;
+    if (r) r[i] = out[j];
+    if (conv) conv[i] = float(out[j]);
+  }
 }
-
-__global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += x[i];
-}
-
 
 }  // namespace
 
@@ -501,11 +515,9 @@ template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t
   LGF_LAUNCH_SIMPLE(correct_kernel<NB, T>)
 }
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
-  LGF_LAUNCH_SIMPLE(residual_kernel<NB>)
-}
-hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  axpy_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(y, x, n);
+  const int64_t wg = assign_wg(t, kResidualSlabs);
+  if (wg == 0) return hipSuccess;
+  LGF_NB_DISPATCH(nb, residual_kernel<NB><<<(unsigned)wg, NB * NB, 0, st>>>(t));
   return hipGetLastError();
 }
 

@@ -166,13 +166,16 @@ template <typename T> struct CorrectItem {
   double inv_h2;
 };
 struct ResidualItem {
-  double* r;             // r = f - h^-2 L u where all 6 neighbours exist, 0 elsewhere
+  double* r;             // r = f - h^-2 L u where all 6 neighbours exist, 0 elsewhere (or null)
+  float* conv;           // the same rounded to FP32 (the correction pass's base-level source
+                         // of a leaf block, written here instead of by a separate convert), or null
   int64_t off;           // block offset of f (in WorkSet::in) and u (in WorkSet::out)
   int64_t nbr_off[6];    // same-level neighbour blocks of u in WorkSet::out (-1: absent)
   double inv_h2;
   int32_t leaf;          // 0: whole block r = 0
   int32_t pad;
 };
+constexpr int kResidualSlabs = 4;       // workgroups (z-slabs) per block of the residual
 
 // ----------------------------------------------------------------------------- launchers
 int quad_nodes();
@@ -189,8 +192,10 @@ hipError_t launch_kernel_spectra(int nb, int nspec, const int32_t* d_sd, const d
 template <typename T> hipError_t launch_fft_fwd(int nb, SetTable& t, hipStream_t st);
 template <typename T> hipError_t launch_fft_inv(int nb, SetTable& t, hipStream_t st);
 template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st, int mode = 0);
-constexpr int kMacModes32[3] = {1, 2, 4};   // candidate launch shapes for the autotuner
-constexpr int kMacModes64[3] = {1, 2, 6};
+// candidate launch shapes for the autotuner, the planner's default first (FP64: shared sources)
+constexpr int kMacModes32[4] = {1, 2, 4, 4};
+constexpr int kMacModes64[4] = {8, 1, 2, 6};
+constexpr int kMacDefault64 = 8;
 template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
 template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
 template <typename T> hipError_t launch_combine(int nb, SetTable& t, hipStream_t st);
@@ -199,7 +204,6 @@ hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_refine(int nb, SetTable& t, hipStream_t st);                          // ws.w = W3
 template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st);  // ws.w = W3
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
-hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st);
 // mode: W (4 or 8) for NearRow items; kNearTiled + 4 for NearTile items

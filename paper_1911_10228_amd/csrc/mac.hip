@@ -214,6 +214,107 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
     }
 }
 
+// Shared-source form (FP64 kernels from memory): the tile's 4 wavefronts (one target row each)
+// walk the tile's source rows together.  Each source row's XW + 6 spectra are loaded once per
+// workgroup, spread over the wavefronts, into one of two LDS buffers, and every wavefront reads
+// them from there; its 7 kernel values come from memory.  The next source row's spectra and
+// kernel values are loaded while the current row is applied, one barrier per source row
+// (double buffering: a buffer is rewritten only after the barrier that follows its last reads).
+template <typename T, int XW>
+__global__ __launch_bounds__(256) void mac_shared_kernel(SetTable sets, int S) {
+  constexpr int NS = XW + 6;
+  constexpr int PW = (NS + 3) / 4;               // staged spectra per wavefront and source row
+  __shared__ cpx<T> sb[2][NS * 64];
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;       // wg_begin is a multiple of 8
+  const int ntiles = ws.count;
+  const int xcd = (int)(local & 7);
+  const int64_t j = local >> 3;
+  const int chunk = (int)(j / ntiles) * 8 + xcd;
+  const int ti = (int)(j % ntiles);
+  if (chunk * 64 >= S) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int k = chunk * 64 + lane;
+  const MacTile<T>* tile = (const MacTile<T>*)ws.items + ti;
+  const cptr64 kp = (cptr64)tile->kptr;
+  gptr<T> F = (gptr<T>)tile->fhat;
+  const int r = wave;
+  const bool row = (tile->row_mask >> r) & 1;
+  const bool base = tile->flags & 1;
+  uint64_t todo = tile->pair_mask;
+  cpx<T> acc[XW];
+#pragma unroll
+  for (int i = 0; i < XW; ++i) acc[i] = {T(0), T(0)};
+  if (todo) {
+    // staged entries of this wavefront: e = wave + 4 q (q < PW, e < NS); kernel values of row r
+    int pj = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    cpx<T> st[PW], ks[7];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int e = wave + 4 * q;
+      if (e < NS) st[q] = gload<T>(F, (int64_t)tile->src[pj][e] * S + k);
+    }
+#pragma unroll
+    for (int d = 0; d < 7; ++d) ks[d] = gload<T>((gptr<T>)kp[kindex(r, pj / 6, pj % 6, d)], k);
+    int buf = 0;
+    for (;;) {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int e = wave + 4 * q;
+        if (e < NS) sb[buf][e * 64 + lane] = st[q];
+      }
+      __syncthreads();
+      // next source row (the last iteration reloads the current one: same loads every time)
+      const bool more = todo != 0;
+      const int pn = more ? __builtin_ctzll(todo) : pj;
+      todo &= todo - 1;
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int e = wave + 4 * q;
+        if (e < NS) st[q] = gload<T>(F, (int64_t)tile->src[pn][e] * S + k);
+      }
+      cpx<T> kn[7];
+#pragma unroll
+      for (int d = 0; d < 7; ++d) kn[d] = gload<T>((gptr<T>)kp[kindex(r, pn / 6, pn % 6, d)], k);
+      if (row) {
+        cpx<T> fs[NS];
+#pragma unroll
+        for (int e = 0; e < NS; ++e) fs[e] = sb[buf][e * 64 + lane];
+        mac_row<T, XW>(acc, fs, r, pj / 6, pj % 6, base, [&](int dxi) { return ks[dxi]; });
+      }
+      if (!more) break;
+#pragma unroll
+      for (int d = 0; d < 7; ++d) ks[d] = kn[d];
+      pj = pn;
+      buf ^= 1;
+    }
+  }
+  if (!row) return;
+  gmut<T> U = (gmut<T>)tile->uhat;
+#pragma unroll
+  for (int i = 0; i < XW; ++i) {
+    const int t = tile->tgt[r][i];
+    if (t >= 0) {
+      U[2 * ((int64_t)t * S + k)] = acc[i].x;
+      U[2 * ((int64_t)t * S + k) + 1] = acc[i].y;
+    }
+  }
+}
+
+template <typename T, int XW> hipError_t launch_shared(int S, SetTable& t, hipStream_t st) {
+  const int chunks8 = (S / 64 + 7) / 8;
+  int64_t wg = 0;
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (int64_t)t.s[i].count * chunks8 * 8;
+  }
+  if (wg == 0) return hipSuccess;
+  mac_shared_kernel<T, XW><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  return hipGetLastError();
+}
+
 template <typename T, int WAVES, int ROWS, bool KLDS, int SPLIT = 1, int XW = kMacL>
 hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
   constexpr int UPT = 4 / ROWS, UPW = WAVES / SPLIT;
@@ -233,9 +334,11 @@ hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
 
 // Launch shape (mode): 1 row, 2 pair, 4 tile = rows per wavefront; 6 split = FP64 source rows
 // over 6 wavefronts; 0 = default (one row per wavefront; FP32 with the kernel spectra in LDS and
-// 16 wavefronts per workgroup, FP64 with the kernel spectra prefetched from memory).  Bit
+// 16 wavefronts per workgroup, FP64 with the kernel spectra prefetched from memory); 8 shared =
+// FP64 tile rows on 4 wavefronts sharing each source row through LDS.  Bit
 // kMacHalfRows marks tiles whose rows hold 4 targets (set by the planner with the items).  The
-// plan's autotuner picks the shape per step; LGF_MAC_MODE = row | pair | tile | split overrides it.
+// plan's autotuner picks the shape per step; LGF_MAC_MODE = row | pair | tile | split | shared
+// overrides it.
 int mac_mode_override() {
   static const int m = [] {
     const char* e = std::getenv("LGF_MAC_MODE");
@@ -244,6 +347,7 @@ int mac_mode_override() {
     if (!std::strcmp(e, "pair")) return 2;
     if (!std::strcmp(e, "tile")) return 4;
     if (!std::strcmp(e, "split")) return 6;
+    if (!std::strcmp(e, "shared")) return 8;
     return 0;
   }();
   return m;
@@ -264,6 +368,7 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
     } else {
       if (mode == 2) return launch_tiles<T, 4, 2, false, 1, 4>(S, t, st);
       if (mode == 6) return launch_tiles<T, 6, 1, false, 6, 4>(S, t, st);
+      if (mode == 8) return launch_shared<T, 4>(S, t, st);
       return launch_tiles<T, 4, 1, false, 1, 4>(S, t, st);
     }
   }
@@ -274,6 +379,7 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
   } else {
     if (mode == 2) return launch_tiles<T, 4, 2, false>(S, t, st);
     if (mode == 6) return launch_tiles<T, 6, 1, false, 6>(S, t, st);
+    if (mode == 8) return launch_shared<T, kMacL>(S, t, st);
     return launch_tiles<T, 4, 1, false>(S, t, st);
   }
 }

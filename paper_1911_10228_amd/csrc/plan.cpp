@@ -541,7 +541,8 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_RESIDUAL: {
         const auto& it = ((const ResidualItem*)items)[i];
-        if (!in_ranges(p, it.r, N3 * 8) || !off_ok(it.off)) return bad("residual", i);
+        if ((it.r && !in_ranges(p, it.r, N3 * 8)) || (it.conv && !in_ranges(p, it.conv, N3 * 4)) || !off_ok(it.off))
+          return bad("residual", i);
         for (int f = 0; f < 6; ++f)
           if (it.nbr_off[f] != -1 && !off_ok(it.nbr_off[f])) return bad("residual neighbour", i);
         break;
@@ -803,8 +804,6 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   if (p->fp32 && p->dc_iters > 0) {
     LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
     p->r = (double*)tmp;
-    LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
-    p->e = (double*)tmp;
   }
   {
     const std::vector<double> W = lagrange_matrix(nb, p->n_i), W3 = refine_table(nb);
@@ -908,6 +907,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 
   HostItems hi;
   std::vector<PendingStep> steps, rsteps, alt_steps;
+  PendingStep corr_conv{};                       // the correction pass's base-level convert
   std::vector<size_t> alt_of;                    // primary step index of each alternative
   // chain: 0 before the level's fork, 1 base-level super-block path, 2 far field, 3 after the
   // join (see run_steps); -1 derives it from the phase
@@ -1089,11 +1089,12 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     for (int k = 0; k < K; ++k) {
       p->n_rows += (int64_t)rows[k].size();
       const int half = wsel[k] == kMacL ? 0 : kMacHalfRows;
+      const int shape = ty_of(k) == TY_F64 ? kMacDefault64 : 0;
       const size_t primary = steps.size();
-      push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k], half);
+      push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k], half | shape);
       if (steps.size() > primary && !alt_mac[k].empty()) {
         push(alt_steps, l, 4, k, K_MAC, ty_of(k), hi.add(alt_mac[k]), alt_mac[k].size(), nullptr, work[k],
-             kMacHalfRows - half);
+             (kMacHalfRows - half) | shape);
         alt_of.push_back(primary);
       }
     }
@@ -1205,10 +1206,21 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   }
 
   if (p->fp32 && p->dc_iters > 0) {
+    // the correction pass's base-level leaf sources are written by the residual in FP32 (the
+    // pass's convert then only handles the coarsened non-leaf blocks); r in FP64 is kept for
+    // the blocks of finer levels, which the pass's coarsening and source correction read
     std::vector<ResidualItem> it;
+    std::vector<ConvertItem<D>> cc;
     for (int64_t i = 0; i < n; ++i) {
       ResidualItem r{};
-      r.r = p->r + i * N3;
+      r.r = lev[i] > 0 ? p->r + i * N3 : nullptr;
+      r.conv = lev[i] == 0 && leaf[i] ? (float*)SRC(TY_F32, base_src_slot[i]) : nullptr;
+      if (lev[i] == 0 && !leaf[i]) {
+        ConvertItem<D> c{};
+        c.dst = SRC(tyb, base_src_slot[i]);
+        c.src = p->fe + i * N3;
+        cc.push_back(c);
+      }
       r.off = i * N3;
       for (int face = 0; face < 6; ++face) {
         const int nbi = face_nbr((int)i, face);
@@ -1220,6 +1232,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       it.push_back(r);
     }
     push(rsteps, 0, 0, 0, K_RESIDUAL, TY_F64, hi.add(it), it.size(), nullptr);
+    corr_conv = {0, 1, 0, K_CONVERT, tyb, hi.add(cc), (int32_t)cc.size(), nullptr, 0, 0, 0};
   }
 
   // every item must stay inside the plan's device ranges before anything is launched
@@ -1230,6 +1243,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       for (const PendingStep& st : *list)
         if (!validate_step(p, st.kind, st.ty, st.mode, hi.buf.data() + st.off, st.count, n, sc, err))
           return hipErrorInvalidValue;
+    if (corr_conv.count &&
+        !validate_step(p, corr_conv.kind, corr_conv.ty, 0, hi.buf.data() + corr_conv.off, corr_conv.count, n, sc, err))
+      return hipErrorInvalidValue;
   }
   void* d_items = nullptr;
   LGF_HIP_CHECK(ar.alloc(&d_items, hi.buf.size()));
@@ -1243,6 +1259,13 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
+  if (p->fp32 && p->dc_iters > 0) {
+    for (size_t i = 0; i < p->pass.size(); ++i)
+      if (p->pass[i].kind == K_CONVERT && p->pass[i].l == 0) p->conv_idx = (int64_t)i;
+    std::vector<Step> cv;
+    fin({corr_conv}, cv);
+    p->conv_corr = cv[0];
+  }
   {
     std::vector<Step> alts;
     fin(alt_steps, alts);
@@ -1296,6 +1319,24 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
     return e;
   }
   *out = p;
+  return hipSuccess;
+}
+
+hipError_t plan_set_mac_shape(Plan* p, int shape) {
+  if (shape != 0 && shape != 1 && shape != 2 && shape != 4 && shape != 6 && shape != 8)
+    return hipErrorInvalidValue;
+  if (p->mac_mode0.empty())
+    for (const Step& s : p->pass) p->mac_mode0.push_back(s.mode);
+  auto has = [](int ty, int m) {
+    return ty == TY_F32 ? (m == 1 || m == 2 || m == 4) : (m == 1 || m == 2 || m == 6 || m == 8);
+  };
+  for (size_t i = 0; i < p->pass.size(); ++i) {
+    Step& s = p->pass[i];
+    if (s.kind != K_MAC) continue;
+    if (shape == 0) s.mode = p->mac_mode0[i];
+    else if (has(s.ty, shape)) s.mode = shape | (p->mac_mode0[i] & kMacHalfRows);
+  }
+  if (!p->dry) graph_forget(p);
   return hipSuccess;
 }
 
@@ -1445,9 +1486,15 @@ hipError_t stream_after(hipStream_t dst, hipStream_t src, size_t ev_index) {
 hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st) {
   std::vector<Ref> refs;
   for (size_t i = 0; i < m.size(); ++i) {
-    const std::vector<Step>& sv = residual ? m[i].p->residual : m[i].p->pass;
-    for (const Step& s : sv)
-      refs.push_back({s.l, s.phase, s.sub, s.kind, m[i].p->nb, s.ty, s.mode, (int)i, &s});
+    const Plan* q = m[i].p;
+    const std::vector<Step>& sv = residual ? q->residual : q->pass;
+    for (size_t j = 0; j < sv.size(); ++j) {
+      const Step* s = &sv[j];
+      // a correction pass's base-level leaf sources were written by the residual
+      if (!residual && m[i].accumulate && (int64_t)j == q->conv_idx) s = &q->conv_corr;
+      if (s->count == 0) continue;
+      refs.push_back({s->l, s->phase, s->sub, s->kind, q->nb, s->ty, s->mode, (int)i, s});
+    }
   }
   std::sort(refs.begin(), refs.end());
   bool prof;
@@ -1480,7 +1527,7 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
       ws.items = refs[b].step->items;
       ws.count = refs[b].step->count;
       ws.wg_begin = 0;
-      ws.aux = 0;
+      ws.aux = mm.accumulate ? kAuxAccumulate : 0;
       ws.in = mm.in;
       ws.out = mm.out;
       ws.w = refs[b].step->w;
@@ -1526,14 +1573,10 @@ hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
     for (const Member& x : m)
       if (x.p->dc_iters > it) {
         act.push_back(x);
-        corr.push_back({x.p, x.p->r, x.p->e});
+        corr.push_back({x.p, x.p->r, x.out, true});
       }
     LGF_HIP_CHECK(run_steps(act, true, st));      // r = f - L u
-    LGF_HIP_CHECK(run_steps(corr, false, st));    // e = S(r)
-    for (const Member& x : act) {
-      const int64_t N3 = (int64_t)x.p->nb * x.p->nb * x.p->nb;
-      LGF_HIP_CHECK(launch_axpy(x.out, x.p->e, x.p->nblocks * N3, st));
-    }
+    LGF_HIP_CHECK(run_steps(corr, false, st));    // u += S(r): the pass's final combine adds into u
   }
   return hipSuccess;
 }
@@ -1661,7 +1704,8 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
       const int* cand = s.ty == 0 ? kMacModes32 : kMacModes64;
       float best = 1e30f;
       int best_mode = 0;
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < 4; ++c) {
+        if (c > 0 && cand[c] == cand[c - 1]) continue;
         float t[3];
         for (int rep = 0; rep < 3; ++rep) {
           SetTable tab;

@@ -84,6 +84,11 @@ struct Plan {
   // alternatives of a pass step (index into pass) with another launch shape and its own items
   std::vector<std::pair<size_t, Step>> alt;
   std::vector<Step> residual;          // r = f - L u (FP32 refine only)
+  std::vector<int> mac_mode0;          // chosen MAC launch shapes, kept when a shape is forced
+  // defect correction: the residual writes the base-level leaf sources of the correction pass
+  // in FP32, so that pass runs conv_corr (non-leaf blocks only) in place of pass[conv_idx]
+  int64_t conv_idx = -1;
+  Step conv_corr{};
 
   // owned device memory
   std::vector<void*> allocs;
@@ -98,7 +103,6 @@ struct Plan {
   void* sfhat = nullptr;               // cpx<T> [nsup_src + 1][S2]: super-block source spectra
   void* suhat = nullptr;               // cpx<T> [nsup_tgt][S2]: super-block target spectra
   double* r = nullptr;                 // DC residual [n][N3]
-  double* e = nullptr;                 // DC correction [n][N3]
   double* d_w = nullptr;               // Lagrange matrix [2 nb][nb]
   double* d_w3 = nullptr;              // quadratic refinement table [(2 nb + 2)][4]
   void* d_items = nullptr;
@@ -112,11 +116,14 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
                       bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err,
                       bool dry = false, bool autotune = false, bool super_base = true);
 void plan_free(Plan* p);
+// Forces the launch shape of every coarse-level MAC step (0: back to the chosen ones).
+hipError_t plan_set_mac_shape(Plan* p, int shape);
 
 struct Member {
   Plan* p;
   const double* in;
   double* out;
+  bool accumulate = false;             // the pass adds its result into out (the DC update u += e)
 };
 // Runs the given step lists of several plans with shared launches, in key order.
 hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st);

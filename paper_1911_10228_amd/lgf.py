@@ -22,7 +22,7 @@ LGF_BASE_BLOCK = 1
 EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
-           "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy"]
+           "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape"]
 
 
 class LgfError(RuntimeError):
@@ -81,6 +81,7 @@ def load() -> C.CDLL:
         "lgf_server_wait_all": ([P], I32),
         "lgf_server_stats": ([P, P, P, P, P], I32),
         "lgf_server_destroy": ([P], I32),
+        "lgf_plan_set_mac_shape": ([P, I32], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -147,6 +148,10 @@ class Plan:
         self._check_field(f)
         self._check_field(u)
         _check(load().lgf_solve(self._h, _ptr(f), _ptr(u), _stream(stream)), "lgf_solve")
+
+    def set_mac_shape(self, shape: int):
+        """Force the coarse-level MAC launch shape (diagnostics; 0 restores the chosen one)."""
+        _check(load().lgf_plan_set_mac_shape(self._h, shape), "lgf_plan_set_mac_shape")
 
     def _check_field(self, t):
         import torch
