@@ -53,8 +53,9 @@ def algorithmic(entry, n_b, info, passes):
     (flops, flop peak in TFLOP/s, compulsory HBM bytes), None where not defined.  MACs: 8 flops
     per complex multiply-add, S per (target, source) pair (work = pairs); a MAC reads each source
     spectrum and each kernel spectrum of its level once and writes each target spectrum once
-    (near MAC: the super-block spectra and the 27 super-block kernels; coarse MAC: the block
-    spectra of the coarse levels and their 316 kernels per level).  FP32 tiles compute in FP32;
+    (near MAC: the super-block spectra and 14 of the 27 super-block kernels, the others being
+    their conjugates; coarse MAC: the block spectra of the coarse levels and their 316 kernels
+    per level).  FP32 tiles compute in FP32;
     FP64 spectra in FP64.  Transforms: per item (work = items) the block or the 8 child blocks
     of a super-block, and the half spectrum (2 S reals)."""
     es = 4 if entry["precision"] == "fp32" else 8
@@ -67,7 +68,7 @@ def algorithmic(entry, n_b, info, passes):
         per_pass = (info["fft_forward"] + info["fft_inverse"] + coarse_kernels) * 2 * S * es
         return 8.0 * S * entry["work"], peak, per_pass * passes
     if k == "near_mac":
-        per_launch = (info["super_forward"] + info["super_inverse"] + 27) * 2 * S2 * es
+        per_launch = (info["super_forward"] + info["super_inverse"] + 14) * 2 * S2 * es
         return 8.0 * S2 * entry["work"], peak, per_launch * entry["launches"]
     if k in ("fft_fwd", "fft_inv"):
         return None, None, float(entry["work"]) * (N3 * es + 2 * S * es)

@@ -1651,7 +1651,7 @@ hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st) {
 
 // ----------------------------------------------------------------------------- autotuner
 // Chooses the launch shape of every MAC step of a plan by timing each candidate on the plan's
-// own work items (3 repetitions, median): the tile MAC's shapes (rows per wavefront, source-row
+// own work items (5 repetitions, median): the tile MAC's shapes (rows per wavefront, source-row
 // split) and the near MAC's (rows of 4 or 8 targets, 2 x 2-row tiles; the planner builds each
 // shape's items).  The choice is remembered per (N_b, element type, tile count or pair count)
 // for the process and in the file named by LGF_TUNE_CACHE (one "nb key count mode" line per
@@ -1684,6 +1684,8 @@ void tune_store(const std::array<int64_t, 3>& k, int mode) {
 }
 }  // namespace
 
+constexpr int kTuneReps = 5;             // timed launches per candidate (the median counts)
+
 hipError_t plan_autotune(Plan* p, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load();
@@ -1706,8 +1708,8 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
       int best_mode = 0;
       for (int c = 0; c < 4; ++c) {
         if (c > 0 && cand[c] == cand[c - 1]) continue;
-        float t[3];
-        for (int rep = 0; rep < 3; ++rep) {
+        float t[kTuneReps];
+        for (int rep = 0; rep < kTuneReps; ++rep) {
           SetTable tab;
           tab.n = 1;
           tab.pad = 0;
@@ -1718,12 +1720,12 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
           LGF_HIP_CHECK(hipEventSynchronize(b));
           LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
         }
-        std::sort(t, t + 3);
+        std::sort(t, t + kTuneReps);
         if (verbose)
           std::fprintf(stderr, "[lgf tune] mac ty %d count %d mode %d: %.1f us\n", s.ty, s.count, cand[c] | half,
-                       1e3f * t[1]);
-        if (c == 0 || t[1] < 0.95f * best) {    // the first candidate is the default shape
-          best = t[1];
+                       1e3f * t[kTuneReps / 2]);
+        if (c == 0 || t[kTuneReps / 2] < 0.95f * best) {    // the first candidate is the default shape
+          best = t[kTuneReps / 2];
           best_mode = cand[c];
         }
       }
@@ -1749,8 +1751,8 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
     float best = 1e30f;
     size_t best_i = 0;
     for (size_t c = 0; c < cands.size(); ++c) {
-      float t[3];
-      for (int rep = 0; rep < 3; ++rep) {
+      float t[kTuneReps];
+      for (int rep = 0; rep < kTuneReps; ++rep) {
         SetTable tab;
         tab.n = 1;
         tab.pad = 0;
@@ -1761,14 +1763,14 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
         LGF_HIP_CHECK(hipEventSynchronize(b));
         LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
       }
-      std::sort(t, t + 3);
+      std::sort(t, t + kTuneReps);
       if (verbose)
         std::fprintf(stderr, "[lgf tune] kind %d ty %d work %lld mode %d: %.1f us\n", cands[c].kind, cands[c].ty,
-                     (long long)cands[c].work, cands[c].mode, 1e3f * t[1]);
+                     (long long)cands[c].work, cands[c].mode, 1e3f * t[kTuneReps / 2]);
       // an alternative replaces the planner's shape only when clearly faster (5%), so that
       // near ties do not flip from run to run
-      if (c == 0 || t[1] < 0.95f * best) {
-        best = t[1];
+      if (c == 0 || t[kTuneReps / 2] < 0.95f * best) {
+        best = t[kTuneReps / 2];
         best_i = c;
       }
     }
