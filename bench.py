@@ -142,7 +142,7 @@ def bench_batch(lgf, workloads, torch, stream, steps, warmup, dc):
     return {"solves": len(Ls), "unknowns": total, "value": total / dt, "ms_per_batch": dt * 1e3}
 
 
-def bench_serving(lgf, workloads, torch, capacity_pts, dc, count=400):
+def bench_serving(lgf, workloads, torch, capacity_pts, dc, count=1000):
     """Poisson-arrival request stream through the continuous-batching server: requests draw a
     layout from a pool of 24 (4096 .. 16.7M unknowns, log-uniform) and bring a source; the rate
     offers 0.7 of the measured batched capacity; latency = completion - arrival."""
@@ -172,18 +172,24 @@ def bench_serving(lgf, workloads, torch, capacity_pts, dc, count=400):
 
 
 def cpu_baseline(n_b=16, nblk=8, order=8):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same workload recipe."""
+    """The FP64 oracle, single-threaded, on a bounded sample of the same workload recipe (here
+    the whole bench workload: one solve).  Also returns the oracle's solution and, untimed, its
+    one-step defect correction with an FP64 inner solve (the FP32 + DC form's reference)."""
     from threadpoolctl import threadpool_limits
-    from oracle import fmm
+    from oracle import fmm, multires
     from paper_1911_10228_amd import workloads
     L = workloads.uniform_mixture(nblk=nblk, n_b=n_b, n_gauss=16, seed=2, interp_order=order)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        fmm.flgf(L.blocks, L.f, L.n_b, order)
+        u = fmm.flgf(L.blocks, L.f, L.n_b, order)
         dt = time.perf_counter() - t0
-    return {"value": L.unknowns / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 oracle solve of {nblk}^3 blocks of {n_b}^3 ({L.unknowns} unknowns, "
-                      f"same recipe, order {order}) in {dt:.1f} s"}
+        mask = multires.residual_mask(L.blocks, L.levels, L.n_b)
+        r = np.where(mask, L.f - multires.apply_laplace(L.blocks, L.levels, u, L.n_b), 0.0)
+        u1 = u + fmm.flgf(L.blocks, r, L.n_b, order)
+    res = {"value": L.unknowns / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
+           "sample": f"one FP64 oracle solve of {nblk}^3 blocks of {n_b}^3 ({L.unknowns} unknowns, "
+                     f"same recipe, order {order}) in {dt:.1f} s"}
+    return res, u, u1
 
 
 def main():
@@ -325,7 +331,16 @@ def main():
         out["serving"] = bench_serving(lgf, workloads, torch, out["batch64"]["value"], args.dc)
         print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], uo, uo1 = cpu_baseline()
+
+        def rel(a, b):
+            return float(np.abs(a - b).max() / np.abs(b).max())
+        # every form against the oracle on the bench workload (FP32 + DC against the oracle's
+        # own defect-correction step)
+        out["err_vs_oracle"] = {"fp64_plain": rel(a64.reshape(uo.shape), uo),
+                                "fp32_no_dc": rel(a0.reshape(uo.shape), uo),
+                                "fp32_dc": rel(a32.reshape(uo.shape), uo1)}
+        print(f"# err vs oracle: {out['err_vs_oracle']}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

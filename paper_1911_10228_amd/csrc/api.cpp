@@ -152,6 +152,12 @@ lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape) {
   return e == hipErrorInvalidValue ? LGF_EINVAL : from_hip(e);
 }
 
+lgf_status lgf_plan_set_near_shape(lgf_plan_t p, int32_t shape) {
+  if (!p) return LGF_EINVAL;
+  const hipError_t e = lgf::plan_set_near_shape(p->p, shape);
+  return e == hipErrorInvalidValue ? LGF_EINVAL : from_hip(e);
+}
+
 lgf_status lgf_plan_destroy(lgf_plan_t p) {
   if (!p) return LGF_EINVAL;
   lgf::plan_free(p->p);

@@ -1149,8 +1149,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         p->near_pairs += pairs;
         push(steps, l, 3, k, K_SUP_FWD, sty, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size(), 0, chain);
         const size_t primary = steps.size();
+        const size_t nt_off = tiled ? hi.add(nt) : 0;
         if (tiled)
-          push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt), nt.size(), nullptr, pairs, kNearTiled + 4, chain);
+          push(steps, l, 4, k, K_NEAR_MAC, sty, nt_off, nt.size(), nullptr, pairs, kNearTiled + 4, chain);
         else
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
         if (p->tune && steps.size() > primary) {
@@ -1336,6 +1337,23 @@ hipError_t plan_set_mac_shape(Plan* p, int shape) {
     if (shape == 0) s.mode = p->mac_mode0[i];
     else if (has(s.ty, shape)) s.mode = shape | (p->mac_mode0[i] & kMacHalfRows);
   }
+  if (!p->dry) graph_forget(p);
+  return hipSuccess;
+}
+
+hipError_t plan_set_near_shape(Plan* p, int shape) {
+  if (p->near0.empty()) p->near0 = p->pass;
+  std::vector<std::pair<size_t, const Step*>> pick;
+  for (size_t i = 0; i < p->near0.size(); ++i) {
+    const Step& s0 = p->near0[i];
+    if (s0.kind != K_NEAR_MAC) continue;
+    const Step* c = (shape == 0 || s0.mode == shape) ? &s0 : nullptr;
+    for (const auto& pa : p->alt)
+      if (!c && pa.first == i && pa.second.mode == shape) c = &pa.second;
+    if (!c) return hipErrorInvalidValue;
+    pick.push_back({i, c});
+  }
+  for (const auto& pc : pick) p->pass[pc.first] = *pc.second;
   if (!p->dry) graph_forget(p);
   return hipSuccess;
 }
@@ -1733,19 +1751,33 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
       tune_store(key, best_mode);
     }
   }
-  // near MAC: the planner built the other launch shapes with their own items; time each
-  // (median of 3) and keep the fastest in the pass
+  // steps with other launch shapes and their own items (near MAC shapes, MAC row widths): time
+  // each and keep the fastest in the pass; the replaced step takes the winner's place among the
+  // alternatives, so that every shape stays available
   std::map<size_t, std::vector<Step>> groups;
   for (const auto& pa : p->alt) groups[pa.first].push_back(pa.second);
+  auto choose = [&](size_t idx, const Step& win) {
+    Step& prim = p->pass[idx];
+    if (win.mode == prim.mode && win.items == prim.items) return;
+    for (auto& pa : p->alt)
+      if (pa.first == idx && pa.second.mode == win.mode && pa.second.items == win.items) {
+        pa.second = prim;
+        break;
+      }
+    prim = win;
+  };
   for (auto& g : groups) {
-    Step& prim = p->pass[g.first];
+    const Step prim = p->pass[g.first];
     std::vector<Step> cands{prim};
     for (const Step& x : g.second) cands.push_back(x);
     const std::array<int64_t, 3> key{p->nb, (prim.kind == K_MAC ? 2000 : 1000) + prim.ty, prim.work};
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
       for (const Step& c : cands)
-        if (c.mode == it->second) prim = c;
+        if (c.mode == it->second) {
+          choose(g.first, c);
+          break;
+        }
       continue;
     }
     float best = 1e30f;
@@ -1774,8 +1806,8 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
         best_i = c;
       }
     }
-    prim = cands[best_i];
-    tune_store(key, prim.mode);
+    choose(g.first, cands[best_i]);
+    tune_store(key, cands[best_i].mode);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

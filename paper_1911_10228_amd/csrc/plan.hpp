@@ -85,6 +85,7 @@ struct Plan {
   std::vector<std::pair<size_t, Step>> alt;
   std::vector<Step> residual;          // r = f - L u (FP32 refine only)
   std::vector<int> mac_mode0;          // chosen MAC launch shapes, kept when a shape is forced
+  std::vector<Step> near0;             // chosen steps (all of pass), kept when a near shape is forced
   // defect correction: the residual writes the base-level leaf sources of the correction pass
   // in FP32, so that pass runs conv_corr (non-leaf blocks only) in place of pass[conv_idx]
   int64_t conv_idx = -1;
@@ -118,6 +119,8 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
 void plan_free(Plan* p);
 // Forces the launch shape of every coarse-level MAC step (0: back to the chosen ones).
 hipError_t plan_set_mac_shape(Plan* p, int shape);
+// Forces the launch shape of every base-level super-block MAC step (0: back to the chosen ones).
+hipError_t plan_set_near_shape(Plan* p, int shape);
 
 struct Member {
   Plan* p;

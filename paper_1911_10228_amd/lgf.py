@@ -22,7 +22,8 @@ LGF_BASE_BLOCK = 1
 EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
-           "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape"]
+           "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape",
+           "lgf_plan_set_near_shape"]
 
 
 class LgfError(RuntimeError):
@@ -82,6 +83,7 @@ def load() -> C.CDLL:
         "lgf_server_stats": ([P, P, P, P, P], I32),
         "lgf_server_destroy": ([P], I32),
         "lgf_plan_set_mac_shape": ([P, I32], I32),
+        "lgf_plan_set_near_shape": ([P, I32], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -152,6 +154,10 @@ class Plan:
     def set_mac_shape(self, shape: int):
         """Force the coarse-level MAC launch shape (diagnostics; 0 restores the chosen one)."""
         _check(load().lgf_plan_set_mac_shape(self._h, shape), "lgf_plan_set_mac_shape")
+
+    def set_near_shape(self, shape: int):
+        """Force the base-level super-block MAC launch shape (diagnostics; autotuned plans)."""
+        _check(load().lgf_plan_set_near_shape(self._h, shape), "lgf_plan_set_near_shape")
 
     def _check_field(self, t):
         import torch
