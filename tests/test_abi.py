@@ -56,6 +56,12 @@ def test_layout_validation_codes():
     assert _plan_code(base, [0, 0], precision=1, dc=99) == -1       # bad DC count
 
 
+def test_empty_layout_is_rejected():
+    assert _plan_code(np.zeros((0, 3), np.int32), np.zeros(0, np.int32)) == -1
+    with pytest.raises(lgf.LgfError):
+        lgf.plan_check(np.zeros((0, 3), np.int32), np.zeros(0, np.int32), 8, 4)
+
+
 def test_null_arguments():
     lib = lgf.load()
     assert lib.lgf_solve(None, None, None, None) == -1

@@ -149,6 +149,38 @@ def test_sparse_negative_ragged_layout_fp64(lgf, base_level):
     assert rel_linf(u, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("base_level", [0, 1])
+def test_point_source_gives_the_green_function(lgf, base_level):
+    """A unit source at one lattice point: on 2x2x2 blocks every pair is in the near field, so
+    the result is the lattice Green's function itself (Sec. 2, eq. discretConv), compared with
+    the oracle's LGF evaluation, not with its FMM."""
+    n_b = 8
+    blocks = workloads.box_blocks(2, 2, 2)
+    f = np.zeros((len(blocks), n_b, n_b, n_b))
+    f[3, 5, 1, 6] = 1.0                                  # block 3, cell (x, y, z) = (6, 1, 5)
+    L = workloads.Layout(blocks, np.zeros(len(blocks), np.int32), n_b, f, 4)
+    u, _ = gpu_solve(lgf, L, base_level=base_level)
+    src = blocks[3] * n_b + np.array([6, 1, 5])
+    pos = direct.cell_coords(blocks, n_b).reshape(len(blocks), n_b, n_b, n_b, 3)
+    g = olgf.lgf(pos - src)
+    assert np.abs(u - g).max() <= 1e-12 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("precision,dc", [(0, 0), (1, 1)])
+def test_zero_source_gives_zero(lgf, precision, dc):
+    L = workloads.uniform_mixture(nblk=4, n_b=8, n_gauss=2, seed=3)
+    L = workloads.Layout(L.blocks, L.levels, L.n_b, np.zeros_like(L.f), L.interp_order)
+    u, _ = gpu_solve(lgf, L, precision=precision, dc=dc)
+    assert not np.any(u)
+
+
+def test_largest_interpolation_order(lgf):
+    """n_I = 10, the paper's largest order, on 16^3 blocks with a far field."""
+    L = workloads.uniform_mixture(nblk=5, n_b=16, n_gauss=4, seed=41, interp_order=10)
+    u, _ = gpu_solve(lgf, L, order=10)
+    assert rel_linf(u, fmm.flgf(L.blocks, L.f, L.n_b, 10)) <= 1e-12
+
+
 def test_single_block(lgf):
     L = workloads.Layout(np.array([[3, -2, 5]], np.int32), np.zeros(1, np.int32), 16,
                          np.random.default_rng(2).normal(size=(1, 16, 16, 16)), 4)
