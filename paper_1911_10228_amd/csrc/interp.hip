@@ -91,14 +91,17 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
 // parent = sum_c (Wz (x) Wy (x) Wx)^T child_c, arithmetic in the parent's type TP.
 // One workgroup computes a slab of NB/8 parent z-planes: the z pass comes first (it mixes child
 // planes into the slab's parent planes), so the y and x passes of different slabs are
-// independent and eight workgroups share a parent without redundant arithmetic.
+// independent and eight workgroups share a parent without redundant arithmetic.  By linearity
+// the children are summed as early as their weights allow: after the z pass per (cx, cy) (the
+// two cz children), after the y pass per cx, so the passes run on 8, 4 and 2 arrays with three
+// barriers in all.
 template <int NB, typename TC, typename TP>
 __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
   using T = TP;
   constexpr int SL = NB / 8;           // parent z-planes per workgroup
   __shared__ T w[2][NB][NB];           // w[c][r][m] = W[c NB + r][m]
-  __shared__ T t1[SL][NB][NB];
-  __shared__ T t2[SL][NB][NB];
+  __shared__ T t1[4][SL][NB][NB];      // z pass, per (cx, cy): [z][Y][X]
+  __shared__ T t2[2][SL][NB][NB];      // y pass, per cx: [z][y][X]
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;
@@ -111,40 +114,60 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
     w[cc][r][m] = T(W[(cc * NB + r) * NB + m]);
   }
   const int a = tid % NB, b = tid / NB;          // (X, Y) in the z pass; (x or X, y) later
-  T acc[SL];
+  int gmask = 0;                                 // (cx, cy) groups with a child
+  T zs[4][SL];
 #pragma unroll
-  for (int zz = 0; zz < SL; ++zz) acc[zz] = T(0);
-  for (int oc = 0; oc < 8; ++oc) {
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int zz = 0; zz < SL; ++zz) zs[g][zz] = T(0);
+#pragma unroll
+  for (int oc = 0; oc < 8; ++oc) {                               // z: sum over cz
     const TC* ch = it.child[oc];
     if (!ch) continue;
-    const int cx = oc & 1, cy = (oc >> 1) & 1, cz = (oc >> 2) & 1;
-    __syncthreads();
+    const int g = oc & 3, cz = oc >> 2;
+    gmask |= 1 << g;
+    T v[NB];
 #pragma unroll
-    for (int zz = 0; zz < SL; ++zz) {                            // z: t1[z][Y][X]
-      T s = 0;
+    for (int Z = 0; Z < NB; ++Z) v[Z] = T(ch[(Z * NB + b) * NB + a]);
 #pragma unroll
-      for (int Z = 0; Z < NB; ++Z) s += w[cz][Z][z0 + zz] * T(ch[(Z * NB + b) * NB + a]);
-      t1[zz][b][a] = s;
-    }
-    __syncthreads();
+    for (int zz = 0; zz < SL; ++zz)
 #pragma unroll
-    for (int zz = 0; zz < SL; ++zz) {                            // y: t2[z][y][X]
-      T s = 0;
-#pragma unroll
-      for (int Y = 0; Y < NB; ++Y) s += w[cy][Y][b] * t1[zz][Y][a];
-      t2[zz][b][a] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int zz = 0; zz < SL; ++zz) {                            // x: out[z][y][x]
-      T s = 0;
-#pragma unroll
-      for (int X = 0; X < NB; ++X) s += w[cx][X][a] * t2[zz][b][X];
-      acc[zz] += s;
-    }
+      for (int Z = 0; Z < NB; ++Z) zs[g][zz] += T(W[(cz * NB + Z) * NB + z0 + zz]) * v[Z];
   }
 #pragma unroll
-  for (int zz = 0; zz < SL; ++zz) it.dst[((z0 + zz) * NB + b) * NB + a] = acc[zz];
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int zz = 0; zz < SL; ++zz) t1[g][zz][b][a] = zs[g][zz];
+  __syncthreads();
+#pragma unroll
+  for (int cx = 0; cx < 2; ++cx)                                 // y: sum over cy
+#pragma unroll
+    for (int zz = 0; zz < SL; ++zz) {
+      T s = 0;
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy) {
+        if (!((gmask >> (cx + 2 * cy)) & 1)) continue;
+#pragma unroll
+        for (int Y = 0; Y < NB; ++Y) s += w[cy][Y][b] * t1[cx + 2 * cy][zz][Y][a];
+      }
+      t2[cx][zz][b][a] = s;
+    }
+  __syncthreads();
+  T acc[SL];
+#pragma unroll
+  for (int zz = 0; zz < SL; ++zz) {                              // x: sum over cx
+    T s = 0;
+#pragma unroll
+    for (int cx = 0; cx < 2; ++cx) {
+      if (!((gmask >> cx) & 5)) continue;
+#pragma unroll
+      for (int X = 0; X < NB; ++X) s += w[cx][X][a] * t2[cx][zz][b][X];
+    }
+    acc[zz] = s;
+  }
+  TP* const dst = it.dst;
+#pragma unroll
+  for (int zz = 0; zz < SL; ++zz) dst[((z0 + zz) * NB + b) * NB + a] = acc[zz];
 }
 
 template <int NB, typename T>
