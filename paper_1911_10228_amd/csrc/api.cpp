@@ -137,7 +137,7 @@ lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out) {
   out->fft_forward = q->n_fwd;
   out->fft_inverse = q->n_inv;
   out->mac_rows = q->n_rows;
-  out->workspace_bytes = q->bytes;
+  out->workspace_bytes = q->bytes + (q->corr ? q->corr->bytes : 0);
   out->spectra = q->n_spectra;
   out->super_forward = q->n_sup_fwd;
   out->super_inverse = q->n_sup_inv;
@@ -294,7 +294,7 @@ struct lgf_server_s {
       while (!queue.empty()) {
         Req r = queue.front();
         queue.pop_front();
-        const int64_t need = r.plan->bytes;
+        const int64_t need = r.plan->bytes + (r.plan->corr ? r.plan->corr->bytes : 0);
         const bool fits = budget == 0 || (uint64_t)(inflight_bytes + b.bytes + need) <= budget ||
                           (inflight.empty() && b.reqs.empty());
         if (!fits || busy.count(r.plan) || in_batch.count(r.plan) || (int)b.reqs.size() >= lgf::kMaxSets) {

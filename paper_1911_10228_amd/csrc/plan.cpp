@@ -613,7 +613,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   const int64_t n = p->nblocks;
   const int LR = p->LR;
   const int tyb = p->fp32 ? TY_F32 : TY_F64;
-  auto ty_of = [&](int k) { return k == 0 ? tyb : TY_F64; };
+  // coarse octree levels run in FP64 except in a correction plan (all FP32)
+  auto ty_of = [&](int k) { return (k == 0 || p->all_fp32) ? tyb : TY_F64; };
   auto es = [](int ty) { return ty == TY_F32 ? (int64_t)4 : (int64_t)8; };
   Arena ar{p, budget};
 
@@ -700,7 +701,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   // error at refinement interfaces: a block-smooth error there stays, and the correction spreads
   // it (by 3-4x in L-inf on the torus layouts), while on a single level only the outer boundary
   // is excluded.
-  const int tys = (p->fp32 && LR > 1) ? TY_MIX : tyb;
+  // A defect-correction re-solve computes a correction of the size of the FP32 error, whose own
+  // FP32 rounding is negligible: its plan keeps FP32 spectra everywhere.
+  const int tys = p->all_fp32 ? TY_F32 : (p->fp32 && LR > 1) ? TY_MIX : tyb;
   auto arena_of = [&](int k) { return (k == 0 && tys == TY_F32) ? 0 : 1; };
   auto sup_ty = [&](int k) { return k == 0 ? tys : TY_F64; };
   if (p->super_base) {
@@ -801,7 +804,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   p->fhat = fhatA[tyb];
   p->uhat = uhatA[tyb];
   p->v = vA[tyb];
-  if (p->fp32 && p->dc_iters > 0) {
+  if (p->fp32 && p->dc_iters > 0 && LR > 1) {      // r of the finer levels' blocks (FP64)
     LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
     p->r = (double*)tmp;
   }
@@ -1206,22 +1209,29 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     push(steps, l, 7, 0, K_COMBINE, tyb, hi.add(cmb), cmb.size(), nullptr);
   }
 
-  if (p->fp32 && p->dc_iters > 0) {
-    // the correction pass's base-level leaf sources are written by the residual in FP32 (the
-    // pass's convert then only handles the coarsened non-leaf blocks); r in FP64 is kept for
-    // the blocks of finer levels, which the pass's coarsening and source correction read
-    std::vector<ResidualItem> it;
+  p->base_slot = base_src_slot;
+  if (p->correction) {
+    // run as a correction pass, this plan's base-level leaf sources are written by the
+    // residual in FP32: its convert then only handles the coarsened non-leaf blocks
     std::vector<ConvertItem<D>> cc;
-    for (int64_t i = 0; i < n; ++i) {
-      ResidualItem r{};
-      r.r = lev[i] > 0 ? p->r + i * N3 : nullptr;
-      r.conv = lev[i] == 0 && leaf[i] ? (float*)SRC(TY_F32, base_src_slot[i]) : nullptr;
+    for (int64_t i = 0; i < n; ++i)
       if (lev[i] == 0 && !leaf[i]) {
         ConvertItem<D> c{};
         c.dst = SRC(tyb, base_src_slot[i]);
         c.src = p->fe + i * N3;
         cc.push_back(c);
       }
+    corr_conv = {0, 1, 0, K_CONVERT, tyb, hi.add(cc), (int32_t)cc.size(), nullptr, 0, 0, 0};
+  }
+  if (p->fp32 && p->dc_iters > 0) {
+    // r = f - L u: in FP32 straight into the correction plan's base-level leaf sources, in FP64
+    // for the blocks of finer levels, which the correction pass coarsens and corrects
+    const Plan* q = p->corr;
+    std::vector<ResidualItem> it;
+    for (int64_t i = 0; i < n; ++i) {
+      ResidualItem r{};
+      r.r = lev[i] > 0 ? p->r + i * N3 : nullptr;
+      r.conv = lev[i] == 0 && leaf[i] ? (float*)q->src + (int64_t)q->base_slot[i] * N3 : nullptr;
       r.off = i * N3;
       for (int face = 0; face < 6; ++face) {
         const int nbi = face_nbr((int)i, face);
@@ -1233,7 +1243,6 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       it.push_back(r);
     }
     push(rsteps, 0, 0, 0, K_RESIDUAL, TY_F64, hi.add(it), it.size(), nullptr);
-    corr_conv = {0, 1, 0, K_CONVERT, tyb, hi.add(cc), (int32_t)cc.size(), nullptr, 0, 0, 0};
   }
 
   // every item must stay inside the plan's device ranges before anything is launched
@@ -1260,7 +1269,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
-  if (p->fp32 && p->dc_iters > 0) {
+  if (p->correction) {
     for (size_t i = 0; i < p->pass.size(); ++i)
       if (p->pass[i].kind == K_CONVERT && p->pass[i].l == 0) p->conv_idx = (int64_t)i;
     std::vector<Step> cv;
@@ -1313,7 +1322,32 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
     LR = std::max(LR, lev[i] + 1);
   }
   p->LR = LR;
-  e = build_plan(p, coords, lev, budget, err);
+  if (p->fp32 && p->dc_iters > 0) {
+    // the defect-correction re-solve: the same layout, every level and spectrum in FP32
+    Plan* q = new Plan();
+    q->super_base = super_base;
+    q->tune = autotune;
+    q->nb = nb;
+    q->n_i = n_i;
+    q->fp32 = true;
+    q->all_fp32 = true;
+    q->correction = true;
+    q->nblocks = n;
+    q->dry = dry;
+    q->ctx = p->ctx;
+    q->LR = LR;
+    p->corr = q;
+    e = build_plan(q, coords, lev, budget, err);
+    if (e == hipSuccess && autotune && !dry) e = plan_autotune(q, q->ctx->stream);
+    // the residual writes into the correction plan's buffers
+    p->ranges = q->ranges;
+    p->next_fake = q->next_fake;
+  }
+  if (e == hipSuccess) {
+    // one HBM budget for both plans (1 byte: already exhausted)
+    const uint64_t used = p->corr ? (uint64_t)p->corr->bytes : 0;
+    e = build_plan(p, coords, lev, budget == 0 ? 0 : budget > used ? budget - used : 1, err);
+  }
   if (e == hipSuccess && autotune && !dry) e = plan_autotune(p, p->ctx->stream);
   if (e != hipSuccess) {
     plan_free(p);
@@ -1326,6 +1360,7 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
 hipError_t plan_set_mac_shape(Plan* p, int shape) {
   if (shape != 0 && shape != 1 && shape != 2 && shape != 4 && shape != 6 && shape != 8)
     return hipErrorInvalidValue;
+  if (p->corr) LGF_HIP_CHECK(plan_set_mac_shape(p->corr, shape));
   if (p->mac_mode0.empty())
     for (const Step& s : p->pass) p->mac_mode0.push_back(s.mode);
   auto has = [](int ty, int m) {
@@ -1342,6 +1377,8 @@ hipError_t plan_set_mac_shape(Plan* p, int shape) {
 }
 
 hipError_t plan_set_near_shape(Plan* p, int shape) {
+  // the correction plan (FP32 spectra) takes the shape where it has it
+  if (p->corr) (void)plan_set_near_shape(p->corr, shape);
   if (p->near0.empty()) p->near0 = p->pass;
   std::vector<std::pair<size_t, const Step*>> pick;
   for (size_t i = 0; i < p->near0.size(); ++i) {
@@ -1360,6 +1397,7 @@ hipError_t plan_set_near_shape(Plan* p, int shape) {
 
 void plan_free(Plan* p) {
   if (!p) return;
+  plan_free(p->corr);
   if (!p->dry) graph_forget(p);
   if (!p->dry)
     for (void* a : p->allocs) (void)hipFree(a);
@@ -1591,7 +1629,7 @@ hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
     for (const Member& x : m)
       if (x.p->dc_iters > it) {
         act.push_back(x);
-        corr.push_back({x.p, x.p->r, x.out, true});
+        corr.push_back({x.p->corr, x.p->r, x.out, true});
       }
     LGF_HIP_CHECK(run_steps(act, true, st));      // r = f - L u
     LGF_HIP_CHECK(run_steps(corr, false, st));    // u += S(r): the pass's final combine adds into u

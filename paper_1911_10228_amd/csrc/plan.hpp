@@ -80,14 +80,18 @@ struct Plan {
   DeviceCtx* ctx = nullptr;
 
   bool tune = false;                   // build launch-shape alternatives for the autotuner
+  bool all_fp32 = false;               // every octree level and spectrum in FP32 (correction plan)
+  bool correction = false;             // run as a defect-correction pass (see conv_corr)
+  Plan* corr = nullptr;                // FP32 + DC: the plan of the correction re-solve (owned)
+  std::vector<int> base_slot;          // per block: its base-level source slot
   std::vector<Step> pass;              // one solve pass: input field -> output field
   // alternatives of a pass step (index into pass) with another launch shape and its own items
   std::vector<std::pair<size_t, Step>> alt;
   std::vector<Step> residual;          // r = f - L u (FP32 refine only)
   std::vector<int> mac_mode0;          // chosen MAC launch shapes, kept when a shape is forced
   std::vector<Step> near0;             // chosen steps (all of pass), kept when a near shape is forced
-  // defect correction: the residual writes the base-level leaf sources of the correction pass
-  // in FP32, so that pass runs conv_corr (non-leaf blocks only) in place of pass[conv_idx]
+  // correction plan: the residual writes its base-level leaf sources in FP32, so its pass runs
+  // conv_corr (non-leaf blocks only) in place of pass[conv_idx]
   int64_t conv_idx = -1;
   Step conv_corr{};
 
