@@ -133,8 +133,8 @@ lgf_status lgf_green_eval(const int32_t* n, int64_t m, double* out, lgf_stream_t
  *   octree levels; also the base level with LGF_BASE_BLOCK) whose element type has it: shape 1
  *   one target row per wavefront, 2 two rows, 4 the tile's four rows (FP32 steps), 6 source rows
  *   split over 6 wavefronts (FP64 steps), 8 the tile's rows on 4 wavefronts sharing each source
- *   row through LDS (FP64 steps); 0 restores the planner's and autotuner's choice.  So that every
- *   shape can be checked; results agree up to rounding order.  LGF_EINVAL for another value. */
+ *   row through LDS; 0 restores the planner's and autotuner's choice.  So that every shape can
+ *   be checked; results agree up to rounding order.  LGF_EINVAL for another value. */
 lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape);
 /* lgf_plan_set_near_shape: the same for the base-level super-block MAC steps: shape 4 or 8 rows
  *   of that many target super-blocks per wavefront, 20 tiles of 2 x 2 rows of 4 (FP32 spectra);

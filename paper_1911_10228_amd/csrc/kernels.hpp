@@ -193,9 +193,9 @@ template <typename T> hipError_t launch_fft_fwd(int nb, SetTable& t, hipStream_t
 template <typename T> hipError_t launch_fft_inv(int nb, SetTable& t, hipStream_t st);
 template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st, int mode = 0);
 // candidate launch shapes for the autotuner, the planner's default first (FP64: shared sources)
-constexpr int kMacModes32[4] = {1, 2, 4, 4};
-constexpr int kMacModes64[4] = {8, 1, 2, 6};
-constexpr int kMacDefault64 = 8;
+constexpr int kMacModes32[4] = {1, 2, 4, 8};
+constexpr int kMacModes64[4] = {1, 2, 6, 8};
+constexpr int kMacDefault64 = 8;                 // shared sources (FP64 steps, coarse levels)
 template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
 template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t, hipStream_t st);  // ws.w = W
 template <typename T> hipError_t launch_combine(int nb, SetTable& t, hipStream_t st);

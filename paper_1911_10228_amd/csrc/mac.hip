@@ -214,7 +214,7 @@ __global__ __launch_bounds__(64 * WAVES) void mac_tile_kernel(SetTable sets, int
     }
 }
 
-// Shared-source form (FP64 kernels from memory): the tile's 4 wavefronts (one target row each)
+// Shared-source form (kernel spectra from memory): the tile's 4 wavefronts (one target row each)
 // walk the tile's source rows together.  Each source row's XW + 6 spectra are loaded once per
 // workgroup, spread over the wavefronts, into one of two LDS buffers, and every wavefront reads
 // them from there; its 7 kernel values come from memory.  The next source row's spectra and
@@ -335,7 +335,9 @@ hipError_t launch_tiles(int S, SetTable& t, hipStream_t st) {
 // Launch shape (mode): 1 row, 2 pair, 4 tile = rows per wavefront; 6 split = FP64 source rows
 // over 6 wavefronts; 0 = default (one row per wavefront; FP32 with the kernel spectra in LDS and
 // 16 wavefronts per workgroup, FP64 with the kernel spectra prefetched from memory); 8 shared =
-// FP64 tile rows on 4 wavefronts sharing each source row through LDS.  Bit
+// the tile's rows on 4 wavefronts sharing each source row through LDS, kernel spectra from
+// memory (the default on coarse levels: few tiles per frequency chunk cannot amortise staging
+// all kernel spectra of a chunk).  Bit
 // kMacHalfRows marks tiles whose rows hold 4 targets (set by the planner with the items).  The
 // plan's autotuner picks the shape per step; LGF_MAC_MODE = row | pair | tile | split | shared
 // overrides it.
@@ -362,6 +364,7 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
   if (const int o = mac_mode_override()) mode = o;
   if (half) {
     if constexpr (sizeof(T) == 4) {
+      if (mode == 8) return launch_shared<T, 4>(S, t, st);
       if (mode == 4) return launch_tiles<T, 16, 4, true, 1, 4>(S, t, st);
       if (mode == 2) return launch_tiles<T, 16, 2, true, 1, 4>(S, t, st);
       return launch_tiles<T, 16, 1, true, 1, 4>(S, t, st);
@@ -373,6 +376,7 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
     }
   }
   if constexpr (sizeof(T) == 4) {
+    if (mode == 8) return launch_shared<T, kMacL>(S, t, st);
     if (mode == 4) return launch_tiles<T, 16, 4, true>(S, t, st);
     if (mode == 2) return launch_tiles<T, 16, 2, true>(S, t, st);
     return launch_tiles<T, 16, 1, true>(S, t, st);

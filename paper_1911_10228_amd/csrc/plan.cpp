@@ -1092,7 +1092,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     for (int k = 0; k < K; ++k) {
       p->n_rows += (int64_t)rows[k].size();
       const int half = wsel[k] == kMacL ? 0 : kMacHalfRows;
-      const int shape = ty_of(k) == TY_F64 ? kMacDefault64 : 0;
+      // the shared-source form on coarse levels (and FP64 everywhere); FP32 per-block base
+      // levels stage the kernel spectra in LDS
+      const int shape = (ty_of(k) == TY_F64 || k > 0) ? kMacDefault64 : 0;
       const size_t primary = steps.size();
       push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k], half | shape);
       if (steps.size() > primary && !alt_mac[k].empty()) {
@@ -1364,7 +1366,7 @@ hipError_t plan_set_mac_shape(Plan* p, int shape) {
   if (p->mac_mode0.empty())
     for (const Step& s : p->pass) p->mac_mode0.push_back(s.mode);
   auto has = [](int ty, int m) {
-    return ty == TY_F32 ? (m == 1 || m == 2 || m == 4) : (m == 1 || m == 2 || m == 6 || m == 8);
+    return ty == TY_F32 ? (m == 1 || m == 2 || m == 4 || m == 8) : (m == 1 || m == 2 || m == 6 || m == 8);
   };
   for (size_t i = 0; i < p->pass.size(); ++i) {
     Step& s = p->pass[i];
@@ -1759,11 +1761,13 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
         s.mode = it->second | half;
         continue;
       }
-      const int* cand = s.ty == 0 ? kMacModes32 : kMacModes64;
+      // the planner's shape first, then the type's other shapes
+      std::vector<int> cand{s.mode & (kMacHalfRows - 1)};
+      for (int m : (s.ty == 0 ? kMacModes32 : kMacModes64))
+        if (std::find(cand.begin(), cand.end(), m) == cand.end() && !(m == 1 && cand[0] == 0)) cand.push_back(m);
       float best = 1e30f;
       int best_mode = 0;
-      for (int c = 0; c < 4; ++c) {
-        if (c > 0 && cand[c] == cand[c - 1]) continue;
+      for (size_t c = 0; c < cand.size(); ++c) {
         float t[kTuneReps];
         for (int rep = 0; rep < kTuneReps; ++rep) {
           SetTable tab;
