@@ -47,15 +47,22 @@ __device__ __forceinline__ int kindex(int r, int jz, int jy, int dxi) {
   return (rz + 5 - jz) * 49 + (ry + 5 - jy) * 7 + dxi;   // (dz+3)*49 + (dy+3)*7 + dx+3
 }
 
+// kernel value of offset index h (only h < kHalfK is read: K_{-d}[k] = conj(K_d[k]), so each
+// frequency chunk touches 172 kernel spectra instead of 343)
+template <typename T>
+__device__ __forceinline__ cpx<T> kload(cptr64 kp, int h, int k) {
+  const bool mirror = h >= kHalfK;
+  cpx<T> v = gload<T>((gptr<T>)kp[mirror ? 342 - h : h], k);
+  if (mirror) v.y = -v.y;
+  return v;
+}
+
 template <typename T, int ROWS>
 __device__ __forceinline__ void load_k(cpx<T> (&ks)[ROWS][7], cptr64 kp, int r0, int jz, int jy, int k) {
 #pragma unroll
   for (int q = 0; q < ROWS; ++q)
 #pragma unroll
-    for (int dxi = 0; dxi < 7; ++dxi) {
-      const uint64_t p = kp[kindex(r0 + q, jz, jy, dxi)];
-      ks[q][dxi] = gload<T>((gptr<T>)p, k);
-    }
+    for (int dxi = 0; dxi < 7; ++dxi) ks[q][dxi] = kload<T>(kp, kindex(r0 + q, jz, jy, dxi), k);
 }
 
 // accumulate one source row (jz, jy) into target row r (XW targets) with kernel values kv(dxi)
@@ -257,7 +264,7 @@ __global__ __launch_bounds__(256) void mac_shared_kernel(SetTable sets, int S) {
       if (e < NS) st[q] = gload<T>(F, (int64_t)tile->src[pj][e] * S + k);
     }
 #pragma unroll
-    for (int d = 0; d < 7; ++d) ks[d] = gload<T>((gptr<T>)kp[kindex(r, pj / 6, pj % 6, d)], k);
+    for (int d = 0; d < 7; ++d) ks[d] = kload<T>(kp, kindex(r, pj / 6, pj % 6, d), k);
     int buf = 0;
     for (;;) {
 #pragma unroll
@@ -277,7 +284,7 @@ __global__ __launch_bounds__(256) void mac_shared_kernel(SetTable sets, int S) {
       }
       cpx<T> kn[7];
 #pragma unroll
-      for (int d = 0; d < 7; ++d) kn[d] = gload<T>((gptr<T>)kp[kindex(r, pn / 6, pn % 6, d)], k);
+      for (int d = 0; d < 7; ++d) kn[d] = kload<T>(kp, kindex(r, pn / 6, pn % 6, d), k);
       if (row) {
         cpx<T> fs[NS];
 #pragma unroll
