@@ -54,8 +54,8 @@ def algorithmic(entry, n_b, info, passes):
     per complex multiply-add, S per (target, source) pair (work = pairs); a MAC reads each source
     spectrum and each kernel spectrum of its level once and writes each target spectrum once
     (near MAC: the super-block spectra and 14 of the 27 super-block kernels, the others being
-    their conjugates; coarse MAC: the block spectra of the coarse levels and their 316 kernels
-    per level).  FP32 tiles compute in FP32;
+    their conjugates; coarse MAC: the block spectra of the coarse levels and 172 of the 316
+    kernels per level, likewise).  FP32 tiles compute in FP32;
     FP64 spectra in FP64.  Transforms: per item (work = items) the block or the 8 child blocks
     of a super-block, and the half spectrum (2 S reals)."""
     es = 4 if entry["precision"] == "fp32" else 8
@@ -64,8 +64,9 @@ def algorithmic(entry, n_b, info, passes):
     k = entry["kernel"]
     peak = PEAK["fp32_vector_tflops"] if entry["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
     if k == "mac":
-        coarse_kernels = info["spectra"] - (27 if info["super_forward"] else 343)
-        per_pass = (info["fft_forward"] + info["fft_inverse"] + coarse_kernels) * 2 * S * es
+        # 172 of each coarse level's 316 kernel spectra (d >= 0; the others are conjugates)
+        levels = (info["spectra"] - (27 if info["super_forward"] else 343)) // 316
+        per_pass = (info["fft_forward"] + info["fft_inverse"] + 172 * levels) * 2 * S * es
         return 8.0 * S * entry["work"], peak, per_pass * passes
     if k == "near_mac":
         per_launch = (info["super_forward"] + info["super_inverse"] + 14) * 2 * S2 * es
