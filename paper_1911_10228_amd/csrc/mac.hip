@@ -594,7 +594,7 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
 
 }  // namespace
 
-// mode: targets per row W (4 or 8) with NearRow items, kNearTiled + 4 with NearTile items;
+// mode: targets per row W (2, 4 or 8) with NearRow items, kNearTiled + 4 with NearTile items;
 // chosen by the planner.  All rows of a work set share one kernel table (the wavefronts of a
 // workgroup stage the kernels for all its rows).
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode) {
@@ -609,7 +609,8 @@ template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_
     wg += (int64_t)(tiled ? t.s[i].count : (t.s[i].count + 3) / 4) * chunks8 * 8;
   }
   if (wg == 0) return hipSuccess;
-  if (mode == 4) near_mac_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  if (mode == 2) near_mac_kernel<T, 2><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else if (mode == 4) near_mac_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == 8) near_mac_kernel<T, 8><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == kNearTiled + 4) near_tile_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else return hipErrorInvalidValue;

@@ -576,7 +576,7 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
           if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
           break;
         }
-        if (mode != 4 && mode != 8) return bad("near row width", i);
+        if (mode != 2 && mode != 4 && mode != 8) return bad("near row width", i);
         const auto& it = ((const NearRow<double>*)items)[i];
         if (it.ngroups < 0 || it.ngroups > 3) return bad("near row groups", i);
         for (int j = 0; j < 9; ++j) {
@@ -1161,7 +1161,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
         if (p->tune && steps.size() > primary) {
           // the other launch shapes for the autotuner: rows of 4 or 8 targets (FP32 also tiles)
-          for (int shape : {4, 8}) {
+          for (int shape : {2, 4, 8}) {        // rows of 2 suit sparse levels
             if (!tiled && shape == 4) continue;
             std::vector<NearRow<D>> alt_rows;
             for (const SupInst& si : sup) {
