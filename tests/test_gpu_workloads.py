@@ -9,7 +9,8 @@
   manufactured solution;
 * 64 independent layouts solved in shared launches: equal to each solved alone, and the
   smallest against the oracle;
-* a Poisson-arrival request stream through the server: every result equal to its solve alone.
+* a Poisson-arrival request stream through the server: every result equal to its solve alone,
+  and the smallest served layouts against the oracle.
 """
 import time
 
@@ -131,3 +132,9 @@ def test_serving_poisson_stream(lgf):
     for u, k in zip(outs, which):
         assert np.array_equal(u.cpu().numpy(), alone[k])
     srv.close()
+    # a sample of the served layouts against the oracle's one-step defect correction
+    for k in sorted(set(which.tolist()), key=lambda k: pool[k].unknowns)[:2]:
+        L = pool[k]
+        its = dc_oracle.solve_dc(L.blocks, L.levels, L.f, L.n_b, L.interp_order, iters=1,
+                                 dtype=np.float64)
+        assert rel(alone[k], its[1]) <= 1e-6, L.name
