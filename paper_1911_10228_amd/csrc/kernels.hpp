@@ -95,19 +95,21 @@ template <typename T> struct NearRow {
   const c64* const* kptr;              // 27 FP64 kernel spectra, index (dz+1)*9+(dy+1)*3+dx+1
 };
 
-// A near tile: 2 x 2 rows (y0 + ry, z0 + rz), row r = ry + 2 rz, of up to 4 targets along x at
-// x0 = 4 wx.  The 4 x 4 source rows (y0 - 1 + qy, z0 - 1 + qz), q = qy + 4 qz, cover the 27
-// neighbours of every target of the tile; a workgroup stages them in LDS once per frequency
-// chunk.
+// A near tile: 2 x RZ rows (y0 + ry, z0 + rz), row r = ry + 2 rz, of up to 4 targets along x at
+// x0 = 4 wx (RZ = 2 or 4).  The 4 x (RZ + 2) source rows (y0 - 1 + qy, z0 - 1 + qz),
+// q = qy + 4 qz, cover the 27 neighbours of every target of the tile; a workgroup stages them
+// in LDS once per frequency chunk.
 constexpr int kTileW = 4;                 // targets per tile row
+constexpr int kTileRowsMax = 8;           // 2 x RZ rows
+constexpr int kTileSrcRowsMax = 24;       // 4 x (RZ + 2) source rows
 template <typename T> struct NearTile {
-  int32_t tgt[4][kMacL];               // target super slots (-1: none), first kTileW used
-  int32_t src[16 * (kTileW + 2)];      // source super slot of row q at x0 - 1 + s: [q * 6 + s]
-                                       // (the zero slot where absent)
+  int32_t tgt[kTileRowsMax][kMacL];    // target super slots (-1: none), first kTileW used
+  int32_t src[kTileSrcRowsMax * (kTileW + 2)];   // source super slot of row q at x0 - 1 + s:
+                                       // [q * 6 + s] (the zero slot where absent)
   uint32_t src_mask;                   // bit q: source row q holds a source
   uint32_t row_mask;                   // bit r: row r holds a target
   int32_t zero;                        // the zero slot (not loaded: staged as zeros)
-  int32_t pad;
+  int32_t rz;                          // rows along z: 2 or 4
   const cpx<T>* fhat;
   cpx<T>* uhat;
   const cpx<T>* const* kptr;           // 27 kernel spectra in the storage type, index

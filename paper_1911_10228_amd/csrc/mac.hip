@@ -502,21 +502,23 @@ __global__ __launch_bounds__(256) void near_mac_kernel(SetTable sets, int S) {
   }
 }
 
-// Tiled form: one workgroup of 4 wavefronts per (tile, frequency chunk); the 16 source rows of
-// the tile ((W + 2) spectra each, 64 frequencies) are staged in LDS with all loads of a
-// wavefront in flight together, and each wavefront holds the 14 kernel values h <= 13 of its
-// frequency in registers (the others are their conjugates).  Each wavefront then applies its row's 9 source rows from LDS, in the storage
-// type (the planner uses tiles for FP32 spectra on single-level layouts, where defect
-// correction removes FP32 error: an FP64 sum there changed nothing measurable).  Compared
-// with one wavefront per row loading its own 9 source rows, each source spectrum chunk is read
-// from L2 once per tile instead of up to 4 times.
-template <typename T, int W>
-__global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
+// Tiled form: one workgroup of 2 RZ wavefronts (one per target row) per (tile, frequency chunk);
+// the 4 (RZ + 2) source rows of the tile ((W + 2) spectra each, 64 frequencies) are staged in LDS
+// with all loads of a wavefront in flight together, and each wavefront holds the 14 kernel
+// values h <= 13 of its frequency in registers (the others are their conjugates).  Each
+// wavefront then applies its row's 9 source rows from LDS, in the storage type (the planner uses
+// tiles for FP32 spectra on single-level layouts, where defect correction removes FP32 error:
+// an FP64 sum there changed nothing measurable).  Compared with one wavefront per row loading
+// its own 9 source rows, each source spectrum chunk is read from L2 once per tile instead of up
+// to 4 times; taller tiles (RZ = 4) stage fewer spectra per row, in more LDS per workgroup.
+template <typename T, int W, int RZ>
+__global__ __launch_bounds__(128 * RZ) void near_tile_kernel(SetTable sets, int S) {
   static_assert(W == kTileW, "tile rows hold kTileW targets");
+  constexpr int WAVES = 2 * RZ;                    // one per target row
   constexpr int NS = W + 2;
-  constexpr int NE = 16 * NS;                      // staged spectra per tile
-  constexpr int PER_WAVE = NE / 4;
-  static_assert(NE % 4 == 0, "tile entries split evenly over 4 wavefronts");
+  constexpr int NE = 4 * (RZ + 2) * NS;            // staged spectra per tile
+  constexpr int PER_WAVE = NE / WAVES;
+  static_assert(NE % WAVES == 0 && 4 * (RZ + 2) <= kTileSrcRowsMax, "tile entries split evenly");
   __shared__ cpx<T> fl[NE * 64];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
@@ -594,7 +596,8 @@ __global__ __launch_bounds__(256) void near_tile_kernel(SetTable sets, int S) {
 
 }  // namespace
 
-// mode: targets per row W (2, 4 or 8) with NearRow items, kNearTiled + 4 with NearTile items;
+// mode: targets per row W (2, 4 or 8) with NearRow items, kNearTiled + 4 / + 6 with NearTile items
+// of 2 x 2 / 2 x 4 rows;
 // chosen by the planner.  All rows of a work set share one kernel table (the wavefronts of a
 // workgroup stage the kernels for all its rows).
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode) {
@@ -612,7 +615,8 @@ template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_
   if (mode == 2) near_mac_kernel<T, 2><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == 4) near_mac_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == 8) near_mac_kernel<T, 8><<<(unsigned)wg, 256, 0, st>>>(t, S);
-  else if (mode == kNearTiled + 4) near_tile_kernel<T, 4><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else if (mode == kNearTiled + 4) near_tile_kernel<T, kTileW, 2><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else if (mode == kNearTiled + 6) near_tile_kernel<T, kTileW, 4><<<(unsigned)wg, 512, 0, st>>>(t, S);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -564,11 +564,12 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       case K_NEAR_MAC: {
         const int t = ty == 0 ? 0 : 1;
         if (mode > kNearTiled) {
-          if (mode != kNearTiled + 4) return bad("near tile width", i);
           const auto& it = ((const NearTile<double>*)items)[i];
-          for (int j = 0; j < 16 * (kTileW + 2); ++j)
+          if (!(mode == kNearTiled + 4 && it.rz == 2) && !(mode == kNearTiled + 6 && it.rz == 4))
+            return bad("near tile shape", i);
+          for (int j = 0; j < 4 * (it.rz + 2) * (kTileW + 2); ++j)
             if (it.src[j] < 0 || it.src[j] > sc.nsup_src[t]) return bad("near tile source slot", i);
-          for (int r = 0; r < 4; ++r)
+          for (int r = 0; r < kTileRowsMax; ++r)
             for (int q = 0; q < kMacL; ++q)
               if (it.tgt[r][q] < -1 || it.tgt[r][q] >= sc.nsup_tgt[t]) return bad("near tile target slot", i);
           if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
@@ -873,34 +874,37 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       out[it->second].tgt[t.first.x - wx * W] = t.second;
     }
   };
-  // Near tiles: 2 x 2 rows of kTileW targets sharing their 4 x 4 source rows (staged in LDS)
+  // Near tiles: 2 x RZ rows of kTileW targets sharing their 4 x (RZ + 2) source rows (staged in
+  // LDS)
   auto make_tiles = [&](const std::vector<std::pair<I3, int>>& tg, const I3Map& srcs, int zero,
                         const cpx<D>* fhat, cpx<D>* uhat, const cpx<D>* const* kptr,
-                        std::vector<NearTile<D>>& out) {
+                        std::vector<NearTile<D>>& out, int RZ = 2) {
     std::map<I3, size_t> tile_of;
     for (const auto& t : tg) {
-      const int wx = floordiv(t.first.x, kTileW), ty2 = floordiv(t.first.y, 2), tz2 = floordiv(t.first.z, 2);
+      const int wx = floordiv(t.first.x, kTileW), ty2 = floordiv(t.first.y, 2), tz2 = floordiv(t.first.z, RZ);
       const I3 key{wx, ty2, tz2};
       auto it = tile_of.find(key);
       if (it == tile_of.end()) {
         NearTile<D> q{};
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < kTileRowsMax; ++r)
           for (int i = 0; i < kMacL; ++i) q.tgt[r][i] = -1;
-        for (int qz = 0; qz < 4; ++qz)
+        for (int j = 0; j < kTileSrcRowsMax * (kTileW + 2); ++j) q.src[j] = zero;
+        for (int qz = 0; qz < RZ + 2; ++qz)
           for (int qy = 0; qy < 4; ++qy)
             for (int x = 0; x < kTileW + 2; ++x) {
-              auto sit = srcs.find({wx * kTileW - 1 + x, 2 * ty2 - 1 + qy, 2 * tz2 - 1 + qz});
+              auto sit = srcs.find({wx * kTileW - 1 + x, 2 * ty2 - 1 + qy, RZ * tz2 - 1 + qz});
               q.src[(qy + 4 * qz) * (kTileW + 2) + x] = sit != srcs.end() ? sit->second : zero;
               if (sit != srcs.end()) q.src_mask |= 1u << (qy + 4 * qz);
             }
         q.zero = zero;
+        q.rz = RZ;
         q.fhat = fhat;
         q.uhat = uhat;
         q.kptr = kptr;
         it = tile_of.emplace(key, out.size()).first;
         out.push_back(q);
       }
-      const int r = (t.first.y - 2 * ty2) + 2 * (t.first.z - 2 * tz2);
+      const int r = (t.first.y - 2 * ty2) + 2 * (t.first.z - RZ * tz2);
       out[it->second].tgt[r][t.first.x - wx * kTileW] = t.second;
       out[it->second].row_mask |= 1u << r;
     }
@@ -1124,7 +1128,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         const SpecSet* ns = nullptr;
         LGF_HIP_CHECK(plan_spectra(p, nb, -(1 << k), &ns));     // super-block kernels, scale 2^k
         std::vector<NearRow<D>> nr;
-        std::vector<NearTile<D>> nt;
+        std::vector<NearTile<D>> nt, nt4;
         std::vector<SuperInvItem<D>> si_items;
         int64_t pairs = 0;
         const bool tiled = sty == TY_F32;      // FP32 storage: 2 x 2 rows of 4 share staged sources
@@ -1133,10 +1137,12 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
           pairs += si.pairs;
           std::vector<std::pair<I3, int>> tg;
           for (const SupTgt& t : si.tg) tg.push_back({t.c, t.slot});
-          if (tiled)
+          if (tiled) {
             make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0),
                        (const cpx<D>* const*)ns->kp32, nt);
-          else
+            make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0),
+                       (const cpx<D>* const*)ns->kp32, nt4, 4);
+          } else
             make_rows(tg, si.sslot, (int)nsup_src[a], 4, SFH(a, 0), SUH(a, 0), ns->kp64, nr);
           const OctLevel& L = (si.ch == 0 ? chT[l] : chA[l]).lv[k];
           for (const SupTgt& t : si.tg) {
@@ -1154,13 +1160,24 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         p->near_pairs += pairs;
         push(steps, l, 3, k, K_SUP_FWD, sty, hi.add(sf), sf.size(), nullptr, (int64_t)sf.size(), 0, chain);
         const size_t primary = steps.size();
+        // tiles of 2 x 4 rows (fewer staged spectra per row, more LDS) where they are about as
+        // full as tiles of 2 x 2 (dense levels); the other height is an autotuner candidate
+        const bool tall = tiled && 8 * nt4.size() <= 9 * nt.size() / 2;
+        if (tall) std::swap(nt, nt4);
         const size_t nt_off = tiled ? hi.add(nt) : 0;
         if (tiled)
-          push(steps, l, 4, k, K_NEAR_MAC, sty, nt_off, nt.size(), nullptr, pairs, kNearTiled + 4, chain);
+          push(steps, l, 4, k, K_NEAR_MAC, sty, nt_off, nt.size(), nullptr, pairs,
+               tall ? kNearTiled + 6 : kNearTiled + 4, chain);
         else
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
         if (p->tune && steps.size() > primary) {
-          // the other launch shapes for the autotuner: rows of 4 or 8 targets (FP32 also tiles)
+          // the other launch shapes for the autotuner: tiles of 2 x 4 rows (FP32), rows of 2, 4 or
+          // 8 targets
+          if (tiled) {
+            push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt4), nt4.size(), nullptr, pairs,
+                 tall ? kNearTiled + 4 : kNearTiled + 6, chain);
+            alt_of.push_back(primary);
+          }
           for (int shape : {2, 4, 8}) {        // rows of 2 suit sparse levels
             if (!tiled && shape == 4) continue;
             std::vector<NearRow<D>> alt_rows;
