@@ -31,6 +31,23 @@ __device__ __forceinline__ void cmac(cpx<T>& acc, cpx<T> a, cpx<T> b) {
   acc.y = fma(a.y, b.x, acc.y);
 }
 
+// Global-memory views of generic pointers.  Accesses through them compile to global_* rather
+// than flat_* instructions; a flat access also counts against the LDS/scalar wait counter, so in
+// a kernel that mixes memory and LDS traffic every wait for an LDS result would also wait for all
+// memory accesses still in flight.
+template <typename T> using gview = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gview<T> gl(T* p) { return (gview<T>)p; }
+// complex element i of a global array (as two scalars: class assignment has no global form)
+template <typename T> __device__ __forceinline__ cpx<T> gld(const cpx<T>* p, int64_t i) {
+  const gview<const T> q = gl((const T*)p);
+  return {q[2 * i], q[2 * i + 1]};
+}
+template <typename T> __device__ __forceinline__ void gst(cpx<T>* p, int64_t i, cpx<T> v) {
+  const gview<T> q = gl((T*)p);
+  q[2 * i] = v.x;
+  q[2 * i + 1] = v.y;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Compile-time twiddle factors cos/sin(2 pi m / N), from Taylor series on the first octant and
 // the exact symmetries of the circle (no math-library constants involved).

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_fwd_kernel(SetTable sets
   for (int l = tid; l < BPW * NB * NB; l += NT) {
     const int y = l % NB, z = (l / NB) % NB, b = l / (NB * NB);
     if (first + b >= ws.count) continue;
-    const T* src = items[first + b].src + (z * NB + y) * NB;
+    const gview<const T> src = gl(items[first + b].src + (z * NB + y) * NB);
     T xr[NB], xi[NB], Xr[P], Xi[P];
 #pragma unroll
     for (int x = 0; x < NB; ++x) { xr[x] = src[x]; xi[x] = T(0); }
@@ -84,9 +84,9 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_fwd_kernel(SetTable sets
       zr[zz] = v.x; zi[zz] = v.y;
     }
     fwd_padded<NB>(zr, zi, Zr, Zi);
-    cpx<T>* dst = items[first + bb].dst + ky * H + kxx;
+    cpx<T>* const dst = items[first + bb].dst + ky * H + kxx;
 #pragma unroll
-    for (int kz = 0; kz < P; ++kz) dst[kz * P * H] = {Zr[kz], Zi[kz]};
+    for (int kz = 0; kz < P; ++kz) gst(dst, kz * P * H, cpx<T>{Zr[kz], Zi[kz]});
   }
 }
 
@@ -105,11 +105,11 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_inv_kernel(SetTable sets
   for (int l = tid; l < BPW * P * H; l += NT) {
     const int kx = l % H, ky = (l / H) % P, b = l / (H * P);
     if (first + b >= ws.count) continue;
-    const cpx<T>* src = items[first + b].src + ky * H + kx;
+    const cpx<T>* const src = items[first + b].src + ky * H + kx;
     T Zr[P], Zi[P], zr[NB], zi[NB];
 #pragma unroll
     for (int kz = 0; kz < P; ++kz) {
-      const cpx<T> v = src[kz * P * H];
+      const cpx<T> v = gld(src, kz * P * H);
       Zr[kz] = v.x; Zi[kz] = v.y;
     }
     inv_cropped<NB>(Zr, Zi, zr, zi);
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_inv_kernel(SetTable sets
 #pragma unroll
     for (int k = 1; k < NB; ++k) { Xr[P - k] = Xr[k]; Xi[P - k] = -Xi[k]; }
     inv_cropped<NB>(Xr, Xi, xr, xi);
-    T* dst = items[first + bb].dst + (zz * NB + y) * NB;
+    const gview<T> dst = gl(items[first + bb].dst + (zz * NB + y) * NB);
 #pragma unroll
     for (int x = 0; x < NB; ++x) dst[x] = xr[x] * inv;
   }

@@ -33,7 +33,7 @@ __device__ __forceinline__ T child_value(const T* const* ch, int x, int y, int z
   const T* c = ch[oc];
   if (!c) return T(0);
   const int lx = x & (NB - 1), ly = y & (NB - 1), lz = z & (NB - 1);
-  return c[(lz * NB + ly) * NB + lx];
+  return gl(c)[(lz * NB + ly) * NB + lx];
 }
 
 // forward (x, y) pass: one workgroup per (super-block, z-plane); lanes own x-lines, then y-lines
@@ -59,14 +59,14 @@ __global__ __launch_bounds__(64) void sup_fwd_xy(SetTable sets) {
     for (int k = 0; k < H; ++k) pl[y * H + k] = {Xr[k], Xi[k]};
   }
   __syncthreads();
-  cpx<T>* out = it.tmp + (int64_t)z * Sh::PLANE;
+  cpx<T>* const out = it.tmp + (int64_t)z * Sh::PLANE;
   for (int kx = tid; kx < H; kx += 64) {
     T yr[B2], yi[B2], Yr[P], Yi[P];
 #pragma unroll
     for (int y = 0; y < B2; ++y) { yr[y] = pl[y * H + kx].x; yi[y] = pl[y * H + kx].y; }
     fwd_padded<B2>(yr, yi, Yr, Yi);
 #pragma unroll
-    for (int ky = 0; ky < P; ++ky) out[ky * H + kx] = {Yr[ky], Yi[ky]};
+    for (int ky = 0; ky < P; ++ky) gst(out, ky * H + kx, cpx<T>{Yr[ky], Yi[ky]});
   }
 }
 
@@ -83,14 +83,14 @@ __global__ __launch_bounds__(256) void sup_fwd_z(SetTable sets) {
   const SuperFwdItem<T>& it = ((const SuperFwdItem<T>*)ws.items)[local / WG_PER_ITEM];
   const int line = (int)(local % WG_PER_ITEM) * 256 + threadIdx.x;
   if (line >= LINES) return;
-  const cpx<T>* in = it.tmp + line;
+  const cpx<T>* const in = it.tmp + line;
   T zr[B], zi[B], Zr[P], Zi[P];
 #pragma unroll
-  for (int z = 0; z < B; ++z) { const cpx<T> v = in[(int64_t)z * LINES]; zr[z] = v.x; zi[z] = v.y; }
+  for (int z = 0; z < B; ++z) { const cpx<T> v = gld(in, (int64_t)z * LINES); zr[z] = v.x; zi[z] = v.y; }
   fwd_padded<B>(zr, zi, Zr, Zi);
-  cpx<T>* out = it.dst + line;
+  cpx<T>* const out = it.dst + line;
 #pragma unroll
-  for (int kz = 0; kz < P; ++kz) out[(int64_t)kz * LINES] = {Zr[kz], Zi[kz]};
+  for (int kz = 0; kz < P; ++kz) gst(out, (int64_t)kz * LINES, cpx<T>{Zr[kz], Zi[kz]});
 }
 
 // inverse z pass: one lane per (kx, ky) line, keep z < B2
@@ -106,14 +106,14 @@ __global__ __launch_bounds__(256) void sup_inv_z(SetTable sets) {
   const SuperInvItem<T>& it = ((const SuperInvItem<T>*)ws.items)[local / WG_PER_ITEM];
   const int line = (int)(local % WG_PER_ITEM) * 256 + threadIdx.x;
   if (line >= LINES) return;
-  const cpx<T>* in = it.src + line;
+  const cpx<T>* const in = it.src + line;
   T Zr[P], Zi[P], zr[B], zi[B];
 #pragma unroll
-  for (int kz = 0; kz < P; ++kz) { const cpx<T> v = in[(int64_t)kz * LINES]; Zr[kz] = v.x; Zi[kz] = v.y; }
+  for (int kz = 0; kz < P; ++kz) { const cpx<T> v = gld(in, (int64_t)kz * LINES); Zr[kz] = v.x; Zi[kz] = v.y; }
   inv_cropped<B>(Zr, Zi, zr, zi);
-  cpx<T>* out = it.tmp + line;
+  cpx<T>* const out = it.tmp + line;
 #pragma unroll
-  for (int z = 0; z < B; ++z) out[(int64_t)z * LINES] = {zr[z], zi[z]};
+  for (int z = 0; z < B; ++z) gst(out, (int64_t)z * LINES, cpx<T>{zr[z], zi[z]});
 }
 
 // inverse (y, x) pass: one workgroup per (super-block, z-plane); crop, scale by 1/P^3 and write
@@ -129,11 +129,11 @@ __global__ __launch_bounds__(64) void sup_inv_yx(SetTable sets) {
   const SuperInvItem<T>& it = ((const SuperInvItem<T>*)ws.items)[local / B2];
   const int z = (int)(local % B2);
   const int tid = threadIdx.x;
-  const cpx<T>* in = it.tmp + (int64_t)z * Sh::PLANE;
+  const cpx<T>* const in = it.tmp + (int64_t)z * Sh::PLANE;
   for (int kx = tid; kx < H; kx += 64) {
     T Yr[P], Yi[P], yr[B2], yi[B2];
 #pragma unroll
-    for (int ky = 0; ky < P; ++ky) { const cpx<T> v = in[ky * H + kx]; Yr[ky] = v.x; Yi[ky] = v.y; }
+    for (int ky = 0; ky < P; ++ky) { const cpx<T> v = gld(in, ky * H + kx); Yr[ky] = v.x; Yi[ky] = v.y; }
     inv_cropped<B2>(Yr, Yi, yr, yi);
 #pragma unroll
     for (int y = 0; y < B2; ++y) pl[y * H + kx] = {yr[y], yi[y]};
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(64) void sup_inv_yx(SetTable sets) {
     for (int half = 0; half < 2; ++half) {
       TC* c = (TC*)it.child[half + 2 * cy + 4 * cz];
       if (!c) continue;
-      TC* row = c + (lz * NB + ly) * NB;
+      const gview<TC> row = gl(c + (lz * NB + ly) * NB);
 #pragma unroll
       for (int x = 0; x < NB; ++x) row[x] = TC(xr[half * NB + x] * inv);
     }

@@ -36,20 +36,20 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const InterpItem<TC, TP>& it = ((const InterpItem<TC, TP>*)ws.items)[blockIdx.x - ws.wg_begin];
-  const double* __restrict__ W = ws.w;
+  const gview<const double> __restrict__ W = gl(ws.w);
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
   constexpr int PT = per_thread<NB>();
   {
     TP pv[PT];
 #pragma unroll
-    for (int j = 0; j < PT; ++j) pv[j] = it.parent[threadIdx.x + j * kOpThreads];
+    for (int j = 0; j < PT; ++j) pv[j] = gl(it.parent)[threadIdx.x + j * kOpThreads];
 #pragma unroll
     for (int j = 0; j < PT; ++j) b0[threadIdx.x + j * kOpThreads] = pv[j];
   }
   TC cv[PT];
   if (it.accumulate) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j) cv[j] = it.child[threadIdx.x + j * kOpThreads];
+    for (int j = 0; j < PT; ++j) cv[j] = gl(it.child)[threadIdx.x + j * kOpThreads];
   }
   for (int i = threadIdx.x; i < 3 * NB * NB; i += kOpThreads) {
     const int d = i / (NB * NB), r = (i / NB) % NB, m = i % NB;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
     b0[i] = s;
   }
   __syncthreads();
-  TC* const child = it.child;
+  const gview<TC> child = gl(it.child);
   const bool accumulate = it.accumulate;
   TC out[PT];
 #pragma unroll
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
   const int64_t local = blockIdx.x - ws.wg_begin;
   const AnterpItem<TC, TP>& it = ((const AnterpItem<TC, TP>*)ws.items)[local / 8];
   const int z0 = (int)(local % 8) * SL;
-  const double* __restrict__ W = ws.w;
+  const gview<const double> __restrict__ W = gl(ws.w);
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * NB * NB; i += NB * NB) {
     const int cc = i / (NB * NB), r = (i / NB) % NB, m = i % NB;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
     gmask |= 1 << g;
     T v[NB];
 #pragma unroll
-    for (int Z = 0; Z < NB; ++Z) v[Z] = T(ch[(Z * NB + b) * NB + a]);
+    for (int Z = 0; Z < NB; ++Z) v[Z] = T(gl(ch)[(Z * NB + b) * NB + a]);
 #pragma unroll
     for (int zz = 0; zz < SL; ++zz)
 #pragma unroll
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
     }
     acc[zz] = s;
   }
-  TP* const dst = it.dst;
+  const gview<TP> dst = gl(it.dst);
 #pragma unroll
   for (int zz = 0; zz < SL; ++zz) dst[((z0 + zz) * NB + b) * NB + a] = acc[zz];
 }
@@ -177,14 +177,14 @@ __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
   const WorkSet& ws = sets.s[set];
   const CombineItem<T>& it = ((const CombineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
   const double sc = it.scale;
-  double* dd = it.dst_d ? it.dst_d : ws.out + it.dst_out;
+  const gview<double> dd = gl(it.dst_d ? it.dst_d : ws.out + it.dst_out);
   constexpr int PT = per_thread<NB>();
   double v[PT];
 #pragma unroll
-  for (int j = 0; j < PT; ++j) v[j] = it.v ? sc * double(it.v[threadIdx.x + j * kOpThreads]) : 0.0;
+  for (int j = 0; j < PT; ++j) v[j] = it.v ? sc * double(gl(it.v)[threadIdx.x + j * kOpThreads]) : 0.0;
   if (it.base) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j) v[j] += it.base[threadIdx.x + j * kOpThreads];
+    for (int j = 0; j < PT; ++j) v[j] += gl(it.base)[threadIdx.x + j * kOpThreads];
   }
   if (!it.dst_d && (ws.aux & kAuxAccumulate)) {       // defect-correction update of u
 #pragma unroll
@@ -200,12 +200,12 @@ __global__ __launch_bounds__(kOpThreads) void convert_kernel(SetTable sets) {
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const ConvertItem<T>& it = ((const ConvertItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
-  const double* src = it.src ? it.src : ws.in + it.src_in;
+  const gview<const double> src = gl(it.src ? it.src : ws.in + it.src_in);
   constexpr int PT = per_thread<NB>();
   double v[PT];
 #pragma unroll
   for (int j = 0; j < PT; ++j) v[j] = src[threadIdx.x + j * kOpThreads];
-  T* const dst = it.dst;
+  const gview<T> dst = gl(it.dst);
 #pragma unroll
   for (int j = 0; j < PT; ++j) dst[threadIdx.x + j * kOpThreads] = T(v[j]);
 }
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kOpThreads) void coarsen_kernel(SetTable sets) {
   const WorkSet& ws = sets.s[set];
   const CoarsenItem& it = ((const CoarsenItem*)ws.items)[blockIdx.x - ws.wg_begin];
   constexpr int PT = per_thread<NB>(), G = PT < 8 ? PT : 8;   // groups of G cells (registers)
-  double* const dst = it.dst;
+  const gview<double> dst = gl(it.dst);
 #pragma unroll 1
   for (int j0 = 0; j0 < PT; j0 += G) {
     double out[G];
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kOpThreads) void coarsen_kernel(SetTable sets) {
       const int j = jj, i = threadIdx.x + (j0 + jj) * kOpThreads;
       const int x = i % NB, y = (i / NB) % NB, z = i / (NB * NB);
       const int oc = (x / HB) + 2 * (y / HB) + 4 * (z / HB);
-      const double* ch = it.child[oc] ? it.child[oc] : ws.in + it.child_in[oc];
+      const gview<const double> ch = gl(it.child[oc] ? it.child[oc] : ws.in + it.child_in[oc]);
       const int fx = 2 * (x % HB), fy = 2 * (y % HB), fz = 2 * (z % HB);
       double s = 0.0;
 #pragma unroll
@@ -244,11 +244,11 @@ __global__ __launch_bounds__(kOpThreads) void coarsen_kernel(SetTable sets) {
 
 // Quadratic refinement table: row j in [-1, 2 NB] at index j + 1 holds {lo, w0, w1, w2}.
 template <int NB, typename T>
-__device__ __forceinline__ T refine_point(const T* __restrict__ pw, const double* __restrict__ w3,
-                                          int jx, int jy, int jz) {
-  const double* rx = w3 + 4 * (jx + 1);
-  const double* ry = w3 + 4 * (jy + 1);
-  const double* rz = w3 + 4 * (jz + 1);
+__device__ __forceinline__ T refine_point(gview<const T> __restrict__ pw,
+                                          gview<const double> __restrict__ w3, int jx, int jy, int jz) {
+  const gview<const double> rx = w3 + 4 * (jx + 1);
+  const gview<const double> ry = w3 + 4 * (jy + 1);
+  const gview<const double> rz = w3 + 4 * (jz + 1);
   const int lx = (int)rx[0], ly = (int)ry[0], lz = (int)rz[0];
   T s = 0;
 #pragma unroll
@@ -256,7 +256,7 @@ __device__ __forceinline__ T refine_point(const T* __restrict__ pw, const double
     T sy = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const T* row = pw + ((lz + a) * NB + (ly + b)) * NB + lx;
+      const gview<const T> row = pw + ((lz + a) * NB + (ly + b)) * NB + lx;
       const T sx = T(rx[1]) * row[0] + T(rx[2]) * row[1] + T(rx[3]) * row[2];
       sy += T(ry[1 + b]) * sx;
     }
@@ -279,15 +279,15 @@ __global__ __launch_bounds__(kOpThreads) void refine_kernel(SetTable sets) {
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const RefineItem& it = ((const RefineItem*)ws.items)[blockIdx.x - ws.wg_begin];
-  const double* __restrict__ w3 = ws.w;
-  const double* __restrict__ pw = it.parent_w;
+  const gview<const double> __restrict__ w3 = gl(ws.w);
+  const gview<const double> __restrict__ pw = gl(it.parent_w);
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
   // table row of child index j along axis d: w3[4 (c_d NB + j + 1) ...]
   const int b0 = (int)w3[4 * (c[0] * NB + 1)], b1 = (int)w3[4 * (c[1] * NB + 1)],
             b2 = (int)w3[4 * (c[2] * NB + 1)];
   if (threadIdx.x < 3 * NB) {
     const int d = threadIdx.x / NB, j = threadIdx.x % NB;
-    const double* r = w3 + 4 * (c[d] * NB + j + 1);
+    const gview<const double> r = w3 + 4 * (c[d] * NB + j + 1);
     const int base = d == 0 ? b0 : d == 1 ? b1 : b2;
     tab[d][j][0] = r[0] - base;
     tab[d][j][1] = r[1];
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kOpThreads) void refine_kernel(SetTable sets) {
     for (int k = 0; k < 3; ++k) s += tab[2][Z][1 + k] * pl[(lo + k) * NB * NB + XY];
     out[j] = s;
   }
-  double* const jw = it.jw;
+  const gview<double> jw = gl(it.jw);
 #pragma unroll
   for (int j = 0; j < PT; ++j) jw[threadIdx.x + j * kOpThreads] = out[j];
 }
@@ -350,10 +350,10 @@ __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const CorrectItem<T>& it = ((const CorrectItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
-  const double* __restrict__ w3 = ws.w;
-  const double* __restrict__ f = it.f ? it.f : ws.in + it.f_in;
-  const double* __restrict__ jw = it.jw;
-  const double* __restrict__ pw = it.parent_w;
+  const gview<const double> __restrict__ w3 = gl(ws.w);
+  const gview<const double> __restrict__ f = gl(it.f ? it.f : ws.in + it.f_in);
+  const gview<const double> __restrict__ jw = gl(it.jw);
+  const gview<const double> __restrict__ pw = gl(it.parent_w);
   const int c[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
   double fv[PT], jv[PT];
 #pragma unroll
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
     if (const double* nb = it.nbr[face]) {
       int p[3] = {q[0], q[1], q[2]};
       p[ax] = hi ? 0 : NB - 1;
-      v = nb[(p[2] * NB + p[1]) * NB + p[0]];
+      v = gl(nb)[(p[2] * NB + p[1]) * NB + p[0]];
     } else {
       v = refine_point<NB, double>(pw, w3, c[0] * NB + q[0], c[1] * NB + q[1], c[2] * NB + q[2]);
     }
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kOpThreads) void correct_kernel(SetTable sets) {
                        ext[cc + E * E] - 6.0 * ext[cc];
     out[j] = T(fv[j] - inv_h2 * lap);
   }
-  T* const g = it.g;
+  const gview<T> g = gl(it.g);
 #pragma unroll
   for (int j = 0; j < PT; ++j) g[threadIdx.x + j * kOpThreads] = out[j];
 }
@@ -420,8 +420,8 @@ __global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
   const int64_t local = blockIdx.x - ws.wg_begin;
   const ResidualItem& it = ((const ResidualItem*)ws.items)[local / kResidualSlabs];
   const int z0 = (int)(local % kResidualSlabs) * SZ;
-  double* const r = it.r;
-  float* const conv = it.conv;
+  const gview<double> r = gl(it.r);
+  const gview<float> conv = gl(it.conv);
   if (!r && !conv) return;
   const int t = threadIdx.x, x = t % NB, y = t / NB;
   if (!it.leaf) {
@@ -433,8 +433,9 @@ __global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
     }
     return;
   }
-  const double* __restrict__ f = ws.in + it.off;
-  const double* __restrict__ u = ws.out + it.off;
+  const gview<const double> __restrict__ f = gl(ws.in + it.off);
+  const gview<const double> __restrict__ u = gl(ws.out + it.off);
+  const gview<const double> out_all = gl((const double*)ws.out);
   int missing = 0;
 #pragma unroll
   for (int face = 0; face < 6; ++face)
@@ -448,8 +449,8 @@ __global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
     const int z = z0 - 1 + j;
     uv[j] = 0.0;
     if (z >= 0 && z < NB) uv[j] = u[z * N2 + t];
-    else if (z < 0 && !(missing & 16)) uv[j] = ws.out[it.nbr_off[4] + (NB - 1) * N2 + t];
-    else if (z >= NB && !(missing & 32)) uv[j] = ws.out[it.nbr_off[5] + t];
+    else if (z < 0 && !(missing & 16)) uv[j] = out_all[it.nbr_off[4] + (NB - 1) * N2 + t];
+    else if (z >= NB && !(missing & 32)) uv[j] = out_all[it.nbr_off[5] + t];
   }
   // x and y faces of the slab's planes: 4 faces x NB x SZ cells over the threads
   constexpr int HP = (4 * NB * SZ + N2 - 1) / N2;
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
     if (jj >= 4 * NB * SZ) continue;
     const int face = jj / (NB * SZ), rem = jj % (NB * SZ), a = rem % NB, zz = rem / NB;
     if ((missing >> face) & 1) continue;
-    const double* nb = ws.out + it.nbr_off[face];
+    const gview<const double> nb = out_all + it.nbr_off[face];
     const int ax = face >> 1, hi = face & 1;
     const int src = hi ? 0 : NB - 1, dst = hi ? NB + 1 : 0;
     int px, py, qx, qy;                   // cell in the neighbour, halo cell in ext
