@@ -181,7 +181,13 @@ __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
   constexpr int PT = per_thread<NB>();
   double v[PT];
 #pragma unroll
-  for (int j = 0; j < PT; ++j) v[j] = it.v ? sc * double(gl(it.v)[threadIdx.x + j * kOpThreads]) : 0.0;
+  for (int j = 0; j < PT; ++j) v[j] = it.v ? double(gl(it.v)[threadIdx.x + j * kOpThreads]) : 0.0;
+  if (it.far) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) v[j] += double(gl(it.far)[threadIdx.x + j * kOpThreads]);
+  }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) v[j] *= sc;
   if (it.base) {
 #pragma unroll
     for (int j = 0; j < PT; ++j) v[j] += gl(it.base)[threadIdx.x + j * kOpThreads];

@@ -134,8 +134,9 @@ template <typename T> struct CombineItem {
   double* dst_d;         // plan buffer destination, or, if null,
   int64_t dst_out;       // offset into WorkSet::out
   const T* v;            // level field (nullptr: zero)
+  const T* far;          // interpolated coarse-level field, kept apart from v (nullptr: zero)
   const double* base;    // added field (nullptr: zero)
-  double scale;          // dst = base + scale * v
+  double scale;          // dst = base + scale * (v + far)
 };
 template <typename T> struct ConvertItem {
   T* dst;

@@ -509,6 +509,7 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
         const auto& it = ((const CombineItem<double>*)items)[i];
         if (it.dst_d ? !in_ranges(p, it.dst_d, N3 * 8) : !off_ok(it.dst_out)) return bad("combine dst", i);
         if (it.v && !in_ranges(p, it.v, N3 * es)) return bad("combine v", i);
+        if (it.far && !in_ranges(p, it.far, N3 * es)) return bad("combine far", i);
         if (it.base && !in_ranges(p, it.base, N3 * 8)) return bad("combine base", i);
         break;
       }
@@ -805,6 +806,16 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   p->fhat = fhatA[tyb];
   p->uhat = uhatA[tyb];
   p->v = vA[tyb];
+  // With the super-block base level, the coarse field interpolated into a base block goes to an
+  // array of its own (indexed like the block's level field) and the combine adds the two: the
+  // interpolation then runs on the far-field chain, beside the super-block inverse transforms,
+  // instead of after their join.
+  uint8_t* farA = nullptr;
+  if (p->super_base && ntgt[tyb]) {
+    LGF_HIP_CHECK(ar.alloc(&tmp, ntgt[tyb] * N3 * es(tyb)));
+    farA = (uint8_t*)tmp;
+  }
+  std::vector<char> far_used(ntgt[tyb], 0);
   if (p->fp32 && p->dc_iters > 0 && LR > 1) {      // r of the finer levels' blocks (FP64)
     LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
     p->r = (double*)tmp;
@@ -833,6 +844,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   auto FH = [&](int ty, int64_t slot) { return (cpx<D>*)(fhatA[ty] + slot * S * 2 * es(ty)); };
   auto UH = [&](int ty, int64_t slot) { return (cpx<D>*)(uhatA[ty] + slot * S * 2 * es(ty)); };
   auto V = [&](int ty, int64_t slot) { return (D*)(vA[ty] + slot * N3 * es(ty)); };
+  auto FAR = [&](int64_t slot) { return (D*)(farA + slot * N3 * es(tyb)); };
   auto SFH = [&](int a, int64_t slot) { return (cpx<D>*)(sfhA[a] + slot * S2 * 2 * (a == 0 ? 4 : 8)); };
   auto SUH = [&](int a, int64_t slot) { return (cpx<D>*)(suhA[a] + slot * S2 * 2 * (a == 0 ? 4 : 8)); };
   // Near rows: W targets along x at x0 = W wx, their 27 neighbours' spectra in groups of 3
@@ -1052,6 +1064,11 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
             q.parent = V(ty_of((int)k + 1), F.lv[k + 1].tgt_slot[L.parent[i]]);
             q.octant = octant_of(L.nodes[i]);
             q.accumulate = L.has_ifft[i];
+            if (k == 0 && farA && L.has_ifft[i]) {
+              q.child = FAR(L.tgt_slot[i]);
+              q.accumulate = 0;
+              far_used[L.tgt_slot[i]] = 1;
+            }
             itp[k].push_back(q);
           }
         }
@@ -1202,7 +1219,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     }
     for (int k = K - 2; k >= 0; --k) {
       const int ty = (ty_of(k) == TY_F32 && ty_of(k + 1) == TY_F64) ? TY_MIX : ty_of(k);
-      push(steps, l, 6, 100 - k, K_INTERP, ty, hi.add(itp[k]), itp[k].size(), p->d_w);
+      push(steps, l, 6, 100 - k, K_INTERP, ty, hi.add(itp[k]), itp[k].size(), p->d_w, 0, 0,
+           k == 0 && farA ? 2 : -1);
     }
     std::vector<CombineItem<D>> cmb;
     const double h2 = h * h;
@@ -1212,6 +1230,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       c.dst_out = i * N3;
       const int ts = chT[l].lv[0].tgt_slot[a];
       c.v = ts >= 0 ? V(tyb, ts) : nullptr;
+      c.far = ts >= 0 && far_used[ts] ? FAR(ts) : nullptr;
       c.base = l > 0 ? JW(i) : nullptr;
       c.scale = h2;
       cmb.push_back(c);
@@ -1220,6 +1239,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         q.dst_d = WW(i);
         const int ta = chA[l].lv[0].tgt_slot[a];
         q.v = ta >= 0 ? V(tyb, ta) : nullptr;
+        q.far = ta >= 0 && far_used[ta] ? FAR(ta) : nullptr;
         q.base = l > 0 ? JW(i) : nullptr;
         q.scale = h2;
         cmb.push_back(q);
