@@ -26,14 +26,35 @@ template <int B2> struct SupShape {
   static constexpr int S = P * P * H;
 };
 
-// child element (x, y, z) of a super-block, children indexed by octant cx + 2 cy + 4 cz
-template <int NB, typename T>
-__device__ __forceinline__ T child_value(const T* const* ch, int x, int y, int z) {
-  const int oc = (x >= NB) + 2 * (y >= NB) + 4 * (z >= NB);
-  const T* c = ch[oc];
-  if (!c) return T(0);
-  const int lx = x & (NB - 1), ly = y & (NB - 1), lz = z & (NB - 1);
-  return gl(c)[(lz * NB + ly) * NB + lx];
+// 16-byte vectors of the child element type (rows are loaded whole, not element by element)
+template <typename TC> struct Row16;
+template <> struct Row16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Row16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// row y of plane z of the assembled super-block: x < NB from the octant with cx = 0, the rest
+// from cx = 1 (absent children read as zeros)
+template <int NB, typename T, typename TC>
+__device__ __forceinline__ void load_row(const TC* const* ch, int y, int z, T (&xr)[2 * NB]) {
+  using V = typename Row16<TC>::type;
+  constexpr int E = 16 / sizeof(TC), NV = NB / E;
+  const int oc0 = 2 * (y >= NB) + 4 * (z >= NB);
+  const int off = ((z & (NB - 1)) * NB + (y & (NB - 1))) * NB;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const TC* c = ch[oc0 + h];
+    if (c) {
+      const gview<const V> row = (gview<const V>)gl(c + off);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const V v = row[q];
+#pragma unroll
+        for (int e = 0; e < E; ++e) xr[h * NB + q * E + e] = T(v[e]);
+      }
+    } else {
+#pragma unroll
+      for (int x = 0; x < NB; ++x) xr[h * NB + x] = T(0);
+    }
+  }
 }
 
 // forward (x, y) pass: one workgroup per (super-block, z-plane); lanes own x-lines, then y-lines
@@ -52,8 +73,9 @@ __global__ __launch_bounds__(64) void sup_fwd_xy(SetTable sets) {
   const int tid = threadIdx.x;
   for (int y = tid; y < B2; y += 64) {
     T xr[B2], xi[B2], Xr[P], Xi[P];
+    load_row<NB>(ch, y, z, xr);
 #pragma unroll
-    for (int x = 0; x < B2; ++x) { xr[x] = T(child_value<NB>(ch, x, y, z)); xi[x] = T(0); }
+    for (int x = 0; x < B2; ++x) xi[x] = T(0);
     fwd_padded<B2>(xr, xi, Xr, Xi);
 #pragma unroll
     for (int k = 0; k < H; ++k) pl[y * H + k] = {Xr[k], Xi[k]};
