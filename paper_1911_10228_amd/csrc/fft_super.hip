@@ -34,14 +34,15 @@ template <> struct Row16<double> { typedef double type __attribute__((ext_vector
 // row y of plane z of the assembled super-block: x < NB from the octant with cx = 0, the rest
 // from cx = 1 (absent children read as zeros)
 template <int NB, typename T, typename TC>
-__device__ __forceinline__ void load_row(const TC* const* ch, int y, int z, T (&xr)[2 * NB]) {
+__device__ __forceinline__ void load_row(const SuperFwdItem<T>& it, const double* in, int y, int z,
+                                         T (&xr)[2 * NB]) {
   using V = typename Row16<TC>::type;
   constexpr int E = 16 / sizeof(TC), NV = NB / E;
   const int oc0 = 2 * (y >= NB) + 4 * (z >= NB);
   const int off = ((z & (NB - 1)) * NB + (y & (NB - 1))) * NB;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const TC* c = ch[oc0 + h];
+    const TC* c = child_ptr<TC>((const TC*)it.child[oc0 + h], it.child_in[oc0 + h], in);
     if (c) {
       const gview<const V> row = (gview<const V>)gl(c + off);
 #pragma unroll
@@ -68,12 +69,11 @@ __global__ __launch_bounds__(64) void sup_fwd_xy(SetTable sets) {
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;
   const SuperFwdItem<T>& it = ((const SuperFwdItem<T>*)ws.items)[local / B2];
-  const TC* const* ch = (const TC* const*)it.child;
   const int z = (int)(local % B2);
   const int tid = threadIdx.x;
   for (int y = tid; y < B2; y += 64) {
     T xr[B2], xi[B2], Xr[P], Xi[P];
-    load_row<NB>(ch, y, z, xr);
+    load_row<NB, T, TC>(it, ws.in, y, z, xr);
 #pragma unroll
     for (int x = 0; x < B2; ++x) xi[x] = T(0);
     fwd_padded<B2>(xr, xi, Xr, Xi);

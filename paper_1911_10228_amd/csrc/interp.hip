@@ -122,7 +122,7 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
     for (int zz = 0; zz < SL; ++zz) zs[g][zz] = T(0);
 #pragma unroll
   for (int oc = 0; oc < 8; ++oc) {                               // z: sum over cz
-    const TC* ch = it.child[oc];
+    const TC* ch = child_ptr<TC>(it.child[oc], it.child_in[oc], ws.in);
     if (!ch) continue;
     const int g = oc & 3, cz = oc >> 2;
     gmask |= 1 << g;

@@ -69,7 +69,9 @@ template <typename T> struct MacTile {
 };
 // Base-level super-blocks (the 2x2x2 children of one parent, side B2 = 2 N_b, FFT size P = 2 B2)
 template <typename T> struct SuperFwdItem {
-  const T* child[8];     // child source blocks, octant cx + 2 cy + 4 cz (nullptr: zero)
+  const T* child[8];     // child source blocks, octant cx + 2 cy + 4 cz (nullptr: see child_in)
+  int64_t child_in[8];   // where child is null: offset of the child in WorkSet::in (FP64
+                         // children only), -1: zero
   cpx<T>* tmp;           // intermediate planes [B2][P][B2+1]
   cpx<T>* dst;           // super-block half spectrum [P][P][B2+1]
 };
@@ -120,8 +122,19 @@ template <typename T> struct NearTile {
 // base level meets FP64 coarse levels).
 template <typename TC, typename TP> struct AnterpItem {
   TP* dst;               // parent block, overwritten with sum_c R_c child_c
-  const TC* child[8];    // octant c = cx + 2 cy + 4 cz (nullptr: absent)
+  const TC* child[8];    // octant c = cx + 2 cy + 4 cz (nullptr: see child_in)
+  int64_t child_in[8];   // where child is null: offset of the child in WorkSet::in (FP64
+                         // children only), -1: absent
 };
+
+// child block pointer of a work item: its own pointer, else (FP64 children) the pass's input
+template <typename TC>
+__device__ __forceinline__ const TC* child_ptr(const TC* c, int64_t in_off, const double* in) {
+  if constexpr (sizeof(TC) == sizeof(double)) {
+    if (!c && in_off >= 0) return (const TC*)(in + in_off);
+  }
+  return c;
+}
 template <typename TC, typename TP> struct InterpItem {
   TC* child;             // child block: child (+)= J_c parent
   const TP* parent;

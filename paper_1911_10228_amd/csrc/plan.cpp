@@ -457,6 +457,7 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
   const int64_t* nsrc = sc.nsrc;
   const int64_t* ntgt = sc.ntgt;
   const size_t es = ty == 0 ? 4 : 8, esc = ty == 1 ? 8 : 4, esp = ty == 0 ? 4 : 8;  // MIX: child 4, parent 8
+  const bool child_in_ok = ty == 1;                    // FP64 children may come from the input
   const int64_t nmax = n * (int64_t)N3;
   auto bad = [&](const char* what, int i) {
     if (err) *err = std::string("internal plan check failed: ") + what + " (kind " + std::to_string(kind) +
@@ -495,8 +496,11 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       case K_ANTERP: {
         const auto& it = ((const AnterpItem<double, double>*)items)[i];
         if (!in_ranges(p, it.dst, N3 * esp)) return bad("anterp parent", i);
-        for (int c = 0; c < 8; ++c)
+        for (int c = 0; c < 8; ++c) {
           if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("anterp child", i);
+          if (it.child_in[c] != -1 && (it.child[c] || !child_in_ok || !off_ok(it.child_in[c])))
+            return bad("anterp child offset", i);
+        }
         break;
       }
       case K_INTERP: {
@@ -551,8 +555,11 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       case K_SUP_FWD: {
         const auto& it = ((const SuperFwdItem<double>*)items)[i];
         if (!in_ranges(p, it.dst, 2 * S2 * es) || !in_ranges(p, it.tmp, 2 * TMP2 * es)) return bad("super fwd", i);
-        for (int c = 0; c < 8; ++c)
+        for (int c = 0; c < 8; ++c) {
           if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("super fwd child", i);
+          if (it.child_in[c] != -1 && (it.child[c] || !child_in_ok || !off_ok(it.child_in[c])))
+            return bad("super fwd child offset", i);
+        }
         break;
       }
       case K_SUP_INV: {
@@ -954,9 +961,16 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     push(steps, 0, 0, LR - 2 - l, K_COARSEN, TY_F64, hi.add(it), it.size(), nullptr);
   }
 
+  // An FP64 plan on a single-level layout reads its base-level sources straight from the pass's
+  // input in the super-block transforms and the first anterpolation, so its convert pass (a
+  // copy) is dropped.  FP32 plans keep the FP32 copy: the anterpolation reads each child block
+  // once per parent slab, and FP64 children there cost more than the convert saves.
+  const bool direct_in = p->super_base && LR == 1 && tyb == TY_F64 && !p->correction;
+  std::vector<int64_t> block_of_src(nsrc[tyb], -1);    // base source slot -> block index
+  for (int i : ids[0]) block_of_src[base_src_slot[i]] = i;
   for (int l = 0; l < LR; ++l) {
     const double h = std::ldexp(1.0, -l);
-    if (l == 0) {
+    if (l == 0 && !direct_in) {
       std::vector<ConvertItem<D>> it;
       for (int i : ids[0]) {
         ConvertItem<D> c{};
@@ -966,7 +980,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         it.push_back(c);
       }
       push(steps, l, 1, 0, K_CONVERT, tyb, hi.add(it), it.size(), nullptr);
-    } else {
+    } else if (l > 0) {
       std::vector<RefineItem> rit;
       std::vector<CorrectItem<D>> cit;
       for (int i : ids[l]) {
@@ -1038,12 +1052,18 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         std::vector<AnterpItem<D, D>> tmpi(L.nodes.size());
         for (size_t i = 0; i < L.nodes.size(); ++i) {
           tmpi[i].dst = L.need_src[i] ? SRC(tp, L.src_slot[i]) : nullptr;
-          for (int oc = 0; oc < 8; ++oc) tmpi[i].child[oc] = nullptr;
+          for (int oc = 0; oc < 8; ++oc) {
+            tmpi[i].child[oc] = nullptr;
+            tmpi[i].child_in[oc] = -1;
+          }
         }
         for (size_t c = 0; c < C.nodes.size(); ++c) {
           const int pi = C.parent[c];
           if (!L.need_src[pi] || !C.is_src[c]) continue;
-          tmpi[pi].child[octant_of(C.nodes[c])] = SRC(tc, C.src_slot[c]);
+          if (k == 1 && direct_in)
+            tmpi[pi].child_in[octant_of(C.nodes[c])] = block_of_src[C.src_slot[c]] * N3;
+          else
+            tmpi[pi].child[octant_of(C.nodes[c])] = SRC(tc, C.src_slot[c]);
         }
         for (size_t i = 0; i < L.nodes.size(); ++i)
           if (L.need_src[i]) ant[k].push_back(tmpi[i]);
@@ -1136,7 +1156,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
           SuperFwdItem<D> it{};
           for (int oc = 0; oc < 8; ++oc) {
             const int sl = ss.children[oc];
-            it.child[oc] = sl >= 0 ? SRC(ty_of(k), sl) : nullptr;
+            it.child[oc] = sl >= 0 && !direct_in ? SRC(ty_of(k), sl) : nullptr;
+            it.child_in[oc] = sl >= 0 && direct_in ? block_of_src[sl] * N3 : -1;
           }
           it.dst = SFH(a, (int64_t)q);
           it.tmp = it.dst;                 // the z pass transforms the plane stack in place
@@ -1214,7 +1235,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       }
     }
     for (int k = 1; k < K; ++k) {
-      const int ty = (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
+      const int ty = (k == 1 && direct_in) ? TY_F64
+                     : (ty_of(k - 1) == TY_F32 && ty_of(k) == TY_F64) ? TY_MIX : ty_of(k);
       push(steps, l, 2, k, K_ANTERP, ty, hi.add(ant[k]), ant[k].size(), p->d_w);
     }
     for (int k = K - 2; k >= 0; --k) {
