@@ -191,6 +191,25 @@ def plan_check(blocks, levels, n_b: int, interp_order: int, precision: int = LGF
     return inf.as_dict()
 
 
+class VectorPlan:
+    """Vector Poisson problem L u_c = f_c, c < components, on one block layout: one plan per
+    component (the kernel spectra are process-wide, so only the workspaces repeat), and every
+    solve advances all components together in shared launches (lgf_solve_batch)."""
+
+    def __init__(self, blocks, levels, n_b: int, interp_order: int, components: int = 3, **kw):
+        self.plans = [Plan(blocks, levels, n_b, interp_order, **kw) for _ in range(components)]
+
+    def solve(self, f, u, stream=None):
+        """u <- solution for f; both float64 CUDA tensors [components, n, N_b, N_b, N_b]."""
+        if len(f) != len(self.plans) or len(u) != len(self.plans):
+            raise ValueError("one source and one solution field per component")
+        solve_batch(self.plans, [f[c] for c in range(len(f))], [u[c] for c in range(len(u))], stream)
+
+    def close(self):
+        for p in self.plans:
+            p.close()
+
+
 def solve_batch(plans, fs, us, stream=None):
     n = len(plans)
     for p, f, u in zip(plans, fs, us):
