@@ -118,6 +118,28 @@ template <typename T> struct NearTile {
                                        // (dz+1)*9+(dy+1)*3+dx+1
 };
 
+// A compact near tile (FP32, pipelined form): the rows and source rows of a NearTile, but only
+// the source spectra that exist are staged: entry e < nreal holds slot src[e], and
+// loff[q * 6 + s] is the LDS element offset (entry * 64) of source row q at x0 - 1 + s, that of
+// the all-zero entry NC where the source is absent.  NC, the staging capacity, comes with the
+// launch mode (near_ctile_cap): tiles with more source super-blocks take the one-chunk form.
+constexpr int kCTileCapMax = 48;
+template <typename T> struct NearCTile {
+  int32_t tgt[kTileRowsMax][kMacL];    // target super slots (-1: none), first kTileW used
+  int32_t src[kCTileCapMax];           // slots of the staged entries (the zero slot past nreal)
+  uint32_t loff[kTileSrcRowsMax * (kTileW + 2)];
+  uint32_t src_mask;                   // bit q: source row q holds a source
+  uint32_t row_mask;                   // bit r: row r holds a target
+  int32_t nreal;                       // staged entries
+  int32_t rz;                          // rows along z: 2 or 4
+  int32_t zero;                        // the zero slot (an all-zero spectrum)
+  int32_t pad;
+  const cpx<T>* fhat;
+  cpx<T>* uhat;
+  const cpx<T>* const* kptr;           // as in NearTile
+};
+constexpr int kNearRunMin = 2, kNearRunMax = 8;   // frequency chunks a pipelined workgroup walks
+
 // TC: element type of the child level, TP: of the parent level (they differ where an FP32
 // base level meets FP64 coarse levels).
 template <typename TC, typename TP> struct AnterpItem {
@@ -222,8 +244,13 @@ template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st);
 template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st);
-// mode: W (4 or 8) for NearRow items; kNearTiled + 4 for NearTile items
+// mode: W (2, 4 or 8) for NearRow items; kNearTiled + 4 / + 6 for NearTile items of RZ = 2 / 4;
+// NearCTile items (pipelined form, FP32): kNearTiled + 5 / + 7 for RZ = 2 / 4, staging at most
+// 36 / 48 source spectra per tile
 constexpr int kNearTiled = 16;
+constexpr bool near_piped(int mode) { return mode == kNearTiled + 5 || mode == kNearTiled + 7; }
+constexpr int near_ctile_rz(int mode) { return mode == kNearTiled + 5 ? 2 : 4; }
+constexpr int near_ctile_cap(int mode) { return mode == kNearTiled + 5 ? 36 : 48; }
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode);
 
 // number of workgroups each item of a kernel needs (for set-table bookkeeping)

@@ -594,6 +594,130 @@ __global__ __launch_bounds__(128 * RZ) void near_tile_kernel(SetTable sets, int 
   }
 }
 
+// Pipelined tiled form (FP32 spectra): a workgroup walks a run of RUN consecutive frequency
+// chunks for one compact tile.  The next chunk's source and kernel spectra are copied
+// straight from memory into the other of two LDS buffers (global_load_lds: nothing in flight in
+// registers) while the current chunk is applied, so loads and arithmetic overlap inside each
+// workgroup; in the one-chunk form every resident workgroup loads, then computes, in step with
+// the others.  Only the source spectra that exist are staged (NC entries at most, one all-zero
+// entry for the absent ones), and the 14 kernel values come from LDS as well.
+template <int RZ, int NC>
+__global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int S, int RUN) {
+  using T = float;
+  constexpr int W = kTileW, WAVES = 2 * RZ, NS = W + 2;
+  constexpr int KE = NC + 1;                     // first kernel entry (entry NC: all zeros)
+  constexpr int NE = NC + 16;                    // entries per buffer: NC, zero, 14 kernels, spare
+  static_assert(NC % 2 == 0 && NC <= kCTileCapMax, "staged entries come in pairs");
+  // two separate LDS objects, each use naming one statically, so that the compiler can tell
+  // the copies into one buffer from the reads of the other and does not wait for the copies
+  __shared__ cpx<T> fa[NE * 64];
+  __shared__ cpx<T> fz[NE * 64];
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;       // wg_begin is a multiple of 8
+  const int ntiles = ws.count;
+  const int xcd = (int)(local & 7);
+  const int64_t j = local >> 3;
+  const int run = (int)(j / ntiles) * 8 + xcd;           // all tiles of a run on one XCD
+  const int ti = (int)(j % ntiles);
+  const int nchunks = S / 64;
+  const int c0 = run * RUN;
+  if (c0 >= nchunks) return;
+  const int nrun = min(RUN, nchunks - c0);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  // the tile through the constant address space: every field read is a scalar load, so the
+  // only vector-memory operations in flight are the copies and stores (a wait for a vector load
+  // of tile data would also wait for the copies of the next chunk)
+  const __attribute__((address_space(4))) NearCTile<T>* tile =
+      (const __attribute__((address_space(4))) NearCTile<T>*)ws.items + ti;
+  const uint32_t smask = tile->src_mask;
+  const int ry = wave & 1, rz = wave >> 1;
+  const bool has_row = (tile->row_mask >> wave) & 1u;
+  const int nreal = tile->nreal, zero = tile->zero;
+  const int npair = (nreal + 1) >> 1;                    // then 7 pairs of kernel spectra
+  const cptr64 kp = (cptr64)tile->kptr;
+  const gview<const float> Ff = gl((const float*)tile->fhat);
+  const int half = lane >> 5, l4 = (lane & 31) * 4;       // 16 bytes (2 frequencies) per lane
+  // copy chunk c into buffer b: copy m < npair + 7 on wavefront m % WAVES, lanes 0-31 taking
+  // the first entry of the pair, lanes 32-63 the second
+  auto issue = [&](cpx<T>* dst, int c) {
+    for (int m = wave; m < npair + 7; m += WAVES) {
+      gview<const float> src;
+      int e0;
+      if (m < npair) {
+        const int s0 = 2 * m < nreal ? tile->src[2 * m] : zero;
+        const int s1 = 2 * m + 1 < nreal ? tile->src[2 * m + 1] : zero;
+        src = Ff + 2 * ((int64_t)(half ? s1 : s0) * S + (int64_t)c * 64) + l4;
+        e0 = 2 * m;
+      } else {
+        const int h = 2 * (m - npair);
+        const gview<const float> k0 = gl((const float*)kp[h]), k1 = gl((const float*)kp[h + 1]);
+        src = (half ? k1 : k0) + 2 * (int64_t)c * 64 + l4;
+        e0 = KE + h;
+      }
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)&dst[e0 * 64], 16, 0, 0);
+    }
+  };
+  gmut<T> U = (gmut<T>)tile->uhat;
+  // apply chunk c from buffer fb
+  auto apply = [&](const cpx<T>* fb, int c) {
+    if (!has_row) return;
+    cpx<T> kv[kNearHalfK];
+#pragma unroll
+    for (int h = 0; h < kNearHalfK; ++h) kv[h] = fb[(KE + h) * 64 + lane];
+    cpx<T> acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = {T(0), T(0)};
+#pragma unroll
+    for (int pj = 0; pj < 9; ++pj) {
+      const int dz = pj / 3 - 1, dy = pj % 3 - 1;
+      const int q = (ry + 1 - dy) + 4 * (rz + 1 - dz);
+      if (!((smask >> q) & 1u)) continue;
+      cpx<T> fd[NS];
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) fd[s2] = fb[tile->loff[q * NS + s2] + lane];
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi) {
+        const int h = pj * 3 + dxi;
+        const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
+#pragma unroll
+        for (int x = 0; x < W; ++x) cmac(acc[x], kk, fd[x - dxi + 2]);   // src x = x0 + x - dx
+      }
+    }
+    const int k = c * 64 + lane;
+#pragma unroll
+    for (int x = 0; x < W; ++x) {
+      const int t = tile->tgt[wave][x];
+      if (t >= 0) {
+        U[2 * ((int64_t)t * S + k)] = acc[x].x;
+        U[2 * ((int64_t)t * S + k) + 1] = acc[x].y;
+      }
+    }
+  };
+  if (wave == 0) {
+    fa[NC * 64 + lane] = cpx<T>{T(0), T(0)};
+    fz[NC * 64 + lane] = cpx<T>{T(0), T(0)};
+  }
+  issue(fa, c0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // chunks alternate between the buffers; after each chunk every wavefront waits for its copies
+  // (and stores), and the barrier makes the copies visible and ends the reads of the buffer the
+  // next copies go to
+  for (int i = 0; i < nrun; i += 2) {
+    if (i + 1 < nrun) issue(fz, c0 + i + 1);
+    apply(fa, c0 + i);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (i + 1 >= nrun) break;
+    if (i + 2 < nrun) issue(fa, c0 + i + 2);
+    apply(fz, c0 + i + 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 // mode: targets per row W (2, 4 or 8) with NearRow items, kNearTiled + 4 / + 6 with NearTile items
@@ -606,10 +730,21 @@ template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_
   if (S % 64) return hipErrorInvalidValue;
   const int chunks8 = (S / 64 + 7) / 8;
   const bool tiled = mode > kNearTiled;
+  const bool piped = near_piped(mode);
+  // pipelined form: runs of 2 to 8 chunks per workgroup, longer where the launch has work for
+  // more than about 2048 workgroups (small levels need the workgroups, large ones the pipeline)
+  int RUN = kNearRunMin;
+  if (piped) {
+    int64_t tiles = 0;
+    for (int i = 0; i < t.n; ++i) tiles += t.s[i].count;
+    while (RUN < kNearRunMax && tiles * (S / 64) / (2 * RUN) >= 2048) RUN *= 2;
+  }
+  const int runs8 = (S / 64 / RUN + 7) / 8 + 1;     // runs of chunks per XCD (covering)
   int64_t wg = 0;
   for (int i = 0; i < t.n; ++i) {
     t.s[i].wg_begin = wg;
-    wg += (int64_t)(tiled ? t.s[i].count : (t.s[i].count + 3) / 4) * chunks8 * 8;
+    wg += piped ? (int64_t)t.s[i].count * runs8 * 8
+                : (int64_t)(tiled ? t.s[i].count : (t.s[i].count + 3) / 4) * chunks8 * 8;
   }
   if (wg == 0) return hipSuccess;
   if (mode == 2) near_mac_kernel<T, 2><<<(unsigned)wg, 256, 0, st>>>(t, S);
@@ -617,6 +752,14 @@ template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_
   else if (mode == 8) near_mac_kernel<T, 8><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == kNearTiled + 4) near_tile_kernel<T, kTileW, 2><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == kNearTiled + 6) near_tile_kernel<T, kTileW, 4><<<(unsigned)wg, 512, 0, st>>>(t, S);
+  else if (piped) {
+    if constexpr (sizeof(T) == 4) {
+      if (mode == kNearTiled + 5) near_pipe_kernel<2, near_ctile_cap(kNearTiled + 5)><<<(unsigned)wg, 256, 0, st>>>(t, S, RUN);
+      else near_pipe_kernel<4, near_ctile_cap(kNearTiled + 7)><<<(unsigned)wg, 512, 0, st>>>(t, S, RUN);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -571,6 +571,28 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_NEAR_MAC: {
         const int t = ty == 0 ? 0 : 1;
+        if (near_piped(mode)) {
+          const auto& it = ((const NearCTile<double>*)items)[i];
+          const int rz = near_ctile_rz(mode), cap = near_ctile_cap(mode);
+          if (ty != 0 || it.rz != rz) return bad("near pipelined tile shape", i);   // FP32 only
+          if (it.nreal < 0 || it.nreal > cap || it.zero != sc.nsup_src[t]) return bad("near pipelined tile entries", i);
+          for (int e = 0; e < kCTileCapMax; ++e)
+            if (it.src[e] < 0 || it.src[e] > sc.nsup_src[t] || (e < it.nreal && it.src[e] == it.zero))
+              return bad("near pipelined tile source slot", i);
+          for (int j = 0; j < kTileSrcRowsMax * (kTileW + 2); ++j) {
+            const uint32_t o = it.loff[j];
+            if (o % 64 || (o / 64 >= (uint32_t)it.nreal && o / 64 != (uint32_t)cap)) return bad("near pipelined tile offset", i);
+          }
+          for (int r = 0; r < kTileRowsMax; ++r)
+            for (int q = 0; q < kMacL; ++q)
+              if (it.tgt[r][q] < -1 || it.tgt[r][q] >= sc.nsup_tgt[t]) return bad("near tile target slot", i);
+          // 16-byte copies straight into LDS: the arena must be 16-byte aligned
+          if ((uintptr_t)it.fhat % 16) return bad("near pipelined tile alignment", i);
+          if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
+          if (sc.nsup_tgt[t] && !in_ranges(p, it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
+          if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
+          break;
+        }
         if (mode > kNearTiled) {
           const auto& it = ((const NearTile<double>*)items)[i];
           if (!(mode == kNearTiled + 4 && it.rz == 2) && !(mode == kNearTiled + 6 && it.rz == 4))
@@ -928,6 +950,34 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       out[it->second].row_mask |= 1u << r;
     }
   };
+  // compact tiles for the pipelined form: the same tiles staging only the source spectra that
+  // exist; false where a tile holds more than the staging capacity of its height
+  auto compact_tiles = [&](const std::vector<NearTile<D>>& in, int cap, std::vector<NearCTile<D>>& out) {
+    for (const NearTile<D>& t : in) {
+      NearCTile<D> c{};
+      std::memcpy(c.tgt, t.tgt, sizeof c.tgt);
+      for (int e = 0; e < kCTileCapMax; ++e) c.src[e] = t.zero;
+      for (int j = 0; j < kTileSrcRowsMax * (kTileW + 2); ++j) c.loff[j] = (uint32_t)(cap * 64);
+      int n = 0;
+      for (int j = 0; j < 4 * (t.rz + 2) * (kTileW + 2); ++j) {
+        if (t.src[j] == t.zero) continue;
+        if (n == cap) return false;
+        c.src[n] = t.src[j];
+        c.loff[j] = (uint32_t)(n * 64);
+        ++n;
+      }
+      c.src_mask = t.src_mask;
+      c.row_mask = t.row_mask;
+      c.nreal = n;
+      c.rz = t.rz;
+      c.zero = t.zero;
+      c.fhat = t.fhat;
+      c.uhat = t.uhat;
+      c.kptr = t.kptr;
+      out.push_back(c);
+    }
+    return !out.empty();
+  };
   auto JW = [&](int64_t blk) { return (double*)p->jw + blk * N3; };
   auto WW = [&](int64_t blk) { return (double*)p->w + blk * N3; };
 
@@ -1202,9 +1252,21 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         // full as tiles of 2 x 2 (dense levels); the other height is an autotuner candidate
         const bool tall = tiled && 8 * nt4.size() <= 9 * nt.size() / 2;
         if (tall) std::swap(nt, nt4);
-        const size_t nt_off = tiled ? hi.add(nt) : 0;
-        if (tiled)
-          push(steps, l, 4, k, K_NEAR_MAC, sty, nt_off, nt.size(), nullptr, pairs,
+        // the pipelined form where every tile fits its staging (2 x 4 rows first): it overlaps
+        // each workgroup's copies with its arithmetic and was the fastest wherever it applied;
+        // else the one-chunk tiles, 2 x 4 rows where about as full as 2 x 2 (dense levels)
+        std::vector<NearCTile<D>> ct[2];           // [0]: 2 x 2 rows, [1]: 2 x 4 rows
+        for (const std::vector<NearTile<D>>* lst : {&nt, &nt4})
+          if (tiled && !lst->empty()) {
+            const int h = (*lst)[0].rz == 4;
+            if (!compact_tiles(*lst, near_ctile_cap(h ? kNearTiled + 7 : kNearTiled + 5), ct[h])) ct[h].clear();
+          }
+        const int piped = !ct[1].empty() ? 1 : !ct[0].empty() ? 0 : -1;
+        if (piped >= 0)
+          push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(ct[piped]), ct[piped].size(), nullptr, pairs,
+               piped ? kNearTiled + 7 : kNearTiled + 5, chain);
+        else if (tiled)
+          push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt), nt.size(), nullptr, pairs,
                tall ? kNearTiled + 6 : kNearTiled + 4, chain);
         else
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
@@ -1212,9 +1274,21 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
           // the other launch shapes for the autotuner: tiles of 2 x 4 rows (FP32), rows of 2, 4 or
           // 8 targets
           if (tiled) {
-            push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt4), nt4.size(), nullptr, pairs,
-                 tall ? kNearTiled + 4 : kNearTiled + 6, chain);
-            alt_of.push_back(primary);
+            // the one-chunk tiles of both heights (one of them is the primary where no pipelined
+            // form applies) and the other pipelined height
+            for (const std::vector<NearTile<D>>* lst : {&nt, &nt4}) {
+              if (lst->empty()) continue;
+              const int mode = (*lst)[0].rz == 4 ? kNearTiled + 6 : kNearTiled + 4;
+              if (piped < 0 && lst == &nt) continue;
+              push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(*lst), lst->size(), nullptr, pairs, mode, chain);
+              alt_of.push_back(primary);
+            }
+            for (int h = 0; h < 2; ++h)
+              if (h != piped && !ct[h].empty()) {
+                push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(ct[h]), ct[h].size(), nullptr, pairs,
+                     h ? kNearTiled + 7 : kNearTiled + 5, chain);
+                alt_of.push_back(primary);
+              }
           }
           for (int shape : {2, 4, 8}) {        // rows of 2 suit sparse levels
             if (!tiled && shape == 4) continue;
