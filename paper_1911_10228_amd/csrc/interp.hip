@@ -170,27 +170,34 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
   for (int zz = 0; zz < SL; ++zz) dst[((z0 + zz) * NB + b) * NB + a] = acc[zz];
 }
 
+// The combine and the convert stream a few bytes per cell: each block is split over
+// split_of<NB>() workgroups (a quarter of its cells each on 16^3 blocks), so that a level's
+// launch has enough wavefronts in flight to cover the memory latency.
+template <int NB> constexpr int split_of() { return per_thread<NB>() >= 4 ? 4 : per_thread<NB>(); }
+
 template <int NB, typename T>
 __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
-  constexpr int N3 = NB * NB * NB;
+  constexpr int N3 = NB * NB * NB, SP = split_of<NB>();
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
-  const CombineItem<T>& it = ((const CombineItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const CombineItem<T>& it = ((const CombineItem<T>*)ws.items)[local / SP];
+  const int c0 = (int)(local % SP) * (N3 / SP);         // this workgroup's cells c0 .. + N3 / SP
   const double sc = it.scale;
-  const gview<double> dd = gl(it.dst_d ? it.dst_d : ws.out + it.dst_out);
-  constexpr int PT = per_thread<NB>();
+  const gview<double> dd = gl(it.dst_d ? it.dst_d : ws.out + it.dst_out) + c0;
+  constexpr int PT = per_thread<NB>() / SP;
   double v[PT];
 #pragma unroll
-  for (int j = 0; j < PT; ++j) v[j] = it.v ? double(gl(it.v)[threadIdx.x + j * kOpThreads]) : 0.0;
+  for (int j = 0; j < PT; ++j) v[j] = it.v ? double(gl(it.v + c0)[threadIdx.x + j * kOpThreads]) : 0.0;
   if (it.far) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j) v[j] += double(gl(it.far)[threadIdx.x + j * kOpThreads]);
+    for (int j = 0; j < PT; ++j) v[j] += double(gl(it.far + c0)[threadIdx.x + j * kOpThreads]);
   }
 #pragma unroll
   for (int j = 0; j < PT; ++j) v[j] *= sc;
   if (it.base) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j) v[j] += gl(it.base)[threadIdx.x + j * kOpThreads];
+    for (int j = 0; j < PT; ++j) v[j] += gl(it.base + c0)[threadIdx.x + j * kOpThreads];
   }
   if (!it.dst_d && (ws.aux & kAuxAccumulate)) {       // defect-correction update of u
 #pragma unroll
@@ -202,16 +209,18 @@ __global__ __launch_bounds__(kOpThreads) void combine_kernel(SetTable sets) {
 
 template <int NB, typename T>
 __global__ __launch_bounds__(kOpThreads) void convert_kernel(SetTable sets) {
-  constexpr int N3 = NB * NB * NB;
+  constexpr int N3 = NB * NB * NB, SP = split_of<NB>();
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
-  const ConvertItem<T>& it = ((const ConvertItem<T>*)ws.items)[blockIdx.x - ws.wg_begin];
-  const gview<const double> src = gl(it.src ? it.src : ws.in + it.src_in);
-  constexpr int PT = per_thread<NB>();
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const ConvertItem<T>& it = ((const ConvertItem<T>*)ws.items)[local / SP];
+  const int c0 = (int)(local % SP) * (N3 / SP);
+  const gview<const double> src = gl(it.src ? it.src : ws.in + it.src_in) + c0;
+  constexpr int PT = per_thread<NB>() / SP;
   double v[PT];
 #pragma unroll
   for (int j = 0; j < PT; ++j) v[j] = src[threadIdx.x + j * kOpThreads];
-  const gview<T> dst = gl(it.dst);
+  const gview<T> dst = gl(it.dst) + c0;
 #pragma unroll
   for (int j = 0; j < PT; ++j) dst[threadIdx.x + j * kOpThreads] = T(v[j]);
 }
@@ -530,10 +539,16 @@ template <typename TC, typename TP> hipError_t launch_interp(int nb, SetTable& t
   LGF_LAUNCH_SIMPLE(interp_kernel<NB, TC, TP>)
 }
 template <typename T> hipError_t launch_combine(int nb, SetTable& t, hipStream_t st) {
-  LGF_LAUNCH_SIMPLE(combine_kernel<NB, T>)
+  const int64_t wg = assign_wg(t, nb == 16 ? split_of<16>() : split_of<8>());
+  if (wg == 0) return hipSuccess;
+  LGF_NB_DISPATCH(nb, combine_kernel<NB, T><<<(unsigned)wg, kOpThreads, 0, st>>>(t));
+  return hipGetLastError();
 }
 template <typename T> hipError_t launch_convert(int nb, SetTable& t, hipStream_t st) {
-  LGF_LAUNCH_SIMPLE(convert_kernel<NB, T>)
+  const int64_t wg = assign_wg(t, nb == 16 ? split_of<16>() : split_of<8>());
+  if (wg == 0) return hipSuccess;
+  LGF_NB_DISPATCH(nb, convert_kernel<NB, T><<<(unsigned)wg, kOpThreads, 0, st>>>(t));
+  return hipGetLastError();
 }
 hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st) {
   LGF_LAUNCH_SIMPLE(coarsen_kernel<NB>)
