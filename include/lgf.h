@@ -138,8 +138,8 @@ lgf_status lgf_green_eval(const int32_t* n, int64_t m, double* out, lgf_stream_t
 lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape);
 /* lgf_plan_set_near_shape: the same for the base-level super-block MAC steps: shape 2, 4 or 8
  *   rows of that many target super-blocks per wavefront, 20 or 22 tiles of 2 x 2 or 2 x 4 rows of 4
- *   (FP32 spectra), 21 or 23 the same tiles pipelined over runs of frequency chunks (FP32 spectra;
- *   only where every tile of the step has at most 36 or 48 source super-blocks);
+ *   (FP32 spectra), 21 or 23 the same tiles pipelined over runs of frequency chunks (FP32 and
+ *   FP64 spectra; only where every tile of the step has at most 36 or 48 source super-blocks);
  *   0 restores the chosen shape.  The other shapes' work items exist only in plans built with
  *   lgf_options.autotune = 1; returns LGF_EINVAL, changing nothing, if a step lacks the shape. */
 lgf_status lgf_plan_set_near_shape(lgf_plan_t p, int32_t shape);

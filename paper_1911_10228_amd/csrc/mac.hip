@@ -594,20 +594,21 @@ __global__ __launch_bounds__(128 * RZ) void near_tile_kernel(SetTable sets, int 
   }
 }
 
-// Pipelined tiled form (FP32 spectra): a workgroup walks a run of RUN consecutive frequency
+// Pipelined tiled form: a workgroup walks a run of RUN consecutive frequency
 // chunks for one compact tile.  The next chunk's source and kernel spectra are copied
 // straight from memory into the other of two LDS buffers (global_load_lds: nothing in flight in
 // registers) while the current chunk is applied, so loads and arithmetic overlap inside each
 // workgroup; in the one-chunk form every resident workgroup loads, then computes, in step with
 // the others.  Only the source spectra that exist are staged (NC entries at most, one all-zero
 // entry for the absent ones), and the 14 kernel values come from LDS as well.
-template <int RZ, int NC>
+template <typename T, int RZ, int NC>
 __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int S, int RUN) {
-  using T = float;
   constexpr int W = kTileW, WAVES = 2 * RZ, NS = W + 2;
+  constexpr int EPC = 16 / (int)sizeof(cpx<T>);  // entries per 16-byte-per-lane copy: 2 (FP32), 1
+  constexpr int LPE = 64 / EPC;                  // lanes per entry
   constexpr int KE = NC + 1;                     // first kernel entry (entry NC: all zeros)
   constexpr int NE = NC + 16;                    // entries per buffer: NC, zero, 14 kernels, spare
-  static_assert(NC % 2 == 0 && NC <= kCTileCapMax, "staged entries come in pairs");
+  static_assert(NC % 2 == 0 && NC <= kCTileCapMax, "FP32 entries are copied in pairs");
   // two separate LDS objects, each use naming one statically, so that the compiler can tell
   // the copies into one buffer from the reads of the other and does not wait for the copies
   __shared__ cpx<T> fa[NE * 64];
@@ -634,25 +635,34 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
   const int ry = wave & 1, rz = wave >> 1;
   const bool has_row = (tile->row_mask >> wave) & 1u;
   const int nreal = tile->nreal, zero = tile->zero;
-  const int npair = (nreal + 1) >> 1;                    // then 7 pairs of kernel spectra
+  const int nsc = (nreal + EPC - 1) / EPC;               // source copies, then kernel copies
   const cptr64 kp = (cptr64)tile->kptr;
-  const gview<const float> Ff = gl((const float*)tile->fhat);
-  const int half = lane >> 5, l4 = (lane & 31) * 4;       // 16 bytes (2 frequencies) per lane
-  // copy chunk c into buffer b: copy m < npair + 7 on wavefront m % WAVES, lanes 0-31 taking
-  // the first entry of the pair, lanes 32-63 the second
+  const gview<const T> Ft = gl((const T*)tile->fhat);
+  // 16 bytes (2 FP32 or 1 FP64 frequencies) per lane; with FP32 lanes 0-31 copy the first entry
+  // of a pair and lanes 32-63 the second
+  const int sub = lane / LPE, lo = (lane % LPE) * (16 / (int)sizeof(T));
+  // copy chunk c into buffer dst: copy m < nsc + 14 / EPC on wavefront m % WAVES
   auto issue = [&](cpx<T>* dst, int c) {
-    for (int m = wave; m < npair + 7; m += WAVES) {
-      gview<const float> src;
+    for (int m = wave; m < nsc + kNearHalfK / EPC; m += WAVES) {
+      gview<const T> src;
       int e0;
-      if (m < npair) {
-        const int s0 = 2 * m < nreal ? tile->src[2 * m] : zero;
-        const int s1 = 2 * m + 1 < nreal ? tile->src[2 * m + 1] : zero;
-        src = Ff + 2 * ((int64_t)(half ? s1 : s0) * S + (int64_t)c * 64) + l4;
-        e0 = 2 * m;
+      if (m < nsc) {
+        const int s0 = EPC * m < nreal ? tile->src[EPC * m] : zero;
+        int sl = s0;
+        if constexpr (EPC == 2) {
+          const int s1 = 2 * m + 1 < nreal ? tile->src[2 * m + 1] : zero;
+          sl = sub ? s1 : s0;
+        }
+        src = Ft + 2 * ((int64_t)sl * S + (int64_t)c * 64) + lo;
+        e0 = EPC * m;
       } else {
-        const int h = 2 * (m - npair);
-        const gview<const float> k0 = gl((const float*)kp[h]), k1 = gl((const float*)kp[h + 1]);
-        src = (half ? k1 : k0) + 2 * (int64_t)c * 64 + l4;
+        const int h = EPC * (m - nsc);
+        gview<const T> kb = gl((const T*)kp[h]);
+        if constexpr (EPC == 2) {
+          const gview<const T> k1 = gl((const T*)kp[h + 1]);
+          kb = sub ? k1 : kb;
+        }
+        src = kb + 2 * (int64_t)c * 64 + lo;
         e0 = KE + h;
       }
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
@@ -753,12 +763,8 @@ template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_
   else if (mode == kNearTiled + 4) near_tile_kernel<T, kTileW, 2><<<(unsigned)wg, 256, 0, st>>>(t, S);
   else if (mode == kNearTiled + 6) near_tile_kernel<T, kTileW, 4><<<(unsigned)wg, 512, 0, st>>>(t, S);
   else if (piped) {
-    if constexpr (sizeof(T) == 4) {
-      if (mode == kNearTiled + 5) near_pipe_kernel<2, near_ctile_cap(kNearTiled + 5)><<<(unsigned)wg, 256, 0, st>>>(t, S, RUN);
-      else near_pipe_kernel<4, near_ctile_cap(kNearTiled + 7)><<<(unsigned)wg, 512, 0, st>>>(t, S, RUN);
-    } else {
-      return hipErrorInvalidValue;
-    }
+    if (mode == kNearTiled + 5) near_pipe_kernel<T, 2, near_ctile_cap(kNearTiled + 5)><<<(unsigned)wg, 256, 0, st>>>(t, S, RUN);
+    else near_pipe_kernel<T, 4, near_ctile_cap(kNearTiled + 7)><<<(unsigned)wg, 512, 0, st>>>(t, S, RUN);
   }
   else return hipErrorInvalidValue;
   return hipGetLastError();

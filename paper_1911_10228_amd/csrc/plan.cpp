@@ -574,7 +574,7 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
         if (near_piped(mode)) {
           const auto& it = ((const NearCTile<double>*)items)[i];
           const int rz = near_ctile_rz(mode), cap = near_ctile_cap(mode);
-          if (ty != 0 || it.rz != rz) return bad("near pipelined tile shape", i);   // FP32 only
+          if (it.rz != rz) return bad("near pipelined tile shape", i);
           if (it.nreal < 0 || it.nreal > cap || it.zero != sc.nsup_src[t]) return bad("near pipelined tile entries", i);
           for (int e = 0; e < kCTileCapMax; ++e)
             if (it.src[e] < 0 || it.src[e] > sc.nsup_src[t] || (e < it.nreal && it.src[e] == it.zero))
@@ -1289,6 +1289,24 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
                      h ? kNearTiled + 7 : kNearTiled + 5, chain);
                 alt_of.push_back(primary);
               }
+          } else {
+            // FP64 spectra: the pipelined tiles (FP64 kernel spectra, FP64 sums) as candidates
+            std::vector<NearTile<D>> t64[2];
+            for (const SupInst& si : sup) {
+              if (si.l != l || si.k != k) continue;
+              std::vector<std::pair<I3, int>> tg;
+              for (const SupTgt& t : si.tg) tg.push_back({t.c, t.slot});
+              for (int h = 0; h < 2; ++h)
+                make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0),
+                           (const cpx<D>* const*)ns->kp64, t64[h], h ? 4 : 2);
+            }
+            for (int h = 0; h < 2; ++h) {
+              std::vector<NearCTile<D>> c64;
+              if (!compact_tiles(t64[h], near_ctile_cap(h ? kNearTiled + 7 : kNearTiled + 5), c64)) continue;
+              push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(c64), c64.size(), nullptr, pairs,
+                   h ? kNearTiled + 7 : kNearTiled + 5, chain);
+              alt_of.push_back(primary);
+            }
           }
           for (int shape : {2, 4, 8}) {        // rows of 2 suit sparse levels
             if (!tiled && shape == 4) continue;
