@@ -133,7 +133,7 @@ template <typename T> struct NearCTile {
   int32_t nreal;                       // staged entries
   int32_t rz;                          // rows along z: 2 or 4
   int32_t zero;                        // the zero slot (an all-zero spectrum)
-  int32_t pad;
+  int32_t edges;                       // 1: some source row holds a source at x0 - 1 or x0 + 4
   const cpx<T>* fhat;
   cpx<T>* uhat;
   const cpx<T>* const* kptr;           // as in NearTile

@@ -17,6 +17,7 @@
 // K_{-d}[k] = conj(K_d[k]).  All control flow is uniform per wavefront.
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -670,9 +671,12 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
     }
   };
   gmut<T> U = (gmut<T>)tile->uhat;
-  // apply chunk c from buffer fb
-  auto apply = [&](const cpx<T>* fb, int c) {
-    if (!has_row) return;
+  // a tile without sources at x0 - 1 and x0 + 4 (a level no wider than its row, as on small
+  // uniform layouts) skips the products with those positions: a sixth of the multiply-adds and
+  // a third of the LDS reads
+  const bool edges = tile->edges != 0;
+  auto apply_e = [&](const cpx<T>* fb, int c, auto has_edges) {
+    constexpr bool EDGES = decltype(has_edges)::value;
     cpx<T> kv[kNearHalfK];
 #pragma unroll
     for (int h = 0; h < kNearHalfK; ++h) kv[h] = fb[(KE + h) * 64 + lane];
@@ -686,13 +690,17 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
       if (!((smask >> q) & 1u)) continue;
       cpx<T> fd[NS];
 #pragma unroll
-      for (int s2 = 0; s2 < NS; ++s2) fd[s2] = fb[tile->loff[q * NS + s2] + lane];
+      for (int s2 = 0; s2 < NS; ++s2)
+        if (EDGES || (s2 > 0 && s2 < NS - 1)) fd[s2] = fb[tile->loff[q * NS + s2] + lane];
 #pragma unroll
       for (int dxi = 0; dxi < 3; ++dxi) {
         const int h = pj * 3 + dxi;
         const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
 #pragma unroll
-        for (int x = 0; x < W; ++x) cmac(acc[x], kk, fd[x - dxi + 2]);   // src x = x0 + x - dx
+        for (int x = 0; x < W; ++x) {                 // src x = x0 + x - dx
+          const int e = x - dxi + 2;
+          if (EDGES || (e > 0 && e < NS - 1)) cmac(acc[x], kk, fd[e]);
+        }
       }
     }
     const int k = c * 64 + lane;
@@ -704,6 +712,12 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
         U[2 * ((int64_t)t * S + k) + 1] = acc[x].y;
       }
     }
+  };
+  // apply chunk c from buffer fb
+  auto apply = [&](const cpx<T>* fb, int c) {
+    if (!has_row) return;
+    if (edges) apply_e(fb, c, std::true_type{});
+    else apply_e(fb, c, std::false_type{});
   };
   if (wave == 0) {
     fa[NC * 64 + lane] = cpx<T>{T(0), T(0)};

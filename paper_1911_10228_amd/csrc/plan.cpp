@@ -576,6 +576,11 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
           const int rz = near_ctile_rz(mode), cap = near_ctile_cap(mode);
           if (it.rz != rz) return bad("near pipelined tile shape", i);
           if (it.nreal < 0 || it.nreal > cap || it.zero != sc.nsup_src[t]) return bad("near pipelined tile entries", i);
+          for (int j = 0; j < 4 * (rz + 2) * (kTileW + 2); ++j) {
+            const int x = j % (kTileW + 2);
+            if (!it.edges && (x == 0 || x == kTileW + 1) && it.loff[j] != (uint32_t)(cap * 64))
+              return bad("near pipelined tile edges", i);
+          }
           for (int e = 0; e < kCTileCapMax; ++e)
             if (it.src[e] < 0 || it.src[e] > sc.nsup_src[t] || (e < it.nreal && it.src[e] == it.zero))
               return bad("near pipelined tile source slot", i);
@@ -964,6 +969,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         if (n == cap) return false;
         c.src[n] = t.src[j];
         c.loff[j] = (uint32_t)(n * 64);
+        const int x = j % (kTileW + 2);
+        if (x == 0 || x == kTileW + 1) c.edges = 1;
         ++n;
       }
       c.src_mask = t.src_mask;
