@@ -190,6 +190,51 @@ def torus(seed: int = 3, n_b: int = 16, nblk: int = 8, n_levels: int = 3,
                   meta=dict(axis=axis, centre=centre, R=R, sigma=sigma))
 
 
+def vortex_ring_field(pos, R: float, c1: float, c2: float):
+    """The paper's manufactured test field (Sec. 4, eqs. streamfunc and streamfunc_f): a vortex
+    ring of radius R about the z axis whose streamfunction is f(t) e_theta, t = d / R, d the
+    distance to the ring's core circle, f(t) = c1 exp(-c2 / (1 - t^2)) for |t| < 1 (0 beyond).
+    Returns the Cartesian components psi_x = -f y / rho, psi_y = f x / rho and their Laplacians
+    (the sources of the two scalar Poisson problems): for g(rho, z) sin(theta) the Laplacian is
+    (g_rr + g_zz + g_r / rho - g / rho^2) sin(theta), and g_rr + g_zz = f'' / R^2 + f' / (R d)
+    because g depends on d alone.  pos: physical positions [..., 3] relative to the ring centre."""
+    x, y, z = pos[..., 0], pos[..., 1], pos[..., 2]
+    rho = np.sqrt(x * x + y * y)
+    d = np.sqrt((rho - R) ** 2 + z * z)
+    inside = d < R
+    t = np.where(inside, d / R, 0.0)
+    om = np.where(inside, 1.0 - t * t, 1.0)
+    f = np.where(inside, c1 * np.exp(-c2 / om), 0.0)
+    fp_t = -2.0 * c2 * f / om**2                        # f'(t) / t (finite on the core circle)
+    fp = fp_t * t                                       # f'(t)
+    fpp = fp_t * (1.0 + 4.0 * t * t / om) + fp_t * t * t * (-2.0 * c2 / om**2)  # f''(t)
+    lap_rz = (fpp + fp_t) / R**2                        # g_rr + g_zz
+    g_r = fp / R * np.where(d > 0, (rho - R) / np.where(d > 0, d, 1.0), 0.0)
+    part = lap_rz + g_r / rho - f / rho**2
+    s, c = y / rho, x / rho
+    return -f * s, f * c, -part * s, part * c
+
+
+def vortex_ring(nblk: int = 4, n_b: int = 16, n_levels: int = 1, interp_order: int = 8,
+                R: float = 0.125, c1: float = 1e3, c2: float = 10.0, alpha: float = 1.0 / 32) -> Layout:
+    """The single vortex ring of the paper's convergence test (R = 0.125, c1 = 1e3, c2 = 10) in
+    the cube [-1/4, 1/4]^3 (the ring's support), nblk^3 base blocks of n_b^3 (base spacing
+    h = 1 / (2 nblk n_b)) refined around the ring by the refinement criterion.  ``f`` holds the
+    x component's source in base-lattice units (h^2 times the physical Laplacian) and ``exact``
+    the x component psi_x; ``meta`` holds the y component's source and solution."""
+    h = 0.5 / (nblk * n_b)
+    def phys(b, lv, nb):
+        return (cell_centres(b, lv, nb) + 0.5) * h - 0.25
+    def src(b, lv, nb):                 # the vorticity magnitude, as in the refinement criterion
+        _, _, ox, oy = vortex_ring_field(phys(b, lv, nb), R, c1, c2)
+        return np.sqrt(ox * ox + oy * oy)
+    blocks, levels = refine_by_criterion(box_blocks(nblk, nblk, nblk), n_b, n_levels, src, alpha)
+    px, py, ox, oy = vortex_ring_field(phys(blocks, levels, n_b), R, c1, c2)
+    return Layout(blocks, levels, n_b, h * h * ox, interp_order,
+                  f"vortex ring, {nblk}^3 base blocks of {n_b}^3, {n_levels} levels", px,
+                  meta=dict(f_y=h * h * oy, exact_y=py, h=h))
+
+
 def most_cubic_box(B: int) -> tuple[int, int, int]:
     """Smallest-surface a x b x c >= B with a >= b >= c (ties: smallest volume)."""
     best = None

@@ -89,6 +89,34 @@ def test_torus_second_order_convergence(lgf):
     assert errs[-1] < 1e-2 and order[-1] >= 1.8 and order[0] >= 1.5
 
 
+def test_vortex_ring_vector_second_order(lgf):
+    """The paper's manufactured solution (Sec. 4: the vortex ring R = 0.125, c1 = 1e3, c2 = 10)
+    as a vector Poisson problem: both Cartesian streamfunction components through one
+    VectorPlan (FP32 + defect correction), on a uniform grid (16^3 blocks) and with one
+    refinement level around the ring (8^3 blocks): the errors against psi_x and psi_y fall at
+    second order, and the two components (mirror images of each other) have the same error."""
+    for n_b, n_levels in ((16, 1), (8, 2)):
+        errs = []
+        for nblk in (2, 4, 8):
+            L = workloads.vortex_ring(nblk=nblk, n_b=n_b, n_levels=n_levels, interp_order=8)
+            print(f"case: {L.name}", flush=True)
+            vp = lgf.VectorPlan(L.blocks, L.levels, L.n_b, L.interp_order, components=2,
+                                precision=1, dc_iters=1)
+            f = torch.from_numpy(np.ascontiguousarray(np.stack([L.f, L.meta["f_y"]]))).cuda()
+            u = torch.zeros_like(f)
+            vp.solve(f, u)
+            torch.cuda.synchronize()
+            got = u.cpu().numpy()
+            vp.close()
+            ex = np.abs(got[0] - L.exact).max() / np.abs(L.exact).max()
+            ey = np.abs(got[1] - L.meta["exact_y"]).max() / np.abs(L.meta["exact_y"]).max()
+            assert abs(ex - ey) <= 1e-3 * ex
+            errs.append(ex)
+        order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        print("errors", errs, "orders", order, flush=True)
+        assert order[-1] >= 1.8 and errs[-1] < 1e-2
+
+
 def test_batch_of_64_layouts(lgf):
     Ls = workloads.batch()
     plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, 1, 1, autotune=1) for L in Ls]

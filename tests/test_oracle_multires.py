@@ -113,3 +113,27 @@ def test_defect_correction_approaches_fp64_solve():
     err = [np.abs(u - ref).max() / np.abs(ref).max() for u in its]
     assert err[0] < 1e-5
     assert err[1] < err[0]
+
+
+def test_vortex_ring_second_order():
+    """The paper's manufactured solution (Sec. 4: the vortex ring with R = 0.125, c1 = 1e3,
+    c2 = 10, whose Cartesian streamfunction components solve scalar Poisson problems with
+    analytic sources): the oracle's error against psi_x falls at second order under uniform
+    refinement of the grid, and with one refinement level around the ring the fine level keeps
+    the accuracy of a uniform grid of its spacing."""
+    uni, ref, ref_fine = [], [], []
+    for nblk in (2, 4, 8):
+        L = workloads.vortex_ring(nblk=nblk, n_b=8, n_levels=1, interp_order=8)
+        u = fmm.flgf(L.blocks, L.f, L.n_b, 8)
+        uni.append(np.abs(u - L.exact).max() / np.abs(L.exact).max())
+        L = workloads.vortex_ring(nblk=nblk, n_b=8, n_levels=2, interp_order=8)
+        u = multires.solve(L.blocks, L.levels, L.f, L.n_b, 8)
+        fine = L.levels == 1
+        ref.append(np.abs(u - L.exact).max() / np.abs(L.exact).max())
+        ref_fine.append(np.abs(u[fine] - L.exact[fine]).max() / np.abs(L.exact).max())
+    o_uni = np.log2(np.array(uni[:-1]) / np.array(uni[1:]))
+    o_ref = np.log2(np.array(ref[:-1]) / np.array(ref[1:]))
+    assert o_uni.min() >= 1.8 and o_ref[-1] >= 1.8
+    # fine level of nblk base blocks (spacing h / 2) against the uniform grid of 2 nblk blocks
+    for a, b in zip(ref_fine[:-1], uni[1:]):
+        assert abs(a - b) <= 0.1 * b
