@@ -401,7 +401,9 @@ template hipError_t launch_mac<double>(int, SetTable&, hipStream_t, int);
 
 // ============================================================================= near (super) MAC
 // U_P[k] = sum over the 27 super-blocks Q with |P - Q|_inf <= 1 of K_{P-Q}[k] F_Q[k].
-// One wavefront owns a row of W target super-blocks along x and 64 frequencies.  The source rows
+// Three forms follow: rows (below), one-chunk tiles and pipelined tiles (further down; the
+// planner's choice where a level's tiles fit the pipelined form's staging).
+// Rows: one wavefront owns a row of W target super-blocks along x and 64 frequencies.  The source rows
 // (dy, dz) that hold sources come in groups of 3; a group's 3 (W + 2) source spectra are loaded
 // together while the previous group is applied (3 kernel offsets along x each, kernels from LDS).
 // Kernel offsets are numbered h = 9 (dz + 1) + 3 (dy + 1) + dx + 1; only h <= 13 is read: the
