@@ -58,6 +58,16 @@ def test_uniform_full_size(lgf):
     r = np.where(mask, L.f - multires.apply_laplace(L.blocks, L.levels, ref, L.n_b), 0.0)
     ref1 = ref + fmm.flgf(L.blocks, r, L.n_b, L.interp_order)
     assert rel(solve(lgf, L, 1, 1), ref1) <= 1e-6
+    # the benchmark's configuration: autotuned plans, repeated solves replaying a captured graph
+    for precision, dc, want, tol in ((1, 1, ref1, 1e-6), (0, 0, ref, 1e-12)):
+        p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, precision, dc, autotune=1)
+        fd = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
+        for rep in range(3):
+            u = torch.zeros_like(fd)
+            p.solve(fd, u)
+            torch.cuda.synchronize()
+            assert rel(u.cpu().numpy(), want) <= tol, f"precision {precision} solve {rep}"
+        p.close()
 
 
 def test_torus_full_size(lgf):
