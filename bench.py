@@ -224,8 +224,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "copies": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library solves on a "
+              "single GPU and has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
 
     import torch
