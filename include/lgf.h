@@ -103,6 +103,20 @@ lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int
 /* u = solution for source f (device pointers, layout above); asynchronous on stream. */
 lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream);
 
+/* Forward operators on the layout's per-level lattice (Sec. 3: the source correction makes the
+ * 7-point operator of each level consistent with the computed inverse, and applications need at
+ * least the gradient of the solution).  Evaluated on every leaf cell whose six face neighbours lie
+ * in blocks of the same level, with h = 2^-level base cells; every other cell (non-leaf blocks,
+ * cells next to a level boundary or the layout's edge) is set to 0:
+ *   LGF_OP_LAPLACIAN  u [n][N_b^3]     -> out [n][N_b^3]     h^-2 (6 neighbours - 6 centre)
+ *   LGF_OP_GRADIENT   u [n][N_b^3]     -> out [3][n][N_b^3]  (u(x + e_a) - u(x - e_a)) / 2h
+ *   LGF_OP_CURL       u [3][n][N_b^3]  -> out [3][n][N_b^3]  curl by the same central differences
+ * u and out are FP64 device arrays in the block layout of lgf_solve (component-major), owned by
+ * the caller and not overlapping; asynchronous on stream.  LGF_EINVAL for a null argument or an
+ * unknown op. */
+typedef enum { LGF_OP_LAPLACIAN = 0, LGF_OP_GRADIENT = 1, LGF_OP_CURL = 2 } lgf_op;
+lgf_status lgf_apply(lgf_plan_t p, int32_t op, const double* u, double* out, lgf_stream_t stream);
+
 /* n independent solves advanced together: every phase of all plans runs in shared launches.
  * Plans must be distinct.  Results equal n separate lgf_solve calls. */
 lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* const* u, int32_t n,

@@ -113,6 +113,11 @@ lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stre
   return from_hip(lgf::solve_members_graph(m, (hipStream_t)stream));
 }
 
+lgf_status lgf_apply(lgf_plan_t p, int32_t op, const double* u, double* out, lgf_stream_t stream) {
+  if (!p || !u || !out || op < LGF_OP_LAPLACIAN || op > LGF_OP_CURL) return LGF_EINVAL;
+  return from_hip(lgf::plan_apply(p->p, op, u, out, (hipStream_t)stream));
+}
+
 lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* const* u, int32_t n,
                            lgf_stream_t stream) {
   if (!p || !f || !u || n < 0) return LGF_EINVAL;

@@ -566,6 +566,69 @@ hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Forward operators of the per-level lattice on the leaf cells whose six neighbours lie in
+// same-level blocks (the cells on which the solve makes the 7-point equation hold, Sec. 3); 0 on
+// every other cell.  Laplacian h^-2 (6 neighbours - 6 centre); gradient by central differences
+// (u(x + e_a) - u(x - e_a)) / 2h; curl of a three-component field from the same differences.
+// One thread per cell; a neighbour across a block face is read from the block on that side.
+template <int NB>
+__global__ __launch_bounds__(256) void fwd_op_kernel(const OpItem* __restrict__ items, int op,
+                                                     const double* __restrict__ u,
+                                                     double* __restrict__ out, int64_t cs) {
+  constexpr int N3 = NB * NB * NB, PER = (N3 + 255) / 256;
+  const OpItem& it = items[blockIdx.x / PER];
+  const int i = (int)(blockIdx.x % PER) * 256 + (int)threadIdx.x;
+  if (i >= N3) return;
+  const int q[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
+  bool ok = it.leaf != 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (q[a] == 0) ok = ok && it.nbr_off[2 * a] >= 0;
+    if (q[a] == NB - 1) ok = ok && it.nbr_off[2 * a + 1] >= 0;
+  }
+  const gview<double> o = gl(out);
+  const int64_t at = it.off + i;
+  if (!ok) {
+    const int nout = op == 0 ? 1 : 3;
+    for (int c = 0; c < nout; ++c) o[c * cs + at] = 0.0;
+    return;
+  }
+  const gview<const double> U = gl(u);
+  // component c at the neighbour one cell along axis a in direction s (-1 or +1)
+  auto nbv = [&](int c, int a, int s) -> double {
+    const int stride = a == 0 ? 1 : (a == 1 ? NB : NB * NB);
+    int qa = q[a] + s;
+    int64_t b = it.off;
+    if (qa < 0) { b = it.nbr_off[2 * a]; qa += NB; }
+    else if (qa >= NB) { b = it.nbr_off[2 * a + 1]; qa -= NB; }
+    return U[c * cs + b + i + (int64_t)(qa - q[a]) * stride];
+  };
+  const double hh = 0.5 * it.inv_h;
+  if (op == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s += nbv(0, a, -1) + nbv(0, a, 1);
+    o[at] = it.inv_h * it.inv_h * (s - 6.0 * U[at]);
+  } else if (op == 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[a * cs + at] = (nbv(0, a, 1) - nbv(0, a, -1)) * hh;
+  } else {
+    auto d = [&](int c, int a) { return (nbv(c, a, 1) - nbv(c, a, -1)) * hh; };
+    o[at] = d(2, 1) - d(1, 2);
+    o[cs + at] = d(0, 2) - d(2, 0);
+    o[2 * cs + at] = d(1, 0) - d(0, 1);
+  }
+}
+
+hipError_t launch_fwd_op(int nb, int op, const OpItem* items, int64_t n, const double* u, double* out,
+                         hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!items || op < 0 || op > 2) return hipErrorInvalidValue;
+  const int64_t n3 = (int64_t)nb * nb * nb, per = (n3 + 255) / 256;
+  LGF_NB_DISPATCH(nb, fwd_op_kernel<NB><<<(unsigned)(n * per), 256, 0, st>>>(items, op, u, out, n * n3));
+  return hipGetLastError();
+}
+
 template hipError_t launch_anterp<float, float>(int, SetTable&, hipStream_t);
 template hipError_t launch_anterp<double, double>(int, SetTable&, hipStream_t);
 template hipError_t launch_anterp<float, double>(int, SetTable&, hipStream_t);

@@ -215,8 +215,21 @@ struct ResidualItem {
 };
 constexpr int kResidualSlabs = 4;       // workgroups (z-slabs) per block of the residual
 
+// forward operators of the per-level lattice (7-point Laplacian, gradient, curl): one per block
+struct OpItem {
+  int64_t off;           // block offset in every component array
+  int64_t nbr_off[6];    // same-level blocks across faces (-x,+x,-y,+y,-z,+z) (-1: absent)
+  double inv_h;          // 2^level: inverse spacing in base cells
+  int32_t leaf;          // 0: every output cell of the block is 0
+  int32_t pad;
+};
+
 // ----------------------------------------------------------------------------- launchers
 int quad_nodes();
+// op 0: Laplacian (1 -> 1 component), 1: gradient (1 -> 3), 2: curl (3 -> 3); components of
+// u and out are n * nb^3 apart
+hipError_t launch_fwd_op(int nb, int op, const OpItem* items, int64_t n, const double* u, double* out,
+                         hipStream_t st);
 hipError_t launch_green_table(double* d_cube, double* d_nodes, double* d_wts, const int16_t* d_tri,
                               int ntri, hipStream_t st);
 hipError_t launch_green_eval(const int32_t* d_n, int64_t m, const double* d_cube, double* d_out,

@@ -1422,6 +1422,24 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   if (!hi.buf.empty() && !p->dry)
     LGF_HIP_CHECK(hipMemcpy(d_items, hi.buf.data(), hi.buf.size(), hipMemcpyHostToDevice));
   p->d_items = d_items;
+  {
+    // block table of the forward operators (every plan, every block)
+    std::vector<OpItem> ops(n);
+    for (int64_t i = 0; i < n; ++i) {
+      OpItem& o = ops[i];
+      o.off = i * N3;
+      for (int face = 0; face < 6; ++face) {
+        const int nbi = face_nbr((int)i, face);
+        o.nbr_off[face] = nbi >= 0 ? (int64_t)nbi * N3 : -1;
+      }
+      o.inv_h = std::ldexp(1.0, lev[i]);
+      o.leaf = leaf[i];
+      o.pad = 0;
+    }
+    LGF_HIP_CHECK(ar.alloc(&p->d_ops, ops.size() * sizeof(OpItem)));
+    if (n > 0 && !p->dry)
+      LGF_HIP_CHECK(hipMemcpy(p->d_ops, ops.data(), ops.size() * sizeof(OpItem), hipMemcpyHostToDevice));
+  }
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
     for (const PendingStep& s : in)
       out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work,
@@ -2012,6 +2030,11 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return hipSuccess;
+}
+
+hipError_t plan_apply(Plan* p, int op, const double* u, double* out, hipStream_t st) {
+  if (!p || p->dry || op < 0 || op > 2 || !u || !out) return hipErrorInvalidValue;
+  return launch_fwd_op(p->nb, op, (const OpItem*)p->d_ops, p->nblocks, u, out, st);
 }
 
 }  // namespace lgf

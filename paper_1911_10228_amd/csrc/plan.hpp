@@ -111,6 +111,7 @@ struct Plan {
   double* d_w = nullptr;               // Lagrange matrix [2 nb][nb]
   double* d_w3 = nullptr;              // quadratic refinement table [(2 nb + 2)][4]
   void* d_items = nullptr;
+  void* d_ops = nullptr;                // OpItem [n]: the forward operators' block table
 
   // statistics
   int64_t interactions = 0, n_fwd = 0, n_inv = 0, n_rows = 0, n_spectra = 0;
@@ -132,6 +133,8 @@ struct Member {
   double* out;
   bool accumulate = false;             // the pass adds its result into out (the DC update u += e)
 };
+// out = op(u) on the plan's layout: 0 Laplacian, 1 gradient, 2 curl (see launch_fwd_op).
+hipError_t plan_apply(Plan* p, int op, const double* u, double* out, hipStream_t st);
 // Runs the given step lists of several plans with shared launches, in key order.
 hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st);
 // Full solve of several plans (pass, then defect-correction iterations), shared launches.

@@ -18,8 +18,12 @@ LGF_FP64_PLAIN = 0
 LGF_FP32_REFINE = 1
 LGF_BASE_SUPER = 0
 LGF_BASE_BLOCK = 1
+# forward operators of Plan.apply (lgf_op)
+LAPLACIAN = 0
+GRADIENT = 1
+CURL = 2
 
-EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_solve_batch", "lgf_plan_get_info",
+EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_apply", "lgf_solve_batch", "lgf_plan_get_info",
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
            "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape",
@@ -67,6 +71,7 @@ def load() -> C.CDLL:
         "lgf_plan": ([P, P, I64, I32, I32, P, P], I32),
         "lgf_plan_check": ([P, P, I64, I32, I32, P, P], I32),
         "lgf_solve": ([P, P, P, P], I32),
+        "lgf_apply": ([P, I32, P, P, P], I32),
         "lgf_solve_batch": ([P, P, P, I32, P], I32),
         "lgf_plan_get_info": ([P, P], I32),
         "lgf_plan_destroy": ([P], I32),
@@ -150,6 +155,19 @@ class Plan:
         self._check_field(f)
         self._check_field(u)
         _check(load().lgf_solve(self._h, _ptr(f), _ptr(u), _stream(stream)), "lgf_solve")
+
+    def apply(self, op: int, u, out, stream=None):
+        """out <- op(u) on the layout's per-level lattice (LAPLACIAN, GRADIENT or CURL; float64
+        CUDA tensors, [n, N_b, N_b, N_b] per component, 3 components where the op has them)."""
+        import torch
+        nin = 3 if op == CURL else 1
+        nout = 1 if op == LAPLACIAN else 3
+        m = self.nblocks * self.n_b ** 3
+        for t, c in ((u, nin), (out, nout)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == c * m):
+                raise ValueError(f"op {op}: fields must be contiguous float64 CUDA tensors of {c} x "
+                                 "[n, N_b, N_b, N_b]")
+        _check(load().lgf_apply(self._h, int(op), _ptr(u), _ptr(out), _stream(stream)), "lgf_apply")
 
     def set_mac_shape(self, shape: int):
         """Force the coarse-level MAC launch shape (diagnostics; 0 restores the chosen one)."""
