@@ -90,6 +90,30 @@ def time_solves(plan, f, u, steps, warmup, torch, stream):
     return (time.perf_counter() - t0) / steps
 
 
+def bench_fwd_ops(lgf, plan, m, torch, stream, reps=20):
+    """lgf_apply (Laplacian, gradient, curl) on the bench layout: microseconds per launch from HIP
+    events on the launch stream around `reps` back-to-back launches, and the algorithmic HBM bytes
+    (every input component read once, every output component written once, 8 bytes a value) over
+    that time."""
+    res = {}
+    for op, name, nin, nout in ((lgf.LAPLACIAN, "laplacian", 1, 1), (lgf.GRADIENT, "gradient", 1, 3),
+                                (lgf.CURL, "curl", 3, 3)):
+        x = torch.randn(nin * m, dtype=torch.float64, device="cuda")
+        y = torch.empty(nout * m, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            plan.apply(op, x, y, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.apply(op, x, y, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = 8.0 * (nin + nout) * m / us / 1e3
+        res[name] = {"us": round(us, 2), "GB/s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 3)}
+    return res
+
+
 def profiled(lgf, plan, f, u, steps, torch, stream):
     """Per-kernel HIP-event times over `steps` solves (direct launches on one stream: events
     bracket each kernel running alone)."""
@@ -325,6 +349,8 @@ def main():
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()} for e in kern],
     }
     if not args.no_extra:
+        out["forward_ops"] = bench_fwd_ops(lgf, p64, u64.numel(), torch, stream)
+        print(f"# forward ops (FP64, bench layout): {out['forward_ops']}", file=sys.stderr, flush=True)
         out["multires_torus"] = bench_torus(lgf, workloads, torch, stream, max(args.steps // 4, 3), 1, args.dc)
         print(f"# torus: {out['multires_torus']}", file=sys.stderr, flush=True)
         out["batch64"] = bench_batch(lgf, workloads, torch, stream, max(args.steps // 4, 3), 1, args.dc)
