@@ -65,5 +65,13 @@ def test_empty_layout_is_rejected():
 def test_null_arguments():
     lib = lgf.load()
     assert lib.lgf_solve(None, None, None, None) == -1
+    assert lib.lgf_apply(None, 0, None, None, None) == -1
+    assert lib.lgf_apply(None, 7, None, None, None) == -1
     assert lib.lgf_plan_destroy(None) == -1
     assert lib.lgf_server_poll(None, 1, None) == -1
+
+
+def test_operator_codes_match_header():
+    text = open(os.path.join(ROOT, "include", "lgf.h")).read()
+    codes = {k: int(v) for k, v in re.findall(r"\bLGF_OP_([A-Z]+)\s*=\s*(\d+)", text)}
+    assert codes == {"LAPLACIAN": lgf.LAPLACIAN, "GRADIENT": lgf.GRADIENT, "CURL": lgf.CURL}
