@@ -191,8 +191,9 @@ def torus(seed: int = 3, n_b: int = 16, nblk: int = 8, n_levels: int = 3,
 
 
 def vortex_ring_field(pos, R: float, c1: float, c2: float):
-    """The paper's manufactured test field (Sec. 4, eqs. streamfunc and streamfunc_f): a vortex
-    ring of radius R about the z axis whose streamfunction is f(t) e_theta, t = d / R, d the
+    """The paper's manufactured test field (Sec. 3, Convergence subsection, eqs. streamfunc and
+    streamfunc_f): a vortex ring of radius R about the z axis whose streamfunction is
+    f(t) e_theta, t = d / R, d the
     distance to the ring's core circle, f(t) = c1 exp(-c2 / (1 - t^2)) for |t| < 1 (0 beyond).
     Returns the Cartesian components psi_x = -f y / rho, psi_y = f x / rho and their Laplacians
     (the sources of the two scalar Poisson problems): for g(rho, z) sin(theta) the Laplacian is

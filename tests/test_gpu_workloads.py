@@ -100,7 +100,8 @@ def test_torus_second_order_convergence(lgf):
 
 
 def test_vortex_ring_vector_second_order(lgf):
-    """The paper's manufactured solution (Sec. 4: the vortex ring R = 0.125, c1 = 1e3, c2 = 10)
+    """The paper's manufactured solution (Sec. 3, Convergence subsection: the vortex ring
+    R = 0.125, c1 = 1e3, c2 = 10)
     as a vector Poisson problem: both Cartesian streamfunction components through one
     VectorPlan (FP32 + defect correction), on a uniform grid (16^3 blocks) and with one
     refinement level around the ring (8^3 blocks): the errors against psi_x and psi_y fall at

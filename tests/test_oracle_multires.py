@@ -116,8 +116,8 @@ def test_defect_correction_approaches_fp64_solve():
 
 
 def test_vortex_ring_second_order():
-    """The paper's manufactured solution (Sec. 4: the vortex ring with R = 0.125, c1 = 1e3,
-    c2 = 10, whose Cartesian streamfunction components solve scalar Poisson problems with
+    """The paper's manufactured solution (Sec. 3, Convergence subsection: the vortex ring with
+    R = 0.125, c1 = 1e3, c2 = 10, whose Cartesian streamfunction components solve scalar Poisson problems with
     analytic sources): the oracle's error against psi_x falls at second order under uniform
     refinement of the grid, and with one refinement level around the ring the fine level keeps
     the accuracy of a uniform grid of its spacing."""
