@@ -20,12 +20,17 @@
  *  - Field arrays f and u are device pointers to [n][N_b][N_b][N_b] doubles, x fastest, in the
  *    order of `blocks`.  f on non-leaf blocks is ignored (recomputed by coarsening);
  *    u on a non-leaf block receives that level's total field.
- *  - Ownership: the caller owns f and u (device memory, e.g. torch tensors).  The plan owns all
- *    internal device buffers; the LGF table and kernel spectra are process-wide and shared.
+ *  - Ownership: the caller owns f and u (device memory, e.g. torch tensors).  A plan owns its
+ *    layout tables and constants (work-item images, weights); the LGF table and kernel spectra
+ *    are process-wide and shared.  The buffers of a solve (source and target spectra, level
+ *    fields) form a workspace that is not part of the plan: lgf_solve takes one per stream
+ *    (allocated on the first solve on that stream, under the plan's hbm_budget, and kept until
+ *    lgf_plan_destroy), the server takes one per admitted request from its own memory.  So
+ *    solves of one plan may run concurrently on different streams.
  *  - Errors are returned as lgf_status; nothing throws across the ABI.  HIP launch errors give
  *    LGF_EHIP; asynchronous faults surface at the caller's next synchronisation.
- *  - Solves are asynchronous on the given stream.  A plan's workspace is used by one solve at a
- *    time: solves of one plan on different streams must be serialised by the caller.
+ *  - Solves are asynchronous on the given stream; solves of one plan on one stream run in
+ *    stream order.
  */
 #ifndef LGF_H_
 #define LGF_H_
@@ -52,8 +57,11 @@ typedef enum {
 
 typedef enum {
   LGF_FP64_PLAIN = 0,   /* FFTs, spectral MAC and operators in FP64 */
-  LGF_FP32_REFINE = 1   /* FP32 FFTs/MAC/operators; FP64 residual r = f - L u and update,
-                           repeated dc_iters times (defect correction) */
+  LGF_FP32_REFINE = 1   /* the base octree level of every refinement level (block or super-block
+                           FFTs and their MAC, about 95 % of the work) in FP32, the coarse octree
+                           levels (far field) in FP64, level fields J w and w in FP64; then
+                           dc_iters defect-correction iterations: FP64 residual r = f - L u, an
+                           all-FP32 re-solve of r and the FP64 update u += e */
 } lgf_precision;
 
 /* How the base octree level of every refinement level is convolved.  Both give the same result
@@ -70,7 +78,11 @@ typedef struct {
   int32_t dc_iters;      /* defect-correction iterations for LGF_FP32_REFINE (0..8) */
   int32_t autotune;      /* 1: time the launch shapes of the far-field MAC steps at plan time */
   int32_t base_level;    /* lgf_base_level */
-  uint64_t hbm_budget;   /* bytes the plan may allocate; 0 = unlimited */
+  uint64_t hbm_budget;   /* bytes the plan may hold: its constants plus the workspaces lgf_solve and
+                            lgf_solve_batch allocate (one per stream and occurrence); lgf_plan
+                            fails with LGF_ENOMEM if constants and one workspace exceed it, a solve
+                            that needs one more workspace than fits returns LGF_ENOMEM; 0 = no
+                            limit */
 } lgf_options;
 
 typedef struct {
@@ -82,7 +94,7 @@ typedef struct {
   int64_t fft_forward;        /* forward block FFTs per solve pass */
   int64_t fft_inverse;        /* inverse block FFTs per solve pass */
   int64_t mac_rows;
-  int64_t workspace_bytes;    /* device bytes owned by the plan */
+  int64_t workspace_bytes;    /* device bytes of one solve's workspace (with the item images) */
   int64_t spectra;            /* distinct kernel spectra referenced */
   int64_t super_forward;      /* forward super-block FFTs per solve pass (LGF_BASE_SUPER) */
   int64_t super_inverse;      /* inverse super-block FFTs per solve pass */
@@ -118,7 +130,9 @@ typedef enum { LGF_OP_LAPLACIAN = 0, LGF_OP_GRADIENT = 1, LGF_OP_CURL = 2 } lgf_
 lgf_status lgf_apply(lgf_plan_t p, int32_t op, const double* u, double* out, lgf_stream_t stream);
 
 /* n independent solves advanced together: every phase of all plans runs in shared launches.
- * Plans must be distinct.  Results equal n separate lgf_solve calls. */
+ * A plan may appear several times (e.g. the components of a vector field on one layout): its
+ * k-th occurrence runs on the plan's k-th workspace of that stream.  Results equal n separate
+ * lgf_solve calls. */
 lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* const* u, int32_t n,
                            lgf_stream_t stream);
 
@@ -181,22 +195,56 @@ lgf_status lgf_profile(int32_t enable);
 lgf_status lgf_profile_read(lgf_profile_entry* out, int32_t cap, int32_t* n);
 
 /* Serving: continuous batching of solve requests under an HBM budget.
- * submit enqueues (plan, f, u) and returns at once; the caller keeps f and u alive until the
- * request completes.  A launcher thread forms a batch from the queued requests whose plans fit
- * the budget next to the batches already on the GPU (a plan runs in one batch at a time: its
- * workspace is shared) and enqueues the batch as one multi-plan solve (lgf_solve_batch: every
- * kernel step of all members in shared launches) on the server's stream, while earlier batches
- * still run; requests arriving meanwhile form the next batch.  A completion thread retires
- * batches in order.  poll reports completion (1) or not (0).
+ * lgf_server_create: hbm_budget bounds the device memory the server takes for request workspaces
+ *   (reserved in chunks of up to 16 GiB as requests need it and kept until lgf_server_destroy;
+ *   0 = no bound).  Requests are admitted in arrival order while their workspace fits; a request
+ *   passed over four times stops later ones from overtaking it.  Each admitted request gets its
+ *   own workspace slot, so requests of one plan run concurrently.  A launcher thread enqueues
+ *   every admitted request as one multi-plan solve (every kernel step of all members in shared
+ *   launches) on the server's stream, while earlier batches still run; requests arriving
+ *   meanwhile form the next batch.  A completion thread retires batches in order and frees
+ *   their slots.  A request whose workspace exceeds the budget fails with LGF_ENOMEM.
+ * lgf_server_submit: enqueues (plan, f, u) and returns at once; the caller keeps the plan, f and
+ *   u alive until the request completes.
+ * lgf_server_submit_layout: the same for a block layout (arguments as lgf_plan; opt->hbm_budget
+ *   is ignored): a planner thread takes the plan from the server's cache keyed by the layout and
+ *   options, or builds it (kept for later requests, at most 256 plans, least recently used first
+ *   out), so latency includes plan building on a miss.
+ * lgf_server_poll: completion (1) or not (0); the request's error if it failed.
  * Latency = completion - submission, reported as p50/p99 over completed requests; points_per_s
- * = unknowns completed / (last completion - first submission). */
+ * = unknowns completed / (last completion - first submission).
+ * lgf_server_info: memory and plan-cache counters: bytes reserved from HIP, in use and at most in
+ *   use, slots in use and at most in use, relocations of item images into slots, cached plans,
+ *   cache hits and misses, total and largest plan-build time (ms). */
+typedef struct {
+  int64_t reserved_bytes;
+  int64_t in_use_bytes;
+  int64_t peak_in_use_bytes;
+  int64_t slots;
+  int64_t peak_slots;
+  int64_t binds;
+  int64_t plans_cached;
+  int64_t plan_hits;
+  int64_t plan_misses;
+  double plan_ms_total;
+  double plan_ms_max;
+} lgf_server_memory;
 lgf_status lgf_server_create(uint64_t hbm_budget, lgf_stream_t stream, lgf_server_t* out);
 lgf_status lgf_server_submit(lgf_server_t s, lgf_plan_t p, const double* f, double* u, int64_t* req_id);
+lgf_status lgf_server_submit_layout(lgf_server_t s, const int32_t* blocks, const int32_t* levels, int64_t n,
+                                    int32_t N_b, int32_t interp_order, const lgf_options* opt, const double* f,
+                                    double* u, int64_t* req_id);
 lgf_status lgf_server_poll(lgf_server_t s, int64_t req_id, int32_t* done);
 lgf_status lgf_server_wait_all(lgf_server_t s);
 lgf_status lgf_server_stats(lgf_server_t s, double* p50_us, double* p99_us, double* points_per_s,
                             int64_t* completed);
+lgf_status lgf_server_info(lgf_server_t s, lgf_server_memory* out);
 lgf_status lgf_server_destroy(lgf_server_t s);
+
+/* Diagnostics: with enable = 1 every workspace is filled with 0xFF bytes (NaN) each time a
+ * plan's items are placed into it, before the ranges that must read as zero are cleared; a
+ * solve that read anything it had not written would then return NaN.  Process-wide. */
+lgf_status lgf_workspace_poison(int32_t enable);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@
 #include <deque>
 #include <map>
 #include <set>
+#include <cmath>
 #include <thread>
 
 #include "plan.hpp"
@@ -109,7 +110,10 @@ lgf_status lgf_plan_check(const int32_t* blocks, const int32_t* levels, int64_t 
 
 lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream) {
   if (!p || !f || !u) return LGF_EINVAL;
-  std::vector<lgf::Member> m{{p->p, f, u}};
+  lgf::Binding* b = nullptr;
+  hipError_t e = lgf::plan_binding(p->p, (hipStream_t)stream, 0, &b);
+  if (e != hipSuccess) return from_hip(e);
+  std::vector<lgf::Member> m{{p->p, f, u, false, b}};
   return from_hip(lgf::solve_members_graph(m, (hipStream_t)stream));
 }
 
@@ -122,11 +126,13 @@ lgf_status lgf_solve_batch(const lgf_plan_t* p, const double* const* f, double* 
                            lgf_stream_t stream) {
   if (!p || !f || !u || n < 0) return LGF_EINVAL;
   std::vector<lgf::Member> m;
-  std::set<lgf::Plan*> seen;
+  std::map<lgf::Plan*, int> seen;           // occurrence k of a plan takes its k-th binding
   for (int i = 0; i < n; ++i) {
     if (!p[i] || !f[i] || !u[i]) return LGF_EINVAL;
-    if (!seen.insert(p[i]->p).second) return LGF_EINVAL;
-    m.push_back({p[i]->p, f[i], u[i]});
+    lgf::Binding* b = nullptr;
+    hipError_t e = lgf::plan_binding(p[i]->p, (hipStream_t)stream, seen[p[i]->p]++, &b);
+    if (e != hipSuccess) return from_hip(e);
+    m.push_back({p[i]->p, f[i], u[i], false, b});
   }
   return from_hip(lgf::solve_members_graph(m, (hipStream_t)stream));
 }
@@ -142,7 +148,7 @@ lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out) {
   out->fft_forward = q->n_fwd;
   out->fft_inverse = q->n_inv;
   out->mac_rows = q->n_rows;
-  out->workspace_bytes = q->bytes + (q->corr ? q->corr->bytes : 0);
+  out->workspace_bytes = q->bind_bytes;
   out->spectra = q->n_spectra;
   out->super_forward = q->n_sup_fwd;
   out->super_inverse = q->n_sup_inv;
@@ -219,6 +225,11 @@ lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, i
                                  (hipStream_t)stream));
 }
 
+lgf_status lgf_workspace_poison(int32_t enable) {
+  lgf::set_poison(enable != 0);
+  return LGF_OK;
+}
+
 lgf_status lgf_profile(int32_t enable) {
   lgf::profile_enable(enable != 0);
   return LGF_OK;
@@ -244,33 +255,66 @@ lgf_status lgf_profile_read(lgf_profile_entry* out, int32_t cap, int32_t* n) {
 }  // extern "C"
 
 // ============================================================================= server
-// Requests are admitted in arrival order while the workspace of the plans in flight fits the
-// budget (one request per plan at a time: a plan's workspace serves one solve).  Each launcher
-// step solves every admitted request with shared launches (all phases of all admitted plans
-// interleaved by refinement level and phase) and records an event; a completion thread stamps
-// the finish time of each request when its step's event has fired.  Requests arriving while a
+// Requests carry a plan (caller-owned, or resolved by layout from the server's plan cache by a
+// planner thread) and are admitted in arrival order as workspace slots free up: a slot is a
+// range of the server's device memory (grown in chunks of up to 16 GiB within the budget, kept
+// while the server lives) that the plan's items are relocated into.  Several
+// requests of one plan run at once on distinct slots.  Each launcher step solves every admitted
+// request with shared launches (all phases of all admitted plans interleaved by refinement
+// level and phase) and records an event; a completion thread stamps the finish time of each
+// request when its step's event has fired and returns its slot.  Requests arriving while a
 // step runs join the next step.
 struct lgf_server_s {
   struct Req {
     int64_t id;
-    lgf::Plan* plan;
+    lgf::Plan* plan;                       // null until the planner resolved the layout
     const double* f;
     double* u;
     std::chrono::steady_clock::time_point t0;
+    int skipped = 0;                       // launcher steps that passed this request over
+    // layout of a request submitted by layout
+    std::vector<int32_t> blocks, levels;
+    int32_t nb = 0, order = 0;
+    lgf_options opt{};
+  };
+  struct Slot {
+    int region;
+    int64_t off, len;
+    lgf::Binding* b;
   };
   struct Batch {
     hipEvent_t ev;
     std::vector<Req> reqs;
-    int64_t bytes;
+    std::vector<Slot> slots;
   };
+  struct Region {
+    uint8_t* base;
+    int64_t bytes;
+    std::map<int64_t, int64_t> free;       // offset -> length, coalesced
+    std::map<int64_t, std::pair<const lgf::Plan*, int64_t>> image;   // offset -> (plan, length)
+  };
+  struct CachedPlan {
+    lgf::Plan* plan;
+    int64_t users = 0;                     // queued or running requests
+    uint64_t last_use = 0;
+  };
+  static constexpr int64_t kChunk = (int64_t)16 << 30;
+  static constexpr size_t kPlanCacheMax = 256;
+
   uint64_t budget;
   hipStream_t stream;
+  int device = 0;
   std::mutex mu;
-  std::condition_variable cv, cv_done;
-  std::deque<Req> queue;
+  std::condition_variable cv, cv_done, cv_plan;
+  std::deque<Req> queue, plan_queue;
   std::deque<Batch> inflight;
-  std::set<lgf::Plan*> busy;
-  int64_t inflight_bytes = 0;
+  std::vector<Region> regions;
+  std::map<std::vector<int32_t>, CachedPlan> plans;   // layout key -> plan
+  uint64_t use_clock = 0;
+  int64_t reserved = 0, in_use = 0, peak_in_use = 0, slots = 0, peak_slots = 0, binds = 0;
+  int64_t plan_hits = 0, plan_misses = 0;
+  double plan_ms_total = 0.0, plan_ms_max = 0.0;
+  int64_t running = 0;                     // requests in launched steps
   std::map<int64_t, int> state;            // 0 queued, 1 running, 2 done, -1 failed
   std::vector<double> lat_us;
   int64_t next_id = 1;
@@ -278,66 +322,253 @@ struct lgf_server_s {
   std::chrono::steady_clock::time_point first_submit, last_done;
   bool have_first = false;
   bool stop = false;
-  bool launcher_done = false;
+  bool planner_done = false, launcher_done = false;
   int64_t completions = 0;
   lgf_status error = LGF_OK;
-  std::thread launcher, completer;
+  std::thread planner, launcher, completer;
 
-  void launch_loop() {
+  static std::vector<int32_t> layout_key(const Req& r) {
+    std::vector<int32_t> k{r.nb, r.order, r.opt.precision, r.opt.dc_iters, r.opt.autotune, r.opt.base_level};
+    k.insert(k.end(), r.blocks.begin(), r.blocks.end());
+    k.insert(k.end(), r.levels.begin(), r.levels.end());
+    return k;
+  }
+
+  // first fit over the regions; a new chunk while the budget allows.  Called with mu held.
+  bool take(int64_t need, Slot* out) {
+    need = (need + 255) / 256 * 256;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (size_t ri = 0; ri < regions.size(); ++ri) {
+        Region& R = regions[ri];
+        for (auto it = R.free.begin(); it != R.free.end(); ++it) {
+          if (it->second < need) continue;
+          const int64_t off = it->first, rest = it->second - need;
+          R.free.erase(it);
+          if (rest) R.free[off + need] = rest;
+          out->region = (int)ri;
+          out->off = off;
+          out->len = need;
+          return true;
+        }
+      }
+      if (pass == 1) break;
+      const int64_t left = budget ? (int64_t)budget - reserved : INT64_MAX;
+      if (left < need) return false;
+      const int64_t sz = std::max(need, std::min(left, kChunk));
+      void* base = nullptr;
+      if (hipMalloc(&base, (size_t)sz) != hipSuccess) {
+        // a smaller chunk if the device cannot give the larger one
+        if (sz == need || hipMalloc(&base, (size_t)need) != hipSuccess) return false;
+        regions.push_back({(uint8_t*)base, need, {{0, need}}, {}});
+        reserved += need;
+        continue;
+      }
+      regions.push_back({(uint8_t*)base, sz, {{0, sz}}, {}});
+      reserved += sz;
+    }
+    return false;
+  }
+
+  void give_back(const Slot& sl) {
+    Region& R = regions[sl.region];
+    int64_t off = sl.off, len = sl.len;
+    auto nx = R.free.lower_bound(off);
+    if (nx != R.free.end() && nx->first == off + len) {
+      len += nx->second;
+      nx = R.free.erase(nx);
+    }
+    if (nx != R.free.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        len += pv->second;
+        R.free.erase(pv);
+      }
+    }
+    R.free[off] = len;
+  }
+
+  // the binding of a slot for plan p: the plan's item images stay valid where the same plan
+  // used the same range last (a solve writes neither its items nor its zero ranges)
+  lgf::Binding* slot_binding(Slot& sl, const lgf::Plan* p) {
+    Region& R = regions[sl.region];
+    const lgf::Plan* have = nullptr;
+    for (auto it = R.image.begin(); it != R.image.end();) {
+      const int64_t o = it->first, l = it->second.second;
+      if (o < sl.off + sl.len && sl.off < o + l) {
+        if (o == sl.off && l == sl.len) have = it->second.first;
+        it = R.image.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    R.image[sl.off] = {p, sl.len};
+    return new lgf::Binding{R.base + sl.off, sl.len, have, false};
+  }
+
+  void fail(const Req& r, lgf_status why) {
+    state[r.id] = -1;
+    error = why;
+    ++completions;
+    cv_done.notify_all();
+  }
+
+  void release_plan(lgf::Plan* p) {
+    for (auto& kv : plans)
+      if (kv.second.plan == p) {
+        --kv.second.users;
+        break;
+      }
+  }
+
+  void plan_loop() {
+    (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-      cv.wait(lk, [&] { return stop || !queue.empty(); });
-      if (stop && queue.empty()) {
+      cv_plan.wait(lk, [&] { return stop || !plan_queue.empty(); });
+      if (plan_queue.empty()) {
+        planner_done = true;
+        cv.notify_all();
+        return;
+      }
+      Req r = std::move(plan_queue.front());
+      plan_queue.pop_front();
+      const std::vector<int32_t> key = layout_key(r);
+      auto it = plans.find(key);
+      if (it != plans.end()) {
+        ++plan_hits;
+      } else {
+        lk.unlock();
+        const auto t0 = std::chrono::steady_clock::now();
+        lgf::Plan* p = nullptr;
+        std::string err;
+        hipError_t e = lgf::plan_build(r.blocks.data(), r.levels.data(), (int64_t)r.levels.size(), r.nb, r.order,
+                                       r.opt.precision == LGF_FP32_REFINE, r.opt.dc_iters, 0, &p, &err, false,
+                                       r.opt.autotune != 0, r.opt.base_level == LGF_BASE_SUPER);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        lk.lock();
+        if (e == hipSuccess) e = lgf::plan_trim(p);     // the tuning workspace: slots serve the plan
+        if (e != hipSuccess) {
+          lgf::plan_free(p);
+          fail(r, from_hip(e));
+          continue;
+        }
+        ++plan_misses;
+        plan_ms_total += ms;
+        plan_ms_max = std::max(plan_ms_max, ms);
+        // evict the least recently used plans that no request holds
+        while (plans.size() >= kPlanCacheMax) {
+          auto victim = plans.end();
+          for (auto q = plans.begin(); q != plans.end(); ++q)
+            if (q->second.users == 0 && (victim == plans.end() || q->second.last_use < victim->second.last_use))
+              victim = q;
+          if (victim == plans.end()) break;
+          for (Region& R : regions)
+            for (auto q = R.image.begin(); q != R.image.end();)
+              q = q->second.first == victim->second.plan ? R.image.erase(q) : std::next(q);
+          lgf::plan_free(victim->second.plan);
+          plans.erase(victim);
+        }
+        it = plans.emplace(key, CachedPlan{p, 0, 0}).first;
+      }
+      it->second.users += 1;
+      it->second.last_use = ++use_clock;
+      r.plan = it->second.plan;
+      r.blocks.clear();
+      r.levels.clear();
+      queue.push_back(std::move(r));
+      cv.notify_all();
+    }
+  }
+
+  void launch_loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      cv.wait(lk, [&] { return (stop && planner_done) || !queue.empty(); });
+      if (queue.empty()) {
         launcher_done = true;
         cv_done.notify_all();
         return;
       }
       Batch b;
-      b.bytes = 0;
       std::deque<Req> rest;
-      std::set<lgf::Plan*> in_batch;
+      bool blocked = false;                // an old request waits: admit nothing past it
       while (!queue.empty()) {
-        Req r = queue.front();
+        Req r = std::move(queue.front());
         queue.pop_front();
-        const int64_t need = r.plan->bytes + (r.plan->corr ? r.plan->corr->bytes : 0);
-        const bool fits = budget == 0 || (uint64_t)(inflight_bytes + b.bytes + need) <= budget ||
-                          (inflight.empty() && b.reqs.empty());
-        if (!fits || busy.count(r.plan) || in_batch.count(r.plan) || (int)b.reqs.size() >= lgf::kMaxSets) {
-          rest.push_back(r);
+        const int64_t need = r.plan->bind_bytes;
+        if (budget && (uint64_t)need > budget) {          // can never be admitted
+          release_plan(r.plan);
+          fail(r, LGF_ENOMEM);
           continue;
         }
-        in_batch.insert(r.plan);
-        b.bytes += need;
-        b.reqs.push_back(r);
+        Slot sl{};
+        if (blocked || (int)b.reqs.size() >= lgf::kMaxSets || !take(need, &sl)) {
+          if (!blocked && ++r.skipped >= 4) blocked = true;
+          rest.push_back(std::move(r));
+          continue;
+        }
+        sl.b = slot_binding(sl, r.plan);
+        b.slots.push_back(sl);
+        b.reqs.push_back(std::move(r));
       }
       queue.swap(rest);
       if (b.reqs.empty()) {
-        // everything queued waits for a plan or budget held by a step in flight
+        if (queue.empty()) continue;       // every request was rejected: wait for more
+        // everything queued waits for slots held by a step in flight
         const int64_t seen = completions;
+        if (running == 0) {
+          // nothing in flight: every region is free.  Chunks taken for earlier sizes may still
+          // be too small for the head request; give them back once and retry, else it cannot fit.
+          if (!regions.empty()) {
+            (void)hipStreamSynchronize(stream);
+            for (Region& R : regions) (void)hipFree(R.base);
+            regions.clear();
+            reserved = 0;
+            continue;
+          }
+          Req r = std::move(queue.front());
+          queue.pop_front();
+          release_plan(r.plan);
+          fail(r, LGF_ENOMEM);
+          continue;
+        }
         cv.wait(lk, [&] { return completions != seen; });
         continue;
       }
-      for (const Req& r : b.reqs) {
-        busy.insert(r.plan);
-        state[r.id] = 1;
+      for (size_t i = 0; i < b.reqs.size(); ++i) {
+        state[b.reqs[i].id] = 1;
+        in_use += b.slots[i].len;
+        ++slots;
       }
-      inflight_bytes += b.bytes;
+      peak_in_use = std::max(peak_in_use, in_use);
+      peak_slots = std::max(peak_slots, slots);
+      running += (int64_t)b.reqs.size();
       lk.unlock();
       std::vector<lgf::Member> m;
-      for (const Req& r : b.reqs) m.push_back({r.plan, r.f, r.u});
-      hipError_t e = lgf::solve_members(m, stream);
+      hipError_t e = hipSuccess;
+      int64_t nbind = 0;
+      for (size_t i = 0; i < b.reqs.size() && e == hipSuccess; ++i) {
+        nbind += b.slots[i].b->plan != b.reqs[i].plan;
+        e = lgf::bind(b.reqs[i].plan, b.slots[i].b, stream);
+        m.push_back({b.reqs[i].plan, b.reqs[i].f, b.reqs[i].u, false, b.slots[i].b});
+      }
+      if (e == hipSuccess) e = lgf::solve_members(m, stream);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventRecord(b.ev, stream);
       lk.lock();
+      binds += nbind;
       if (e != hipSuccess) {
-        error = LGF_EHIP;
-        for (const Req& r : b.reqs) {
-          state[r.id] = -1;
-          busy.erase(r.plan);
+        for (size_t i = 0; i < b.reqs.size(); ++i) {
+          fail(b.reqs[i], LGF_EHIP);
+          release_plan(b.reqs[i].plan);
+          in_use -= b.slots[i].len;
+          --slots;
+          give_back(b.slots[i]);
+          delete b.slots[i].b;
         }
-        inflight_bytes -= b.bytes;
-        ++completions;
-        cv_done.notify_all();
+        running -= (int64_t)b.reqs.size();
         continue;
       }
       inflight.push_back(std::move(b));
@@ -346,30 +577,51 @@ struct lgf_server_s {
   }
 
   void complete_loop() {
+    (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
       cv_done.wait(lk, [&] { return !inflight.empty() || launcher_done; });
       if (inflight.empty()) return;
-      Batch b = inflight.front();
+      Batch b = std::move(inflight.front());
+      inflight.pop_front();
       lk.unlock();
       hipError_t e = hipEventSynchronize(b.ev);
       const auto t1 = std::chrono::steady_clock::now();
       (void)hipEventDestroy(b.ev);
       lk.lock();
-      inflight.pop_front();
-      for (const Req& r : b.reqs) {
+      for (size_t i = 0; i < b.reqs.size(); ++i) {
+        const Req& r = b.reqs[i];
         state[r.id] = e == hipSuccess ? 2 : -1;
-        busy.erase(r.plan);
         lat_us.push_back(std::chrono::duration<double, std::micro>(t1 - r.t0).count());
         points_done += r.plan->nblocks * r.plan->nb * r.plan->nb * r.plan->nb;
+        release_plan(r.plan);
+        in_use -= b.slots[i].len;
+        --slots;
+        give_back(b.slots[i]);
+        delete b.slots[i].b;
       }
+      running -= (int64_t)b.reqs.size();
       if (e != hipSuccess) error = LGF_EHIP;
       last_done = t1;
       ++completions;
-      inflight_bytes -= b.bytes;
       cv.notify_all();
       cv_done.notify_all();
     }
+  }
+
+  Req new_req(const double* f, double* u) {
+    Req r;
+    r.id = next_id++;
+    r.plan = nullptr;
+    r.f = f;
+    r.u = u;
+    r.t0 = std::chrono::steady_clock::now();
+    if (!have_first) {
+      first_submit = r.t0;
+      have_first = true;
+    }
+    state[r.id] = 0;
+    return r;
   }
 };
 
@@ -380,6 +632,11 @@ lgf_status lgf_server_create(uint64_t hbm_budget, lgf_stream_t stream, lgf_serve
   auto* s = new lgf_server_s();
   s->budget = hbm_budget;
   s->stream = (hipStream_t)stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return LGF_EHIP;
+  }
+  s->planner = std::thread([s] { s->plan_loop(); });
   s->launcher = std::thread([s] { s->launch_loop(); });
   s->completer = std::thread([s] { s->complete_loop(); });
   *out = s;
@@ -389,15 +646,38 @@ lgf_status lgf_server_create(uint64_t hbm_budget, lgf_stream_t stream, lgf_serve
 lgf_status lgf_server_submit(lgf_server_t s, lgf_plan_t p, const double* f, double* u, int64_t* req_id) {
   if (!s || !p || !f || !u || !req_id) return LGF_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
-  lgf_server_s::Req r{s->next_id++, p->p, f, u, std::chrono::steady_clock::now()};
-  if (!s->have_first) {
-    s->first_submit = r.t0;
-    s->have_first = true;
-  }
-  s->state[r.id] = 0;
-  s->queue.push_back(r);
+  lgf_server_s::Req r = s->new_req(f, u);
+  r.plan = p->p;
   *req_id = r.id;
+  s->queue.push_back(std::move(r));
   s->cv.notify_all();
+  return LGF_OK;
+}
+
+lgf_status lgf_server_submit_layout(lgf_server_t s, const int32_t* blocks, const int32_t* levels, int64_t n,
+                                    int32_t N_b, int32_t interp_order, const lgf_options* opt, const double* f,
+                                    double* u, int64_t* req_id) {
+  if (!s || !blocks || n <= 0 || !f || !u || !req_id) return LGF_EINVAL;
+  if (N_b != 8 && N_b != 16) return LGF_ELAYOUT;
+  if (interp_order < 2 || interp_order > N_b) return LGF_ELAYOUT;
+  lgf_options o{};
+  if (opt) o = *opt;
+  if (o.precision != LGF_FP64_PLAIN && o.precision != LGF_FP32_REFINE) return LGF_EINVAL;
+  if (o.dc_iters < 0 || o.dc_iters > 8) return LGF_EINVAL;
+  if (o.base_level != LGF_BASE_SUPER && o.base_level != LGF_BASE_BLOCK) return LGF_EINVAL;
+  if (!validate_layout(blocks, levels, n)) return LGF_ELAYOUT;
+  std::lock_guard<std::mutex> lk(s->mu);
+  lgf_server_s::Req r = s->new_req(f, u);
+  r.blocks.assign(blocks, blocks + 3 * n);
+  r.levels.assign((size_t)n, 0);
+  if (levels) r.levels.assign(levels, levels + n);
+  r.nb = N_b;
+  r.order = interp_order;
+  r.opt = o;
+  r.opt.hbm_budget = 0;
+  *req_id = r.id;
+  s->plan_queue.push_back(std::move(r));
+  s->cv_plan.notify_all();
   return LGF_OK;
 }
 
@@ -406,7 +686,7 @@ lgf_status lgf_server_poll(lgf_server_t s, int64_t req_id, int32_t* done) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->state.find(req_id);
   if (it == s->state.end()) return LGF_EINVAL;
-  if (it->second < 0) return LGF_EHIP;
+  if (it->second < 0) return s->error == LGF_OK ? LGF_EHIP : s->error;
   *done = it->second == 2 ? 1 : 0;
   return LGF_OK;
 }
@@ -414,7 +694,9 @@ lgf_status lgf_server_poll(lgf_server_t s, int64_t req_id, int32_t* done) {
 lgf_status lgf_server_wait_all(lgf_server_t s) {
   if (!s) return LGF_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
-  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight.empty() && s->busy.empty(); });
+  s->cv_done.wait(lk, [&] {
+    return s->plan_queue.empty() && s->queue.empty() && s->inflight.empty() && s->running == 0;
+  });
   return s->error;
 }
 
@@ -441,16 +723,38 @@ lgf_status lgf_server_stats(lgf_server_t s, double* p50_us, double* p99_us, doub
   return LGF_OK;
 }
 
+lgf_status lgf_server_info(lgf_server_t s, lgf_server_memory* out) {
+  if (!s || !out) return LGF_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->reserved_bytes = s->reserved;
+  out->in_use_bytes = s->in_use;
+  out->peak_in_use_bytes = s->peak_in_use;
+  out->slots = s->slots;
+  out->peak_slots = s->peak_slots;
+  out->binds = s->binds;
+  out->plans_cached = (int64_t)s->plans.size();
+  out->plan_hits = s->plan_hits;
+  out->plan_misses = s->plan_misses;
+  out->plan_ms_total = s->plan_ms_total;
+  out->plan_ms_max = s->plan_ms_max;
+  return LGF_OK;
+}
+
 lgf_status lgf_server_destroy(lgf_server_t s) {
   if (!s) return LGF_EINVAL;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
     s->cv.notify_all();
+    s->cv_plan.notify_all();
     s->cv_done.notify_all();
   }
+  s->planner.join();
   s->launcher.join();
   s->completer.join();
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->plans) lgf::plan_free(kv.second.plan);
+  for (auto& R : s->regions) (void)hipFree(R.base);
   delete s;
   return LGF_OK;
 }

@@ -225,6 +225,17 @@ struct OpItem {
 };
 
 // ----------------------------------------------------------------------------- launchers
+// workspace binding: img[idx[i]] += delta for i < n (8-byte words); fill of up to kFillMax
+// device ranges (16-byte multiples at 16-byte aligned offsets from base) with a 32-bit pattern
+constexpr int kFillMax = 16;
+struct FillRanges {
+  int32_t n;
+  int32_t pad;
+  int64_t off[kFillMax];
+  int64_t bytes[kFillMax];
+};
+hipError_t launch_relocate(uint64_t* img, const uint32_t* idx, int64_t n, uint64_t delta, hipStream_t st);
+hipError_t launch_fill(uint8_t* base, const FillRanges& r, uint32_t pattern, hipStream_t st);
 int quad_nodes();
 // op 0: Laplacian (1 -> 1 component), 1: gradient (1 -> 3), 2: curl (3 -> 3); components of
 // u and out are n * nb^3 apart

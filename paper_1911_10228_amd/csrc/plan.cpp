@@ -12,6 +12,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -247,6 +248,7 @@ void* fake_alloc(Plan* p, size_t bytes) {
   return q;
 }
 
+// Constants of the plan (device memory it owns for its lifetime; fake ranges in a dry build).
 struct Arena {
   Plan* p;
   uint64_t budget;
@@ -264,6 +266,25 @@ struct Arena {
     }
     p->bytes += (int64_t)bytes;
     return hipSuccess;
+  }
+};
+
+// The solve workspace: virtual addresses kVBase + offset, 256-byte aligned (see Binding).
+struct VArena {
+  Plan* p;
+  hipError_t alloc(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) return hipSuccess;
+    const int64_t off = (p->vnext + 255) / 256 * 256;
+    if (off + (int64_t)bytes >= ((int64_t)1 << kVTagShift)) return hipErrorOutOfMemory;
+    *ptr = (void*)(uintptr_t)(kVBase + (uint64_t)off);
+    p->ranges.push_back({(uintptr_t)*ptr, bytes});
+    p->vnext = off + (int64_t)bytes;
+    return hipSuccess;
+  }
+  // the range reads as zero in every solve (cleared when a binding takes the plan's items)
+  void zero(const void* ptr, size_t bytes) {
+    if (bytes) p->zero.push_back({(int64_t)((uint64_t)(uintptr_t)ptr - kVBase), (int64_t)bytes});
   }
 };
 
@@ -447,8 +468,10 @@ struct SlotCounts {
   int64_t nsup_src[2], nsup_tgt[2];    // super-block spectra slots
 };
 
+// Checks every item of a step (slots in range, pointers inside the plan's ranges) and records, in
+// *rel, the 8-byte words of the item image (starting at image) that hold a workspace address.
 bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* items, int count, int64_t n,
-                   const SlotCounts& sc, std::string* err) {
+                   const SlotCounts& sc, std::string* err, const uint8_t* image, std::set<uint32_t>* rel) {
   const int nb = p->nb;
   const size_t N3 = (size_t)nb * nb * nb;
   const size_t S = (size_t)(2 * nb) * (2 * nb) * (nb + 1);
@@ -465,16 +488,23 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
     return false;
   };
   auto off_ok = [&](int64_t o) { return o >= 0 && o % (int64_t)N3 == 0 && o + (int64_t)N3 <= nmax; };
+  // a pointer field: inside the plan's ranges; a workspace address is recorded for relocation
+  auto rg = [&](const auto& field, size_t len) {
+    const uint64_t v = (uint64_t)(uintptr_t)field;
+    if ((v >> kVTagShift) == (kVBase >> kVTagShift))
+      rel->insert((uint32_t)(((const uint8_t*)&field - image) / 8));
+    return in_ranges(p, (const void*)field, len);
+  };
   for (int i = 0; i < count; ++i) {
     switch (kind) {
       case K_FWD: {
         const auto& it = ((const FftFwdItem<double>*)items)[i];
-        if (!in_ranges(p, it.src, N3 * es) || !in_ranges(p, it.dst, 2 * S * es)) return bad("fft_fwd", i);
+        if (!rg(it.src, N3 * es) || !rg(it.dst, 2 * S * es)) return bad("fft_fwd", i);
         break;
       }
       case K_INV: {
         const auto& it = ((const FftInvItem<double>*)items)[i];
-        if (!in_ranges(p, it.src, 2 * S * es) || !in_ranges(p, it.dst, N3 * es)) return bad("fft_inv", i);
+        if (!rg(it.src, 2 * S * es) || !rg(it.dst, N3 * es)) return bad("fft_inv", i);
         break;
       }
       case K_MAC: {
@@ -488,16 +518,16 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
           for (int q = 0; q < kMacL; ++q)
             if (it.tgt[r][q] < -1 || it.tgt[r][q] >= ntgt[t] || (q >= w && it.tgt[r][q] != -1))
               return bad("mac target slot", i);
-        if (!in_ranges(p, it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("mac source arena", i);
-        if (ntgt[t] && !in_ranges(p, it.uhat, ntgt[t] * 2 * S * es)) return bad("mac target arena", i);
-        if (!in_ranges(p, it.kptr, 343 * sizeof(void*))) return bad("mac kernel table", i);
+        if (!rg(it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("mac source arena", i);
+        if (ntgt[t] && !rg(it.uhat, ntgt[t] * 2 * S * es)) return bad("mac target arena", i);
+        if (!rg(it.kptr, 343 * sizeof(void*))) return bad("mac kernel table", i);
         break;
       }
       case K_ANTERP: {
         const auto& it = ((const AnterpItem<double, double>*)items)[i];
-        if (!in_ranges(p, it.dst, N3 * esp)) return bad("anterp parent", i);
+        if (!rg(it.dst, N3 * esp)) return bad("anterp parent", i);
         for (int c = 0; c < 8; ++c) {
-          if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("anterp child", i);
+          if (it.child[c] && !rg(it.child[c], N3 * esc)) return bad("anterp child", i);
           if (it.child_in[c] != -1 && (it.child[c] || !child_in_ok || !off_ok(it.child_in[c])))
             return bad("anterp child offset", i);
         }
@@ -505,48 +535,48 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_INTERP: {
         const auto& it = ((const InterpItem<double, double>*)items)[i];
-        if (!in_ranges(p, it.child, N3 * esc) || !in_ranges(p, it.parent, N3 * esp)) return bad("interp", i);
+        if (!rg(it.child, N3 * esc) || !rg(it.parent, N3 * esp)) return bad("interp", i);
         if (it.octant < 0 || it.octant > 7) return bad("interp octant", i);
         break;
       }
       case K_COMBINE: {
         const auto& it = ((const CombineItem<double>*)items)[i];
-        if (it.dst_d ? !in_ranges(p, it.dst_d, N3 * 8) : !off_ok(it.dst_out)) return bad("combine dst", i);
-        if (it.v && !in_ranges(p, it.v, N3 * es)) return bad("combine v", i);
-        if (it.far && !in_ranges(p, it.far, N3 * es)) return bad("combine far", i);
-        if (it.base && !in_ranges(p, it.base, N3 * 8)) return bad("combine base", i);
+        if (it.dst_d ? !rg(it.dst_d, N3 * 8) : !off_ok(it.dst_out)) return bad("combine dst", i);
+        if (it.v && !rg(it.v, N3 * es)) return bad("combine v", i);
+        if (it.far && !rg(it.far, N3 * es)) return bad("combine far", i);
+        if (it.base && !rg(it.base, N3 * 8)) return bad("combine base", i);
         break;
       }
       case K_CONVERT: {
         const auto& it = ((const ConvertItem<double>*)items)[i];
-        if (!in_ranges(p, it.dst, N3 * es)) return bad("convert dst", i);
-        if (it.src ? !in_ranges(p, it.src, N3 * 8) : !off_ok(it.src_in)) return bad("convert src", i);
+        if (!rg(it.dst, N3 * es)) return bad("convert dst", i);
+        if (it.src ? !rg(it.src, N3 * 8) : !off_ok(it.src_in)) return bad("convert src", i);
         break;
       }
       case K_COARSEN: {
         const auto& it = ((const CoarsenItem*)items)[i];
-        if (!in_ranges(p, it.dst, N3 * 8)) return bad("coarsen dst", i);
+        if (!rg(it.dst, N3 * 8)) return bad("coarsen dst", i);
         for (int c = 0; c < 8; ++c)
-          if (it.child[c] ? !in_ranges(p, it.child[c], N3 * 8) : !off_ok(it.child_in[c])) return bad("coarsen child", i);
+          if (it.child[c] ? !rg(it.child[c], N3 * 8) : !off_ok(it.child_in[c])) return bad("coarsen child", i);
         break;
       }
       case K_REFINE: {
         const auto& it = ((const RefineItem*)items)[i];
-        if (!in_ranges(p, it.jw, N3 * 8) || !in_ranges(p, it.parent_w, N3 * 8)) return bad("refine", i);
+        if (!rg(it.jw, N3 * 8) || !rg(it.parent_w, N3 * 8)) return bad("refine", i);
         break;
       }
       case K_CORRECT: {
         const auto& it = ((const CorrectItem<double>*)items)[i];
-        if (!in_ranges(p, it.g, N3 * es) || !in_ranges(p, it.jw, N3 * 8) || !in_ranges(p, it.parent_w, N3 * 8))
+        if (!rg(it.g, N3 * es) || !rg(it.jw, N3 * 8) || !rg(it.parent_w, N3 * 8))
           return bad("correct", i);
-        if (it.f ? !in_ranges(p, it.f, N3 * 8) : !off_ok(it.f_in)) return bad("correct f", i);
+        if (it.f ? !rg(it.f, N3 * 8) : !off_ok(it.f_in)) return bad("correct f", i);
         for (int f = 0; f < 6; ++f)
-          if (it.nbr[f] && !in_ranges(p, it.nbr[f], N3 * 8)) return bad("correct neighbour", i);
+          if (it.nbr[f] && !rg(it.nbr[f], N3 * 8)) return bad("correct neighbour", i);
         break;
       }
       case K_RESIDUAL: {
         const auto& it = ((const ResidualItem*)items)[i];
-        if ((it.r && !in_ranges(p, it.r, N3 * 8)) || (it.conv && !in_ranges(p, it.conv, N3 * 4)) || !off_ok(it.off))
+        if ((it.r && !rg(it.r, N3 * 8)) || (it.conv && !rg(it.conv, N3 * 4)) || !off_ok(it.off))
           return bad("residual", i);
         for (int f = 0; f < 6; ++f)
           if (it.nbr_off[f] != -1 && !off_ok(it.nbr_off[f])) return bad("residual neighbour", i);
@@ -554,9 +584,9 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_SUP_FWD: {
         const auto& it = ((const SuperFwdItem<double>*)items)[i];
-        if (!in_ranges(p, it.dst, 2 * S2 * es) || !in_ranges(p, it.tmp, 2 * TMP2 * es)) return bad("super fwd", i);
+        if (!rg(it.dst, 2 * S2 * es) || !rg(it.tmp, 2 * TMP2 * es)) return bad("super fwd", i);
         for (int c = 0; c < 8; ++c) {
-          if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("super fwd child", i);
+          if (it.child[c] && !rg(it.child[c], N3 * esc)) return bad("super fwd child", i);
           if (it.child_in[c] != -1 && (it.child[c] || !child_in_ok || !off_ok(it.child_in[c])))
             return bad("super fwd child offset", i);
         }
@@ -564,9 +594,9 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_SUP_INV: {
         const auto& it = ((const SuperInvItem<double>*)items)[i];
-        if (!in_ranges(p, it.src, 2 * S2 * es) || !in_ranges(p, it.tmp, 2 * TMP2 * es)) return bad("super inv", i);
+        if (!rg(it.src, 2 * S2 * es) || !rg(it.tmp, 2 * TMP2 * es)) return bad("super inv", i);
         for (int c = 0; c < 8; ++c)
-          if (it.child[c] && !in_ranges(p, it.child[c], N3 * esc)) return bad("super inv child", i);
+          if (it.child[c] && !rg(it.child[c], N3 * esc)) return bad("super inv child", i);
         break;
       }
       case K_NEAR_MAC: {
@@ -593,9 +623,9 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
               if (it.tgt[r][q] < -1 || it.tgt[r][q] >= sc.nsup_tgt[t]) return bad("near tile target slot", i);
           // 16-byte copies straight into LDS: the arena must be 16-byte aligned
           if ((uintptr_t)it.fhat % 16) return bad("near pipelined tile alignment", i);
-          if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
-          if (sc.nsup_tgt[t] && !in_ranges(p, it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
-          if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
+          if (!rg(it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
+          if (sc.nsup_tgt[t] && !rg(it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
+          if (!rg(it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
           break;
         }
         if (mode > kNearTiled) {
@@ -607,9 +637,9 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
           for (int r = 0; r < kTileRowsMax; ++r)
             for (int q = 0; q < kMacL; ++q)
               if (it.tgt[r][q] < -1 || it.tgt[r][q] >= sc.nsup_tgt[t]) return bad("near tile target slot", i);
-          if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
-          if (sc.nsup_tgt[t] && !in_ranges(p, it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
-          if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
+          if (!rg(it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
+          if (sc.nsup_tgt[t] && !rg(it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
+          if (!rg(it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
           break;
         }
         if (mode != 2 && mode != 4 && mode != 8) return bad("near row width", i);
@@ -622,9 +652,9 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
         }
         for (int q = 0; q < kMacL; ++q)
           if (it.tgt[q] < -1 || it.tgt[q] >= sc.nsup_tgt[t]) return bad("near target slot", i);
-        if (!in_ranges(p, it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
-        if (sc.nsup_tgt[t] && !in_ranges(p, it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
-        if (!in_ranges(p, it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
+        if (!rg(it.fhat, (sc.nsup_src[t] + 1) * 2 * S2 * es)) return bad("near source arena", i);
+        if (sc.nsup_tgt[t] && !rg(it.uhat, sc.nsup_tgt[t] * 2 * S2 * es)) return bad("near target arena", i);
+        if (!rg(it.kptr, 27 * sizeof(void*))) return bad("near kernel table", i);
         break;
       }
       default:
@@ -652,7 +682,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   // coarse octree levels run in FP64 except in a correction plan (all FP32)
   auto ty_of = [&](int k) { return (k == 0 || p->all_fp32) ? tyb : TY_F64; };
   auto es = [](int ty) { return ty == TY_F32 ? (int64_t)4 : (int64_t)8; };
-  Arena ar{p, budget};
+  Arena ar{p, budget};                 // constants
+  VArena va{p};                        // solve workspace (virtual addresses)
 
   std::vector<std::vector<int>> ids(LR);
   for (int64_t i = 0; i < n; ++i) ids[lev[i]].push_back((int)i);
@@ -801,24 +832,24 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       }
   }
 
-  // arenas
+  // workspace arenas
   void* tmp = nullptr;
   if (LR > 1) {
-    LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
+    LGF_HIP_CHECK(va.alloc(&tmp, n * N3 * sizeof(double)));
     p->fe = (double*)tmp;
-    LGF_HIP_CHECK(ar.alloc(&p->jw, n * N3 * sizeof(double)));
-    LGF_HIP_CHECK(ar.alloc(&p->w, n * N3 * sizeof(double)));
+    LGF_HIP_CHECK(va.alloc(&p->jw, n * N3 * sizeof(double)));
+    LGF_HIP_CHECK(va.alloc(&p->w, n * N3 * sizeof(double)));
   }
   uint8_t *srcA[2], *fhatA[2], *uhatA[2], *vA[2];
   for (int ty = 0; ty < 2; ++ty) {
     void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
-    LGF_HIP_CHECK(ar.alloc(&a, nsrc[ty] * N3 * es(ty)));
+    LGF_HIP_CHECK(va.alloc(&a, nsrc[ty] * N3 * es(ty)));
     // one extra all-zero spectrum (slot nsrc[ty]) stands in for absent sources in MAC tiles;
-    // the whole arena starts zeroed (plan time, outside any captured graph)
-    LGF_HIP_CHECK(ar.alloc(&b, (nsrc[ty] + 1) * S * 2 * es(ty)));
-    if (!p->dry) LGF_HIP_CHECK(hipMemset(b, 0, (nsrc[ty] + 1) * S * 2 * es(ty)));
-    LGF_HIP_CHECK(ar.alloc(&c, ntgt[ty] * S * 2 * es(ty)));
-    LGF_HIP_CHECK(ar.alloc(&d, ntgt[ty] * N3 * es(ty)));
+    // the whole source-spectrum arena reads as zero before the pass writes it
+    LGF_HIP_CHECK(va.alloc(&b, (nsrc[ty] + 1) * S * 2 * es(ty)));
+    va.zero(b, (nsrc[ty] + 1) * S * 2 * es(ty));
+    LGF_HIP_CHECK(va.alloc(&c, ntgt[ty] * S * 2 * es(ty)));
+    LGF_HIP_CHECK(va.alloc(&d, ntgt[ty] * N3 * es(ty)));
     srcA[ty] = (uint8_t*)a; fhatA[ty] = (uint8_t*)b; uhatA[ty] = (uint8_t*)c; vA[ty] = (uint8_t*)d;
   }
   const int64_t S2 = spec_size(nb, -1);
@@ -828,9 +859,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
     if (!nsup_tgt[a]) continue;
     const int64_t ea = a == 0 ? 4 : 8;
     void *b = nullptr, *c = nullptr;
-    LGF_HIP_CHECK(ar.alloc(&b, (nsup_src[a] + 1) * S2 * 2 * ea));   // last slot: zero spectrum
-    if (!p->dry) LGF_HIP_CHECK(hipMemset(b, 0, (nsup_src[a] + 1) * S2 * 2 * ea));
-    LGF_HIP_CHECK(ar.alloc(&c, nsup_tgt[a] * S2 * 2 * ea));
+    LGF_HIP_CHECK(va.alloc(&b, (nsup_src[a] + 1) * S2 * 2 * ea));   // last slot: zero spectrum
+    va.zero((uint8_t*)b + nsup_src[a] * S2 * 2 * ea, S2 * 2 * ea);
+    LGF_HIP_CHECK(va.alloc(&c, nsup_tgt[a] * S2 * 2 * ea));
     sfhA[a] = (uint8_t*)b;
     suhA[a] = (uint8_t*)c;
   }
@@ -846,14 +877,15 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   // instead of after their join.
   uint8_t* farA = nullptr;
   if (p->super_base && ntgt[tyb]) {
-    LGF_HIP_CHECK(ar.alloc(&tmp, ntgt[tyb] * N3 * es(tyb)));
+    LGF_HIP_CHECK(va.alloc(&tmp, ntgt[tyb] * N3 * es(tyb)));
     farA = (uint8_t*)tmp;
   }
   std::vector<char> far_used(ntgt[tyb], 0);
   if (p->fp32 && p->dc_iters > 0 && LR > 1) {      // r of the finer levels' blocks (FP64)
-    LGF_HIP_CHECK(ar.alloc(&tmp, n * N3 * sizeof(double)));
+    LGF_HIP_CHECK(va.alloc(&tmp, n * N3 * sizeof(double)));
     p->r = (double*)tmp;
   }
+  p->ws_bytes = p->vnext;
   {
     const std::vector<double> W = lagrange_matrix(nb, p->n_i), W3 = refine_table(nb);
     // the refinement kernel stages nb/2 + 2 parent cells per axis from the stencil start of
@@ -1409,19 +1441,47 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   {
     SlotCounts sc{{nsrc[0], nsrc[1]}, {ntgt[0], ntgt[1]}, {nsup_src[0], nsup_src[1]},
                   {nsup_tgt[0], nsup_tgt[1]}};
+    std::set<uint32_t> rel;
+    const uint8_t* img = hi.buf.data();
     for (const auto* list : {&steps, &rsteps, &alt_steps})
       for (const PendingStep& st : *list)
-        if (!validate_step(p, st.kind, st.ty, st.mode, hi.buf.data() + st.off, st.count, n, sc, err))
+        if (!validate_step(p, st.kind, st.ty, st.mode, img + st.off, st.count, n, sc, err, img, &rel))
           return hipErrorInvalidValue;
     if (corr_conv.count &&
-        !validate_step(p, corr_conv.kind, corr_conv.ty, 0, hi.buf.data() + corr_conv.off, corr_conv.count, n, sc, err))
+        !validate_step(p, corr_conv.kind, corr_conv.ty, 0, img + corr_conv.off, corr_conv.count, n, sc, err, img, &rel))
       return hipErrorInvalidValue;
+    // every word of the image that carries the workspace tag must be a pointer field the checks
+    // above recorded (else relocation would miss it, or the tag would hit a non-pointer)
+    hi.buf.resize((hi.buf.size() + 7) / 8 * 8);
+    int64_t tagged = 0;
+    for (size_t w = 0; w < hi.buf.size() / 8; ++w) {
+      uint64_t v;
+      std::memcpy(&v, hi.buf.data() + 8 * w, 8);
+      if ((v >> kVTagShift) != (kVBase >> kVTagShift)) continue;
+      ++tagged;
+      if (!rel.count((uint32_t)w) || v - kVBase >= (uint64_t)p->vnext) {
+        if (err) *err = "internal: item word " + std::to_string(w) + " holds an unrecorded workspace address";
+        return hipErrorInvalidValue;
+      }
+    }
+    if (tagged != (int64_t)rel.size() || hi.buf.size() / 8 >= ((size_t)1 << 32)) {
+      if (err) *err = "internal: relocation table does not match the item image";
+      return hipErrorInvalidValue;
+    }
+    p->relocs.assign(rel.begin(), rel.end());
   }
-  void* d_items = nullptr;
-  LGF_HIP_CHECK(ar.alloc(&d_items, hi.buf.size()));
+  p->h_items = hi.buf;
+  LGF_HIP_CHECK(ar.alloc(&p->d_items, hi.buf.size()));
   if (!hi.buf.empty() && !p->dry)
-    LGF_HIP_CHECK(hipMemcpy(d_items, hi.buf.data(), hi.buf.size(), hipMemcpyHostToDevice));
-  p->d_items = d_items;
+    LGF_HIP_CHECK(hipMemcpy(p->d_items, hi.buf.data(), hi.buf.size(), hipMemcpyHostToDevice));
+  {
+    void* d = nullptr;
+    LGF_HIP_CHECK(ar.alloc(&d, p->relocs.size() * sizeof(uint32_t)));
+    p->d_relocs = (uint32_t*)d;
+    if (!p->relocs.empty() && !p->dry)
+      LGF_HIP_CHECK(hipMemcpy(p->d_relocs, p->relocs.data(), p->relocs.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+  }
   {
     // block table of the forward operators (every plan, every block)
     std::vector<OpItem> ops(n);
@@ -1442,8 +1502,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   }
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
     for (const PendingStep& s : in)
-      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (const uint8_t*)d_items + s.off, s.count, s.w, s.work,
-                     s.mode, s.chain});
+      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (int64_t)s.off, s.count, s.w, s.work, s.mode, s.chain});
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
@@ -1472,7 +1531,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 
 }  // namespace
 
-hipError_t plan_autotune(Plan* p, hipStream_t st);
+hipError_t plan_autotune(Plan* p, Binding* b, hipStream_t st);
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
                       bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err, bool dry,
@@ -1516,17 +1575,44 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
     q->LR = LR;
     p->corr = q;
     e = build_plan(q, coords, lev, budget, err);
-    if (e == hipSuccess && autotune && !dry) e = plan_autotune(q, q->ctx->stream);
-    // the residual writes into the correction plan's buffers
+    // the residual writes into the correction plan's buffers; its workspace continues the same
+    // virtual range
     p->ranges = q->ranges;
     p->next_fake = q->next_fake;
+    p->vnext = q->vnext;
   }
   if (e == hipSuccess) {
     // one HBM budget for both plans (1 byte: already exhausted)
     const uint64_t used = p->corr ? (uint64_t)p->corr->bytes : 0;
     e = build_plan(p, coords, lev, budget == 0 ? 0 : budget > used ? budget - used : 1, err);
   }
-  if (e == hipSuccess && autotune && !dry) e = plan_autotune(p, p->ctx->stream);
+  if (e == hipSuccess) {
+    // binding layout: [workspace of both plans | main item image | correction item image]
+    auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
+    p->items_at = al(p->ws_bytes);
+    p->bind_bytes = p->items_at + al((int64_t)p->h_items.size());
+    if (p->corr) {
+      p->corr->items_at = p->bind_bytes;
+      p->bind_bytes += al((int64_t)p->corr->h_items.size());
+      p->corr->bind_bytes = p->bind_bytes;
+    }
+    p->budget = budget;
+    // a solve needs one binding next to the constants
+    const int64_t cst = p->bytes + (p->corr ? p->corr->bytes : 0);
+    if (budget && (uint64_t)(cst + p->bind_bytes) > budget) e = hipErrorOutOfMemory;
+  }
+  if (e == hipSuccess && autotune && !dry) {
+    // time the launch shapes on a binding of the plan's own, kept for its first solve
+    Binding* b = nullptr;
+    e = plan_binding(p, p->ctx->stream, 0, &b);
+    if (e == hipSuccess && p->corr) e = plan_autotune(p->corr, b, p->ctx->stream);
+    if (e == hipSuccess) e = plan_autotune(p, b, p->ctx->stream);
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> lk(p->bmu);
+      p->bindings.erase({p->ctx->stream, 0});
+      p->idle.push_back(b);
+    }
+  }
   if (e != hipSuccess) {
     plan_free(p);
     return e;
@@ -1576,10 +1662,109 @@ hipError_t plan_set_near_shape(Plan* p, int shape) {
 void plan_free(Plan* p) {
   if (!p) return;
   plan_free(p->corr);
-  if (!p->dry) graph_forget(p);
-  if (!p->dry)
+  if (!p->dry) {
+    graph_forget(p);
+    // bindings may still be in use by work the caller enqueued
+    (void)hipDeviceSynchronize();
+    for (auto& kv : p->bindings) p->idle.push_back(kv.second);
+    for (Binding* b : p->idle) {
+      if (b->owned) (void)hipFree(b->base);
+      delete b;
+    }
     for (void* a : p->allocs) (void)hipFree(a);
+  }
   delete p;
+}
+
+// ----------------------------------------------------------------------------- bindings
+namespace {
+std::atomic<bool> g_poison{false};
+}  // namespace
+
+void set_poison(bool on) { g_poison = on; }
+
+hipError_t bind(Plan* p, Binding* b, hipStream_t st, bool force) {
+  if (p->dry || !b || !b->base) return hipErrorInvalidValue;
+  if (b->bytes < p->bind_bytes) return hipErrorInvalidValue;
+  if (b->plan == p && !force && !g_poison) return hipSuccess;
+  b->plan = nullptr;
+  const uint64_t delta = (uint64_t)(uintptr_t)b->base - kVBase;
+  for (Plan* q : {p->corr, p}) {
+    if (!q || q->h_items.empty()) continue;
+    uint8_t* dst = b->base + q->items_at;
+    LGF_HIP_CHECK(hipMemcpyAsync(dst, q->d_items, q->h_items.size(), hipMemcpyDeviceToDevice, st));
+    LGF_HIP_CHECK(launch_relocate((uint64_t*)dst, q->d_relocs, (int64_t)q->relocs.size(), delta, st));
+  }
+  if (g_poison) {
+    FillRanges all{};
+    all.n = 1;
+    all.off[0] = 0;
+    all.bytes[0] = p->ws_bytes / 16 * 16;
+    LGF_HIP_CHECK(launch_fill(b->base, all, 0xFFFFFFFFu, st));
+  }
+  FillRanges z{};
+  for (Plan* q : {p->corr, p})
+    if (q)
+      for (const auto& r : q->zero) {
+        if (z.n == kFillMax) {
+          LGF_HIP_CHECK(launch_fill(b->base, z, 0u, st));
+          z.n = 0;
+        }
+        z.off[z.n] = r.first;
+        z.bytes[z.n] = r.second;
+        ++z.n;
+      }
+  LGF_HIP_CHECK(launch_fill(b->base, z, 0u, st));
+  b->plan = p;
+  return hipSuccess;
+}
+
+hipError_t plan_binding(Plan* p, hipStream_t st, int k, Binding** out) {
+  std::lock_guard<std::mutex> lk(p->bmu);
+  const auto key = std::make_pair(st, k);
+  auto it = p->bindings.find(key);
+  if (it != p->bindings.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  Binding* b = nullptr;
+  if (!p->idle.empty()) {
+    b = p->idle.back();
+    p->idle.pop_back();
+  } else {
+    const int64_t cst = p->bytes + (p->corr ? p->corr->bytes : 0);
+    if (p->budget && (uint64_t)(cst + p->bound_bytes + p->bind_bytes) > p->budget) return hipErrorOutOfMemory;
+    void* base = nullptr;
+    LGF_HIP_CHECK(hipMalloc(&base, p->bind_bytes));
+    b = new Binding{(uint8_t*)base, p->bind_bytes, nullptr, true};
+    p->bound_bytes += p->bind_bytes;
+  }
+  hipError_t e = bind(p, b, st);
+  if (e != hipSuccess) {
+    p->idle.push_back(b);
+    return e;
+  }
+  p->bindings[key] = b;
+  *out = b;
+  return hipSuccess;
+}
+
+hipError_t plan_trim(Plan* p) {
+  std::lock_guard<std::mutex> lk(p->bmu);
+  if (p->bindings.empty() && p->idle.empty()) return hipSuccess;
+  LGF_HIP_CHECK(hipDeviceSynchronize());
+  graph_forget(p);
+  for (auto& kv : p->bindings) p->idle.push_back(kv.second);
+  p->bindings.clear();
+  for (Binding* b : p->idle) {
+    if (b->owned) {
+      (void)hipFree(b->base);
+      p->bound_bytes -= b->bytes;
+    }
+    delete b;
+  }
+  p->idle.clear();
+  return hipSuccess;
 }
 
 // ----------------------------------------------------------------------------- execution
@@ -1717,7 +1902,7 @@ hipError_t stream_after(hipStream_t dst, hipStream_t src, size_t ev_index) {
 }
 }  // namespace
 
-hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st) {
+hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st, bool one_stream) {
   std::vector<Ref> refs;
   for (size_t i = 0; i < m.size(); ++i) {
     const Plan* q = m[i].p;
@@ -1734,12 +1919,12 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
   bool prof;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    prof = g_prof_on;
+    prof = g_prof_on && !one_stream;
   }
   // per-launch timing (and LGF_NO_FORK) keeps one stream, so that kernel times are not shared
   static const bool no_fork = std::getenv("LGF_NO_FORK") != nullptr;
   std::set<int> base_chain;                      // levels with a base-level super-block path
-  if (!prof && !no_fork)
+  if (!prof && !no_fork && !one_stream)
     for (const Ref& r : refs)
       if (chain_of(r) == 1) base_chain.insert(r.l);
   hipStream_t aux = nullptr;
@@ -1758,7 +1943,7 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
            refs[b].ty == refs[a].ty && refs[b].mode == refs[a].mode) {
       const Member& mm = m[refs[b].member];
       WorkSet& ws = t.s[t.n++];
-      ws.items = refs[b].step->items;
+      ws.items = mm.b->base + mm.p->items_at + refs[b].step->items;
       ws.count = refs[b].step->count;
       ws.wg_begin = 0;
       ws.aux = mm.accumulate ? kAuxAccumulate : 0;
@@ -1798,8 +1983,10 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
   return hipSuccess;
 }
 
-hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
-  LGF_HIP_CHECK(run_steps(m, false, st));
+hipError_t solve_members(const std::vector<Member>& m, hipStream_t st, bool one_stream) {
+  for (const Member& x : m)
+    if (!x.b || x.b->plan != x.p) return hipErrorInvalidValue;     // not bound to the plan
+  LGF_HIP_CHECK(run_steps(m, false, st, one_stream));
   int iters = 0;
   for (const Member& x : m) iters = std::max(iters, x.p->dc_iters);
   for (int it = 0; it < iters; ++it) {
@@ -1807,10 +1994,12 @@ hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
     for (const Member& x : m)
       if (x.p->dc_iters > it) {
         act.push_back(x);
-        corr.push_back({x.p->corr, x.p->r, x.out, true});
+        // the correction pass reads r (finer levels) from the binding; the residual writes its
+        // base-level leaf sources there directly
+        corr.push_back({x.p->corr, x.p->r ? (const double*)in_binding(x.b, x.p->r) : nullptr, x.out, true, x.b});
       }
-    LGF_HIP_CHECK(run_steps(act, true, st));      // r = f - L u
-    LGF_HIP_CHECK(run_steps(corr, false, st));    // u += S(r): the pass's final combine adds into u
+    LGF_HIP_CHECK(run_steps(act, true, st, one_stream));      // r = f - L u
+    LGF_HIP_CHECK(run_steps(corr, false, st, one_stream));    // u += S(r): the pass's final combine adds into u
   }
   return hipSuccess;
 }
@@ -1818,7 +2007,7 @@ hipError_t solve_members(const std::vector<Member>& m, hipStream_t st) {
 // ----------------------------------------------------------------------------- graphs
 namespace {
 struct GraphKey {
-  std::vector<std::tuple<Plan*, const double*, double*>> m;
+  std::vector<std::tuple<Plan*, Binding*, const double*, double*>> m;
   bool operator<(const GraphKey& o) const { return m < o.m; }
 };
 std::mutex g_graph_mu;
@@ -1853,7 +2042,7 @@ hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st) {
   }
   if (!st || prof || !graphs_enabled()) return solve_members(m, st);
   GraphKey key;
-  for (const Member& x : m) key.m.emplace_back(x.p, x.in, x.out);
+  for (const Member& x : m) key.m.emplace_back(x.p, x.b, x.in, x.out);
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
@@ -1920,8 +2109,10 @@ void tune_store(const std::array<int64_t, 3>& k, int mode) {
 
 constexpr int kTuneReps = 5;             // timed launches per candidate (the median counts)
 
-hipError_t plan_autotune(Plan* p, hipStream_t st) {
+hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  // the candidates run on the plan's items relocated into bd (p or p's correction plan)
+  const uint8_t* img = bd->base + p->items_at;
   tune_load();
   static const bool verbose = std::getenv("LGF_TUNE_VERBOSE") != nullptr;   // candidate times on stderr
   hipEvent_t a, b;
@@ -1949,7 +2140,7 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
           SetTable tab;
           tab.n = 1;
           tab.pad = 0;
-          tab.s[0] = WorkSet{s.items, 0, s.count, 0, nullptr, nullptr, s.w};
+          tab.s[0] = WorkSet{img + s.items, 0, s.count, 0, nullptr, nullptr, s.w};
           LGF_HIP_CHECK(hipEventRecord(a, st));
           LGF_HIP_CHECK(launch_typed(K_MAC, s.ty, p->nb, tab, st, cand[c] | half));
           LGF_HIP_CHECK(hipEventRecord(b, st));
@@ -2006,7 +2197,7 @@ hipError_t plan_autotune(Plan* p, hipStream_t st) {
         SetTable tab;
         tab.n = 1;
         tab.pad = 0;
-        tab.s[0] = WorkSet{cands[c].items, 0, cands[c].count, 0, nullptr, nullptr, cands[c].w};
+        tab.s[0] = WorkSet{img + cands[c].items, 0, cands[c].count, 0, nullptr, nullptr, cands[c].w};
         LGF_HIP_CHECK(hipEventRecord(a, st));
         LGF_HIP_CHECK(launch_typed(cands[c].kind, cands[c].ty, p->nb, tab, st, cands[c].mode));
         LGF_HIP_CHECK(hipEventRecord(b, st));

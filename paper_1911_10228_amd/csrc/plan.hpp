@@ -52,7 +52,7 @@ struct Step {
   int l, phase, sub;                   // ordering key: refinement level, phase, sub-step
   int kind;
   int ty;                              // element type: 0 FP32, 1 FP64, 2 FP32 child / FP64 parent
-  const void* items;                   // device pointer into the plan's item buffer
+  int64_t items;                       // byte offset of the step's items in the plan's item image
   int32_t count;
   const double* w;                     // weight table for the kernel (or nullptr)
   int64_t work;                        // MAC: block interactions in the step (for flop counts)
@@ -66,6 +66,26 @@ struct Step {
 void profile_enable(bool on);
 struct ProfileEntry { int kind, ty, nb; int64_t launches; double ms; int64_t work; };
 hipError_t profile_collect(std::vector<ProfileEntry>* out);
+
+// ----------------------------------------------------------------------------- workspace
+// A solve's buffers (source blocks and spectra, target spectra and fields, the coarsened source,
+// J w, w, the residual) form the plan's workspace.  Work items address it at virtual addresses
+// kVBase + offset; before a solve the items are copied into a Binding -- a device range holding
+// [workspace | item images] -- and every virtual pointer in them is moved by (base - kVBase).
+// So a plan holds only its layout tables and constants, and any number of solves of one plan can
+// run at once on distinct bindings.  The tag in the top 16 bits cannot occur in a non-pointer
+// item field (slot indices, counts, masks, offsets below 2^40, doubles of moderate size), which
+// the plan build checks by scanning every item word against the pointer fields it relocates.
+constexpr uint64_t kVBase = 0x5A5A000000000000ull;
+constexpr int kVTagShift = 48;
+
+struct Plan;
+struct Binding {
+  uint8_t* base = nullptr;             // device range, 256-byte aligned
+  int64_t bytes = 0;                   // capacity
+  const Plan* plan = nullptr;          // plan whose items are relocated here (nullptr: none)
+  bool owned = false;                  // allocated with hipMalloc by the plan (freed with it)
+};
 
 struct Plan {
   int nb = 0, n_i = 0, LR = 0, Kmax = 0;
@@ -95,9 +115,27 @@ struct Plan {
   int64_t conv_idx = -1;
   Step conv_corr{};
 
-  // owned device memory
+  // owned device memory (constants: weight tables, the item template, relocation table, the
+  // forward operators' block table)
   std::vector<void*> allocs;
-  int64_t bytes = 0;
+  int64_t bytes = 0;                   // constant bytes
+  // workspace (virtual addresses, see Binding); the correction plan's workspace comes first in
+  // the same virtual range, so one binding serves both
+  int64_t vnext = 0;                   // end of the virtual workspace so far (offset from kVBase)
+  int64_t ws_bytes = 0;                // this plan's workspace end (main plan: whole range)
+  std::vector<std::pair<int64_t, int64_t>> zero;   // workspace ranges (offset, bytes) read as zero
+  std::vector<uint8_t> h_items;        // item image with virtual addresses (host)
+  void* d_items = nullptr;             // the same image on the device (relocation source)
+  std::vector<uint32_t> relocs;        // 8-byte words of the image holding virtual addresses
+  uint32_t* d_relocs = nullptr;
+  int64_t items_at = 0;                // offset of this plan's item image in a binding
+  int64_t bind_bytes = 0;              // binding size (main plan: workspace + both images)
+  uint64_t budget = 0;                 // bytes the plan may hold (constants + own bindings)
+  // bindings the plan allocated for lgf_solve / lgf_solve_batch: per (stream, occurrence)
+  std::mutex bmu;
+  std::map<std::pair<hipStream_t, int>, Binding*> bindings;
+  std::vector<Binding*> idle;          // allocated but not tied to a stream (plan-time tuning)
+  int64_t bound_bytes = 0;
   double* fe = nullptr;                // coarsened source (multi-level)
   void* jw = nullptr;                  // FP64 [n][N3]: interpolated coarse field J w
   void* w = nullptr;                   // FP64 [n][N3]: leaf-only field of non-leaf blocks
@@ -110,7 +148,6 @@ struct Plan {
   double* r = nullptr;                 // DC residual [n][N3]
   double* d_w = nullptr;               // Lagrange matrix [2 nb][nb]
   double* d_w3 = nullptr;              // quadratic refinement table [(2 nb + 2)][4]
-  void* d_items = nullptr;
   void* d_ops = nullptr;                // OpItem [n]: the forward operators' block table
 
   // statistics
@@ -132,13 +169,31 @@ struct Member {
   const double* in;
   double* out;
   bool accumulate = false;             // the pass adds its result into out (the DC update u += e)
+  Binding* b = nullptr;                // workspace of the solve (the main plan's binding)
 };
+
+// Relocates p's item images (and its correction plan's) into b and clears b's zero ranges,
+// asynchronously on st, unless b already holds p's images.  With set_poison(true) the workspace
+// is first filled with 0xFF bytes (NaN) on every bind (diagnostics: a solve must read nothing it
+// has not written).
+hipError_t bind(Plan* p, Binding* b, hipStream_t st, bool force = false);
+// The binding of p for occurrence k of the plan in a solve on stream st, allocated (under the
+// plan's budget) and bound on first use.
+hipError_t plan_binding(Plan* p, hipStream_t st, int k, Binding** out);
+void set_poison(bool on);
+// Frees the bindings p allocated (after the device finished with them).
+hipError_t plan_trim(Plan* p);
+// device address of a workspace buffer (virtual address v of p's workspace) in binding b
+inline const void* in_binding(const Binding* b, const void* v) {
+  return b->base + ((uint64_t)(uintptr_t)v - kVBase);
+}
 // out = op(u) on the plan's layout: 0 Laplacian, 1 gradient, 2 curl (see launch_fwd_op).
 hipError_t plan_apply(Plan* p, int op, const double* u, double* out, hipStream_t st);
 // Runs the given step lists of several plans with shared launches, in key order.
-hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st);
+// one_stream: no second stream for the base-level path (and no stream or event creation).
+hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st, bool one_stream = false);
 // Full solve of several plans (pass, then defect-correction iterations), shared launches.
-hipError_t solve_members(const std::vector<Member>& m, hipStream_t st);
+hipError_t solve_members(const std::vector<Member>& m, hipStream_t st, bool one_stream = false);
 // Same, replayed from a captured hipGraph when the same (plan, in, out) set was solved before on
 // a non-default stream (launch overhead of a solve's ~30-80 kernels paid once).
 hipError_t solve_members_graph(const std::vector<Member>& m, hipStream_t st);

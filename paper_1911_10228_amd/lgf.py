@@ -27,7 +27,7 @@ EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_apply", "
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
            "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape",
-           "lgf_plan_set_near_shape"]
+           "lgf_plan_set_near_shape", "lgf_server_submit_layout", "lgf_server_info", "lgf_workspace_poison"]
 
 
 class LgfError(RuntimeError):
@@ -89,6 +89,9 @@ def load() -> C.CDLL:
         "lgf_server_destroy": ([P], I32),
         "lgf_plan_set_mac_shape": ([P, I32], I32),
         "lgf_plan_set_near_shape": ([P, I32], I32),
+        "lgf_server_submit_layout": ([P, P, P, I64, I32, I32, P, P, P, P], I32),
+        "lgf_server_info": ([P, P], I32),
+        "lgf_workspace_poison": ([I32], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -210,22 +213,23 @@ def plan_check(blocks, levels, n_b: int, interp_order: int, precision: int = LGF
 
 
 class VectorPlan:
-    """Vector Poisson problem L u_c = f_c, c < components, on one block layout: one plan per
-    component (the kernel spectra are process-wide, so only the workspaces repeat), and every
-    solve advances all components together in shared launches (lgf_solve_batch)."""
+    """Vector Poisson problem L u_c = f_c, c < components, on one block layout through one plan:
+    every solve advances all components together in shared launches (lgf_solve_batch with the
+    plan once per component; each occurrence runs on a workspace of its own)."""
 
     def __init__(self, blocks, levels, n_b: int, interp_order: int, components: int = 3, **kw):
-        self.plans = [Plan(blocks, levels, n_b, interp_order, **kw) for _ in range(components)]
+        self.plan = Plan(blocks, levels, n_b, interp_order, **kw)
+        self.components = components
 
     def solve(self, f, u, stream=None):
         """u <- solution for f; both float64 CUDA tensors [components, n, N_b, N_b, N_b]."""
-        if len(f) != len(self.plans) or len(u) != len(self.plans):
+        if len(f) != self.components or len(u) != self.components:
             raise ValueError("one source and one solution field per component")
-        solve_batch(self.plans, [f[c] for c in range(len(f))], [u[c] for c in range(len(u))], stream)
+        solve_batch([self.plan] * self.components, [f[c] for c in range(len(f))],
+                    [u[c] for c in range(len(u))], stream)
 
     def close(self):
-        for p in self.plans:
-            p.close()
+        self.plan.close()
 
 
 def solve_batch(plans, fs, us, stream=None):
@@ -282,6 +286,18 @@ def profile_read() -> list:
             for e in arr[:min(n.value, 64)]]
 
 
+class ServerMemory(C.Structure):
+    _fields_ = [("reserved_bytes", C.c_int64), ("in_use_bytes", C.c_int64),
+                ("peak_in_use_bytes", C.c_int64), ("slots", C.c_int64), ("peak_slots", C.c_int64),
+                ("binds", C.c_int64), ("plans_cached", C.c_int64), ("plan_hits", C.c_int64),
+                ("plan_misses", C.c_int64), ("plan_ms_total", C.c_double), ("plan_ms_max", C.c_double)]
+
+
+def workspace_poison(enable: bool):
+    """Diagnostics: fill every workspace with NaN bytes when a plan's items are placed in it."""
+    _check(load().lgf_workspace_poison(1 if enable else 0), "lgf_workspace_poison")
+
+
 class Server:
     """Continuous-batching solve server (lgf_server_* in include/lgf.h)."""
 
@@ -297,6 +313,30 @@ class Server:
         _check(load().lgf_server_submit(self._h, plan.handle, _ptr(f), _ptr(u), C.byref(rid)),
                "lgf_server_submit")
         return rid.value
+
+    def submit_layout(self, blocks, levels, n_b: int, interp_order: int, f, u,
+                      precision: int = LGF_FP64_PLAIN, dc_iters: int = 0, autotune: int = 0,
+                      base_level: int = 0) -> int:
+        """Submit by layout: the server takes the plan from its layout-keyed cache or builds it."""
+        b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 3))
+        lv = np.ascontiguousarray(np.zeros(len(b), np.int32) if levels is None
+                                  else np.asarray(levels, dtype=np.int32).reshape(-1))
+        import torch
+        m = len(b) * n_b ** 3
+        for t in (f, u):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == m):
+                raise ValueError("fields must be contiguous float64 CUDA tensors [n, N_b, N_b, N_b]")
+        opt = Options(precision, dc_iters, autotune, base_level, 0)
+        rid = C.c_int64()
+        _check(load().lgf_server_submit_layout(self._h, b.ctypes.data, lv.ctypes.data, len(b), n_b,
+                                               interp_order, C.byref(opt), _ptr(f), _ptr(u),
+                                               C.byref(rid)), "lgf_server_submit_layout")
+        return rid.value
+
+    def info(self) -> dict:
+        m = ServerMemory()
+        _check(load().lgf_server_info(self._h, C.byref(m)), "lgf_server_info")
+        return {k: getattr(m, k) for k, _ in m._fields_}
 
     def poll(self, rid: int) -> bool:
         done = C.c_int32()

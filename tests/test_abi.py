@@ -69,6 +69,9 @@ def test_null_arguments():
     assert lib.lgf_apply(None, 7, None, None, None) == -1
     assert lib.lgf_plan_destroy(None) == -1
     assert lib.lgf_server_poll(None, 1, None) == -1
+    assert lib.lgf_server_info(None, None) == -1
+    assert lib.lgf_server_submit_layout(None, None, None, 0, 8, 4, None, None, None, None) == -1
+    assert lib.lgf_solve_batch(None, None, None, 0, None) == -1
 
 
 def test_operator_codes_match_header():

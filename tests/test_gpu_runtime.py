@@ -136,7 +136,7 @@ def test_server_results_equal_alone(lgf):
 def test_server_budget_admission(lgf):
     Ls = small_cases()
     plans = [lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, 0, 0) for L in Ls]
-    budget = min(p.info()["workspace_bytes"] for p in plans)   # only one plan fits at a time
+    budget = max(p.info()["workspace_bytes"] for p in plans)   # the larger runs alone
     fs = [field(L) for L in Ls]
     srv = lgf.Server(hbm_budget=budget, stream=torch.cuda.Stream())
     us = [torch.zeros_like(f) for f in fs]
