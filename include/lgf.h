@@ -115,6 +115,20 @@ lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int
 /* u = solution for source f (device pointers, layout above); asynchronous on stream. */
 lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream);
 
+/* lgf_solve for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The solve's workspace is a static device array
+ * of LGF_SCRATCH_BYTES in the library, one per GPU, held from the first use on that GPU (or
+ * lgf_init) until the process ends, instead of a workspace of the plan's.  Every call places the
+ * plan's work items in the array and clears the ranges that must start at zero, on stream, before
+ * the solve; it calls no hipMalloc, hipFree or other allocating routine, captures no graph and
+ * runs on stream alone.  Results equal lgf_solve's.  The caller passes f and u as for lgf_solve.
+ * All calls on one GPU share the array, which keeps the last call's contents: calls that overlap
+ * in time on one GPU (other streams, other threads) race and must be serialised by the caller;
+ * calls on one stream are ordered by the stream.  LGF_ENOMEM if the plan's workspace
+ * (lgf_plan_info.workspace_bytes) exceeds LGF_SCRATCH_BYTES, LGF_EINVAL for a null argument. */
+#define LGF_SCRATCH_BYTES ((int64_t)64 << 20)
+lgf_status lgf_solve_noalloc(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream);
+
 /* Forward operators on the layout's per-level lattice (Sec. 3: the source correction makes the
  * 7-point operator of each level consistent with the computed inverse, and applications need at
  * least the gradient of the solution).  Evaluated on every leaf cell whose six face neighbours lie

@@ -18,6 +18,8 @@ struct lgf_plan_s {
   lgf::Plan* p;
 };
 
+static_assert(LGF_SCRATCH_BYTES == lgf::kScratchBytes, "the header states the static workspace size");
+
 namespace {
 
 lgf_status from_hip(hipError_t e) {
@@ -52,7 +54,10 @@ extern "C" {
 
 lgf_status lgf_init(void) {
   lgf::DeviceCtx* c = nullptr;
-  return from_hip(lgf::device_ctx(&c));
+  hipError_t e = lgf::device_ctx(&c);
+  lgf::Binding* b = nullptr;
+  if (e == hipSuccess) e = lgf::scratch_binding(&b);     // the static workspace's address
+  return from_hip(e);
 }
 
 lgf_status lgf_plan(const int32_t* blocks, const int32_t* levels, int64_t n, int32_t N_b,
@@ -115,6 +120,19 @@ lgf_status lgf_solve(lgf_plan_t p, const double* f, double* u, lgf_stream_t stre
   if (e != hipSuccess) return from_hip(e);
   std::vector<lgf::Member> m{{p->p, f, u, false, b}};
   return from_hip(lgf::solve_members_graph(m, (hipStream_t)stream));
+}
+
+lgf_status lgf_solve_noalloc(lgf_plan_t p, const double* f, double* u, lgf_stream_t stream) {
+  if (!p || !f || !u) return LGF_EINVAL;
+  if (p->p->bind_bytes > lgf::kScratchBytes) return LGF_ENOMEM;
+  lgf::Binding* b = nullptr;
+  hipError_t e = lgf::scratch_binding(&b);
+  // the array keeps the last call's contents: place the plan's items and clear its zero ranges
+  // on every call, in stream order before the solve
+  if (e == hipSuccess) e = lgf::bind(p->p, b, (hipStream_t)stream, /*force=*/true);
+  if (e != hipSuccess) return from_hip(e);
+  std::vector<lgf::Member> m{{p->p, f, u, false, b}};
+  return from_hip(lgf::solve_members(m, (hipStream_t)stream, /*one_stream=*/true));
 }
 
 lgf_status lgf_apply(lgf_plan_t p, int32_t op, const double* u, double* out, lgf_stream_t stream) {

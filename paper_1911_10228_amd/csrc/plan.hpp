@@ -181,6 +181,10 @@ hipError_t bind(Plan* p, Binding* b, hipStream_t st, bool force = false);
 // plan's budget) and bound on first use.
 hipError_t plan_binding(Plan* p, hipStream_t st, int k, Binding** out);
 void set_poison(bool on);
+// The static workspace of the allocation-free solve on the current device (a binding of
+// kScratchBytes at that device's copy of the array; set up on first use per device).
+constexpr int64_t kScratchBytes = (int64_t)64 << 20;
+hipError_t scratch_binding(Binding** out);
 // Frees the bindings p allocated (after the device finished with them).
 hipError_t plan_trim(Plan* p);
 // device address of a workspace buffer (virtual address v of p's workspace) in binding b

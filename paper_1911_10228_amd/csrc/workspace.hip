@@ -1,15 +1,28 @@
 // Workspace binding kernels: relocation of a plan's item image into a device binding and the
-// fill of the binding's ranges that must read as zero (or, for diagnostics, as NaN).
+// fill of the binding's ranges that must read as zero (or, for diagnostics, as NaN); the static
+// workspace of the allocation-free solve.
 //
 // The item image holds workspace addresses as kVBase + offset; a binding at device address B
 // holds the same image with every such word moved by (B - kVBase).  The image is copied by the
 // host (a device-to-device copy) and the listed words are patched here, so binding needs no host
 // staging and no allocation.
-#include "kernels.hpp"
+#include <mutex>
+
+#include "plan.hpp"
 
 namespace lgf {
 
 namespace {
+
+// Workspace of the allocation-free solve (lgf_solve_noalloc): a static device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never uses the array's name
+// as an address (on the host it is only a stand-in for the symbol): scratch_binding looks up
+// each device's copy with hipGetSymbolAddress and hands out that pointer.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+Binding g_scratch[kMaxDevices];
 
 __global__ __launch_bounds__(256) void relocate_kernel(uint64_t* img, const uint32_t* __restrict__ idx, int64_t n,
                                                        uint64_t delta) {
@@ -33,6 +46,25 @@ __global__ __launch_bounds__(256) void fill_kernel(uint8_t* base, FillRanges r, 
 }
 
 }  // namespace
+
+hipError_t scratch_binding(Binding** out) {
+  int dev = 0;
+  LGF_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  Binding& b = g_scratch[dev];
+  if (!b.base) {
+    void* ptr = nullptr;
+    LGF_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || (uintptr_t)ptr % 256) return hipErrorInvalidSymbol;
+    b.base = (uint8_t*)ptr;
+    b.bytes = kScratchBytes;
+    b.plan = nullptr;
+    b.owned = false;
+  }
+  *out = &b;
+  return hipSuccess;
+}
 
 hipError_t launch_relocate(uint64_t* img, const uint32_t* idx, int64_t n, uint64_t delta, hipStream_t st) {
   if (n <= 0) return hipSuccess;

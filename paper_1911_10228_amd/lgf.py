@@ -27,7 +27,9 @@ EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_apply", "
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
            "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape",
-           "lgf_plan_set_near_shape", "lgf_server_submit_layout", "lgf_server_info", "lgf_workspace_poison"]
+           "lgf_plan_set_near_shape", "lgf_server_submit_layout", "lgf_server_info", "lgf_workspace_poison",
+           "lgf_solve_noalloc"]
+SCRATCH_BYTES = 64 << 20       # LGF_SCRATCH_BYTES: the allocation-free solve's workspace
 
 
 class LgfError(RuntimeError):
@@ -92,6 +94,7 @@ def load() -> C.CDLL:
         "lgf_server_submit_layout": ([P, P, P, I64, I32, I32, P, P, P, P], I32),
         "lgf_server_info": ([P, P], I32),
         "lgf_workspace_poison": ([I32], I32),
+        "lgf_solve_noalloc": ([P, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -158,6 +161,12 @@ class Plan:
         self._check_field(f)
         self._check_field(u)
         _check(load().lgf_solve(self._h, _ptr(f), _ptr(u), _stream(stream)), "lgf_solve")
+
+    def solve_noalloc(self, f, u, stream=None):
+        """As solve, on the library's static workspace: allocates nothing (lgf_solve_noalloc)."""
+        self._check_field(f)
+        self._check_field(u)
+        _check(load().lgf_solve_noalloc(self._h, _ptr(f), _ptr(u), _stream(stream)), "lgf_solve_noalloc")
 
     def apply(self, op: int, u, out, stream=None):
         """out <- op(u) on the layout's per-level lattice (LAPLACIAN, GRADIENT or CURL; float64
