@@ -255,6 +255,26 @@ lgf_status lgf_server_stats(lgf_server_t s, double* p50_us, double* p99_us, doub
 lgf_status lgf_server_info(lgf_server_t s, lgf_server_memory* out);
 lgf_status lgf_server_destroy(lgf_server_t s);
 
+/* Refinement-criterion layout builder (Sec. 3, Convergence subsection, eq. ref_crit), one
+ * adaptation step on the GPU.  Input: a layout (blocks [n][3], levels [n], as for lgf_plan) and a
+ * field on its cells ([n][N_b^3] doubles, e.g. the vorticity or the source), all device arrays.
+ * omega of a block is its largest |value|, omega_max of level l the largest over level l; a
+ * level-l block is flagged when l < n_levels - 1 and omega > alpha^(n_levels - 1 - l) omega_max
+ * (alpha^k by repeated multiplication; alpha = 1/32 in the paper).  The new layout keeps the
+ * base level (level-0 blocks in their order) and, level by level, the 8 children of every
+ * flagged block, in the new order of the flagged blocks, child offset (cx, cy, cz) with cz
+ * fastest; only blocks of the input layout (where the field is known) can be flagged, so a
+ * block loses its children when its criterion fails, and each step adds at most one level.
+ * Repeating the step from the base layout with the field on each new layout builds the layout
+ * of n_levels refinement levels.  Output: out_blocks [cap][3] and out_levels [cap] (device),
+ * *n_out (host) the number of blocks of the new layout; the call synchronises stream.
+ * LGF_ENOMEM (with *n_out set) if n_out > cap; LGF_ELAYOUT for a duplicate block, a level
+ * outside [0, 16) or N_b not in {8, 16}; LGF_EINVAL for other bad arguments.  Temporary device
+ * memory is allocated and freed inside the call. */
+lgf_status lgf_layout_adapt(const int32_t* blocks, const int32_t* levels, int64_t n, int32_t N_b,
+                            const double* field, int32_t n_levels, double alpha, int32_t* out_blocks,
+                            int32_t* out_levels, int64_t cap, int64_t* n_out, lgf_stream_t stream);
+
 /* Diagnostics: with enable = 1 every workspace is filled with 0xFF bytes (NaN) each time a
  * plan's items are placed into it, before the ranges that must read as zero are cleared; a
  * solve that read anything it had not written would then return NaN.  Process-wide. */

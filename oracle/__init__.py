@@ -25,6 +25,8 @@ equations", that it follows):
                  source correction, interpolation and accumulation (Sec. 3, Algorithm 2).
 * ``dc``       - defect correction of a low-precision solve with an FP64 residual of the
                  7-point operator (the problem statement of Sec. 2).
+* ``refine``   - the refinement criterion (Sec. 3, Convergence subsection, eq. ref_crit) as
+                 one adaptation step of a block layout.
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``; the
 multi-resolution operators are pinned only through invariants (consistency L u = f on

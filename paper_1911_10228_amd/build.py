@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblgf.so")
-SOURCES = ["green.hip", "fft_blocks.hip", "fft_super.hip", "mac.hip", "interp.hip", "workspace.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["green.hip", "fft_blocks.hip", "fft_super.hip", "mac.hip", "interp.hip", "workspace.hip", "layout.hip", "plan.cpp", "api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-Wno-unused-result"]

@@ -243,6 +243,19 @@ lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, i
                                  (hipStream_t)stream));
 }
 
+lgf_status lgf_layout_adapt(const int32_t* blocks, const int32_t* levels, int64_t n, int32_t N_b,
+                            const double* field, int32_t n_levels, double alpha, int32_t* out_blocks,
+                            int32_t* out_levels, int64_t cap, int64_t* n_out, lgf_stream_t stream) {
+  if (!blocks || !levels || !field || !n_out || n <= 0 || cap < 0 || (cap > 0 && (!out_blocks || !out_levels)))
+    return LGF_EINVAL;
+  if (N_b != 8 && N_b != 16) return LGF_ELAYOUT;
+  if (n_levels < 1 || n_levels > 16 || !(alpha > 0.0 && alpha < 1.0)) return LGF_EINVAL;
+  const hipError_t e = lgf::layout_adapt(blocks, levels, n, N_b, field, n_levels, alpha, out_blocks, out_levels,
+                                         cap, n_out, (hipStream_t)stream);
+  if (e == hipErrorInvalidValue) return LGF_ELAYOUT;
+  return from_hip(e);
+}
+
 lgf_status lgf_workspace_poison(int32_t enable) {
   lgf::set_poison(enable != 0);
   return LGF_OK;

@@ -236,6 +236,11 @@ struct FillRanges {
 };
 hipError_t launch_relocate(uint64_t* img, const uint32_t* idx, int64_t n, uint64_t delta, hipStream_t st);
 hipError_t launch_fill(uint8_t* base, const FillRanges& r, uint32_t pattern, hipStream_t st);
+// one adaptation step of a block layout by the refinement criterion (layout.hip); device arrays
+// in and out, *n_out = blocks of the new layout (hipErrorOutOfMemory if above cap)
+hipError_t layout_adapt(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, const double* field,
+                        int n_levels, double alpha, int32_t* out_blocks, int32_t* out_levels, int64_t cap,
+                        int64_t* n_out, hipStream_t st);
 int quad_nodes();
 // op 0: Laplacian (1 -> 1 component), 1: gradient (1 -> 3), 2: curl (3 -> 3); components of
 // u and out are n * nb^3 apart

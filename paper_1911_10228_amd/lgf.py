@@ -27,7 +27,7 @@ EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_apply", "
            "lgf_plan_destroy", "lgf_status_string", "lgf_green_eval", "lgf_green_table",
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
            "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape",
-           "lgf_plan_set_near_shape", "lgf_server_submit_layout", "lgf_server_info", "lgf_workspace_poison",
+           "lgf_plan_set_near_shape", "lgf_server_submit_layout", "lgf_server_info", "lgf_workspace_poison", "lgf_layout_adapt",
            "lgf_solve_noalloc"]
 SCRATCH_BYTES = 64 << 20       # LGF_SCRATCH_BYTES: the allocation-free solve's workspace
 
@@ -94,6 +94,7 @@ def load() -> C.CDLL:
         "lgf_server_submit_layout": ([P, P, P, I64, I32, I32, P, P, P, P], I32),
         "lgf_server_info": ([P, P], I32),
         "lgf_workspace_poison": ([I32], I32),
+        "lgf_layout_adapt": ([P, P, I64, I32, P, I32, C.c_double, P, P, I64, P, P], I32),
         "lgf_solve_noalloc": ([P, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
@@ -250,6 +251,32 @@ def solve_batch(plans, fs, us, stream=None):
     fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
     up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
     _check(load().lgf_solve_batch(hp, fp, up, n, _stream(stream)), "lgf_solve_batch")
+
+
+def adapt_layout(blocks, levels, n_b: int, field, n_levels: int, alpha: float = 1.0 / 32,
+                 stream=None):
+    """One adaptation step of the refinement criterion on the GPU (lgf_layout_adapt): field is a
+    float64 CUDA tensor [n, N_b, N_b, N_b] on the layout (blocks, levels).  Returns the new
+    layout as numpy arrays (blocks [m, 3] int32, levels [m] int32)."""
+    import torch
+    b = torch.as_tensor(np.ascontiguousarray(np.asarray(blocks, np.int32).reshape(-1, 3))).cuda()
+    lv = torch.as_tensor(np.ascontiguousarray(np.asarray(levels, np.int32).reshape(-1))).cuda()
+    n = b.shape[0]
+    if not (field.is_cuda and field.dtype == torch.float64 and field.is_contiguous()
+            and field.numel() == n * n_b ** 3):
+        raise ValueError("field must be a contiguous float64 CUDA tensor [n, N_b, N_b, N_b]")
+    cap = 8 * n + 8
+    while True:
+        ob = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+        ol = torch.empty((cap,), dtype=torch.int32, device="cuda")
+        m = C.c_int64()
+        code = load().lgf_layout_adapt(_ptr(b), _ptr(lv), n, n_b, _ptr(field), n_levels, alpha,
+                                       _ptr(ob), _ptr(ol), cap, C.byref(m), _stream(stream))
+        if code == -3 and m.value > cap:
+            cap = m.value
+            continue
+        _check(code, "lgf_layout_adapt")
+        return ob[:m.value].cpu().numpy(), ol[:m.value].cpu().numpy()
 
 
 def green_eval(n_dev, out_dev, stream=None):
