@@ -131,9 +131,13 @@ lgf_status lgf_solve_noalloc(lgf_plan_t p, const double* f, double* u, lgf_strea
 
 /* Forward operators on the layout's per-level lattice (Sec. 3: the source correction makes the
  * 7-point operator of each level consistent with the computed inverse, and applications need at
- * least the gradient of the solution).  Evaluated on every leaf cell whose six face neighbours lie
- * in blocks of the same level, with h = 2^-level base cells; every other cell (non-leaf blocks,
- * cells next to a level boundary or the layout's edge) is set to 0:
+ * least the gradient of the solution), with h = 2^-level base cells.  A neighbour cell across a
+ * block face is the same-level block's value; at a level boundary (a level l >= 1 block with no
+ * same-level block across the face) it is the ghost value of the block's parent field in u, the
+ * parent's quadratic extended one child cell outward (the ghost of the source correction).
+ * Evaluated on every leaf cell of levels >= 1 and on the level-0 leaf cells whose neighbours lie
+ * in level-0 blocks; every other cell (non-leaf blocks, the coarsest level's outer boundary) is
+ * set to 0:
  *   LGF_OP_LAPLACIAN  u [n][N_b^3]     -> out [n][N_b^3]     h^-2 (6 neighbours - 6 centre)
  *   LGF_OP_GRADIENT   u [n][N_b^3]     -> out [3][n][N_b^3]  (u(x + e_a) - u(x - e_a)) / 2h
  *   LGF_OP_CURL       u [3][n][N_b^3]  -> out [3][n][N_b^3]  curl by the same central differences
@@ -181,8 +185,11 @@ lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape);
 /* lgf_plan_set_near_shape: the same for the base-level super-block MAC steps: shape 2, 4 or 8
  *   rows of that many target super-blocks per wavefront, 20 or 22 tiles of 2 x 2 or 2 x 4 rows of 4
  *   (FP32 spectra), 21 or 23 the same tiles pipelined over runs of frequency chunks (FP32 and
- *   FP64 spectra; only where every tile of the step has at most 36 or 48 source super-blocks);
- *   0 restores the chosen shape.  The other shapes' work items exist only in plans built with
+ *   FP64 spectra; only where every tile of the step has at most 36 or 48 source super-blocks),
+ *   42 or 44 the fused form of those tiles (the step also takes the z transforms of the
+ *   super-block FFTs: z transform, MAC and inverse z transform per (kx, ky) line in one kernel;
+ *   the default wherever the tiles fit); 0 restores the chosen shape.  Shapes other than the
+ *   chosen one and its fused / pipelined counterpart exist only in plans built with
  *   lgf_options.autotune = 1; returns LGF_EINVAL, changing nothing, if a step lacks the shape. */
 lgf_status lgf_plan_set_near_shape(lgf_plan_t p, int32_t shape);
 lgf_status lgf_green_table(double* out, lgf_stream_t stream);

@@ -3,17 +3,25 @@
 The refined solve (Sec. 3) inverts the 7-point Laplacian of every level; applications also need
 the gradient of the computed field, and the source correction is what makes each level's 7-point
 operator consistent with the computed inverse.  Each operator acts on a block with its one-cell
-halo from the same-level blocks across its faces, on the cells of ``multires.residual_mask``
-(leaf cells whose six neighbours lie in same-level blocks); every other cell is 0.  Level l has
-spacing h_l = 2^-l base cells; arrays are [block, z, y, x], vector fields [component, block, ...].
+halo: a neighbour cell in a same-level block is that block's value; at a level boundary (no
+same-level block across the face of a level l >= 1 block) it is the ghost value of the block's
+parent field, the parent's quadratic extended one child cell outward (``multires.refine_ext``,
+the ghost the source correction takes; reading: the paper asks for operators consistent with
+the computed inverse and names no boundary stencil).  The operators are evaluated on every leaf
+cell of levels l >= 1 and on the leaf cells of level 0 whose neighbours lie in level-0 blocks
+(the outer boundary of the coarsest level has nothing outside it); every other cell, and every
+non-leaf block, is 0.  Level l has spacing h_l = 2^-l base cells; arrays are [block, z, y, x],
+vector fields [component, block, ...].
 
 - laplacian: h_l^-2 (sum of the six neighbours - 6 centre), the operator the solve inverts;
 - gradient: central differences (u(x + e_a) - u(x - e_a)) / (2 h_l), components (x, y, z);
 - curl of (u_x, u_y, u_z) from the same central differences.
 
 Pinned by exactness on polynomials (central differences are exact for quadratics, the 7-point
-Laplacian for cubics), curl of a gradient = 0 where both are defined, and L^l u = f on the mask
-for a corrected refined solve u of f.
+Laplacian for cubics, and the parent's quadratic reproduces quadratics, so every evaluated cell,
+interface cells included, is exact for quadratics), curl of a gradient = 0 where both are
+defined, and L^l u = f where the solve makes the 7-point equation hold, for a corrected refined
+solve u of f.
 """
 from __future__ import annotations
 
@@ -24,10 +32,24 @@ from . import multires
 OPS = ("laplacian", "gradient", "curl")
 
 
-def _halo(coords: dict, b, field: np.ndarray, i: int, n_b: int) -> np.ndarray:
-    """Block i of ``field`` with its one-cell halo from the same-level blocks across its faces
-    (0 where there is none; the halo's edges and corners are never used)."""
-    E = np.zeros((n_b + 2,) * 3)
+def op_mask(blocks, levels, n_b: int) -> np.ndarray:
+    """Boolean [n, n_b, n_b, n_b]: the cells the operators are evaluated on (module header)."""
+    blocks = np.asarray(blocks, dtype=np.int64).reshape(-1, 3)
+    levels = np.asarray(levels, dtype=np.int64).reshape(-1)
+    mask = multires.residual_mask(blocks, levels, n_b)
+    keys = {(int(l),) + tuple(int(v) for v in b) for b, l in zip(blocks, levels)}
+    for i, (b, l) in enumerate(zip(blocks, levels)):
+        leaf = (int(l) + 1,) + tuple(int(v) for v in 2 * b) not in keys
+        if l > 0 and leaf:
+            mask[i] = True
+    return mask
+
+
+def _halo(coords: dict, b, field: np.ndarray, i: int, n_b: int, ghost=None) -> np.ndarray:
+    """Block i of ``field`` with its one-cell halo from the same-level blocks across its faces;
+    where there is none, from ``ghost`` (the parent's extended quadratic, [(n_b+2)]^3), else 0
+    (the halo's edges and corners are never used)."""
+    E = np.zeros((n_b + 2,) * 3) if ghost is None else ghost.copy()
     E[1:-1, 1:-1, 1:-1] = field[i]
     nb = multires._face_neighbours(coords, b)       # (-x, +x, -y, +y, -z, +z)
     if nb[0] is not None: E[1:-1, 1:-1, 0] = field[nb[0]][:, :, -1]
@@ -58,17 +80,26 @@ def apply(blocks, levels, u, n_b: int, op: str) -> np.ndarray:
     levels = np.asarray(levels, dtype=np.int64).reshape(-1)
     n = len(blocks)
     comps = [np.asarray(u[c], np.float64) for c in range(3)] if op == "curl" else [np.asarray(u, np.float64)]
-    mask = multires.residual_mask(blocks, levels, n_b)
+    mask = op_mask(blocks, levels, n_b)
     out = np.zeros((1 if op == "laplacian" else 3, n, n_b, n_b, n_b))
     c = slice(1, -1)
+    coords_of = []
     for l in range(int(levels.max()) + 1):
         ids = np.nonzero(levels == l)[0]
-        coords = {tuple(int(v) for v in blocks[i]): i for i in ids}
+        coords_of.append({tuple(int(v) for v in blocks[i]): i for i in ids})
+    for l in range(int(levels.max()) + 1):
+        ids = np.nonzero(levels == l)[0]
+        coords = coords_of[l]
         h = 2.0 ** (-l)
         for i in ids:
             if not mask[i].any():
                 continue
-            E = [_halo(coords, blocks[i], f, i, n_b) for f in comps]
+            ghosts = [None] * len(comps)
+            if l > 0:
+                par = coords_of[l - 1][tuple(int(v) for v in np.floor_divide(blocks[i], 2))]
+                octant = tuple(int(v) for v in blocks[i] - 2 * np.floor_divide(blocks[i], 2))
+                ghosts = [multires.refine_ext(f[par], octant) for f in comps]
+            E = [_halo(coords, blocks[i], f, i, n_b, g) for f, g in zip(comps, ghosts)]
             if op == "laplacian":
                 e = E[0]
                 vals = [(e[2:, c, c] + e[:-2, c, c] + e[c, 2:, c] + e[c, :-2, c] + e[c, c, 2:]

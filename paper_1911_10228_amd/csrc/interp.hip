@@ -566,66 +566,103 @@ hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Forward operators of the per-level lattice on the leaf cells whose six neighbours lie in
-// same-level blocks (the cells on which the solve makes the 7-point equation hold, Sec. 3); 0 on
-// every other cell.  Laplacian h^-2 (6 neighbours - 6 centre); gradient by central differences
-// (u(x + e_a) - u(x - e_a)) / 2h; curl of a three-component field from the same differences.
-// One thread per cell; a neighbour across a block face is read from the block on that side.
+// Forward operators of the per-level lattice (Sec. 3: applications need at least the gradient of
+// the computed field; the source correction makes each level's 7-point operator consistent with
+// the computed inverse).  Laplacian h^-2 (6 neighbours - 6 centre); gradient by central
+// differences (u(x + e_a) - u(x - e_a)) / 2h; curl of a three-component field from the same
+// differences.  A neighbour across a block face comes from the same-level block on that side;
+// where there is none, from the block's parent field, the parent's quadratic extended one child
+// cell outward (the ghost of the source correction), or, on the coarsest level, nowhere: those
+// cells, and every cell of a non-leaf block, are 0.  One workgroup per (block, z-slab of
+// NB / kResidualSlabs planes), one thread per (x, y) column: each input component's slab and its
+// one-cell halo are staged in LDS (each halo cell computed once), then every output of the slab
+// is formed from LDS and stored coalesced.
 template <int NB>
-__global__ __launch_bounds__(256) void fwd_op_kernel(const OpItem* __restrict__ items, int op,
-                                                     const double* __restrict__ u,
-                                                     double* __restrict__ out, int64_t cs) {
-  constexpr int N3 = NB * NB * NB, PER = (N3 + 255) / 256;
-  const OpItem& it = items[blockIdx.x / PER];
-  const int i = (int)(blockIdx.x % PER) * 256 + (int)threadIdx.x;
-  if (i >= N3) return;
-  const int q[3] = {i % NB, (i / NB) % NB, i / (NB * NB)};
-  bool ok = it.leaf != 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (q[a] == 0) ok = ok && it.nbr_off[2 * a] >= 0;
-    if (q[a] == NB - 1) ok = ok && it.nbr_off[2 * a + 1] >= 0;
-  }
+__global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restrict__ items, int op,
+                                                         const double* __restrict__ u, double* __restrict__ out,
+                                                         int64_t cs, const double* __restrict__ w3tab) {
+  constexpr int SZ = NB / kResidualSlabs, E = NB + 2, N2 = NB * NB, PL = E * E, SL = (SZ + 2) * PL;
+  __shared__ double ext[3 * SL];
+  const OpItem& it = items[blockIdx.x / kResidualSlabs];
+  const int z0 = (int)(blockIdx.x % kResidualSlabs) * SZ;
+  const int t = threadIdx.x, x = t % NB, y = t / NB;
+  const int nin = op == 2 ? 3 : 1, nout = op == 0 ? 1 : 3;
   const gview<double> o = gl(out);
-  const int64_t at = it.off + i;
-  if (!ok) {
-    const int nout = op == 0 ? 1 : 3;
-    for (int c = 0; c < nout; ++c) o[c * cs + at] = 0.0;
+  if (!it.leaf) {
+    for (int c = 0; c < nout; ++c)
+#pragma unroll
+      for (int j = 0; j < SZ; ++j) o[c * cs + it.off + (z0 + j) * N2 + t] = 0.0;
     return;
   }
   const gview<const double> U = gl(u);
-  // component c at the neighbour one cell along axis a in direction s (-1 or +1)
-  auto nbv = [&](int c, int a, int s) -> double {
-    const int stride = a == 0 ? 1 : (a == 1 ? NB : NB * NB);
-    int qa = q[a] + s;
-    int64_t b = it.off;
-    if (qa < 0) { b = it.nbr_off[2 * a]; qa += NB; }
-    else if (qa >= NB) { b = it.nbr_off[2 * a + 1]; qa -= NB; }
-    return U[c * cs + b + i + (int64_t)(qa - q[a]) * stride];
+  const gview<const double> w3 = gl(w3tab);
+  const int oc[3] = {it.octant & 1, (it.octant >> 1) & 1, (it.octant >> 2) & 1};
+  const bool ghost = it.par_off >= 0;
+  // component c at cell q of the block's frame; at most one coordinate is -1 or NB
+  auto cell = [&](int c, int qx, int qy, int qz) -> double {
+    const int64_t cb = (int64_t)c * cs;
+    int face = -1, q[3] = {qx, qy, qz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (q[a] < 0) face = 2 * a;
+      else if (q[a] >= NB) face = 2 * a + 1;
+    }
+    if (face < 0) return U[cb + it.off + (qz * NB + qy) * NB + qx];
+    const int64_t nb = it.nbr_off[face];
+    if (nb >= 0) {
+      const int a = face >> 1;
+      q[a] = (face & 1) ? 0 : NB - 1;
+      return U[cb + nb + (q[2] * NB + q[1]) * NB + q[0]];
+    }
+    if (ghost) return refine_point<NB, double>(U + cb + it.par_off, w3, oc[0] * NB + qx, oc[1] * NB + qy, oc[2] * NB + qz);
+    return 0.0;
   };
-  const double hh = 0.5 * it.inv_h;
-  if (op == 0) {
-    double s = 0.0;
+  // x and y halo cells of the slab's planes: 4 faces x NB x SZ = NB^2 cells, one per thread
+  const int hf = t / (NB * SZ), hr = t % (NB * SZ), ha = hr % NB, hz = hr / NB;
+  const int hq[3] = {hf == 0 ? -1 : hf == 1 ? NB : ha, hf == 2 ? -1 : hf == 3 ? NB : ha, z0 + hz};
+  for (int c = 0; c < nin; ++c) {
+    double* const e = ext + c * SL;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) s += nbv(0, a, -1) + nbv(0, a, 1);
-    o[at] = it.inv_h * it.inv_h * (s - 6.0 * U[at]);
-  } else if (op == 1) {
+    for (int j = 0; j < SZ + 2; ++j) e[j * PL + (y + 1) * E + x + 1] = cell(c, x, y, z0 - 1 + j);
+    e[(hz + 1) * PL + (hq[1] + 1) * E + hq[0] + 1] = cell(c, hq[0], hq[1], hq[2]);
+  }
+  __syncthreads();
+  const double ih = it.inv_h, hh = 0.5 * it.inv_h;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) o[a * cs + at] = (nbv(0, a, 1) - nbv(0, a, -1)) * hh;
-  } else {
-    auto d = [&](int c, int a) { return (nbv(c, a, 1) - nbv(c, a, -1)) * hh; };
-    o[at] = d(2, 1) - d(1, 2);
-    o[cs + at] = d(0, 2) - d(2, 0);
-    o[2 * cs + at] = d(1, 0) - d(0, 1);
+  for (int j = 0; j < SZ; ++j) {
+    const int z = z0 + j;
+    bool ok = true;
+    if (!ghost) {
+      ok = !((x == 0 && it.nbr_off[0] < 0) || (x == NB - 1 && it.nbr_off[1] < 0) ||
+             (y == 0 && it.nbr_off[2] < 0) || (y == NB - 1 && it.nbr_off[3] < 0) ||
+             (z == 0 && it.nbr_off[4] < 0) || (z == NB - 1 && it.nbr_off[5] < 0));
+    }
+    const int cc = (j + 1) * PL + (y + 1) * E + x + 1;
+    const int64_t at = it.off + (int64_t)z * N2 + t;
+    auto d = [&](int c, int step) { return (ext[c * SL + cc + step] - ext[c * SL + cc - step]) * hh; };
+    if (op == 0) {
+      const double lap = ext[cc - 1] + ext[cc + 1] + ext[cc - E] + ext[cc + E] + ext[cc - PL] + ext[cc + PL] -
+                         6.0 * ext[cc];
+      o[at] = ok ? ih * ih * lap : 0.0;
+    } else if (op == 1) {
+      o[at] = ok ? d(0, 1) : 0.0;
+      o[cs + at] = ok ? d(0, E) : 0.0;
+      o[2 * cs + at] = ok ? d(0, PL) : 0.0;
+    } else {
+      o[at] = ok ? d(2, E) - d(1, PL) : 0.0;
+      o[cs + at] = ok ? d(0, PL) - d(2, 1) : 0.0;
+      o[2 * cs + at] = ok ? d(1, 1) - d(0, E) : 0.0;
+    }
   }
 }
 
 hipError_t launch_fwd_op(int nb, int op, const OpItem* items, int64_t n, const double* u, double* out,
-                         hipStream_t st) {
+                         const double* w3, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (!items || op < 0 || op > 2) return hipErrorInvalidValue;
-  const int64_t n3 = (int64_t)nb * nb * nb, per = (n3 + 255) / 256;
-  LGF_NB_DISPATCH(nb, fwd_op_kernel<NB><<<(unsigned)(n * per), 256, 0, st>>>(items, op, u, out, n * n3));
+  if (!items || !w3 || op < 0 || op > 2) return hipErrorInvalidValue;
+  const int64_t n3 = (int64_t)nb * nb * nb;
+  LGF_NB_DISPATCH(nb, fwd_op_kernel<NB><<<(unsigned)(n * kResidualSlabs), NB * NB, 0, st>>>(items, op, u, out,
+                                                                                               n * n3, w3));
   return hipGetLastError();
 }
 

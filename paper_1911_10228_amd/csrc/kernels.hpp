@@ -134,9 +134,10 @@ template <typename T> struct NearCTile {
   int32_t rz;                          // rows along z: 2 or 4
   int32_t zero;                        // the zero slot (an all-zero spectrum)
   int32_t edges;                       // 1: some source row holds a source at x0 - 1 or x0 + 4
-  const cpx<T>* fhat;
-  cpx<T>* uhat;
+  const cpx<T>* fhat;                  // source super-block slots (spectra, or line-major planes)
+  cpx<T>* uhat;                        // target super-block slots
   const cpx<T>* const* kptr;           // as in NearTile
+  const cpx<T>* ktr;                   // fused form: kernel columns [14][line][kz] (storage type)
 };
 constexpr int kNearRunMin = 2, kNearRunMax = 8;   // frequency chunks a pipelined workgroup walks
 
@@ -219,9 +220,10 @@ constexpr int kResidualSlabs = 4;       // workgroups (z-slabs) per block of the
 struct OpItem {
   int64_t off;           // block offset in every component array
   int64_t nbr_off[6];    // same-level blocks across faces (-x,+x,-y,+y,-z,+z) (-1: absent)
+  int64_t par_off;       // the parent block (ghost values at level boundaries), -1 on level 0
   double inv_h;          // 2^level: inverse spacing in base cells
   int32_t leaf;          // 0: every output cell of the block is 0
-  int32_t pad;
+  int32_t octant;        // the block's octant in its parent, cx + 2 cy + 4 cz
 };
 
 // ----------------------------------------------------------------------------- launchers
@@ -243,9 +245,9 @@ hipError_t layout_adapt(const int32_t* blocks, const int32_t* levels, int64_t n,
                         int64_t* n_out, hipStream_t st);
 int quad_nodes();
 // op 0: Laplacian (1 -> 1 component), 1: gradient (1 -> 3), 2: curl (3 -> 3); components of
-// u and out are n * nb^3 apart
+// u and out are n * nb^3 apart; w3: the quadratic refinement table of the ghost values
 hipError_t launch_fwd_op(int nb, int op, const OpItem* items, int64_t n, const double* u, double* out,
-                         hipStream_t st);
+                         const double* w3, hipStream_t st);
 hipError_t launch_green_table(double* d_cube, double* d_nodes, double* d_wts, const int16_t* d_tri,
                               int ntri, hipStream_t st);
 hipError_t launch_green_eval(const int32_t* d_n, int64_t m, const double* d_cube, double* d_out,
@@ -271,15 +273,28 @@ hipError_t launch_coarsen(int nb, SetTable& t, hipStream_t st);
 hipError_t launch_refine(int nb, SetTable& t, hipStream_t st);                          // ws.w = W3
 template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t st);  // ws.w = W3
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st);
-template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st);
-template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st);
+// mode 0: (x, y) pass and z pass through the plane stack [z][line] (spectra for the near MAC);
+// mode 1: (x, y) pass only, planes line-major [line][z] (for and from the fused near step)
+template <typename T, typename TC> hipError_t launch_super_fwd(int nb, SetTable& t, hipStream_t st, int mode = 0);
+template <typename T, typename TC> hipError_t launch_super_inv(int nb, SetTable& t, hipStream_t st, int mode = 0);
+// kernel columns for the fused form: out[(h * PLANE + line) * P + kz] = K_h[kz * PLANE + line]
+// for the 14 super-block kernels h <= 13 of a set (P = 4 nb, PLANE = P (2 nb + 1))
+template <typename T> hipError_t launch_kernel_columns(int nb, const cpx<T>* spectra, cpx<T>* out, hipStream_t st);
 // mode: W (2, 4 or 8) for NearRow items; kNearTiled + 4 / + 6 for NearTile items of RZ = 2 / 4;
 // NearCTile items (pipelined form, FP32): kNearTiled + 5 / + 7 for RZ = 2 / 4, staging at most
 // 36 / 48 source spectra per tile
+// Fused form (NearCTile items, FP32 and FP64): kNearFused + 2 / + 4 for RZ = 2 / 4.  The
+// super-block transforms of the step's level then take mode 1: the forward (x, y) pass writes the
+// planes line-major, [line][z] in the first half of each slot, the fused kernel does the z
+// transforms, the MAC and the inverse z transforms per (tile, line), and the inverse (y, x) pass
+// reads the line-major target planes.
 constexpr int kNearTiled = 16;
+constexpr int kNearFused = 40;
 constexpr bool near_piped(int mode) { return mode == kNearTiled + 5 || mode == kNearTiled + 7; }
-constexpr int near_ctile_rz(int mode) { return mode == kNearTiled + 5 ? 2 : 4; }
-constexpr int near_ctile_cap(int mode) { return mode == kNearTiled + 5 ? 36 : 48; }
+constexpr bool near_fused(int mode) { return mode == kNearFused + 2 || mode == kNearFused + 4; }
+constexpr bool near_compact(int mode) { return near_piped(mode) || near_fused(mode); }
+constexpr int near_ctile_rz(int mode) { return (mode == kNearTiled + 5 || mode == kNearFused + 2) ? 2 : 4; }
+constexpr int near_ctile_cap(int mode) { return near_ctile_rz(mode) == 2 ? 36 : 48; }
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode);
 
 // number of workgroups each item of a kernel needs (for set-table bookkeeping)

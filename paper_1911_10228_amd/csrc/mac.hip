@@ -744,6 +744,174 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
   }
 }
 
+// Fused form: the base-level convolution of one tile for one group of (kx, ky) lines (one line
+// of P = 64 frequencies kz for N_b = 16, two of 32 for N_b = 8: 64 lanes either way), from the
+// line-major planes of the forward (x, y) pass to the line-major planes of the inverse one.
+//  1. the tile's staged source columns (B2 values of z per line, contiguous) and the 14 kernel
+//     columns of the lines go to LDS;
+//  2. each column's z transform, zero-padded from B2 to P, is two length-B2 FFTs (even and odd
+//     kz, the odd one of the input twiddled by e^{-2 pi i z / P}), one per lane of a pair;
+//  3. the MAC of the tiled form: wavefront = target row, lane = (line, kz);
+//  4. each target's inverse z transform cropped to z < B2 is two length-B2 inverse FFTs (even and
+//     odd kz, the odd one twiddled by e^{+2 pi i z / P} afterwards) on a lane pair, summed with a
+//     lane shuffle; each lane stores half of the column.
+// The 1 / P^3 of the inverse transform is left to the inverse (y, x) pass.  Workgroups: line
+// groups dealt to the XCDs in turn, all tiles of a group on one XCD (they share its source and
+// kernel columns in L2).
+template <typename T, int B2, int RZ, int NC>
+__global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int64_t slot) {
+  constexpr int P = 2 * B2, H = B2 + 1, PLANE = P * H;
+  constexpr int LPW = 64 / P;                    // lines per workgroup
+  constexpr int NGRP = PLANE / LPW;              // line groups
+  constexpr int W = kTileW, WAVES = 2 * RZ, NS = W + 2, NT = WAVES * W, NTH = 64 * WAVES;
+  // LDS strides padded by one complex value so that lanes working on different entries (or
+  // targets) in the transform phases fall on different banks
+  constexpr int FS = 66, XS = 33, OS = 66;       // entry stride of F, column stride, target stride
+  constexpr int XN = NC * XS > NT * OS ? NC * XS : NT * OS;
+  static_assert(PLANE % LPW == 0 && LPW * B2 == 32, "one group: 32 z values and 64 kz values per column");
+  static_assert(2 * LPW * NC <= NTH && 2 * LPW * NT <= NTH, "one transform per lane");
+  __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra: entry e, lane (line, kz); entry NC zero
+  __shared__ cpx<T> X[XN];                       // source columns [e][line][z], then target spectra
+  __shared__ cpx<T> K[kNearHalfK * 64];          // kernel columns [h][line][kz]
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;   // wg_begin is a multiple of 8
+  const int ntiles = ws.count;
+  const int64_t j = local >> 3;
+  const int grp = (int)(j / ntiles) * 8 + (int)(local & 7);
+  const int ti = (int)(j % ntiles);
+  if (grp >= NGRP) return;
+  const int line0 = grp * LPW;
+  const __attribute__((address_space(4))) NearCTile<T>* tile =
+      (const __attribute__((address_space(4))) NearCTile<T>*)ws.items + ti;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int nreal = tile->nreal;
+  // 1. source and kernel columns
+  {
+    const gview<const T> Fp = gl((const T*)tile->fhat);
+    for (int i = tid; i < nreal * 32; i += NTH) {
+      const int e = i >> 5, r = i & 31;
+      const int64_t o = 2 * ((int64_t)tile->src[e] * slot + (int64_t)line0 * B2 + r);
+      X[e * XS + r] = cpx<T>{Fp[o], Fp[o + 1]};
+    }
+    const gview<const T> Kc = gl((const T*)tile->ktr);
+    for (int i = tid; i < kNearHalfK * 64; i += NTH) {
+      const int h = i >> 6, r = i & 63;
+      const int64_t o = 2 * (((int64_t)h * PLANE + line0) * P + r);
+      K[i] = cpx<T>{Kc[o], Kc[o + 1]};
+    }
+    if (tid < 64) F[NC * FS + tid] = cpx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  // 2. forward z transforms: thread (entry, line, half)
+  for (int i = tid; i < 2 * LPW * nreal; i += NTH) {
+    const int e = i / (2 * LPW), r = i % (2 * LPW), ls = r >> 1, hf = r & 1;
+    T xr[B2], xi[B2];
+#pragma unroll
+    for (int n = 0; n < B2; ++n) {
+      const cpx<T> v = X[e * XS + ls * B2 + n];
+      if (hf && n > 0) {
+        const T c = T(TwTable<P>::t.c[n]), sn = T(TwTable<P>::t.s[n]);   // times e^{-2 pi i n / P}
+        xr[n] = v.x * c + v.y * sn;
+        xi[n] = v.y * c - v.x * sn;
+      } else {
+        xr[n] = v.x;
+        xi[n] = v.y;
+      }
+    }
+    fft_inreg<B2, -1>(xr, xi);
+#pragma unroll
+    for (int m = 0; m < B2; ++m) F[e * FS + ls * P + 2 * m + hf] = cpx<T>{xr[m], xi[m]};
+  }
+  __syncthreads();
+  // 3. MAC: wavefront = row (ry, rz) of the tile, lane = (line, kz)
+  {
+    const uint32_t smask = tile->src_mask;
+    const int ry = wave & 1, rz = wave >> 1;
+    cpx<T> kv[kNearHalfK];
+#pragma unroll
+    for (int h = 0; h < kNearHalfK; ++h) kv[h] = K[h * 64 + lane];
+    cpx<T> acc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[q] = {T(0), T(0)};
+    if ((tile->row_mask >> wave) & 1u) {
+#pragma unroll
+      for (int pj = 0; pj < 9; ++pj) {
+        const int dz = pj / 3 - 1, dy = pj % 3 - 1;
+        const int q = (ry + 1 - dy) + 4 * (rz + 1 - dz);
+        if (!((smask >> q) & 1u)) continue;
+        cpx<T> fd[NS];
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) fd[s2] = F[(tile->loff[q * NS + s2] >> 6) * FS + lane];
+#pragma unroll
+        for (int dxi = 0; dxi < 3; ++dxi) {
+          const int h = pj * 3 + dxi;
+          const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
+#pragma unroll
+          for (int x = 0; x < W; ++x) cmac(acc[x], kk, fd[x - dxi + 2]);   // src x = x0 + x - dx
+        }
+      }
+    }
+    __syncthreads();                             // every source column is consumed: X is free
+#pragma unroll
+    for (int x = 0; x < W; ++x) X[(wave * W + x) * OS + lane] = acc[x];
+  }
+  __syncthreads();
+  // 4. inverse z transforms: thread (target position, line, half); pairs are adjacent lanes
+  {
+    gmut<T> U = (gmut<T>)tile->uhat;
+    const int i = tid;
+    if (i < 2 * LPW * NT) {
+      const int jt = i / (2 * LPW), r = i % (2 * LPW), ls = r >> 1, hf = r & 1;
+      T yr[B2], yi[B2];
+#pragma unroll
+      for (int m = 0; m < B2; ++m) {
+        const cpx<T> v = X[jt * OS + ls * P + 2 * m + hf];
+        yr[m] = v.x;
+        yi[m] = v.y;
+      }
+      fft_inreg<B2, +1>(yr, yi);
+      if (hf) {
+#pragma unroll
+        for (int n = 1; n < B2; ++n) {
+          const T c = T(TwTable<P>::t.c[n]), sn = T(TwTable<P>::t.s[n]);   // times e^{+2 pi i n / P}
+          const T a = yr[n] * c - yi[n] * sn, b = yr[n] * sn + yi[n] * c;
+          yr[n] = a;
+          yi[n] = b;
+        }
+      }
+      const int t = tile->tgt[jt / W][jt % W];
+      const int64_t base = 2 * ((int64_t)t * slot + (int64_t)(line0 + ls) * B2);
+#pragma unroll
+      for (int n = 0; n < B2; ++n) {
+        const T sr = yr[n] + __shfl_xor(yr[n], 1), si = yi[n] + __shfl_xor(yi[n], 1);
+        if (t >= 0 && (n < B2 / 2) == (hf == 0)) {
+          U[base + 2 * n] = sr;
+          U[base + 2 * n + 1] = si;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int B2>
+hipError_t launch_fused_b2(SetTable& t, hipStream_t st, int mode) {
+  constexpr int P = 2 * B2, PLANE = P * (B2 + 1), NGRP = PLANE / (64 / P);
+  const int64_t S = (int64_t)P * PLANE;               // complex entries per super-block slot
+  int64_t wg = 0;
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (int64_t)t.s[i].count * ((NGRP + 7) / 8) * 8;
+  }
+  if (wg == 0) return hipSuccess;
+  if (mode == kNearFused + 2)
+    near_fused_kernel<T, B2, 2, near_ctile_cap(kNearFused + 2)><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  else
+    near_fused_kernel<T, B2, 4, near_ctile_cap(kNearFused + 4)><<<(unsigned)wg, 512, 0, st>>>(t, S);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // mode: targets per row W (2, 4 or 8) with NearRow items, kNearTiled + 4 / + 6 with NearTile items
@@ -751,6 +919,11 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
 // chosen by the planner.  All rows of a work set share one kernel table (the wavefronts of a
 // workgroup stage the kernels for all its rows).
 template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_t st, int mode) {
+  if (near_fused(mode)) {
+    if (nb == 16) return launch_fused_b2<T, 32>(t, st, mode);
+    if (nb == 8) return launch_fused_b2<T, 16>(t, st, mode);
+    return hipErrorInvalidValue;
+  }
   const int B2 = 2 * nb, P = 2 * B2;
   const int S = P * P * (B2 + 1);
   if (S % 64) return hipErrorInvalidValue;
@@ -785,6 +958,7 @@ template <typename T> hipError_t launch_near_mac(int nb, SetTable& t, hipStream_
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
+
 
 template hipError_t launch_near_mac<float>(int, SetTable&, hipStream_t, int);
 template hipError_t launch_near_mac<double>(int, SetTable&, hipStream_t, int);

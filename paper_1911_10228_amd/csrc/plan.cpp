@@ -306,6 +306,10 @@ hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
     p->ranges.push_back({(uintptr_t)(*out)->d32, cnt * S * sizeof(c32)});
     p->ranges.push_back({(uintptr_t)(*out)->kp64, cnt * sizeof(void*)});
     p->ranges.push_back({(uintptr_t)(*out)->kp32, cnt * sizeof(void*)});
+    if (s < 0) {
+      p->ranges.push_back({(uintptr_t)(*out)->col64, 14 * S * sizeof(c64)});
+      p->ranges.push_back({(uintptr_t)(*out)->col32, 14 * S * sizeof(c32)});
+    }
     return hipSuccess;
   }
   auto key = std::make_pair(nb, s);
@@ -320,6 +324,10 @@ hipError_t plan_spectra(Plan* p, int nb, int s, const SpecSet** out) {
     ss.d32 = (c32*)fake_alloc(p, cnt * S * sizeof(c32));
     ss.kp64 = (const c64**)fake_alloc(p, cnt * sizeof(void*));
     ss.kp32 = (const c32**)fake_alloc(p, cnt * sizeof(void*));
+    if (s < 0) {
+      ss.col64 = (c64*)fake_alloc(p, 14 * S * sizeof(c64));
+      ss.col32 = (c32*)fake_alloc(p, 14 * S * sizeof(c32));
+    }
     it = p->dry_spectra.emplace(key, ss).first;
   }
   *out = &it->second;
@@ -422,6 +430,14 @@ hipError_t spectra_for(DeviceCtx* ctx, int nb, int s, const SpecSet** out) {
   }
   LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp64, p64.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
   LGF_HIP_CHECK(hipMemcpyAsync((void*)ss.kp32, p32.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, ctx->stream));
+  if (s < 0) {
+    // kernel columns of the fused near step: the 14 kernels h <= 13, [h][line][kz]
+    LGF_HIP_CHECK(hipMalloc(&ss.col64, 14 * S * sizeof(c64)));
+    LGF_HIP_CHECK(hipMalloc(&ss.col32, 14 * S * sizeof(c32)));
+    LGF_HIP_CHECK(launch_kernel_columns<double>(nb, ss.d64, ss.col64, ctx->stream));
+    LGF_HIP_CHECK(launch_kernel_columns<float>(nb, ss.d32, ss.col32, ctx->stream));
+    ctx->bytes += (int64_t)(14 * S * (sizeof(c64) + sizeof(c32)));
+  }
   LGF_HIP_CHECK(hipStreamSynchronize(ctx->stream));
   (void)hipFree(d_sd);
   (void)hipFree(d_real);
@@ -601,8 +617,9 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
       }
       case K_NEAR_MAC: {
         const int t = ty == 0 ? 0 : 1;
-        if (near_piped(mode)) {
+        if (near_compact(mode)) {
           const auto& it = ((const NearCTile<double>*)items)[i];
+          if (near_fused(mode) && !rg(it.ktr, 14 * S2 * es)) return bad("near fused kernel columns", i);
           const int rz = near_ctile_rz(mode), cap = near_ctile_cap(mode);
           if (it.rz != rz) return bad("near pipelined tile shape", i);
           if (it.nreal < 0 || it.nreal > cap || it.zero != sc.nsup_src[t]) return bad("near pipelined tile entries", i);
@@ -669,6 +686,10 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
 // Items are built with the <double> layouts, which are identical to the <float> ones (only
 // pointers change type); each step records the element type its kernel is instantiated for.
 enum : int { TY_F32 = 0, TY_F64 = 1, TY_MIX = 2 };   // TY_MIX: FP32 child level, FP64 parent level
+
+}  // namespace
+void sync_super_modes(Plan* p);
+namespace {
 
 hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<int>& lev,
                       uint64_t budget, std::string* err) {
@@ -1291,64 +1312,68 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         // full as tiles of 2 x 2 (dense levels); the other height is an autotuner candidate
         const bool tall = tiled && 8 * nt4.size() <= 9 * nt.size() / 2;
         if (tall) std::swap(nt, nt4);
-        // the pipelined form where every tile fits its staging (2 x 4 rows first): it overlaps
-        // each workgroup's copies with its arithmetic and was the fastest wherever it applied;
-        // else the one-chunk tiles, 2 x 4 rows where about as full as 2 x 2 (dense levels)
+        // compact tiles (only the source super-blocks that exist staged), 2 x 4 rows first: the
+        // pipelined near MAC where every tile fits (FP32 spectra; FP64 candidates), else the
+        // one-chunk tiles (FP32) or rows (FP64).  The fused form of the compact tiles (z
+        // transforms, MAC and inverse z transforms per line in one kernel) runs on the same
+        // items; it was measured slower than the pipelined MAC with the z passes in HBM (FP32
+        // 0.221 against 0.190 ms per pass on the bench workload, FP64 0.382 against 0.314 ms)
+        // and is kept as a shape to force, not chosen.
         std::vector<NearCTile<D>> ct[2];           // [0]: 2 x 2 rows, [1]: 2 x 4 rows
+        if (!tiled) {
+          nt.clear();
+          nt4.clear();
+          for (const SupInst& si : sup) {
+            if (si.l != l || si.k != k) continue;
+            std::vector<std::pair<I3, int>> tg;
+            for (const SupTgt& t : si.tg) tg.push_back({t.c, t.slot});
+            make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0), (const cpx<D>* const*)ns->kp64, nt, 2);
+            make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0), (const cpx<D>* const*)ns->kp64, nt4, 4);
+          }
+        }
         for (const std::vector<NearTile<D>>* lst : {&nt, &nt4})
-          if (tiled && !lst->empty()) {
+          if (!lst->empty()) {
             const int h = (*lst)[0].rz == 4;
             if (!compact_tiles(*lst, near_ctile_cap(h ? kNearTiled + 7 : kNearTiled + 5), ct[h])) ct[h].clear();
+            for (NearCTile<D>& c : ct[h])
+              c.ktr = tiled ? (const cpx<D>*)ns->col32 : (const cpx<D>*)ns->col64;
           }
         const int piped = !ct[1].empty() ? 1 : !ct[0].empty() ? 0 : -1;
-        if (piped >= 0)
-          push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(ct[piped]), ct[piped].size(), nullptr, pairs,
+        // the image holds a height's compact tiles only where a step (or alternative) uses them
+        size_t ct_off[2] = {0, 0};
+        for (int h = 0; h < 2; ++h)
+          if (!ct[h].empty() && ((h == piped && tiled) || p->tune)) ct_off[h] = hi.add(ct[h]);
+        if (piped >= 0 && tiled)
+          push(steps, l, 4, k, K_NEAR_MAC, sty, ct_off[piped], ct[piped].size(), nullptr, pairs,
                piped ? kNearTiled + 7 : kNearTiled + 5, chain);
         else if (tiled)
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt), nt.size(), nullptr, pairs,
                tall ? kNearTiled + 6 : kNearTiled + 4, chain);
-        else
+        else {
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nr), nr.size(), nullptr, pairs, 4, chain);
+        }
+        const int prim_mode = steps.size() > primary ? steps.back().mode : -1;
         if (p->tune && steps.size() > primary) {
-          // the other launch shapes for the autotuner: tiles of 2 x 4 rows (FP32), rows of 2, 4 or
-          // 8 targets
-          if (tiled) {
-            // the one-chunk tiles of both heights (one of them is the primary where no pipelined
-            // form applies) and the other pipelined height
-            for (const std::vector<NearTile<D>>* lst : {&nt, &nt4}) {
-              if (lst->empty()) continue;
-              const int mode = (*lst)[0].rz == 4 ? kNearTiled + 6 : kNearTiled + 4;
-              if (piped < 0 && lst == &nt) continue;
-              push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(*lst), lst->size(), nullptr, pairs, mode, chain);
-              alt_of.push_back(primary);
-            }
-            for (int h = 0; h < 2; ++h)
-              if (h != piped && !ct[h].empty()) {
-                push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(ct[h]), ct[h].size(), nullptr, pairs,
-                     h ? kNearTiled + 7 : kNearTiled + 5, chain);
-                alt_of.push_back(primary);
-              }
-          } else {
-            // FP64 spectra: the pipelined tiles (FP64 kernel spectra, FP64 sums) as candidates
-            std::vector<NearTile<D>> t64[2];
-            for (const SupInst& si : sup) {
-              if (si.l != l || si.k != k) continue;
-              std::vector<std::pair<I3, int>> tg;
-              for (const SupTgt& t : si.tg) tg.push_back({t.c, t.slot});
-              for (int h = 0; h < 2; ++h)
-                make_tiles(tg, si.sslot, (int)nsup_src[a], SFH(a, 0), SUH(a, 0),
-                           (const cpx<D>* const*)ns->kp64, t64[h], h ? 4 : 2);
-            }
-            for (int h = 0; h < 2; ++h) {
-              std::vector<NearCTile<D>> c64;
-              if (!compact_tiles(t64[h], near_ctile_cap(h ? kNearTiled + 7 : kNearTiled + 5), c64)) continue;
-              push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(c64), c64.size(), nullptr, pairs,
-                   h ? kNearTiled + 7 : kNearTiled + 5, chain);
+          // the other launch shapes for the autotuner: the compact tiles of both heights in the
+          // fused and the pipelined form, the one-chunk tiles (FP32), rows of 2, 4 or 8 targets
+          for (int h = 0; h < 2; ++h) {
+            if (ct[h].empty()) continue;
+            for (int mode : {kNearFused + (h ? 4 : 2), h ? kNearTiled + 7 : kNearTiled + 5}) {
+              if (mode == prim_mode) continue;
+              push(alt_steps, l, 4, k, K_NEAR_MAC, sty, ct_off[h], ct[h].size(), nullptr, pairs, mode, chain);
               alt_of.push_back(primary);
             }
           }
+          if (tiled)
+            for (const std::vector<NearTile<D>>* lst : {&nt, &nt4}) {
+              if (lst->empty()) continue;
+              const int mode = (*lst)[0].rz == 4 ? kNearTiled + 6 : kNearTiled + 4;
+              if (mode == prim_mode) continue;
+              push(alt_steps, l, 4, k, K_NEAR_MAC, sty, hi.add(*lst), lst->size(), nullptr, pairs, mode, chain);
+              alt_of.push_back(primary);
+            }
           for (int shape : {2, 4, 8}) {        // rows of 2 suit sparse levels
-            if (!tiled && shape == 4) continue;
+            if (shape == prim_mode) continue;
             std::vector<NearRow<D>> alt_rows;
             for (const SupInst& si : sup) {
               if (si.l != l || si.k != k) continue;
@@ -1494,7 +1519,8 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       }
       o.inv_h = std::ldexp(1.0, lev[i]);
       o.leaf = leaf[i];
-      o.pad = 0;
+      o.par_off = lev[i] > 0 ? (int64_t)cmap[lev[i] - 1].at(parent_of(coords[i])) * N3 : -1;
+      o.octant = lev[i] > 0 ? octant_of(coords[i]) : 0;
     }
     LGF_HIP_CHECK(ar.alloc(&p->d_ops, ops.size() * sizeof(OpItem)));
     if (n > 0 && !p->dry)
@@ -1506,6 +1532,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
+  sync_super_modes(p);
   if (p->correction) {
     for (size_t i = 0; i < p->pass.size(); ++i)
       if (p->pass[i].kind == K_CONVERT && p->pass[i].l == 0) p->conv_idx = (int64_t)i;
@@ -1532,6 +1559,19 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
 }  // namespace
 
 hipError_t plan_autotune(Plan* p, Binding* b, hipStream_t st);
+
+// The super-block transforms of a level follow its near step: line-major planes (mode 1) for the
+// fused form, the plane stack and spectra (mode 0) for every other form.
+void sync_super_modes(Plan* p) {
+  std::map<std::pair<int, int>, int> lm;
+  for (const Step& s : p->pass)
+    if (s.kind == K_NEAR_MAC) lm[{s.l, s.sub}] = near_fused(s.mode) ? 1 : 0;
+  for (Step& s : p->pass)
+    if (s.kind == K_SUP_FWD || s.kind == K_SUP_INV) {
+      auto it = lm.find({s.l, s.sub});
+      s.mode = it != lm.end() ? it->second : 0;
+    }
+}
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,
                       bool fp32, int dc_iters, uint64_t budget, Plan** out, std::string* err, bool dry,
@@ -1644,17 +1684,28 @@ hipError_t plan_set_near_shape(Plan* p, int shape) {
   // the correction plan (FP32 spectra) takes the shape where it has it
   if (p->corr) (void)plan_set_near_shape(p->corr, shape);
   if (p->near0.empty()) p->near0 = p->pass;
-  std::vector<std::pair<size_t, const Step*>> pick;
+  std::vector<std::pair<size_t, Step>> pick;
   for (size_t i = 0; i < p->near0.size(); ++i) {
     const Step& s0 = p->near0[i];
     if (s0.kind != K_NEAR_MAC) continue;
     const Step* c = (shape == 0 || s0.mode == shape) ? &s0 : nullptr;
     for (const auto& pa : p->alt)
       if (!c && pa.first == i && pa.second.mode == shape) c = &pa.second;
-    if (!c) return hipErrorInvalidValue;
-    pick.push_back({i, c});
+    if (c) {
+      pick.push_back({i, *c});
+      continue;
+    }
+    // the fused and the pipelined form of compact tiles of one height run on the same items
+    if (near_compact(s0.mode) && near_compact(shape) && near_ctile_rz(s0.mode) == near_ctile_rz(shape)) {
+      Step x = s0;
+      x.mode = shape;
+      pick.push_back({i, x});
+      continue;
+    }
+    return hipErrorInvalidValue;
   }
-  for (const auto& pc : pick) p->pass[pc.first] = *pc.second;
+  for (const auto& pc : pick) p->pass[pc.first] = pc.second;
+  sync_super_modes(p);
   if (!p->dry) graph_forget(p);
   return hipSuccess;
 }
@@ -1784,9 +1835,9 @@ hipError_t launch_kind(int kind, int nb, SetTable& t, hipStream_t st, int mode) 
     case K_COMBINE: return launch_combine<T>(nb, t, st);
     case K_COARSEN: return launch_coarsen(nb, t, st);
     case K_RESIDUAL: return launch_residual(nb, t, st);
-    case K_SUP_FWD: return launch_super_fwd<T, T>(nb, t, st);
+    case K_SUP_FWD: return launch_super_fwd<T, T>(nb, t, st, mode);
     case K_NEAR_MAC: return launch_near_mac<T>(nb, t, st, mode);
-    case K_SUP_INV: return launch_super_inv<T, T>(nb, t, st);
+    case K_SUP_INV: return launch_super_inv<T, T>(nb, t, st, mode);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1797,8 +1848,8 @@ hipError_t launch_typed(int kind, int ty, int nb, SetTable& t, hipStream_t st, i
   if (kind == K_ANTERP) return launch_anterp<float, double>(nb, t, st);
   if (kind == K_INTERP) return launch_interp<float, double>(nb, t, st);
   // FP64 super-block spectra of FP32 child blocks
-  if (kind == K_SUP_FWD) return launch_super_fwd<double, float>(nb, t, st);
-  if (kind == K_SUP_INV) return launch_super_inv<double, float>(nb, t, st);
+  if (kind == K_SUP_FWD) return launch_super_fwd<double, float>(nb, t, st, mode);
+  if (kind == K_SUP_INV) return launch_super_inv<double, float>(nb, t, st, mode);
   if (kind == K_NEAR_MAC) return launch_near_mac<double>(nb, t, st, mode);
   return hipErrorInvalidValue;
 }
@@ -2178,7 +2229,10 @@ hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
   for (auto& g : groups) {
     const Step prim = p->pass[g.first];
     std::vector<Step> cands{prim};
-    for (const Step& x : g.second) cands.push_back(x);
+    // the fused near form replaces the z passes of the super-block transforms as well, so its
+    // single-step time does not compare with the other shapes': it is not a candidate
+    for (const Step& x : g.second)
+      if (!(x.kind == K_NEAR_MAC && near_fused(x.mode))) cands.push_back(x);
     const std::array<int64_t, 3> key{p->nb, (prim.kind == K_MAC ? 2000 : 1000) + prim.ty, prim.work};
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
@@ -2220,12 +2274,13 @@ hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  sync_super_modes(p);
   return hipSuccess;
 }
 
 hipError_t plan_apply(Plan* p, int op, const double* u, double* out, hipStream_t st) {
   if (!p || p->dry || op < 0 || op > 2 || !u || !out) return hipErrorInvalidValue;
-  return launch_fwd_op(p->nb, op, (const OpItem*)p->d_ops, p->nblocks, u, out, st);
+  return launch_fwd_op(p->nb, op, (const OpItem*)p->d_ops, p->nblocks, u, out, p->d_w3, st);
 }
 
 }  // namespace lgf

@@ -27,6 +27,8 @@ struct SpecSet {
   c32* d32 = nullptr;
   const c64** kp64 = nullptr;          // device arrays of count pointers
   const c32** kp32 = nullptr;
+  c64* col64 = nullptr;                // super-block sets: kernel columns of the fused near step
+  c32* col32 = nullptr;                // [14][line][kz], FP64 and FP32
 };
 
 struct DeviceCtx {

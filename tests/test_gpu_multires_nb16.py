@@ -113,18 +113,19 @@ def test_refined_nb16_fp32_defect_correction(lgf):
 
 def test_refined_nb16_every_near_shape(lgf):
     """Every launch shape of the base-level super-block MAC, forced on an autotuned plan of the
-    two-level layout: rows of 2, 4 and 8 targets and the pipelined tiles, on FP64 spectra (FP64
-    plans, and FP32 plans of a refined layout, whose super-block spectra are FP64)."""
+    two-level layout: rows of 2, 4 and 8 targets, the pipelined and the fused compact tiles, on
+    FP64 spectra (FP64 plans, and FP32 plans of a refined layout, whose super-block spectra are
+    FP64)."""
     L, ref = case("two")
     f = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
     for precision, tol in ((0, 1e-12), (1, 1e-6)):
         p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, precision, 0, autotune=1)
-        for shape in (2, 4, 8, 21, 23, 0):
+        for shape in (2, 4, 8, 21, 23, 42, 44, 0):
             print(f"case two precision {precision} near shape {shape}", flush=True)
             try:
                 p.set_near_shape(shape)
             except RuntimeError:
-                assert shape in (21, 23), shape     # a pipelined tile needs <= 36 / 48 sources
+                assert shape in (21, 23, 42, 44), shape   # compact tiles need <= 36 / 48 sources
                 continue
             u, _ = solve(lgf, L, plan=p)
             assert rel_linf(u, ref) <= tol, f"precision {precision} shape {shape}"

@@ -98,11 +98,13 @@ def test_every_mac_shape_matches_oracle(lgf):
 def test_every_near_shape_matches_oracle(lgf):
     """Every launch shape of the base-level super-block MAC, forced on an autotuned plan, against
     the FP64 oracle (FP64 spectra: rows of 2, 4 and 8; FP32: also tiles, one chunk per
-    workgroup or pipelined over runs of chunks)."""
+    workgroup or pipelined over runs of chunks; both: the fused form of compact tiles of 2 x 2
+    and 2 x 4 rows, with the super-block transforms switched to line-major planes)."""
     L = workloads.uniform_mixture(nblk=6, n_b=8, n_gauss=4, seed=31, interp_order=6)
     ref = fmm.flgf(L.blocks, L.f, L.n_b, L.interp_order)
     f = field(L)
-    for precision, shapes, tol in ((0, (2, 4, 8, 21, 23), 1e-12), (1, (20, 22, 21, 23, 2, 4, 8), 1e-6)):
+    for precision, shapes, tol in ((0, (2, 4, 8, 21, 23, 42, 44), 1e-12),
+                                   (1, (20, 22, 21, 23, 2, 4, 8, 42, 44), 1e-6)):
         p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, precision, 0, autotune=1)
         for shape in shapes + (0,):
             print(f"case precision {precision} near shape {shape}", flush=True)

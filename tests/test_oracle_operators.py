@@ -1,5 +1,7 @@
 """Pins of the forward operators of ``oracle.operators`` (CPU): exactness on polynomials at every
-level of a refined layout, curl of a gradient = 0, and consistency with the refined solve."""
+level of a refined layout, cells at the refinement interface included (there the neighbour is the
+parent's quadratic, exact for quadratics), curl of a gradient = 0, and consistency with the
+refined solve."""
 import numpy as np
 
 from oracle import multires, operators
@@ -51,20 +53,32 @@ def test_gradient_exact_on_quadratics():
     exact = np.stack([a[0] + 2 * b[0] * X + b[3] * Y + b[5] * Z,
                       a[1] + 2 * b[1] * Y + b[3] * X + b[4] * Z,
                       a[2] + 2 * b[2] * Z + b[4] * Y + b[5] * X])
-    mask = multires.residual_mask(blocks, levels, N_B)
+    mask = operators.op_mask(blocks, levels, N_B)
     assert mask[levels == 1].any() and mask[levels == 0].any()
+    # every cell of the refined blocks is evaluated, the interface cells among them
+    inner = multires.residual_mask(blocks, levels, N_B)
+    assert mask[levels == 1].all() and (mask & ~inner)[levels == 1].any()
     _check_on_mask(operators.apply(blocks, levels, phi, N_B, "gradient"), exact, mask)
 
 
-def test_laplacian_exact_on_cubics():
+def test_laplacian_exact_on_cubics_and_at_interfaces_on_quadratics():
+    """Away from level boundaries the 7-point Laplacian is exact for cubics; on every evaluated
+    cell (the interface cells take the parent's quadratic as neighbour) for quadratics."""
     blocks, levels = refined_layout()
     X, Y, Z = positions(blocks, levels, N_B)
     c = np.random.default_rng(12).normal(size=7)
     phi = (c[0] * X ** 3 + c[1] * X * X * Y + c[2] * X * Y * Z + c[3] * Z ** 3 + c[4] * Y * Y * Z
            + c[5] * X * X + c[6] * Y * Z)
     exact = 6 * c[0] * X + 2 * c[1] * Y + 6 * c[3] * Z + 2 * c[4] * Z + 2 * c[5]
-    mask = multires.residual_mask(blocks, levels, N_B)
-    _check_on_mask(operators.apply(blocks, levels, phi, N_B, "laplacian"), exact, mask)
+    inner = multires.residual_mask(blocks, levels, N_B)
+    got = operators.apply(blocks, levels, phi, N_B, "laplacian")
+    assert np.abs(got[inner] - exact[inner]).max() <= 1e-12 * np.abs(exact[inner]).max()
+    q = np.random.default_rng(15).normal(size=4)
+    quad = q[0] * X * X + q[1] * Y * Z + q[2] * Z * Z + q[3] * X
+    mask = operators.op_mask(blocks, levels, N_B)
+    # rounding: the field reaches |quad| ~ 1e3 and the stencil scales it by h^-2 = 4
+    _check_on_mask(operators.apply(blocks, levels, quad, N_B, "laplacian"),
+                   np.full(X.shape, 2 * q[0] + 2 * q[2]), mask, rel=1e-14 * 4 * np.abs(quad).max())
 
 
 def test_curl_exact_on_quadratic_fields():
@@ -80,8 +94,26 @@ def test_curl_exact_on_quadratic_fields():
     dAx_dz, dAz_dx = k[0, 2] + k[0, 3] * Y, k[2, 1] + k[2, 3] * Y
     dAy_dx, dAx_dy = k[1, 2] + k[1, 3] * Z, k[0, 1] + k[0, 3] * Z
     exact = np.stack([dAz_dy - dAy_dz, dAx_dz - dAz_dx, dAy_dx - dAx_dy])
-    mask = multires.residual_mask(blocks, levels, N_B)
+    mask = operators.op_mask(blocks, levels, N_B)
     _check_on_mask(operators.apply(blocks, levels, A, N_B, "curl"), exact, mask)
+
+
+def test_interface_values_come_from_the_parent():
+    """A field that is a different quadratic on each level: at a refinement interface the
+    operators see the parent's polynomial outside the fine blocks, so the gradient of a fine
+    interface cell mixes the two (not the fine quadratic's exact gradient); a planted zero ghost
+    would give yet another value."""
+    blocks, levels = refined_layout()
+    X, Y, Z = positions(blocks, levels, N_B)
+    fine = levels[:, None, None, None] == 1
+    phi = np.where(fine, X * X, Y * Y + 1.0)          # the parent level holds y^2 + 1
+    g = operators.apply(blocks, levels, phi, N_B, "gradient")
+    i = int(np.nonzero(levels == 1)[0][0])            # child (2, 0, 2): its -x face is an interface
+    h = 0.5
+    x0, y0 = X[i, :, :, 0], Y[i, :, :, 0]
+    # (u(x + h) - ghost) / 2h, the ghost the parent's quadratic y^2 + 1 at the ghost cell
+    assert np.allclose(g[0, i, :, :, 0], ((x0 + h) ** 2 - (y0 * y0 + 1.0)) / (2 * h), rtol=0, atol=1e-11)
+    assert np.allclose(g[0, i, :, :, 1:-1], 2 * X[i, :, :, 1:-1], rtol=0, atol=1e-11)
 
 
 def test_curl_of_gradient_vanishes():
