@@ -260,6 +260,9 @@ lgf_status lgf_server_wait_all(lgf_server_t s);
 lgf_status lgf_server_stats(lgf_server_t s, double* p50_us, double* p99_us, double* points_per_s,
                             int64_t* completed);
 lgf_status lgf_server_info(lgf_server_t s, lgf_server_memory* out);
+/* Starts the statistics afresh (latencies, throughput window, peaks and counters of
+ * lgf_server_info), keeping the cached plans and the reserved memory: e.g. after a warm-up. */
+lgf_status lgf_server_reset_stats(lgf_server_t s);
 lgf_status lgf_server_destroy(lgf_server_t s);
 
 /* Refinement-criterion layout builder (Sec. 3, Convergence subsection, eq. ref_crit), one

@@ -346,6 +346,7 @@ struct lgf_server_s {
   int64_t plan_hits = 0, plan_misses = 0;
   double plan_ms_total = 0.0, plan_ms_max = 0.0;
   int64_t running = 0;                     // requests in launched steps
+  int64_t planning = 0;                    // requests the planner holds
   std::map<int64_t, int> state;            // 0 queued, 1 running, 2 done, -1 failed
   std::vector<double> lat_us;
   int64_t next_id = 1;
@@ -464,6 +465,7 @@ struct lgf_server_s {
       }
       Req r = std::move(plan_queue.front());
       plan_queue.pop_front();
+      ++planning;
       const std::vector<int32_t> key = layout_key(r);
       auto it = plans.find(key);
       if (it != plans.end()) {
@@ -481,6 +483,7 @@ struct lgf_server_s {
         if (e == hipSuccess) e = lgf::plan_trim(p);     // the tuning workspace: slots serve the plan
         if (e != hipSuccess) {
           lgf::plan_free(p);
+          --planning;
           fail(r, from_hip(e));
           continue;
         }
@@ -508,6 +511,7 @@ struct lgf_server_s {
       r.blocks.clear();
       r.levels.clear();
       queue.push_back(std::move(r));
+      --planning;
       cv.notify_all();
     }
   }
@@ -726,7 +730,8 @@ lgf_status lgf_server_wait_all(lgf_server_t s) {
   if (!s) return LGF_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
   s->cv_done.wait(lk, [&] {
-    return s->plan_queue.empty() && s->queue.empty() && s->inflight.empty() && s->running == 0;
+    return s->plan_queue.empty() && s->planning == 0 && s->queue.empty() && s->inflight.empty() &&
+           s->running == 0;
   });
   return s->error;
 }
@@ -768,6 +773,20 @@ lgf_status lgf_server_info(lgf_server_t s, lgf_server_memory* out) {
   out->plan_misses = s->plan_misses;
   out->plan_ms_total = s->plan_ms_total;
   out->plan_ms_max = s->plan_ms_max;
+  return LGF_OK;
+}
+
+lgf_status lgf_server_reset_stats(lgf_server_t s) {
+  if (!s) return LGF_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->lat_us.clear();
+  s->points_done = 0;
+  s->have_first = false;
+  s->peak_in_use = s->in_use;
+  s->peak_slots = s->slots;
+  s->binds = 0;
+  s->plan_hits = s->plan_misses = 0;
+  s->plan_ms_total = s->plan_ms_max = 0.0;
   return LGF_OK;
 }
 

@@ -577,16 +577,22 @@ hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
 // NB / kResidualSlabs planes), one thread per (x, y) column: each input component's slab and its
 // one-cell halo are staged in LDS (each halo cell computed once), then every output of the slab
 // is formed from LDS and stored coalesced.
-template <int NB>
+// workgroups (z-slabs) per block of the forward operators: 2 for one input component, 4 for
+// three (their LDS slabs would hold the occupancy down)
+template <int NIN> constexpr int op_slabs() { return NIN == 1 ? 2 : 4; }
+
+template <int NB, int NIN>
 __global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restrict__ items, int op,
                                                          const double* __restrict__ u, double* __restrict__ out,
                                                          int64_t cs, const double* __restrict__ w3tab) {
-  constexpr int SZ = NB / kResidualSlabs, E = NB + 2, N2 = NB * NB, PL = E * E, SL = (SZ + 2) * PL;
-  __shared__ double ext[3 * SL];
-  const OpItem& it = items[blockIdx.x / kResidualSlabs];
-  const int z0 = (int)(blockIdx.x % kResidualSlabs) * SZ;
+  constexpr int SLABS = op_slabs<NIN>();
+  constexpr int SZ = NB / SLABS, E = NB + 2, N2 = NB * NB, PL = E * E, SL = (SZ + 2) * PL;
+  constexpr int NH = 4 * NB * SZ;           // x and y halo cells of the slab's planes
+  __shared__ double ext[NIN * SL];
+  const OpItem& it = items[blockIdx.x / SLABS];
+  const int z0 = (int)(blockIdx.x % SLABS) * SZ;
   const int t = threadIdx.x, x = t % NB, y = t / NB;
-  const int nin = op == 2 ? 3 : 1, nout = op == 0 ? 1 : 3;
+  const int nout = op == 0 ? 1 : 3;
   const gview<double> o = gl(out);
   if (!it.leaf) {
     for (int c = 0; c < nout; ++c)
@@ -617,14 +623,20 @@ __global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restric
     if (ghost) return refine_point<NB, double>(U + cb + it.par_off, w3, oc[0] * NB + qx, oc[1] * NB + qy, oc[2] * NB + qz);
     return 0.0;
   };
-  // x and y halo cells of the slab's planes: 4 faces x NB x SZ = NB^2 cells, one per thread
-  const int hf = t / (NB * SZ), hr = t % (NB * SZ), ha = hr % NB, hz = hr / NB;
-  const int hq[3] = {hf == 0 ? -1 : hf == 1 ? NB : ha, hf == 2 ? -1 : hf == 3 ? NB : ha, z0 + hz};
-  for (int c = 0; c < nin; ++c) {
-    double* const e = ext + c * SL;
+  // the own column (all loads issued before the LDS stores), then the x and y halo cells
 #pragma unroll
-    for (int j = 0; j < SZ + 2; ++j) e[j * PL + (y + 1) * E + x + 1] = cell(c, x, y, z0 - 1 + j);
-    e[(hz + 1) * PL + (hq[1] + 1) * E + hq[0] + 1] = cell(c, hq[0], hq[1], hq[2]);
+  for (int c = 0; c < NIN; ++c) {
+    double col[SZ + 2];
+#pragma unroll
+    for (int j = 0; j < SZ + 2; ++j) col[j] = cell(c, x, y, z0 - 1 + j);
+#pragma unroll
+    for (int j = 0; j < SZ + 2; ++j) ext[c * SL + j * PL + (y + 1) * E + x + 1] = col[j];
+  }
+  for (int hc = t; hc < NH; hc += N2) {
+    const int hf = hc / (NB * SZ), hr = hc % (NB * SZ), ha = hr % NB, hz = hr / NB;
+    const int qx = hf == 0 ? -1 : hf == 1 ? NB : ha, qy = hf == 2 ? -1 : hf == 3 ? NB : ha;
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) ext[c * SL + (hz + 1) * PL + (qy + 1) * E + qx + 1] = cell(c, qx, qy, z0 + hz);
   }
   __syncthreads();
   const double ih = it.inv_h, hh = 0.5 * it.inv_h;
@@ -648,7 +660,7 @@ __global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restric
       o[at] = ok ? d(0, 1) : 0.0;
       o[cs + at] = ok ? d(0, E) : 0.0;
       o[2 * cs + at] = ok ? d(0, PL) : 0.0;
-    } else {
+    } else if constexpr (NIN == 3) {
       o[at] = ok ? d(2, E) - d(1, PL) : 0.0;
       o[cs + at] = ok ? d(0, PL) - d(2, 1) : 0.0;
       o[2 * cs + at] = ok ? d(1, 1) - d(0, E) : 0.0;
@@ -661,8 +673,13 @@ hipError_t launch_fwd_op(int nb, int op, const OpItem* items, int64_t n, const d
   if (n == 0) return hipSuccess;
   if (!items || !w3 || op < 0 || op > 2) return hipErrorInvalidValue;
   const int64_t n3 = (int64_t)nb * nb * nb;
-  LGF_NB_DISPATCH(nb, fwd_op_kernel<NB><<<(unsigned)(n * kResidualSlabs), NB * NB, 0, st>>>(items, op, u, out,
-                                                                                               n * n3, w3));
+  if (op == 2) {
+    const unsigned g = (unsigned)(n * op_slabs<3>());
+    LGF_NB_DISPATCH(nb, (fwd_op_kernel<NB, 3><<<g, NB * NB, 0, st>>>(items, op, u, out, n * n3, w3)));
+  } else {
+    const unsigned g = (unsigned)(n * op_slabs<1>());
+    LGF_NB_DISPATCH(nb, (fwd_op_kernel<NB, 1><<<g, NB * NB, 0, st>>>(items, op, u, out, n * n3, w3)));
+  }
   return hipGetLastError();
 }
 

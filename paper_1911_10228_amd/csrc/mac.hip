@@ -745,41 +745,39 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
 }
 
 // Fused form: the base-level convolution of one tile for one group of (kx, ky) lines (one line
-// of P = 64 frequencies kz for N_b = 16, two of 32 for N_b = 8: 64 lanes either way), from the
-// line-major planes of the forward (x, y) pass to the line-major planes of the inverse one.
-//  1. the tile's staged source columns (B2 values of z per line, contiguous) and the 14 kernel
-//     columns of the lines go to LDS;
-//  2. each column's z transform, zero-padded from B2 to P, is two length-B2 FFTs (even and odd
-//     kz, the odd one of the input twiddled by e^{-2 pi i z / P}), one per lane of a pair;
-//  3. the MAC of the tiled form: wavefront = target row, lane = (line, kz);
-//  4. each target's inverse z transform cropped to z < B2 is two length-B2 inverse FFTs (even and
-//     odd kz, the odd one twiddled by e^{+2 pi i z / P} afterwards) on a lane pair, summed with a
-//     lane shuffle; each lane stores half of the column.
-// The 1 / P^3 of the inverse transform is left to the inverse (y, x) pass.  Workgroups: line
-// groups dealt to the XCDs in turn, all tiles of a group on one XCD (they share its source and
-// kernel columns in L2).
+// of P = 64 frequencies kz for N_b = 16, two of 32 for N_b = 8: 64 values per column either
+// way), from the line-major planes of the forward (x, y) pass to the line-major planes of the
+// inverse one.  The z transforms are split as P = 8 Q (Cooley-Tukey, Q = P / 8) so that 8 or 16
+// lanes share a column and each holds 4 to 8 values:
+//   forward, zero-padded (z < P/2 = 4 Q nonzero): with z = Q n1 + n2 and kz = k1 + 8 k2,
+//     Y[n2][k1] = W_P^{n2 k1} sum_{n1 < 4} x[Q n1 + n2] W_8^{n1 k1}   (lane n2: an 8-point DFT of 4 inputs)
+//     X[k1 + 8 k2] = sum_{n2 < Q} Y[n2][k1] W_Q^{n2 k2}               (lane k1: a Q-point DFT)
+//   inverse, cropped to z < P/2: with kz = Q k1 + k2 and z = n1 + 8 n2,
+//     Z[k2][n1] = W_P^{-n1 k2} sum_{k1 < 8} X[Q k1 + k2] W_8^{-n1 k1}  (lane k2: an 8-point DFT)
+//     x[n1 + 8 n2] = sum_{k2 < Q} Z[k2][n1] W_Q^{-n2 k2}, n2 < Q/2      (lane n1: a Q-point DFT)
+// Phases (barriers between): 1. forward step 1, each lane loading its 4 inputs straight from the
+// planes, and the kernel columns to LDS; 2. forward step 2 in place; 3. the MAC of the tiled form
+// (wavefront = target row, lane = (line, kz)); the target spectra replace the source spectra in
+// LDS; 4. and 5. the inverse steps, the last storing the cropped column.  The 1 / P^3 of the
+// inverse transform is left to the inverse (y, x) pass.  Workgroups: line groups dealt to the
+// XCDs in turn, all tiles of a group on one XCD (they share its source and kernel columns in L2).
 template <typename T, int B2, int RZ, int NC>
 __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int64_t slot) {
-  constexpr int P = 2 * B2, H = B2 + 1, PLANE = P * H;
+  constexpr int P = 2 * B2, H = B2 + 1, PLANE = P * H, Q = P / 8;
   constexpr int LPW = 64 / P;                    // lines per workgroup
   constexpr int NGRP = PLANE / LPW;              // line groups
   constexpr int W = kTileW, WAVES = 2 * RZ, NS = W + 2, NT = WAVES * W, NTH = 64 * WAVES;
-  // LDS strides padded by one complex value so that lanes working on different entries (or
-  // targets) in the transform phases fall on different banks
-  constexpr int FS = 66, XS = 33, OS = 66;       // entry stride of F, column stride, target stride
-  constexpr int XN = NC * XS > NT * OS ? NC * XS : NT * OS;
-  static_assert(PLANE % LPW == 0 && LPW * B2 == 32, "one group: 32 z values and 64 kz values per column");
-  static_assert(2 * LPW * NC <= NTH && 2 * LPW * NT <= NTH, "one transform per lane");
-  __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra: entry e, lane (line, kz); entry NC zero
-  __shared__ cpx<T> X[XN];                       // source columns [e][line][z], then target spectra
-  __shared__ cpx<T> K[kNearHalfK * 64];          // kernel columns [h][line][kz]
+  constexpr int FS = 66;                         // LDS entry stride (complex), padded
+  static_assert(PLANE % LPW == 0 && LPW * Q == 8 && NT <= NC + 1, "column shape");
+  __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra (entry NC: zeros), then target spectra
+  __shared__ cpx<T> tw[P];                       // e^{-2 pi i m / P}
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;   // wg_begin is a multiple of 8
   const int ntiles = ws.count;
-  const int64_t j = local >> 3;
-  const int grp = (int)(j / ntiles) * 8 + (int)(local & 7);
-  const int ti = (int)(j % ntiles);
+  const int64_t jj = local >> 3;
+  const int grp = (int)(jj / ntiles) * 8 + (int)(local & 7);
+  const int ti = (int)(jj % ntiles);
   if (grp >= NGRP) return;
   const int line0 = grp * LPW;
   const __attribute__((address_space(4))) NearCTile<T>* tile =
@@ -787,51 +785,75 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int tid = threadIdx.x;
   const int nreal = tile->nreal;
-  // 1. source and kernel columns
+  if (tid < P) {
+    double sn, cs;
+    sincospi(2.0 * tid / P, &sn, &cs);
+    tw[tid] = cpx<T>{T(cs), T(-sn)};
+  }
+  if (tid < 64) F[NC * FS + tid] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  // 1. forward step 1: thread (entry, line, n2), 8 per entry
   {
     const gview<const T> Fp = gl((const T*)tile->fhat);
-    for (int i = tid; i < nreal * 32; i += NTH) {
-      const int e = i >> 5, r = i & 31;
-      const int64_t o = 2 * ((int64_t)tile->src[e] * slot + (int64_t)line0 * B2 + r);
-      X[e * XS + r] = cpx<T>{Fp[o], Fp[o + 1]};
-    }
-    const gview<const T> Kc = gl((const T*)tile->ktr);
-    for (int i = tid; i < kNearHalfK * 64; i += NTH) {
-      const int h = i >> 6, r = i & 63;
-      const int64_t o = 2 * (((int64_t)h * PLANE + line0) * P + r);
-      K[i] = cpx<T>{Kc[o], Kc[o + 1]};
-    }
-    if (tid < 64) F[NC * FS + tid] = cpx<T>{T(0), T(0)};
-  }
-  __syncthreads();
-  // 2. forward z transforms: thread (entry, line, half)
-  for (int i = tid; i < 2 * LPW * nreal; i += NTH) {
-    const int e = i / (2 * LPW), r = i % (2 * LPW), ls = r >> 1, hf = r & 1;
-    T xr[B2], xi[B2];
+    for (int i = tid; i < 8 * nreal; i += NTH) {
+      const int e = i >> 3, r = i & 7, ls = r / Q, n2 = r % Q;
+      const int64_t col = 2 * ((int64_t)tile->src[e] * slot + (int64_t)(line0 + ls) * B2);
+      T yr[8], yi[8];
 #pragma unroll
-    for (int n = 0; n < B2; ++n) {
-      const cpx<T> v = X[e * XS + ls * B2 + n];
-      if (hf && n > 0) {
-        const T c = T(TwTable<P>::t.c[n]), sn = T(TwTable<P>::t.s[n]);   // times e^{-2 pi i n / P}
-        xr[n] = v.x * c + v.y * sn;
-        xi[n] = v.y * c - v.x * sn;
-      } else {
-        xr[n] = v.x;
-        xi[n] = v.y;
+      for (int n1 = 0; n1 < 8; ++n1) {
+        if (n1 < 4) {
+          yr[n1] = Fp[col + 2 * (Q * n1 + n2)];
+          yi[n1] = Fp[col + 2 * (Q * n1 + n2) + 1];
+        } else {
+          yr[n1] = T(0);
+          yi[n1] = T(0);
+        }
+      }
+      fft_inreg<8, -1>(yr, yi);
+      cpx<T>* const y = F + e * FS + ls * P + n2 * 8;
+#pragma unroll
+      for (int k1 = 0; k1 < 8; ++k1) {
+        const cpx<T> w = tw[(n2 * k1) % P];          // W_P^{n2 k1}
+        y[k1] = cpx<T>{yr[k1] * w.x - yi[k1] * w.y, yr[k1] * w.y + yi[k1] * w.x};
       }
     }
-    fft_inreg<B2, -1>(xr, xi);
+  }
+  __syncthreads();
+  // 2. forward step 2: thread (entry, line, k1), 8 LPW per entry; read all, then write in place
+  for (int base = 0; base < 8 * LPW * nreal; base += NTH) {
+    const int i = base + tid;
+    const bool on = i < 8 * LPW * nreal;
+    const int e = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, k1 = r & 7;
+    T xr[Q], xi[Q];
+    if (on) {
 #pragma unroll
-    for (int m = 0; m < B2; ++m) F[e * FS + ls * P + 2 * m + hf] = cpx<T>{xr[m], xi[m]};
+      for (int n2 = 0; n2 < Q; ++n2) {
+        const cpx<T> v = F[e * FS + ls * P + n2 * 8 + k1];
+        xr[n2] = v.x;
+        xi[n2] = v.y;
+      }
+      fft_inreg<Q, -1>(xr, xi);
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) F[e * FS + ls * P + k1 + 8 * k2] = cpx<T>{xr[k2], xi[k2]};
+    }
   }
   __syncthreads();
   // 3. MAC: wavefront = row (ry, rz) of the tile, lane = (line, kz)
   {
     const uint32_t smask = tile->src_mask;
     const int ry = wave & 1, rz = wave >> 1;
+    // the 14 kernel values of the lane's (line, kz), straight from memory (L2: every tile of the
+    // line group reads the same 14 columns)
+    const gview<const T> Kc = gl((const T*)tile->ktr);
     cpx<T> kv[kNearHalfK];
 #pragma unroll
-    for (int h = 0; h < kNearHalfK; ++h) kv[h] = K[h * 64 + lane];
+    for (int h = 0; h < kNearHalfK; ++h) {
+      const int64_t o = 2 * (((int64_t)h * PLANE + line0) * P + lane);
+      kv[h] = cpx<T>{Kc[o], Kc[o + 1]};
+    }
     cpx<T> acc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[q] = {T(0), T(0)};
@@ -853,43 +875,56 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
         }
       }
     }
-    __syncthreads();                             // every source column is consumed: X is free
+    __syncthreads();                             // every source spectrum is consumed
 #pragma unroll
-    for (int x = 0; x < W; ++x) X[(wave * W + x) * OS + lane] = acc[x];
+    for (int x = 0; x < W; ++x) F[(wave * W + x) * FS + lane] = acc[x];
   }
   __syncthreads();
-  // 4. inverse z transforms: thread (target position, line, half); pairs are adjacent lanes
+  // 4. inverse step 1: thread (target, line, k2), 8 per target; read all, then write in place
+  {
+    const int i = tid;
+    const bool on = i < 8 * NT;
+    const int jt = i >> 3, r = i & 7, ls = r / Q, k2 = r % Q;
+    T zr[8], zi[8];
+    if (on) {
+#pragma unroll
+      for (int k1 = 0; k1 < 8; ++k1) {
+        const cpx<T> v = F[jt * FS + ls * P + Q * k1 + k2];
+        zr[k1] = v.x;
+        zi[k1] = v.y;
+      }
+      fft_inreg<8, +1>(zr, zi);
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+      for (int n1 = 0; n1 < 8; ++n1) {
+        const cpx<T> w = tw[(n1 * k2) % P];          // W_P^{n1 k2}, conjugated below
+        F[jt * FS + ls * P + k2 * 8 + n1] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
+      }
+    }
+  }
+  __syncthreads();
+  // 5. inverse step 2: thread (target, line, n1), 8 LPW per target; store z = n1 + 8 n2 < B2
   {
     gmut<T> U = (gmut<T>)tile->uhat;
-    const int i = tid;
-    if (i < 2 * LPW * NT) {
-      const int jt = i / (2 * LPW), r = i % (2 * LPW), ls = r >> 1, hf = r & 1;
-      T yr[B2], yi[B2];
-#pragma unroll
-      for (int m = 0; m < B2; ++m) {
-        const cpx<T> v = X[jt * OS + ls * P + 2 * m + hf];
-        yr[m] = v.x;
-        yi[m] = v.y;
-      }
-      fft_inreg<B2, +1>(yr, yi);
-      if (hf) {
-#pragma unroll
-        for (int n = 1; n < B2; ++n) {
-          const T c = T(TwTable<P>::t.c[n]), sn = T(TwTable<P>::t.s[n]);   // times e^{+2 pi i n / P}
-          const T a = yr[n] * c - yi[n] * sn, b = yr[n] * sn + yi[n] * c;
-          yr[n] = a;
-          yi[n] = b;
-        }
-      }
+    for (int i = tid; i < 8 * LPW * NT; i += NTH) {
+      const int jt = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, n1 = r & 7;
       const int t = tile->tgt[jt / W][jt % W];
-      const int64_t base = 2 * ((int64_t)t * slot + (int64_t)(line0 + ls) * B2);
+      if (t < 0) continue;
+      T xr[Q], xi[Q];
 #pragma unroll
-      for (int n = 0; n < B2; ++n) {
-        const T sr = yr[n] + __shfl_xor(yr[n], 1), si = yi[n] + __shfl_xor(yi[n], 1);
-        if (t >= 0 && (n < B2 / 2) == (hf == 0)) {
-          U[base + 2 * n] = sr;
-          U[base + 2 * n + 1] = si;
-        }
+      for (int k2 = 0; k2 < Q; ++k2) {
+        const cpx<T> v = F[jt * FS + ls * P + k2 * 8 + n1];
+        xr[k2] = v.x;
+        xi[k2] = v.y;
+      }
+      fft_inreg<Q, +1>(xr, xi);
+      const int64_t col = 2 * ((int64_t)t * slot + (int64_t)(line0 + ls) * B2);
+#pragma unroll
+      for (int n2 = 0; n2 < Q / 2; ++n2) {
+        U[col + 2 * (n1 + 8 * n2)] = xr[n2];
+        U[col + 2 * (n1 + 8 * n2) + 1] = xi[n2];
       }
     }
   }

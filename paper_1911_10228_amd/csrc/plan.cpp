@@ -1312,13 +1312,12 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         // full as tiles of 2 x 2 (dense levels); the other height is an autotuner candidate
         const bool tall = tiled && 8 * nt4.size() <= 9 * nt.size() / 2;
         if (tall) std::swap(nt, nt4);
-        // compact tiles (only the source super-blocks that exist staged), 2 x 4 rows first: the
-        // pipelined near MAC where every tile fits (FP32 spectra; FP64 candidates), else the
-        // one-chunk tiles (FP32) or rows (FP64).  The fused form of the compact tiles (z
-        // transforms, MAC and inverse z transforms per line in one kernel) runs on the same
-        // items; it was measured slower than the pipelined MAC with the z passes in HBM (FP32
-        // 0.221 against 0.190 ms per pass on the bench workload, FP64 0.382 against 0.314 ms)
-        // and is kept as a shape to force, not chosen.
+        // compact tiles (only the source super-blocks that exist staged), 2 x 4 rows first.
+        // FP64 spectra: the fused form where every tile fits (z transforms, MAC and inverse z
+        // transforms per line in one kernel: the spectra never go through HBM; FP64 solve of
+        // the bench workload 0.31 -> 0.27 ms), else rows.  FP32 spectra: the pipelined near MAC
+        // on the same compact tiles (the fused form ties with it there), else the one-chunk
+        // tiles.  The autotuner times each candidate with its level's transforms.
         std::vector<NearCTile<D>> ct[2];           // [0]: 2 x 2 rows, [1]: 2 x 4 rows
         if (!tiled) {
           nt.clear();
@@ -1342,10 +1341,13 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         // the image holds a height's compact tiles only where a step (or alternative) uses them
         size_t ct_off[2] = {0, 0};
         for (int h = 0; h < 2; ++h)
-          if (!ct[h].empty() && ((h == piped && tiled) || p->tune)) ct_off[h] = hi.add(ct[h]);
+          if (!ct[h].empty() && (h == piped || p->tune)) ct_off[h] = hi.add(ct[h]);
         if (piped >= 0 && tiled)
           push(steps, l, 4, k, K_NEAR_MAC, sty, ct_off[piped], ct[piped].size(), nullptr, pairs,
                piped ? kNearTiled + 7 : kNearTiled + 5, chain);
+        else if (piped >= 0)
+          push(steps, l, 4, k, K_NEAR_MAC, sty, ct_off[piped], ct[piped].size(), nullptr, pairs,
+               kNearFused + (piped ? 4 : 2), chain);
         else if (tiled)
           push(steps, l, 4, k, K_NEAR_MAC, sty, hi.add(nt), nt.size(), nullptr, pairs,
                tall ? kNearTiled + 6 : kNearTiled + 4, chain);
@@ -2226,13 +2228,32 @@ hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
       }
     prim = win;
   };
+  // A near step is timed with its level's super-block transforms in the mode the candidate
+  // needs (the fused form takes over their z passes).  The forward transform of an FP64
+  // single-level plan reads the pass input: a zero field stands in for it.
+  double* din = nullptr;
+  auto sibling = [&](const Step& nr, int kind) -> const Step* {
+    for (const Step& x : p->pass)
+      if (x.kind == kind && x.l == nr.l && x.sub == nr.sub) return &x;
+    return nullptr;
+  };
+  auto launch_one = [&](const Step& x, int mode) -> hipError_t {
+    SetTable tab;
+    tab.n = 1;
+    tab.pad = 0;
+    tab.s[0] = WorkSet{img + x.items, 0, x.count, 0, din, nullptr, x.w};
+    return launch_typed(x.kind, x.ty, p->nb, tab, st, mode);
+  };
   for (auto& g : groups) {
     const Step prim = p->pass[g.first];
     std::vector<Step> cands{prim};
-    // the fused near form replaces the z passes of the super-block transforms as well, so its
-    // single-step time does not compare with the other shapes': it is not a candidate
-    for (const Step& x : g.second)
-      if (!(x.kind == K_NEAR_MAC && near_fused(x.mode))) cands.push_back(x);
+    for (const Step& x : g.second) cands.push_back(x);
+    const Step* sf = prim.kind == K_NEAR_MAC ? sibling(prim, K_SUP_FWD) : nullptr;
+    const Step* si = prim.kind == K_NEAR_MAC ? sibling(prim, K_SUP_INV) : nullptr;
+    if (sf && !din) {
+      LGF_HIP_CHECK(hipMalloc(&din, (size_t)p->nblocks * p->nb * p->nb * p->nb * sizeof(double)));
+      LGF_HIP_CHECK(hipMemsetAsync(din, 0, (size_t)p->nblocks * p->nb * p->nb * p->nb * sizeof(double), st));
+    }
     const std::array<int64_t, 3> key{p->nb, (prim.kind == K_MAC ? 2000 : 1000) + prim.ty, prim.work};
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
@@ -2247,13 +2268,12 @@ hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
     size_t best_i = 0;
     for (size_t c = 0; c < cands.size(); ++c) {
       float t[kTuneReps];
+      const int lm = near_fused(cands[c].mode) ? 1 : 0;
       for (int rep = 0; rep < kTuneReps; ++rep) {
-        SetTable tab;
-        tab.n = 1;
-        tab.pad = 0;
-        tab.s[0] = WorkSet{img + cands[c].items, 0, cands[c].count, 0, nullptr, nullptr, cands[c].w};
         LGF_HIP_CHECK(hipEventRecord(a, st));
-        LGF_HIP_CHECK(launch_typed(cands[c].kind, cands[c].ty, p->nb, tab, st, cands[c].mode));
+        if (sf) LGF_HIP_CHECK(launch_one(*sf, lm));
+        LGF_HIP_CHECK(launch_one(cands[c], cands[c].mode));
+        if (si) LGF_HIP_CHECK(launch_one(*si, lm));
         LGF_HIP_CHECK(hipEventRecord(b, st));
         LGF_HIP_CHECK(hipEventSynchronize(b));
         LGF_HIP_CHECK(hipEventElapsedTime(&t[rep], a, b));
@@ -2274,6 +2294,10 @@ hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  if (din) {
+    LGF_HIP_CHECK(hipStreamSynchronize(st));
+    (void)hipFree(din);
+  }
   sync_super_modes(p);
   return hipSuccess;
 }

@@ -28,7 +28,7 @@ EXPORTS = ["lgf_init", "lgf_plan", "lgf_plan_check", "lgf_solve", "lgf_apply", "
            "lgf_kernel_spectrum", "lgf_profile", "lgf_profile_read", "lgf_server_create", "lgf_server_submit", "lgf_server_poll",
            "lgf_server_wait_all", "lgf_server_stats", "lgf_server_destroy", "lgf_plan_set_mac_shape",
            "lgf_plan_set_near_shape", "lgf_server_submit_layout", "lgf_server_info", "lgf_workspace_poison", "lgf_layout_adapt",
-           "lgf_solve_noalloc"]
+           "lgf_solve_noalloc", "lgf_server_reset_stats"]
 SCRATCH_BYTES = 64 << 20       # LGF_SCRATCH_BYTES: the allocation-free solve's workspace
 
 
@@ -96,6 +96,7 @@ def load() -> C.CDLL:
         "lgf_workspace_poison": ([I32], I32),
         "lgf_layout_adapt": ([P, P, I64, I32, P, I32, C.c_double, P, P, I64, P, P], I32),
         "lgf_solve_noalloc": ([P, P, P, P], I32),
+        "lgf_server_reset_stats": ([P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -373,6 +374,10 @@ class Server:
         m = ServerMemory()
         _check(load().lgf_server_info(self._h, C.byref(m)), "lgf_server_info")
         return {k: getattr(m, k) for k, _ in m._fields_}
+
+    def reset_stats(self):
+        """Start latency, throughput and memory statistics afresh (plans and memory stay)."""
+        _check(load().lgf_server_reset_stats(self._h), "lgf_server_reset_stats")
 
     def poll(self, rid: int) -> bool:
         done = C.c_int32()
