@@ -60,25 +60,34 @@ def algorithmic(entry, n_b, info, passes):
     spectrum and each kernel spectrum of its level once and writes each target spectrum once
     (near MAC: the super-block spectra and 14 of the 27 super-block kernels, the others being
     their conjugates; coarse MAC: the block spectra of the coarse levels and 172 of the 316
-    kernels per level, likewise).  FP32 tiles compute in FP32; FP64 spectra in FP64.
-    Transforms: per item (work = items) the block or the 8 child blocks of a super-block, and
-    the half spectrum (2 S reals)."""
+    kernels per level, likewise).  The fused near step (modes 42, 44) reads the line-major
+    planes of every source super-block (half a spectrum: B2 values of z per line) and the 14
+    kernel columns (a full spectrum each) and writes the planes of every target super-block;
+    its flops are counted as those of the MAC alone.  FP32 tiles compute in FP32; FP64 spectra
+    in FP64.  Transforms: per item (work = items) the block or the 8 child blocks of a
+    super-block, and the half spectrum (2 S reals), or for the line-major super-block passes
+    (mode 1) the planes (S2 reals)."""
     es = 4 if entry["precision"] == "fp32" else 8
+    esc = 4 if entry["precision"] in ("fp32", "fp32/fp64") else 8     # child blocks
     S, S2 = spectrum_size(n_b), spectrum_size(2 * n_b)
     N3 = n_b ** 3
-    k = entry["kernel"]
+    k, mode = entry["kernel"], entry.get("mode", 0)
     peak = PEAK["fp32_vector_tflops"] if entry["precision"] == "fp32" else PEAK["fp64_vector_tflops"]
     if k == "mac":
         levels = (info["spectra"] - (27 if info["super_forward"] else 343)) // 316
         per_pass = (info["fft_forward"] + info["fft_inverse"] + 172 * levels) * 2 * S * es
         return 8.0 * S * entry["work"], peak, per_pass * passes
+    if k == "near_mac" and mode in (42, 44):
+        per_launch = (info["super_forward"] + info["super_inverse"]) * S2 * es + 14 * 2 * S2 * es
+        return 8.0 * S2 * entry["work"], peak, per_launch * entry["launches"]
     if k == "near_mac":
         per_launch = (info["super_forward"] + info["super_inverse"] + 14) * 2 * S2 * es
         return 8.0 * S2 * entry["work"], peak, per_launch * entry["launches"]
     if k in ("fft_fwd", "fft_inv"):
         return None, None, float(entry["work"]) * (N3 * es + 2 * S * es)
     if k in ("super_fwd", "super_inv"):
-        return None, None, float(entry["work"]) * (8 * N3 * es + 2 * S2 * es)
+        planes = S2 * es if mode == 1 else 2 * S2 * es
+        return None, None, float(entry["work"]) * (8 * N3 * esc + planes)
     return None, None, None
 
 
@@ -122,13 +131,13 @@ def roofline_of(prof, n_b, info, passes):
         kern.append(e)
     kern.sort(key=lambda e: -e["ms"])
     dom = kern[0]
-    tag = f"{dom['kernel']}_{dom['precision']}_nb{dom['n_b']}"
+    tag = f"{dom['kernel']}_{dom['precision']}_nb{dom['n_b']}_mode{dom.get('mode', 0)}"
     src = {"mac": "mac.hip", "near_mac": "mac.hip", "fft_fwd": "fft_blocks.hip", "fft_inv": "fft_blocks.hip",
            "super_fwd": "fft_super.hip", "super_inv": "fft_super.hip"}.get(dom["kernel"])
     traffic = measured_traffic(tag, src) if src else None
     t_hbm = dom["bytes_per_launch"] / (PEAK["hbm_gbs"] * 1e9) if "bytes_per_launch" in dom else 0.0
     t_alu = dom["flops_per_launch"] / (dom["flop_peak"] * 1e12) if "flops_per_launch" in dom else 0.0
-    name = f"{dom['kernel']} ({dom['precision']} storage, n_b={dom['n_b']})"
+    name = f"{dom['kernel']} ({dom['precision']} storage, n_b={dom['n_b']}, launch shape {dom.get('mode', 0)})"
     if t_hbm == 0.0 and t_alu == 0.0:
         roof = {"bound": "hbm", "achieved": None, "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": None,
                 "traffic": traffic, "kernel": name}

@@ -198,8 +198,10 @@ lgf_status lgf_kernel_spectrum(int32_t N_b, int32_t s, int32_t dx, int32_t dy, i
 
 /* Launch timing (diagnostics for benchmarks).  lgf_profile(1) brackets every subsequent
  * kernel launch with HIP events on its stream; lgf_profile_read synchronises on them and returns
- * one entry per (kernel kind, element type, N_b) with the launch count, the summed elapsed time
- * and the summed work (spectral MAC: block interactions), then clears the record.
+ * one entry per (kernel kind, element type, N_b, launch shape) with the launch count, the summed
+ * elapsed time and the summed work (spectral MAC: block interactions), then clears the record.
+ * mode is the launch shape (the values of lgf_plan_set_mac_shape / lgf_plan_set_near_shape for
+ * the MAC steps, 1 for super-block transforms on line-major planes, else 0).
  * Kinds: 0 coarsen, 1 convert, 2 refine, 3 correct, 4 anterpolate, 5 forward FFT, 6 spectral MAC,
  * 7 inverse FFT, 8 interpolate, 9 combine, 10 residual.  precision: 0 FP32, 1 FP64,
  * 2 FP32 child level / FP64 parent level. */
@@ -207,7 +209,7 @@ typedef struct {
   int32_t kind;
   int32_t precision;
   int32_t n_b;
-  int32_t reserved;
+  int32_t mode;
   int64_t launches;
   double ms;
   int64_t work;

@@ -276,6 +276,7 @@ lgf_status lgf_profile_read(lgf_profile_entry* out, int32_t cap, int32_t* n) {
     out[i].kind = v[i].kind;
     out[i].precision = v[i].ty;
     out[i].n_b = v[i].nb;
+    out[i].mode = v[i].mode;
     out[i].launches = v[i].launches;
     out[i].ms = v[i].ms;
     out[i].work = v[i].work;

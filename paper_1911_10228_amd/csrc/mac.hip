@@ -767,7 +767,11 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
   constexpr int LPW = 64 / P;                    // lines per workgroup
   constexpr int NGRP = PLANE / LPW;              // line groups
   constexpr int W = kTileW, WAVES = 2 * RZ, NS = W + 2, NT = WAVES * W, NTH = 64 * WAVES;
-  constexpr int FS = 66;                         // LDS entry stride (complex), padded
+  // LDS column layout: value m of an entry's 64 at m + m / 8 (one pad per 8), entries 72
+  // apart: the transposes' stride-8 accesses and the MAC's stride-1 accesses then fall on
+  // distinct banks (8- and 16-byte elements alike)
+  constexpr int FS = 72;
+  auto at = [](int m) { return m + (m >> 3); };
   static_assert(PLANE % LPW == 0 && LPW * Q == 8 && NT <= NC + 1, "column shape");
   __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra (entry NC: zeros), then target spectra
   __shared__ cpx<T> tw[P];                       // e^{-2 pi i m / P}
@@ -790,7 +794,7 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
     sincospi(2.0 * tid / P, &sn, &cs);
     tw[tid] = cpx<T>{T(cs), T(-sn)};
   }
-  if (tid < 64) F[NC * FS + tid] = cpx<T>{T(0), T(0)};
+  if (tid < 64) F[NC * FS + at(tid)] = cpx<T>{T(0), T(0)};
   __syncthreads();
   // 1. forward step 1: thread (entry, line, n2), 8 per entry
   {
@@ -810,11 +814,10 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
         }
       }
       fft_inreg<8, -1>(yr, yi);
-      cpx<T>* const y = F + e * FS + ls * P + n2 * 8;
 #pragma unroll
       for (int k1 = 0; k1 < 8; ++k1) {
         const cpx<T> w = tw[(n2 * k1) % P];          // W_P^{n2 k1}
-        y[k1] = cpx<T>{yr[k1] * w.x - yi[k1] * w.y, yr[k1] * w.y + yi[k1] * w.x};
+        F[e * FS + at(ls * P + n2 * 8 + k1)] = cpx<T>{yr[k1] * w.x - yi[k1] * w.y, yr[k1] * w.y + yi[k1] * w.x};
       }
     }
   }
@@ -828,7 +831,7 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
     if (on) {
 #pragma unroll
       for (int n2 = 0; n2 < Q; ++n2) {
-        const cpx<T> v = F[e * FS + ls * P + n2 * 8 + k1];
+        const cpx<T> v = F[e * FS + at(ls * P + n2 * 8 + k1)];
         xr[n2] = v.x;
         xi[n2] = v.y;
       }
@@ -837,11 +840,12 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
     __syncthreads();
     if (on) {
 #pragma unroll
-      for (int k2 = 0; k2 < Q; ++k2) F[e * FS + ls * P + k1 + 8 * k2] = cpx<T>{xr[k2], xi[k2]};
+      for (int k2 = 0; k2 < Q; ++k2) F[e * FS + at(ls * P + k1 + 8 * k2)] = cpx<T>{xr[k2], xi[k2]};
     }
   }
   __syncthreads();
-  // 3. MAC: wavefront = row (ry, rz) of the tile, lane = (line, kz)
+  // 3. MAC: wavefront = row (ry, rz) of the tile, lane = (line, kz).  A tile without sources at
+  // the row ends (x0 - 1, x0 + 4) skips the products with those positions.
   {
     const uint32_t smask = tile->src_mask;
     const int ry = wave & 1, rz = wave >> 1;
@@ -857,7 +861,8 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
     cpx<T> acc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[q] = {T(0), T(0)};
-    if ((tile->row_mask >> wave) & 1u) {
+    auto mac = [&](auto has_edges) {
+      constexpr bool EDGES = decltype(has_edges)::value;
 #pragma unroll
       for (int pj = 0; pj < 9; ++pj) {
         const int dz = pj / 3 - 1, dy = pj % 3 - 1;
@@ -865,19 +870,27 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
         if (!((smask >> q) & 1u)) continue;
         cpx<T> fd[NS];
 #pragma unroll
-        for (int s2 = 0; s2 < NS; ++s2) fd[s2] = F[(tile->loff[q * NS + s2] >> 6) * FS + lane];
+        for (int s2 = 0; s2 < NS; ++s2)
+          if (EDGES || (s2 > 0 && s2 < NS - 1)) fd[s2] = F[(tile->loff[q * NS + s2] >> 6) * FS + at(lane)];
 #pragma unroll
         for (int dxi = 0; dxi < 3; ++dxi) {
           const int h = pj * 3 + dxi;
           const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
 #pragma unroll
-          for (int x = 0; x < W; ++x) cmac(acc[x], kk, fd[x - dxi + 2]);   // src x = x0 + x - dx
+          for (int x = 0; x < W; ++x) {               // src x = x0 + x - dx
+            const int e = x - dxi + 2;
+            if (EDGES || (e > 0 && e < NS - 1)) cmac(acc[x], kk, fd[e]);
+          }
         }
       }
+    };
+    if ((tile->row_mask >> wave) & 1u) {
+      if (tile->edges) mac(std::true_type{});
+      else mac(std::false_type{});
     }
     __syncthreads();                             // every source spectrum is consumed
 #pragma unroll
-    for (int x = 0; x < W; ++x) F[(wave * W + x) * FS + lane] = acc[x];
+    for (int x = 0; x < W; ++x) F[(wave * W + x) * FS + at(lane)] = acc[x];
   }
   __syncthreads();
   // 4. inverse step 1: thread (target, line, k2), 8 per target; read all, then write in place
@@ -889,7 +902,7 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
     if (on) {
 #pragma unroll
       for (int k1 = 0; k1 < 8; ++k1) {
-        const cpx<T> v = F[jt * FS + ls * P + Q * k1 + k2];
+        const cpx<T> v = F[jt * FS + at(ls * P + Q * k1 + k2)];
         zr[k1] = v.x;
         zi[k1] = v.y;
       }
@@ -900,7 +913,7 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
 #pragma unroll
       for (int n1 = 0; n1 < 8; ++n1) {
         const cpx<T> w = tw[(n1 * k2) % P];          // W_P^{n1 k2}, conjugated below
-        F[jt * FS + ls * P + k2 * 8 + n1] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
+        F[jt * FS + at(ls * P + k2 * 8 + n1)] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
       }
     }
   }
@@ -915,7 +928,7 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
       T xr[Q], xi[Q];
 #pragma unroll
       for (int k2 = 0; k2 < Q; ++k2) {
-        const cpx<T> v = F[jt * FS + ls * P + k2 * 8 + n1];
+        const cpx<T> v = F[jt * FS + at(ls * P + k2 * 8 + n1)];
         xr[k2] = v.x;
         xi[k2] = v.y;
       }

@@ -1875,7 +1875,7 @@ struct Ref {
 }  // namespace
 
 namespace {
-struct ProfRec { int kind, ty, nb; int64_t work; hipEvent_t a, b; };
+struct ProfRec { int kind, ty, nb, mode; int64_t work; hipEvent_t a, b; };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
@@ -1888,13 +1888,13 @@ void profile_enable(bool on) {
 
 hipError_t profile_collect(std::vector<ProfileEntry>* out) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  std::map<std::array<int, 3>, ProfileEntry> acc;
+  std::map<std::array<int, 4>, ProfileEntry> acc;
   for (ProfRec& r : g_prof) {
     LGF_HIP_CHECK(hipEventSynchronize(r.b));
     float ms = 0.f;
     LGF_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
-    ProfileEntry& e = acc[{r.kind, r.ty, r.nb}];
-    e.kind = r.kind; e.ty = r.ty; e.nb = r.nb;
+    ProfileEntry& e = acc[{r.kind, r.ty, r.nb, r.mode}];
+    e.kind = r.kind; e.ty = r.ty; e.nb = r.nb; e.mode = r.mode;
     e.launches += 1;
     e.ms += ms;
     e.work += r.work;
@@ -2016,7 +2016,7 @@ hipError_t run_steps(const std::vector<Member>& m, bool residual, hipStream_t st
       fork_l = l;
     }
     hipStream_t ls = (forked && c == 1) ? aux : st;
-    ProfRec rec{refs[a].kind, refs[a].ty, refs[a].nb, 0, nullptr, nullptr};
+    ProfRec rec{refs[a].kind, refs[a].ty, refs[a].nb, refs[a].mode, 0, nullptr, nullptr};
     if (prof) {
       for (size_t q = a; q < b; ++q) rec.work += refs[q].step->work;
       LGF_HIP_CHECK(hipEventCreate(&rec.a));

@@ -66,7 +66,7 @@ struct Step {
 // Optional launch timing: when enabled, every launch is bracketed by HIP events on its stream
 // and the elapsed times are accumulated per (kind, element type) at profile_collect().
 void profile_enable(bool on);
-struct ProfileEntry { int kind, ty, nb; int64_t launches; double ms; int64_t work; };
+struct ProfileEntry { int kind, ty, nb, mode; int64_t launches; double ms; int64_t work; };
 hipError_t profile_collect(std::vector<ProfileEntry>* out);
 
 // ----------------------------------------------------------------------------- workspace

@@ -301,7 +301,7 @@ def kernel_spectrum(n_b, s, d, out_dev, stream=None):
 
 class ProfileEntry(C.Structure):
     _fields_ = [("kind", C.c_int32), ("precision", C.c_int32), ("n_b", C.c_int32),
-                ("reserved", C.c_int32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("mode", C.c_int32), ("launches", C.c_int64), ("ms", C.c_double),
                 ("work", C.c_int64)]
 
 
@@ -319,7 +319,7 @@ def profile_read() -> list:
     n = C.c_int32()
     _check(load().lgf_profile_read(arr, 64, C.byref(n)), "lgf_profile_read")
     return [{"kernel": KIND_NAMES[e.kind], "precision": ["fp32", "fp64", "fp32/fp64"][e.precision],
-             "n_b": e.n_b, "launches": e.launches, "ms": e.ms, "work": e.work}
+             "n_b": e.n_b, "mode": e.mode, "launches": e.launches, "ms": e.ms, "work": e.work}
             for e in arr[:min(n.value, 64)]]
 
 
