@@ -26,36 +26,18 @@ template <int B2> struct SupShape {
   static constexpr int S = P * P * H;
 };
 
-// 16-byte vectors of the child element type (rows are loaded whole, not element by element)
-template <typename TC> struct Row16;
-template <> struct Row16<float> { typedef float type __attribute__((ext_vector_type(4))); };
-template <> struct Row16<double> { typedef double type __attribute__((ext_vector_type(2))); };
-
-// row y of plane z of the assembled super-block: x < NB from the octant with cx = 0, the rest
-// from cx = 1 (absent children read as zeros)
-template <int NB, typename T, typename TC>
-__device__ __forceinline__ void load_row(const SuperFwdItem<T>& it, const double* in, int y, int z,
-                                         T (&xr)[2 * NB]) {
-  using V = typename Row16<TC>::type;
-  constexpr int E = 16 / sizeof(TC), NV = NB / E;
-  const int oc0 = 2 * (y >= NB) + 4 * (z >= NB);
-  const int off = ((z & (NB - 1)) * NB + (y & (NB - 1))) * NB;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const TC* c = child_ptr<TC>((const TC*)it.child[oc0 + h], it.child_in[oc0 + h], in);
-    if (c) {
-      const gview<const V> row = (gview<const V>)gl(c + off);
-#pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        const V v = row[q];
-#pragma unroll
-        for (int e = 0; e < E; ++e) xr[h * NB + q * E + e] = T(v[e]);
-      }
-    } else {
-#pragma unroll
-      for (int x = 0; x < NB; ++x) xr[h * NB + x] = T(0);
-    }
+// P-th roots of unity e^{-2 pi i m / P} in global memory (read with vector loads: a lane's
+// twiddles depend on its position in the line)
+template <int P, typename T> struct Roots {
+  cpx<T> w[P];
+  constexpr Roots() : w{} {
+    for (int m = 0; m < P; ++m) w[m] = cpx<T>{T(turn_cos(m, P)), T(-turn_sin(m, P))};
   }
+};
+template <int P, typename T> __device__ const Roots<P, T> kRoots{};
+template <int P, typename T> __device__ __forceinline__ cpx<T> root(int m) {
+  const gview<const T> r = gl((const T*)&kRoots<P, T>.w[0]);
+  return {r[2 * m], r[2 * m + 1]};
 }
 
 // (item, z-plane) of a workgroup.  Plane-major (LM = 0): consecutive workgroups take consecutive
@@ -75,14 +57,44 @@ __device__ __forceinline__ bool plane_of(const WorkSet& ws, int64_t local, int64
   return *item < ws.count;
 }
 
-// forward (x, y) pass: one workgroup per (super-block, z-plane); lanes own x-lines, then y-lines
-// T: transform and spectrum type, TC: element type of the child blocks.  LM = 0: plane z goes to
-// the plane stack T[z][line]; LM = 1: to the line-major planes T[line][z] (line = ky H + kx).
+// The (x, y) passes: one workgroup of 8 B2 threads per (super-block, z-plane), every length-P
+// line (P = 2 B2 = 8 Q) split over Q or 8 lanes, with LDS exchanges between the two stages of
+// each direction and between the directions.  Forward, zero-padded (n < B2 nonzero), with
+// n = Q n1 + n2 and k = k1 + 8 k2:
+//   Y[n2][k1] = W_P^{n2 k1} sum_{n1 < 4} x[Q n1 + n2] W_8^{n1 k1}     (lane n2)
+//   X[k1 + 8 k2] = sum_{n2 < Q} Y[n2][k1] W_Q^{n2 k2}                 (lane k1)
+// Inverse, cropped to n < B2, with k = Q k1 + k2 and n = n1 + 8 n2:
+//   Z[k2][n1] = W_P^{-n1 k2} sum_{k1 < 8} X[Q k1 + k2] W_8^{-n1 k1}  (lane k2)
+//   x[n1 + 8 n2] = sum_{k2 < Q} Z[k2][n1] W_Q^{-n2 k2}, n2 < Q / 2    (lane n1)
+// The half spectrum along x of a real plane has B2 + 1 columns; columns kx = 0 and kx = B2 hold
+// real values along y before the y transform, so they travel as one complex column
+// (kx = 0 real, kx = B2 imaginary), and B2 columns fill the 8 B2 lanes.  Their y transforms are
+// separated with the conjugate symmetry of the transform of a real sequence; on the way back the
+// inverse y transform of that packed column is g0 + i g_B2 with both parts real.
+//
+// LDS: an exchange buffer E[line][m] (m = 8 n2 + k1 or 8 k2 + n1, one pad after every 8
+// values) and the plane buffer between the directions, [column][y] forward and [y][column]
+// inverse, each row swizzled by (row index mod 8): with these strides the accesses of every
+// stage fall on distinct banks (one 2-way case: the mirrored reads of the inverse x stage).
+// FP64: the two buffers share their space (two more barriers, twice the workgroups per CU).
+template <int B2, typename T> struct XyShape {
+  static constexpr int P = 2 * B2, Q = P / 8, H = B2 + 1, NB = B2 / 2, NT = 8 * B2;
+  static constexpr int RS = 9 * Q;               // exchange row: 8 Q values and Q pads
+  static constexpr int CS = B2 + 8;              // plane buffer row
+  static constexpr bool ALIAS = sizeof(T) == 8;
+  static constexpr int NE = B2 * RS, NP = B2 * CS;
+  static constexpr int NLDS = ALIAS ? (NE > NP ? NE : NP) : NE + NP;
+  static_assert(P == 8 * Q && (Q == 4 || Q == 8), "line shape");
+};
+__device__ __forceinline__ int xat(int m) { return m + (m >> 3); }
+
 template <int B2, typename T, typename TC, bool LM>
-__global__ __launch_bounds__(64) void sup_fwd_xy(SetTable sets) {
-  using Sh = SupShape<B2>;
-  constexpr int P = Sh::P, H = Sh::H, NB = Sh::NB;
-  __shared__ cpx<T> pl[B2 * H];                 // [y][kx] after the x pass
+__global__ __launch_bounds__(8 * B2) void sup_fwd_xy(SetTable sets) {
+  using X = XyShape<B2, T>;
+  constexpr int P = X::P, Q = X::Q, H = X::H, NB = X::NB, RS = X::RS, CS = X::CS;
+  __shared__ cpx<T> lds[X::NLDS];
+  cpx<T>* const E = lds;
+  cpx<T>* const PL = X::ALIAS ? lds : lds + X::NE;
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;
@@ -90,29 +102,115 @@ __global__ __launch_bounds__(64) void sup_fwd_xy(SetTable sets) {
   int z;
   if (!plane_of<B2, LM>(ws, local, &item, &z)) return;
   const SuperFwdItem<T>& it = ((const SuperFwdItem<T>*)ws.items)[item];
-  const int tid = threadIdx.x;
-  for (int y = tid; y < B2; y += 64) {
-    T xr[B2], xi[B2], Xr[P], Xi[P];
-    load_row<NB, T, TC>(it, ws.in, y, z, xr);
+  const int t = threadIdx.x;
+  const int cz = z / NB, lz = z % NB;
+  // x stage 1: lane (y, n2), the row's real values x = Q n1 + n2 (x < NB: octant cx = 0)
+  if (t < B2 * Q) {
+    const int y = t / Q, n2 = t % Q;
+    const int oc = 2 * (y / NB) + 4 * cz;
+    const int off = (lz * NB + y % NB) * NB;
+    T xr[4], xi[4], Yr[8], Yi[8];
 #pragma unroll
-    for (int x = 0; x < B2; ++x) xi[x] = T(0);
-    fwd_padded<B2>(xr, xi, Xr, Xi);
+    for (int h = 0; h < 2; ++h) {
+      const TC* c = child_ptr<TC>((const TC*)it.child[oc + h], it.child_in[oc + h], ws.in);
 #pragma unroll
-    for (int k = 0; k < H; ++k) pl[y * H + k] = {Xr[k], Xi[k]};
-  }
-  __syncthreads();
-  cpx<T>* const out = LM ? it.tmp : it.tmp + (int64_t)z * Sh::PLANE;
-  for (int kx = tid; kx < H; kx += 64) {
-    T yr[B2], yi[B2], Yr[P], Yi[P];
+      for (int j = 0; j < 2; ++j) {
+        xr[2 * h + j] = c ? T(gl(c + off)[Q * j + n2]) : T(0);
+        xi[2 * h + j] = T(0);
+      }
+    }
+    fwd_padded<4>(xr, xi, Yr, Yi);
 #pragma unroll
-    for (int y = 0; y < B2; ++y) { yr[y] = pl[y * H + kx].x; yi[y] = pl[y * H + kx].y; }
-    fwd_padded<B2>(yr, yi, Yr, Yi);
-#pragma unroll
-    for (int ky = 0; ky < P; ++ky) {
-      if constexpr (LM) gst(out, (int64_t)(ky * H + kx) * B2 + z, cpx<T>{Yr[ky], Yi[ky]});
-      else gst(out, ky * H + kx, cpx<T>{Yr[ky], Yi[ky]});
+    for (int k1 = 0; k1 < 8; ++k1) {
+      const cpx<T> w = k1 ? root<P, T>(n2 * k1) : cpx<T>{T(1), T(0)};
+      E[y * RS + xat(8 * n2 + k1)] = cpx<T>{Yr[k1] * w.x - Yi[k1] * w.y, Yr[k1] * w.y + Yi[k1] * w.x};
     }
   }
+  __syncthreads();
+  // x stage 2: lane (y, k1); columns kx = k1 + 8 k2 <= B2 to the plane buffer [kx][y]
+  {
+    const int y = t >> 3, k1 = t & 7;
+    T xr[Q], xi[Q];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      const cpx<T> v = E[y * RS + xat(8 * n2 + k1)];
+      xr[n2] = v.x;
+      xi[n2] = v.y;
+    }
+    fft_inreg<Q, -1>(xr, xi);
+    if constexpr (X::ALIAS) __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < Q / 2; ++k2) {
+      const int c = k1 + 8 * k2;
+      const cpx<T> v = c ? cpx<T>{xr[k2], xi[k2]} : cpx<T>{xr[0], xr[Q / 2]};   // kx = 0 | B2 packed
+      PL[c * CS + (y ^ (c & 7))] = v;
+    }
+  }
+  __syncthreads();
+  // y stage 1: lane (c, n2), the column's values y = Q n1 + n2 (y < B2)
+  T Yr[8], Yi[8];
+  const bool y1 = t < B2 * Q;
+  const int c1 = t / Q, m2 = t % Q;
+  if (y1) {
+    T vr[4], vi[4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+      const cpx<T> v = PL[c1 * CS + ((Q * n1 + m2) ^ (c1 & 7))];
+      vr[n1] = v.x;
+      vi[n1] = v.y;
+    }
+    fwd_padded<4>(vr, vi, Yr, Yi);
+  }
+  if constexpr (X::ALIAS) __syncthreads();
+  if (y1) {
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      const cpx<T> w = k1 ? root<P, T>(m2 * k1) : cpx<T>{T(1), T(0)};
+      E[c1 * RS + xat(8 * m2 + k1)] = cpx<T>{Yr[k1] * w.x - Yi[k1] * w.y, Yr[k1] * w.y + Yi[k1] * w.x};
+    }
+  }
+  __syncthreads();
+  // y stage 2: lane (c, k1), outputs ky = k1 + 8 k2
+  const int c = t >> 3, k1 = t & 7;
+  T zr[Q], zi[Q];
+#pragma unroll
+  for (int n2 = 0; n2 < Q; ++n2) {
+    const cpx<T> v = E[c * RS + xat(8 * n2 + k1)];
+    zr[n2] = v.x;
+    zi[n2] = v.y;
+  }
+  fft_inreg<Q, -1>(zr, zi);
+  cpx<T>* const out = LM ? it.tmp : it.tmp + (int64_t)z * (P * H);
+  auto put = [&](int ky, int kx, cpx<T> v) {
+    if constexpr (LM) gst(out, (int64_t)(ky * H + kx) * B2 + z, v);
+    else gst(out, ky * H + kx, v);
+  };
+  if ((t >> 6) == 0) {
+    // wave 0 holds the packed column (lanes 0..7): A[ky] + i B[ky] with A, B the transforms of
+    // the real columns kx = 0 and B2, so A[ky] = (Z[ky] + conj Z[-ky]) / 2 and
+    // B[ky] = (Z[ky] - conj Z[-ky]) / 2i.  Z[-ky] of ky = k1 + 8 k2 is held by lane 8 - k1
+    // (k2' = Q - 1 - k2), or for k1 = 0 by the lane itself (k2' = (Q - k2) mod Q).
+    T pr[Q], pi[Q];
+    const int src = (8 - k1) & 7;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      pr[j] = __shfl(zr[j], src, 8);
+      pi[j] = __shfl(zi[j], src, 8);
+    }
+    if (c == 0) {
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) {
+        const T mr = k1 ? pr[Q - 1 - k2] : zr[(Q - k2) % Q];
+        const T mi = k1 ? pi[Q - 1 - k2] : zi[(Q - k2) % Q];
+        const int ky = k1 + 8 * k2;
+        put(ky, 0, cpx<T>{T(0.5) * (zr[k2] + mr), T(0.5) * (zi[k2] - mi)});
+        put(ky, B2, cpx<T>{T(0.5) * (zi[k2] + mi), T(0.5) * (mr - zr[k2])});
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < Q; ++k2) put(k1 + 8 * k2, c, cpx<T>{zr[k2], zi[k2]});
 }
 
 // forward z pass: one lane per (kx, ky) line
@@ -161,13 +259,16 @@ __global__ __launch_bounds__(256) void sup_inv_z(SetTable sets) {
   for (int z = 0; z < B; ++z) gst(out, (int64_t)z * LINES, cpx<T>{zr[z], zi[z]});
 }
 
-// inverse (y, x) pass: one workgroup per (super-block, z-plane); crop, scale by 1/P^3 and write
-// the children's cells.  LM = 0: plane z from the plane stack; LM = 1: from line-major planes.
+// inverse (y, x) pass: one workgroup per (super-block, z-plane) as the forward pass; crop,
+// scale by 1/P^3 and write the children's cells.  LM = 0: plane z from the plane stack;
+// LM = 1: from line-major planes.
 template <int B2, typename T, typename TC, bool LM>
-__global__ __launch_bounds__(64) void sup_inv_yx(SetTable sets) {
-  using Sh = SupShape<B2>;
-  constexpr int P = Sh::P, H = Sh::H, NB = Sh::NB;
-  __shared__ cpx<T> pl[B2 * H];                 // [y][kx] after the y pass
+__global__ __launch_bounds__(8 * B2) void sup_inv_yx(SetTable sets) {
+  using X = XyShape<B2, T>;
+  constexpr int P = X::P, Q = X::Q, H = X::H, NB = X::NB, RS = X::RS, CS = X::CS;
+  __shared__ cpx<T> lds[X::NLDS];
+  cpx<T>* const E = lds;
+  cpx<T>* const PL = X::ALIAS ? lds : lds + X::NE;
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;
@@ -175,39 +276,102 @@ __global__ __launch_bounds__(64) void sup_inv_yx(SetTable sets) {
   int z;
   if (!plane_of<B2, LM>(ws, local, &item, &z)) return;
   const SuperInvItem<T>& it = ((const SuperInvItem<T>*)ws.items)[item];
-  const int tid = threadIdx.x;
-  const cpx<T>* const in = LM ? it.tmp : it.tmp + (int64_t)z * Sh::PLANE;
-  for (int kx = tid; kx < H; kx += 64) {
-    T Yr[P], Yi[P], yr[B2], yi[B2];
+  const int t = threadIdx.x;
+  const cpx<T>* const in = LM ? it.tmp : it.tmp + (int64_t)z * (P * H);
+  auto get = [&](int ky, int kx) {
+    if constexpr (LM) return gld(in, (int64_t)(ky * H + kx) * B2 + z);
+    else return gld(in, ky * H + kx);
+  };
+  // y stage 1: lane (c, k2), ky = Q k1 + k2; column 0 carries kx = 0 + i kx = B2
+  if (t < B2 * Q) {
+    const int c = t / Q, k2 = t % Q;
+    T zr[8], zi[8];
 #pragma unroll
-    for (int ky = 0; ky < P; ++ky) {
-      const cpx<T> v = LM ? gld(in, (int64_t)(ky * H + kx) * B2 + z) : gld(in, ky * H + kx);
-      Yr[ky] = v.x;
-      Yi[ky] = v.y;
+    for (int k1 = 0; k1 < 8; ++k1) {
+      const int ky = Q * k1 + k2;
+      cpx<T> v = get(ky, c);
+      if (c == 0) {
+        const cpx<T> b = get(ky, B2);
+        v = cpx<T>{v.x - b.y, v.y + b.x};
+      }
+      zr[k1] = v.x;
+      zi[k1] = v.y;
     }
-    inv_cropped<B2>(Yr, Yi, yr, yi);
+    fft_inreg<8, +1>(zr, zi);
 #pragma unroll
-    for (int y = 0; y < B2; ++y) pl[y * H + kx] = {yr[y], yi[y]};
+    for (int n1 = 0; n1 < 8; ++n1) {
+      const cpx<T> w = n1 ? root<P, T>(n1 * k2) : cpx<T>{T(1), T(0)};   // conjugated below
+      E[c * RS + xat(8 * k2 + n1)] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
+    }
   }
   __syncthreads();
-  const T inv = T(1.0 / (double(P) * P * P));
-  const int cz = z / NB, lz = z % NB;
-  for (int y = tid; y < B2; y += 64) {
-    T Xr[P], Xi[P], xr[B2], xi[B2];
+  // y stage 2: lane (c, n1), y = n1 + 8 n2 < B2, to the plane buffer [y][c]
+  {
+    const int c = t >> 3, n1 = t & 7;
+    T Zr[Q], Zi[Q], yr[Q / 2], yi[Q / 2];
 #pragma unroll
-    for (int k = 0; k < H; ++k) { Xr[k] = pl[y * H + k].x; Xi[k] = pl[y * H + k].y; }
-#pragma unroll
-    for (int k = 1; k < B2; ++k) { Xr[P - k] = Xr[k]; Xi[P - k] = -Xi[k]; }
-    inv_cropped<B2>(Xr, Xi, xr, xi);
-    const int cy = y / NB, ly = y % NB;
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      TC* c = (TC*)it.child[half + 2 * cy + 4 * cz];
-      if (!c) continue;
-      const gview<TC> row = gl(c + (lz * NB + ly) * NB);
-#pragma unroll
-      for (int x = 0; x < NB; ++x) row[x] = TC(xr[half * NB + x] * inv);
+    for (int k2 = 0; k2 < Q; ++k2) {
+      const cpx<T> v = E[c * RS + xat(8 * k2 + n1)];
+      Zr[k2] = v.x;
+      Zi[k2] = v.y;
     }
+    inv_cropped<Q / 2>(Zr, Zi, yr, yi);
+    if constexpr (X::ALIAS) __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < Q / 2; ++n2) {
+      const int y = n1 + 8 * n2;
+      PL[y * CS + (c ^ (y & 7))] = cpx<T>{yr[n2], yi[n2]};
+    }
+  }
+  __syncthreads();
+  // x stage 1: lane (y, k2), kx = Q k1 + k2 over the full line (kx > B2 from the conjugates)
+  T Xr[8], Xi[8];
+  const bool x1 = t < B2 * Q;
+  const int y1 = t / Q, m2 = t % Q;
+  if (x1) {
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      int col = k1 < 4 ? Q * k1 + m2 : Q * (8 - k1) - m2;
+      col = col == B2 ? 0 : col;
+      const cpx<T> v = PL[y1 * CS + (col ^ (y1 & 7))];
+      if ((k1 == 0 || k1 == 4) && m2 == 0) {
+        Xr[k1] = k1 == 0 ? v.x : v.y;                // the real columns kx = 0 and B2
+        Xi[k1] = T(0);
+      } else {
+        Xr[k1] = v.x;
+        Xi[k1] = k1 < 4 ? v.y : -v.y;
+      }
+    }
+    fft_inreg<8, +1>(Xr, Xi);
+  }
+  if constexpr (X::ALIAS) __syncthreads();
+  if (x1) {
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) {
+      const cpx<T> w = n1 ? root<P, T>(n1 * m2) : cpx<T>{T(1), T(0)};
+      E[y1 * RS + xat(8 * m2 + n1)] = cpx<T>{Xr[n1] * w.x + Xi[n1] * w.y, Xi[n1] * w.x - Xr[n1] * w.y};
+    }
+  }
+  __syncthreads();
+  // x stage 2: lane (y, n1), x = n1 + 8 n2 < B2 (real part), scaled, to the children
+  const int y = t >> 3, n1 = t & 7;
+  T Zr[Q], Zi[Q], xr[Q / 2], xi[Q / 2];
+#pragma unroll
+  for (int k2 = 0; k2 < Q; ++k2) {
+    const cpx<T> v = E[y * RS + xat(8 * k2 + n1)];
+    Zr[k2] = v.x;
+    Zi[k2] = v.y;
+  }
+  inv_cropped<Q / 2>(Zr, Zi, xr, xi);
+  const T inv = T(1.0 / (double(P) * P * P));
+  const int cz = z / NB, lz = z % NB, cy = y / NB, ly = y % NB;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    TC* ch = (TC*)it.child[half + 2 * cy + 4 * cz];
+    if (!ch) continue;
+    const gview<TC> row = gl(ch + (lz * NB + ly) * NB);
+#pragma unroll
+    for (int j = 0; j < Q / 4; ++j) row[n1 + 8 * j] = TC(xr[half * (Q / 4) + j] * inv);
   }
 }
 
@@ -239,12 +403,12 @@ template <int B2, typename T, typename TC> hipError_t fwd_b2(SetTable& t, hipStr
   if (mode == 1) {
     const int64_t wg = assign_wg_lm(t, B2);
     if (wg == 0) return hipSuccess;
-    sup_fwd_xy<B2, T, TC, true><<<(unsigned)wg, 64, 0, st>>>(t);
+    sup_fwd_xy<B2, T, TC, true><<<(unsigned)wg, 8 * B2, 0, st>>>(t);
     return hipGetLastError();
   }
   const int64_t wg1 = assign_wg(t, B2);
   if (wg1 == 0) return hipSuccess;
-  sup_fwd_xy<B2, T, TC, false><<<(unsigned)wg1, 64, 0, st>>>(t);
+  sup_fwd_xy<B2, T, TC, false><<<(unsigned)wg1, 8 * B2, 0, st>>>(t);
   LGF_HIP_CHECK(hipGetLastError());
   const int64_t wg2 = assign_wg(t, (Sh::PLANE + 255) / 256);
   sup_fwd_z<B2, T><<<(unsigned)wg2, 256, 0, st>>>(t);
@@ -256,7 +420,7 @@ template <int B2, typename T, typename TC> hipError_t inv_b2(SetTable& t, hipStr
   if (mode == 1) {
     const int64_t wg = assign_wg_lm(t, B2);
     if (wg == 0) return hipSuccess;
-    sup_inv_yx<B2, T, TC, true><<<(unsigned)wg, 64, 0, st>>>(t);
+    sup_inv_yx<B2, T, TC, true><<<(unsigned)wg, 8 * B2, 0, st>>>(t);
     return hipGetLastError();
   }
   const int64_t wg1 = assign_wg(t, (Sh::PLANE + 255) / 256);
@@ -264,7 +428,7 @@ template <int B2, typename T, typename TC> hipError_t inv_b2(SetTable& t, hipStr
   sup_inv_z<B2, T><<<(unsigned)wg1, 256, 0, st>>>(t);
   LGF_HIP_CHECK(hipGetLastError());
   const int64_t wg2 = assign_wg(t, B2);
-  sup_inv_yx<B2, T, TC, false><<<(unsigned)wg2, 64, 0, st>>>(t);
+  sup_inv_yx<B2, T, TC, false><<<(unsigned)wg2, 8 * B2, 0, st>>>(t);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 // level are staged in LDS for the workgroup's 64 frequencies; only offsets d >= 0
 // (lexicographically) are stored: the kernel is real and even in every coordinate, so
 // K_{-d}[k] = conj(K_d[k]).  All control flow is uniform per wavefront.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -755,151 +756,206 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
 //   inverse, cropped to z < P/2: with kz = Q k1 + k2 and z = n1 + 8 n2,
 //     Z[k2][n1] = W_P^{-n1 k2} sum_{k1 < 8} X[Q k1 + k2] W_8^{-n1 k1}  (lane k2: an 8-point DFT)
 //     x[n1 + 8 n2] = sum_{k2 < Q} Z[k2][n1] W_Q^{-n2 k2}, n2 < Q/2      (lane n1: a Q-point DFT)
-// Phases (barriers between): 1. forward step 1, each lane loading its 4 inputs straight from the
-// planes, and the kernel columns to LDS; 2. forward step 2 in place; 3. the MAC of the tiled form
-// (wavefront = target row, lane = (line, kz)); the target spectra replace the source spectra in
-// LDS; 4. and 5. the inverse steps, the last storing the cropped column.  The 1 / P^3 of the
-// inverse transform is left to the inverse (y, x) pass.  Workgroups: line groups dealt to the
-// XCDs in turn, all tiles of a group on one XCD (they share its source and kernel columns in L2).
+// Each step of a transform writes back to the LDS positions it read (Y[n2][k1] at 8 n2 + k1,
+// X[k1 + 8 k2] there too; Z[k2][n1] at Q n1 + k2), so no barrier separates its reads and writes.
+// The 1 / P^3 of the inverse transform is left to the inverse (y, x) pass.
+//
+// Persistent workgroups: each takes the units (tile, line group) w, w + G, w + 2 G, ... of the
+// launch (G workgroups, a multiple of 8, so that a workgroup keeps to the XCD of its units; the
+// units of one line group lie on one XCD and share its source and kernel columns in L2).  While
+// a unit's MAC and inverse transforms run, the source columns of the workgroup's next unit are
+// already loading into registers (issued after the unit's kernel values, so the MAC does not
+// wait for them: loads return in issue order).  A wavefront owns the two target rows (ry = 0, 1)
+// at rz = its index and walks the 4 x 3 source rows they draw from, each loaded once for both.
+// Every lane keeps its 8 twiddles W_P^{m k}, m = its position mod Q, for the whole launch: the
+// forward step 1 (m = n2) and the inverse step 1 (m = k2) use the same ones.
 template <typename T, int B2, int RZ, int NC>
-__global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int64_t slot) {
+__global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int64_t slot, int64_t units) {
   constexpr int P = 2 * B2, H = B2 + 1, PLANE = P * H, Q = P / 8;
-  constexpr int LPW = 64 / P;                    // lines per workgroup
+  constexpr int LPW = 64 / P;                    // lines per unit
   constexpr int NGRP = PLANE / LPW;              // line groups
-  constexpr int W = kTileW, WAVES = 2 * RZ, NS = W + 2, NT = WAVES * W, NTH = 64 * WAVES;
+  constexpr int W = kTileW, NS = W + 2, NT = 2 * RZ * W, NTH = 64 * RZ;
+  constexpr int IPT = (8 * NC + NTH - 1) / NTH;  // forward step 1 items per thread
   // LDS column layout: value m of an entry's 64 at m + m / 8 (one pad per 8), entries 72
   // apart: the transposes' stride-8 accesses and the MAC's stride-1 accesses then fall on
   // distinct banks (8- and 16-byte elements alike)
   constexpr int FS = 72;
   auto at = [](int m) { return m + (m >> 3); };
-  static_assert(PLANE % LPW == 0 && LPW * Q == 8 && NT <= NC + 1, "column shape");
+  static_assert(PLANE % LPW == 0 && NGRP % 8 == 0 && LPW * Q == 8 && NT <= NC && NT * 8 == NTH, "column shape");
   __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra (entry NC: zeros), then target spectra
-  __shared__ cpx<T> tw[P];                       // e^{-2 pi i m / P}
-  const int set = find_set(sets, blockIdx.x);
-  const WorkSet& ws = sets.s[set];
-  const int64_t local = blockIdx.x - ws.wg_begin;   // wg_begin is a multiple of 8
-  const int ntiles = ws.count;
-  const int64_t jj = local >> 3;
-  const int grp = (int)(jj / ntiles) * 8 + (int)(local & 7);
-  const int ti = (int)(jj % ntiles);
-  if (grp >= NGRP) return;
-  const int line0 = grp * LPW;
-  const __attribute__((address_space(4))) NearCTile<T>* tile =
-      (const __attribute__((address_space(4))) NearCTile<T>*)ws.items + ti;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int tid = threadIdx.x;
-  const int nreal = tile->nreal;
-  if (tid < P) {
-    double sn, cs;
-    sincospi(2.0 * tid / P, &sn, &cs);
-    tw[tid] = cpx<T>{T(cs), T(-sn)};
-  }
-  if (tid < 64) F[NC * FS + at(tid)] = cpx<T>{T(0), T(0)};
-  __syncthreads();
-  // 1. forward step 1: thread (entry, line, n2), 8 per entry
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // twiddles W_P^{m k}, k < 8, m = this thread's n2 (forward step 1) = k2 (inverse step 1)
+  cpx<T> tw[8];
   {
-    const gview<const T> Fp = gl((const T*)tile->fhat);
-    for (int i = tid; i < 8 * nreal; i += NTH) {
-      const int e = i >> 3, r = i & 7, ls = r / Q, n2 = r % Q;
-      const int64_t col = 2 * ((int64_t)tile->src[e] * slot + (int64_t)(line0 + ls) * B2);
-      T yr[8], yi[8];
+    const int m = (tid & 7) % Q;
 #pragma unroll
-      for (int n1 = 0; n1 < 8; ++n1) {
-        if (n1 < 4) {
-          yr[n1] = Fp[col + 2 * (Q * n1 + n2)];
-          yi[n1] = Fp[col + 2 * (Q * n1 + n2) + 1];
-        } else {
-          yr[n1] = T(0);
-          yi[n1] = T(0);
-        }
-      }
-      fft_inreg<8, -1>(yr, yi);
-#pragma unroll
-      for (int k1 = 0; k1 < 8; ++k1) {
-        const cpx<T> w = tw[(n2 * k1) % P];          // W_P^{n2 k1}
-        F[e * FS + at(ls * P + n2 * 8 + k1)] = cpx<T>{yr[k1] * w.x - yi[k1] * w.y, yr[k1] * w.y + yi[k1] * w.x};
-      }
+    for (int k = 0; k < 8; ++k) {
+      double sn, cs;
+      sincospi(2.0 * ((m * k) % P) / P, &sn, &cs);
+      tw[k] = cpx<T>{T(cs), T(-sn)};
     }
   }
-  __syncthreads();
-  // 2. forward step 2: thread (entry, line, k1), 8 LPW per entry; read all, then write in place
-  for (int base = 0; base < 8 * LPW * nreal; base += NTH) {
-    const int i = base + tid;
-    const bool on = i < 8 * LPW * nreal;
-    const int e = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, k1 = r & 7;
-    T xr[Q], xi[Q];
-    if (on) {
+  if (tid < 64) F[NC * FS + at(tid)] = cpx<T>{T(0), T(0)};
+  struct Unit {
+    const __attribute__((address_space(4))) NearCTile<T>* tile;
+    int line0;
+  };
+  auto unit_of = [&](int64_t u) {
+    const WorkSet& ws = sets.s[find_set(sets, u)];
+    const int64_t local = u - ws.wg_begin;       // wg_begin (first unit of the set) is a multiple of 8
+    const int64_t jj = local >> 3;
+    const int grp = (int)(jj / ws.count) * 8 + (int)(local & 7);
+    Unit r;
+    r.tile = (const __attribute__((address_space(4))) NearCTile<T>*)ws.items + jj % ws.count;
+    r.line0 = grp * LPW;
+    return r;
+  };
+  // forward step 1 inputs of a unit: item i = 8 e + (ls, n2) loads x[Q n1 + n2], n1 < 4, of line
+  // line0 + ls of staged entry e.  The slots of the entries are read first (fetch_slots), the
+  // values later (fetch_values), so that the value loads go out without waiting.  Every load is
+  // issued unconditionally (items past the staged entries read the all-zero slot, which src[]
+  // holds past nreal), so that the waits for the kernel values, issued before them, are exact.
+  T xr[IPT][4], xi[IPT][4];
+  int slots[IPT];
+  int nnext = 0;
+  auto fetch_slots = [&](const Unit& un) {
+    nnext = un.tile->nreal;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) slots[j] = un.tile->src[min((tid + j * NTH) >> 3, NC - 1)];
+  };
+  auto fetch_values = [&](const Unit& un) {
+    const gview<const T> Fp = gl((const T*)un.tile->fhat);
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int r = (tid + j * NTH) & 7, ls = r / Q, n2 = r % Q;
+      const int64_t col = 2 * ((int64_t)slots[j] * slot + (int64_t)(un.line0 + ls) * B2);
+#pragma unroll
+      for (int n1 = 0; n1 < 4; ++n1) {
+        xr[j][n1] = Fp[col + 2 * (Q * n1 + n2)];
+        xi[j][n1] = Fp[col + 2 * (Q * n1 + n2) + 1];
+      }
+    }
+  };
+  int64_t u = blockIdx.x;
+  if (u >= units) return;
+  Unit cur = unit_of(u);
+  fetch_slots(cur);
+  fetch_values(cur);
+  for (; u < units; u += gridDim.x) {
+    const auto* tile = cur.tile;
+    const int line0 = cur.line0;
+    const int nreal = nnext;
+    int tg[LPW];                                 // the inverse step 2's targets
+#pragma unroll
+    for (int j = 0; j < LPW; ++j) {
+      const int jt = (tid + j * NTH) / (8 * LPW);
+      tg[j] = tile->tgt[jt / W][jt % W];
+    }
+    // the next unit (the last one refetches its own inputs, unused)
+    if (u + gridDim.x < units) cur = unit_of(u + gridDim.x);
+    __syncthreads();                             // the previous unit's reads of F are done
+    // 1. forward step 1 from the prefetched inputs
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const int i = tid + j * NTH;
+      if (i < 8 * nreal) {
+        const int e = i >> 3, r = i & 7, ls = r / Q, n2 = r % Q;
+        T yr[8], yi[8];
+        fwd_padded<4>(xr[j], xi[j], yr, yi);
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) {
+          const cpx<T> w = tw[k1];                 // W_P^{n2 k1}
+          F[e * FS + at(ls * P + n2 * 8 + k1)] =
+              k1 ? cpx<T>{yr[k1] * w.x - yi[k1] * w.y, yr[k1] * w.y + yi[k1] * w.x} : cpx<T>{yr[0], yi[0]};
+        }
+      }
+    }
+    fetch_slots(cur);
+    __syncthreads();
+    // 2. forward step 2 in place: item (entry, line, k1)
+    for (int i = tid; i < 8 * LPW * nreal; i += NTH) {
+      const int e = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, k1 = r & 7;
+      T vr[Q], vi[Q];
 #pragma unroll
       for (int n2 = 0; n2 < Q; ++n2) {
         const cpx<T> v = F[e * FS + at(ls * P + n2 * 8 + k1)];
-        xr[n2] = v.x;
-        xi[n2] = v.y;
+        vr[n2] = v.x;
+        vi[n2] = v.y;
       }
-      fft_inreg<Q, -1>(xr, xi);
+      fft_inreg<Q, -1>(vr, vi);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) F[e * FS + at(ls * P + k1 + 8 * k2)] = cpx<T>{vr[k2], vi[k2]};
     }
     __syncthreads();
-    if (on) {
+    // 3. MAC: wavefront = target rows (0, rz) and (1, rz), lane = (line, kz).  The 14 kernel
+    // values of the lane's (line, kz) come straight from memory (L2: every tile of the line
+    // group reads the same 14 columns); then the next unit's inputs are requested.
+    cpx<T> acc[2][W];
+    {
+      const gview<const T> Kc = gl((const T*)tile->ktr);
+      cpx<T> kv[kNearHalfK];
 #pragma unroll
-      for (int k2 = 0; k2 < Q; ++k2) F[e * FS + at(ls * P + k1 + 8 * k2)] = cpx<T>{xr[k2], xi[k2]};
-    }
-  }
-  __syncthreads();
-  // 3. MAC: wavefront = row (ry, rz) of the tile, lane = (line, kz).  A tile without sources at
-  // the row ends (x0 - 1, x0 + 4) skips the products with those positions.
-  {
-    const uint32_t smask = tile->src_mask;
-    const int ry = wave & 1, rz = wave >> 1;
-    // the 14 kernel values of the lane's (line, kz), straight from memory (L2: every tile of the
-    // line group reads the same 14 columns)
-    const gview<const T> Kc = gl((const T*)tile->ktr);
-    cpx<T> kv[kNearHalfK];
+      for (int h = 0; h < kNearHalfK; ++h) {
+        const int64_t o = 2 * (((int64_t)h * PLANE + line0) * P + lane);
+        kv[h] = cpx<T>{Kc[o], Kc[o + 1]};
+      }
+      __builtin_amdgcn_sched_barrier(0);          // keep the kernel-value loads ahead of the prefetch
+      fetch_values(cur);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int h = 0; h < kNearHalfK; ++h) {
-      const int64_t o = 2 * (((int64_t)h * PLANE + line0) * P + lane);
-      kv[h] = cpx<T>{Kc[o], Kc[o + 1]};
-    }
-    cpx<T> acc[W];
+      for (int ry = 0; ry < 2; ++ry)
 #pragma unroll
-    for (int q = 0; q < W; ++q) acc[q] = {T(0), T(0)};
-    auto mac = [&](auto has_edges) {
-      constexpr bool EDGES = decltype(has_edges)::value;
+        for (int x = 0; x < W; ++x) acc[ry][x] = {T(0), T(0)};
+      const uint32_t smask = tile->src_mask;
+      const int rz = wave;
+      auto mac = [&](auto has_edges) {
+        constexpr bool EDGES = decltype(has_edges)::value;
 #pragma unroll
-      for (int pj = 0; pj < 9; ++pj) {
-        const int dz = pj / 3 - 1, dy = pj % 3 - 1;
-        const int q = (ry + 1 - dy) + 4 * (rz + 1 - dz);
-        if (!((smask >> q) & 1u)) continue;
-        cpx<T> fd[NS];
+        for (int qzi = 0; qzi < 3; ++qzi) {
 #pragma unroll
-        for (int s2 = 0; s2 < NS; ++s2)
-          if (EDGES || (s2 > 0 && s2 < NS - 1)) fd[s2] = F[(tile->loff[q * NS + s2] >> 6) * FS + at(lane)];
+          for (int qy = 0; qy < 4; ++qy) {
+            const int q = qy + 4 * (rz + qzi);     // source row (y0 - 1 + qy, z0 - 1 + rz + qzi)
+            if (!((smask >> q) & 1u)) continue;
+            cpx<T> fd[NS];
 #pragma unroll
-        for (int dxi = 0; dxi < 3; ++dxi) {
-          const int h = pj * 3 + dxi;
-          const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
+            for (int s2 = 0; s2 < NS; ++s2)
+              if (EDGES || (s2 > 0 && s2 < NS - 1)) fd[s2] = F[(tile->loff[q * NS + s2] >> 6) * FS + at(lane)];
 #pragma unroll
-          for (int x = 0; x < W; ++x) {               // src x = x0 + x - dx
-            const int e = x - dxi + 2;
-            if (EDGES || (e > 0 && e < NS - 1)) cmac(acc[x], kk, fd[e]);
+            for (int ry = 0; ry < 2; ++ry) {
+              const int dyi = ry + 2 - qy;         // dy + 1 of target row ry
+              if (dyi < 0 || dyi > 2) continue;
+              const int pj = 3 * (2 - qzi) + dyi;  // 3 (dz + 1) + dy + 1
+#pragma unroll
+              for (int dxi = 0; dxi < 3; ++dxi) {
+                const int h = pj * 3 + dxi;
+                const cpx<T> kk = h < kNearHalfK ? kv[h] : cpx<T>{kv[26 - h].x, -kv[26 - h].y};
+#pragma unroll
+                for (int x = 0; x < W; ++x) {     // src x = x0 + x - dx
+                  const int e = x - dxi + 2;
+                  if (EDGES || (e > 0 && e < NS - 1)) cmac(acc[ry][x], kk, fd[e]);
+                }
+              }
+            }
           }
         }
+      };
+      if ((tile->row_mask >> (2 * wave)) & 3u) {
+        if (tile->edges) mac(std::true_type{});
+        else mac(std::false_type{});
       }
-    };
-    if ((tile->row_mask >> wave) & 1u) {
-      if (tile->edges) mac(std::true_type{});
-      else mac(std::false_type{});
     }
     __syncthreads();                             // every source spectrum is consumed
 #pragma unroll
-    for (int x = 0; x < W; ++x) F[(wave * W + x) * FS + at(lane)] = acc[x];
-  }
-  __syncthreads();
-  // 4. inverse step 1: thread (target, line, k2), 8 per target; read all, then write in place
-  {
-    const int i = tid;
-    const bool on = i < 8 * NT;
-    const int jt = i >> 3, r = i & 7, ls = r / Q, k2 = r % Q;
-    T zr[8], zi[8];
-    if (on) {
+    for (int ry = 0; ry < 2; ++ry)
+#pragma unroll
+      for (int x = 0; x < W; ++x) F[((2 * wave + ry) * W + x) * FS + at(lane)] = acc[ry][x];
+    __syncthreads();
+    // 4. inverse step 1 in place: item (target, line, k2) = this thread; Z[k2][n1] goes to the
+    // position Q n1 + k2 of X[Q n1 + k2]
+    {
+      const int jt = tid >> 3, r = tid & 7, ls = r / Q, k2 = r % Q;
+      T zr[8], zi[8];
 #pragma unroll
       for (int k1 = 0; k1 < 8; ++k1) {
         const cpx<T> v = F[jt * FS + at(ls * P + Q * k1 + k2)];
@@ -907,57 +963,72 @@ __global__ __launch_bounds__(128 * RZ) void near_fused_kernel(SetTable sets, int
         zi[k1] = v.y;
       }
       fft_inreg<8, +1>(zr, zi);
-    }
-    __syncthreads();
-    if (on) {
 #pragma unroll
       for (int n1 = 0; n1 < 8; ++n1) {
-        const cpx<T> w = tw[(n1 * k2) % P];          // W_P^{n1 k2}, conjugated below
-        F[jt * FS + at(ls * P + k2 * 8 + n1)] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
+        const cpx<T> w = tw[n1];                   // W_P^{n1 k2}, conjugated
+        F[jt * FS + at(ls * P + Q * n1 + k2)] =
+            n1 ? cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y} : cpx<T>{zr[0], zi[0]};
       }
     }
-  }
-  __syncthreads();
-  // 5. inverse step 2: thread (target, line, n1), 8 LPW per target; store z = n1 + 8 n2 < B2
-  {
-    gmut<T> U = (gmut<T>)tile->uhat;
-    for (int i = tid; i < 8 * LPW * NT; i += NTH) {
-      const int jt = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, n1 = r & 7;
-      const int t = tile->tgt[jt / W][jt % W];
-      if (t < 0) continue;
-      T xr[Q], xi[Q];
+    __syncthreads();
+    // 5. inverse step 2: item (target, line, n1); store z = n1 + 8 n2 < B2
+    {
+      gmut<T> U = (gmut<T>)tile->uhat;
 #pragma unroll
-      for (int k2 = 0; k2 < Q; ++k2) {
-        const cpx<T> v = F[jt * FS + at(ls * P + k2 * 8 + n1)];
-        xr[k2] = v.x;
-        xi[k2] = v.y;
-      }
-      fft_inreg<Q, +1>(xr, xi);
-      const int64_t col = 2 * ((int64_t)t * slot + (int64_t)(line0 + ls) * B2);
+      for (int j = 0; j < LPW; ++j) {
+        const int i = tid + j * NTH;
+        const int jt = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, n1 = r & 7;
+        const int t = tg[j];
+        if (t < 0) continue;
+        T vr[Q], vi[Q], zr[Q / 2], zi[Q / 2];
 #pragma unroll
-      for (int n2 = 0; n2 < Q / 2; ++n2) {
-        U[col + 2 * (n1 + 8 * n2)] = xr[n2];
-        U[col + 2 * (n1 + 8 * n2) + 1] = xi[n2];
+        for (int k2 = 0; k2 < Q; ++k2) {
+          const cpx<T> v = F[jt * FS + at(ls * P + Q * n1 + k2)];
+          vr[k2] = v.x;
+          vi[k2] = v.y;
+        }
+        inv_cropped<Q / 2>(vr, vi, zr, zi);
+        const int64_t col = 2 * ((int64_t)t * slot + (int64_t)(line0 + ls) * B2);
+#pragma unroll
+        for (int n2 = 0; n2 < Q / 2; ++n2) {
+          U[col + 2 * (n1 + 8 * n2)] = zr[n2];
+          U[col + 2 * (n1 + 8 * n2) + 1] = zi[n2];
+        }
       }
     }
   }
 }
 
+template <typename T, int B2, int RZ>
+hipError_t launch_fused_rz(SetTable& t, hipStream_t st) {
+  constexpr int P = 2 * B2, PLANE = P * (B2 + 1), NGRP = PLANE / (64 / P);
+  constexpr int NC = near_ctile_cap(RZ == 2 ? kNearFused + 2 : kNearFused + 4);
+  const int64_t S = (int64_t)P * PLANE;               // complex entries per super-block slot
+  int64_t units = 0;
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = units;
+    units += (int64_t)t.s[i].count * NGRP;
+  }
+  if (units == 0) return hipSuccess;
+  // as many workgroups as are resident at once (a multiple of 8), each walking its units
+  static int resident = 0;
+  if (resident == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    LGF_HIP_CHECK(hipGetDevice(&dev));
+    LGF_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LGF_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, near_fused_kernel<T, B2, RZ, NC>,
+                                                               64 * RZ, 0));
+    resident = std::max(8, (per_cu * cus) / 8 * 8);
+  }
+  const int64_t wg = std::min<int64_t>(resident, (units + 7) / 8 * 8);
+  near_fused_kernel<T, B2, RZ, NC><<<(unsigned)wg, 64 * RZ, 0, st>>>(t, S, units);
+  return hipGetLastError();
+}
+
 template <typename T, int B2>
 hipError_t launch_fused_b2(SetTable& t, hipStream_t st, int mode) {
-  constexpr int P = 2 * B2, PLANE = P * (B2 + 1), NGRP = PLANE / (64 / P);
-  const int64_t S = (int64_t)P * PLANE;               // complex entries per super-block slot
-  int64_t wg = 0;
-  for (int i = 0; i < t.n; ++i) {
-    t.s[i].wg_begin = wg;
-    wg += (int64_t)t.s[i].count * ((NGRP + 7) / 8) * 8;
-  }
-  if (wg == 0) return hipSuccess;
-  if (mode == kNearFused + 2)
-    near_fused_kernel<T, B2, 2, near_ctile_cap(kNearFused + 2)><<<(unsigned)wg, 256, 0, st>>>(t, S);
-  else
-    near_fused_kernel<T, B2, 4, near_ctile_cap(kNearFused + 4)><<<(unsigned)wg, 512, 0, st>>>(t, S);
-  return hipGetLastError();
+  if (mode == kNearFused + 2) return launch_fused_rz<T, B2, 2>(t, st);
+  return launch_fused_rz<T, B2, 4>(t, st);
 }
 
 }  // namespace
