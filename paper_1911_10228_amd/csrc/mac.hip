@@ -762,26 +762,28 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
 //
 // Persistent workgroups: each takes the units (tile, line group) w, w + G, w + 2 G, ... of the
 // launch (G workgroups, a multiple of 8, so that a workgroup keeps to the XCD of its units; the
-// units of one line group lie on one XCD and share its source and kernel columns in L2).  While
-// a unit's MAC and inverse transforms run, the source columns of the workgroup's next unit are
-// already loading into registers (issued after the unit's kernel values, so the MAC does not
-// wait for them: loads return in issue order).  A wavefront owns the two target rows (ry = 0, 1)
-// at rz = its index and walks the 4 x 3 source rows they draw from, each loaded once for both.
-// Every lane keeps its 8 twiddles W_P^{m k}, m = its position mod Q, for the whole launch: the
-// forward step 1 (m = n2) and the inverse step 1 (m = k2) use the same ones.
-template <typename T, int B2, int RZ, int NC>
-__global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int64_t slot, int64_t units) {
+// units of one line group lie on one XCD and share its source and kernel columns in L2).  Loads
+// return in issue order, so each is issued where no earlier wait has to cover it: the source
+// slots of the next unit after the forward step 1, its source columns (into registers) at the
+// start of the MAC, its 14 kernel values after the MAC, while the inverse transforms run.  A
+// wavefront owns RPW = 2 target rows (ry = 0, 1 at rz = its index) and walks the 4 x 3 source
+// rows they draw from, each loaded once for both (one row per wavefront: more wavefronts, more
+// LDS reads, slower); the LDS entries of those rows sit in two registers and are taken with
+// readlane.  Every lane keeps its 8 twiddles W_P^{m k}, m = its position mod Q, for the whole
+// launch: the forward step 1 (m = n2) and the inverse step 1 (m = k2) use the same ones.
+template <typename T, int B2, int RZ, int NC, int RPW>
+__global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable sets, int64_t slot, int64_t units) {
   constexpr int P = 2 * B2, H = B2 + 1, PLANE = P * H, Q = P / 8;
   constexpr int LPW = 64 / P;                    // lines per unit
   constexpr int NGRP = PLANE / LPW;              // line groups
-  constexpr int W = kTileW, NS = W + 2, NT = 2 * RZ * W, NTH = 64 * RZ;
+  constexpr int W = kTileW, NS = W + 2, NT = 2 * RZ * W, NTH = 128 * RZ / RPW;
   constexpr int IPT = (8 * NC + NTH - 1) / NTH;  // forward step 1 items per thread
   // LDS column layout: value m of an entry's 64 at m + m / 8 (one pad per 8), entries 72
   // apart: the transposes' stride-8 accesses and the MAC's stride-1 accesses then fall on
   // distinct banks (8- and 16-byte elements alike)
   constexpr int FS = 72;
   auto at = [](int m) { return m + (m >> 3); };
-  static_assert(PLANE % LPW == 0 && NGRP % 8 == 0 && LPW * Q == 8 && NT <= NC && NT * 8 == NTH, "column shape");
+  static_assert(PLANE % LPW == 0 && NGRP % 8 == 0 && LPW * Q == 8 && NT <= NC && NT * 8 <= NTH, "column shape");
   __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra (entry NC: zeros), then target spectra
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -837,11 +839,23 @@ __global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int6
       }
     }
   };
+  // the 14 kernel values of a lane's (line, kz) of a unit (L2, or HBM on the first tile of a
+  // line group); requested a unit ahead, while the previous unit's inverse transforms run
+  cpx<T> kv[kNearHalfK];
+  auto fetch_kernels = [&](const Unit& un) {
+    const gview<const T> Kc = gl((const T*)un.tile->ktr);
+#pragma unroll
+    for (int h = 0; h < kNearHalfK; ++h) {
+      const int64_t o = 2 * (((int64_t)h * PLANE + un.line0) * P + lane);
+      kv[h] = cpx<T>{Kc[o], Kc[o + 1]};
+    }
+  };
   int64_t u = blockIdx.x;
   if (u >= units) return;
   Unit cur = unit_of(u);
   fetch_slots(cur);
   fetch_values(cur);
+  fetch_kernels(cur);
   for (; u < units; u += gridDim.x) {
     const auto* tile = cur.tile;
     const int line0 = cur.line0;
@@ -849,9 +863,16 @@ __global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int6
     int tg[LPW];                                 // the inverse step 2's targets
 #pragma unroll
     for (int j = 0; j < LPW; ++j) {
-      const int jt = (tid + j * NTH) / (8 * LPW);
+      const int jt = min((tid + j * NTH) / (8 * LPW), NT - 1);
       tg[j] = tile->tgt[jt / W][jt % W];
     }
+    // the LDS entries of the wavefront's source rows (rows 4 rz .. 4 rz + 11, NS each) in two
+    // registers, lane l holding entry 24 rz + l and 24 rz + 64 + l: the MAC takes them with
+    // readlane at compile-time lanes instead of scalar loads (which would share the LDS wait
+    // counter and serialise the rows)
+    const int lbase = 4 * NS * ((wave * RPW) >> 1);
+    const uint32_t lv0 = tile->loff[min(lbase + lane, kTileSrcRowsMax * NS - 1)];
+    const uint32_t lv1 = tile->loff[min(lbase + 64 + lane, kTileSrcRowsMax * NS - 1)];
     // the next unit (the last one refetches its own inputs, unused)
     if (u + gridDim.x < units) cur = unit_of(u + gridDim.x);
     __syncthreads();                             // the previous unit's reads of F are done
@@ -888,42 +909,38 @@ __global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int6
       for (int k2 = 0; k2 < Q; ++k2) F[e * FS + at(ls * P + k1 + 8 * k2)] = cpx<T>{vr[k2], vi[k2]};
     }
     __syncthreads();
-    // 3. MAC: wavefront = target rows (0, rz) and (1, rz), lane = (line, kz).  The 14 kernel
-    // values of the lane's (line, kz) come straight from memory (L2: every tile of the line
-    // group reads the same 14 columns); then the next unit's inputs are requested.
-    cpx<T> acc[2][W];
+    // 3. MAC: wavefront = RPW target rows, lane = (line, kz), the kernel values requested during
+    // the previous unit; the next unit's inputs are requested first.
+    cpx<T> acc[RPW][W];
     {
-      const gview<const T> Kc = gl((const T*)tile->ktr);
-      cpx<T> kv[kNearHalfK];
-#pragma unroll
-      for (int h = 0; h < kNearHalfK; ++h) {
-        const int64_t o = 2 * (((int64_t)h * PLANE + line0) * P + lane);
-        kv[h] = cpx<T>{Kc[o], Kc[o + 1]};
-      }
-      __builtin_amdgcn_sched_barrier(0);          // keep the kernel-value loads ahead of the prefetch
       fetch_values(cur);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int ry = 0; ry < 2; ++ry)
+      for (int j = 0; j < RPW; ++j)
 #pragma unroll
-        for (int x = 0; x < W; ++x) acc[ry][x] = {T(0), T(0)};
+        for (int x = 0; x < W; ++x) acc[j][x] = {T(0), T(0)};
       const uint32_t smask = tile->src_mask;
-      const int rz = wave;
+      const int r0 = wave * RPW;                 // the wavefront's rows r0 .. r0 + RPW - 1
+      const int ry0 = r0 & 1, rz = r0 >> 1;      // (RPW = 2: both rows at rz)
       auto mac = [&](auto has_edges) {
         constexpr bool EDGES = decltype(has_edges)::value;
 #pragma unroll
         for (int qzi = 0; qzi < 3; ++qzi) {
 #pragma unroll
-          for (int qy = 0; qy < 4; ++qy) {
-            const int q = qy + 4 * (rz + qzi);     // source row (y0 - 1 + qy, z0 - 1 + rz + qzi)
+          for (int qyi = 0; qyi < RPW + 2; ++qyi) {
+            const int q = ry0 + qyi + 4 * (rz + qzi);   // source row (y0 - 1 + qy, z0 - 1 + rz + qzi)
             if (!((smask >> q) & 1u)) continue;
             cpx<T> fd[NS];
 #pragma unroll
             for (int s2 = 0; s2 < NS; ++s2)
-              if (EDGES || (s2 > 0 && s2 < NS - 1)) fd[s2] = F[(tile->loff[q * NS + s2] >> 6) * FS + at(lane)];
+              if (EDGES || (s2 > 0 && s2 < NS - 1)) {
+                const int li = (ry0 + qyi + 4 * qzi) * NS + s2;   // q NS + s2 - lbase
+                const uint32_t off = __builtin_amdgcn_readlane(li < 64 ? lv0 : lv1, li & 63);
+                fd[s2] = F[(off >> 6) * FS + at(lane)];
+              }
 #pragma unroll
-            for (int ry = 0; ry < 2; ++ry) {
-              const int dyi = ry + 2 - qy;         // dy + 1 of target row ry
+            for (int j = 0; j < RPW; ++j) {
+              const int dyi = j + 2 - qyi;         // dy + 1 of target row ry0 + j
               if (dyi < 0 || dyi > 2) continue;
               const int pj = 3 * (2 - qzi) + dyi;  // 3 (dz + 1) + dy + 1
 #pragma unroll
@@ -933,27 +950,30 @@ __global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int6
 #pragma unroll
                 for (int x = 0; x < W; ++x) {     // src x = x0 + x - dx
                   const int e = x - dxi + 2;
-                  if (EDGES || (e > 0 && e < NS - 1)) cmac(acc[ry][x], kk, fd[e]);
+                  if (EDGES || (e > 0 && e < NS - 1)) cmac(acc[j][x], kk, fd[e]);
                 }
               }
             }
           }
         }
       };
-      if ((tile->row_mask >> (2 * wave)) & 3u) {
+      if ((tile->row_mask >> r0) & ((1u << RPW) - 1)) {
         if (tile->edges) mac(std::true_type{});
         else mac(std::false_type{});
       }
     }
     __syncthreads();                             // every source spectrum is consumed
 #pragma unroll
-    for (int ry = 0; ry < 2; ++ry)
+    for (int j = 0; j < RPW; ++j)
 #pragma unroll
-      for (int x = 0; x < W; ++x) F[((2 * wave + ry) * W + x) * FS + at(lane)] = acc[ry][x];
+      for (int x = 0; x < W; ++x) F[((wave * RPW + j) * W + x) * FS + at(lane)] = acc[j][x];
     __syncthreads();
     // 4. inverse step 1 in place: item (target, line, k2) = this thread; Z[k2][n1] goes to the
     // position Q n1 + k2 of X[Q n1 + k2]
-    {
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_kernels(cur);                          // the next unit's (kv is free after the MAC)
+    __builtin_amdgcn_sched_barrier(0);
+    if (tid < 8 * NT) {
       const int jt = tid >> 3, r = tid & 7, ls = r / Q, k2 = r % Q;
       T zr[8], zi[8];
 #pragma unroll
@@ -979,7 +999,7 @@ __global__ __launch_bounds__(64 * RZ) void near_fused_kernel(SetTable sets, int6
         const int i = tid + j * NTH;
         const int jt = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, n1 = r & 7;
         const int t = tg[j];
-        if (t < 0) continue;
+        if (jt >= NT || t < 0) continue;
         T vr[Q], vi[Q], zr[Q / 2], zi[Q / 2];
 #pragma unroll
         for (int k2 = 0; k2 < Q; ++k2) {
@@ -1003,6 +1023,7 @@ template <typename T, int B2, int RZ>
 hipError_t launch_fused_rz(SetTable& t, hipStream_t st) {
   constexpr int P = 2 * B2, PLANE = P * (B2 + 1), NGRP = PLANE / (64 / P);
   constexpr int NC = near_ctile_cap(RZ == 2 ? kNearFused + 2 : kNearFused + 4);
+  constexpr int RPW = 2, NTH = 128 * RZ / RPW;
   const int64_t S = (int64_t)P * PLANE;               // complex entries per super-block slot
   int64_t units = 0;
   for (int i = 0; i < t.n; ++i) {
@@ -1016,12 +1037,12 @@ hipError_t launch_fused_rz(SetTable& t, hipStream_t st) {
     int per_cu = 0, dev = 0, cus = 0;
     LGF_HIP_CHECK(hipGetDevice(&dev));
     LGF_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    LGF_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, near_fused_kernel<T, B2, RZ, NC>,
-                                                               64 * RZ, 0));
+    LGF_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, near_fused_kernel<T, B2, RZ, NC, RPW>,
+                                                               NTH, 0));
     resident = std::max(8, (per_cu * cus) / 8 * 8);
   }
   const int64_t wg = std::min<int64_t>(resident, (units + 7) / 8 * 8);
-  near_fused_kernel<T, B2, RZ, NC><<<(unsigned)wg, 64 * RZ, 0, st>>>(t, S, units);
+  near_fused_kernel<T, B2, RZ, NC, RPW><<<(unsigned)wg, NTH, 0, st>>>(t, S, units);
   return hipGetLastError();
 }
 
