@@ -104,9 +104,14 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
   __shared__ T t2[2][SL][NB][NB];      // y pass, per cx: [z][y][X]
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
+  // workgroup w of the set: parent 8 (w / 64) + w mod 8, slab (w / 8) mod 8, so that the eight
+  // slabs of a parent run on one XCD (workgroups go to the XCDs in turn; set starts are
+  // multiples of 64) and read its children once from HBM into that XCD's L2
   const int64_t local = blockIdx.x - ws.wg_begin;
-  const AnterpItem<TC, TP>& it = ((const AnterpItem<TC, TP>*)ws.items)[local / 8];
-  const int z0 = (int)(local % 8) * SL;
+  const int64_t item = (local >> 6) * 8 + (local & 7);
+  if (item >= ws.count) return;
+  const AnterpItem<TC, TP>& it = ((const AnterpItem<TC, TP>*)ws.items)[item];
+  const int z0 = (int)((local >> 3) & 7) * SL;
   const gview<const double> __restrict__ W = gl(ws.w);
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * NB * NB; i += NB * NB) {
@@ -530,7 +535,11 @@ __global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
   return hipGetLastError();
 
 template <typename TC, typename TP> hipError_t launch_anterp(int nb, SetTable& t, hipStream_t st) {
-  const int64_t wg = assign_wg(t, 8);
+  int64_t wg = 0;                                // 64 workgroups per 8 parents (see anterp_kernel)
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (t.s[i].count + 7) / 8 * 64;
+  }
   if (wg == 0) return hipSuccess;
   LGF_NB_DISPATCH(nb, anterp_kernel<NB, TC, TP><<<(unsigned)wg, NB * NB, 0, st>>>(t));
   return hipGetLastError();
