@@ -90,6 +90,83 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_fwd_kernel(SetTable sets
   }
 }
 
+// Forward transform of 16^3 blocks split over 4 workgroups per block by kx (groups of 5, 4, 4
+// and 4 of the 17 half-spectrum columns): each workgroup runs the x pass of every row (keeping
+// its columns; the rows are read from the XCD's L2 after the first workgroup), then the y and z
+// passes of its columns only.  So a level of 64 blocks is 256 workgroups instead of 64, and each
+// workgroup's y and z passes are a quarter as long.  Workgroup w of a set takes block
+// 8 (w / 32) + w mod 8, group (w / 8) mod 4: the groups of a block share one XCD.
+template <typename T>
+__global__ __launch_bounds__(256) void fft_fwd16_split_kernel(SetTable sets) {
+  constexpr int NB = 16, P = 32, H = 17, KW = 5;
+  __shared__ cpx<T> lds[NB * P * KW];            // after x: A[z][y][j]; after y: B[z][ky][j]
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;
+  const int64_t item = (local >> 5) * 8 + (local & 7);
+  if (item >= ws.count) return;
+  const int g = (int)((local >> 3) & 3);
+  const int k0 = g == 0 ? 0 : 1 + 4 * g, kw = g == 0 ? 5 : 4;
+  const FftFwdItem<T>& it = ((const FftFwdItem<T>*)ws.items)[item];
+  const int tid = threadIdx.x;
+  // x pass: row (z, y) = tid
+  {
+    const int y = tid % NB, z = tid / NB;
+    const gview<const T> src = gl(it.src + (z * NB + y) * NB);
+    T xr[NB], xi[NB], Xr[P], Xi[P];
+#pragma unroll
+    for (int x = 0; x < NB; ++x) { xr[x] = src[x]; xi[x] = T(0); }
+    fwd_padded<NB>(xr, xi, Xr, Xi);
+#pragma unroll
+    for (int j = 0; j < KW; ++j) {
+      // compile-time register index: select the group's column k0 + j among the candidates
+      cpx<T> v{T(0), T(0)};
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        const int kk = (gg == 0 ? 0 : 1 + 4 * gg) + j;
+        if (gg == g && kk < H) v = cpx<T>{Xr[kk], Xi[kk]};
+      }
+      if (j < kw) lds[(z * NB + y) * KW + j] = v;
+    }
+  }
+  __syncthreads();
+  // y pass: line (z, j), staged in registers (A and B overlap)
+  const bool yact = tid < NB * kw;
+  const int yz = tid / kw, yj = tid % kw;
+  T yr[NB], yi[NB];
+  if (yact) {
+#pragma unroll
+    for (int y = 0; y < NB; ++y) {
+      const cpx<T> v = lds[(yz * NB + y) * KW + yj];
+      yr[y] = v.x;
+      yi[y] = v.y;
+    }
+  }
+  __syncthreads();
+  if (yact) {
+    T Yr[P], Yi[P];
+    fwd_padded<NB>(yr, yi, Yr, Yi);
+#pragma unroll
+    for (int ky = 0; ky < P; ++ky) lds[(yz * P + ky) * KW + yj] = {Yr[ky], Yi[ky]};
+  }
+  __syncthreads();
+  // z pass: line (ky, j) -> global [kz][ky][k0 + j]
+  if (tid < P * kw) {
+    const int ky = tid / kw, j = tid % kw;
+    T zr[NB], zi[NB], Zr[P], Zi[P];
+#pragma unroll
+    for (int z = 0; z < NB; ++z) {
+      const cpx<T> v = lds[(z * P + ky) * KW + j];
+      zr[z] = v.x;
+      zi[z] = v.y;
+    }
+    fwd_padded<NB>(zr, zi, Zr, Zi);
+    cpx<T>* const dst = it.dst + ky * H + k0 + j;
+#pragma unroll
+    for (int kz = 0; kz < P; ++kz) gst(dst, kz * P * H, cpx<T>{Zr[kz], Zi[kz]});
+  }
+}
+
 template <int NB, typename T>
 __global__ __launch_bounds__(FftShape<NB>::NT) void fft_inv_kernel(SetTable sets) {
   using Sh = FftShape<NB>;
@@ -162,6 +239,16 @@ __global__ __launch_bounds__(FftShape<NB>::NT) void fft_inv_kernel(SetTable sets
 
 template <int NB, typename T> hipError_t fwd_nb(SetTable& t, hipStream_t st) {
   using Sh = FftShape<NB>;
+  if constexpr (NB == 16) {                    // 4 workgroups per block (see fft_fwd16_split_kernel)
+    int64_t wg = 0;
+    for (int i = 0; i < t.n; ++i) {
+      t.s[i].wg_begin = wg;
+      wg += (t.s[i].count + 7) / 8 * 32;
+    }
+    if (wg == 0) return hipSuccess;
+    fft_fwd16_split_kernel<T><<<(unsigned)wg, 256, 0, st>>>(t);
+    return hipGetLastError();
+  }
   const int64_t wg = assign_wg(t, 1, Sh::BPW);
   if (wg == 0) return hipSuccess;
   fft_fwd_kernel<NB, T><<<(unsigned)wg, Sh::NT, 0, st>>>(t);
