@@ -591,15 +591,21 @@ hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
 template <int NIN> constexpr int op_slabs() { return NIN == 1 ? 2 : 4; }
 
 template <int NB, int NIN>
-__global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restrict__ items, int op,
+__global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restrict__ items, int64_t nblk, int op,
                                                          const double* __restrict__ u, double* __restrict__ out,
                                                          int64_t cs, const double* __restrict__ w3tab) {
   constexpr int SLABS = op_slabs<NIN>();
   constexpr int SZ = NB / SLABS, E = NB + 2, N2 = NB * NB, PL = E * E, SL = (SZ + 2) * PL;
   constexpr int NH = 4 * NB * SZ;           // x and y halo cells of the slab's planes
   __shared__ double ext[NIN * SL];
-  const OpItem& it = items[blockIdx.x / SLABS];
-  const int z0 = (int)(blockIdx.x % SLABS) * SZ;
+  // workgroup w runs on XCD w mod 8; XCD x takes the blocks [x nper, (x + 1) nper) of the
+  // layout, so that the halo cells a block reads from its neighbours (in layout order mostly
+  // nearby) are in that XCD's L2
+  const int64_t nper = (nblk + 7) / 8, j = blockIdx.x >> 3;
+  const int64_t blk = (blockIdx.x & 7) * nper + j / SLABS;
+  if (blk >= nblk) return;
+  const OpItem& it = items[blk];
+  const int z0 = (int)(j % SLABS) * SZ;
   const int t = threadIdx.x, x = t % NB, y = t / NB;
   const int nout = op == 0 ? 1 : 3;
   const gview<double> o = gl(out);
@@ -632,12 +638,16 @@ __global__ __launch_bounds__(NB * NB) void fwd_op_kernel(const OpItem* __restric
     if (ghost) return refine_point<NB, double>(U + cb + it.par_off, w3, oc[0] * NB + qx, oc[1] * NB + qy, oc[2] * NB + qz);
     return 0.0;
   };
-  // the own column (all loads issued before the LDS stores), then the x and y halo cells
+  // the own column (all loads issued before the LDS stores; the slab's own cells directly, only
+  // the two z-halo cells through cell()), then the x and y halo cells
 #pragma unroll
   for (int c = 0; c < NIN; ++c) {
     double col[SZ + 2];
+    const gview<const double> Uc = U + (int64_t)c * cs + it.off + (z0 * NB + y) * NB + x;
 #pragma unroll
-    for (int j = 0; j < SZ + 2; ++j) col[j] = cell(c, x, y, z0 - 1 + j);
+    for (int j = 0; j < SZ; ++j) col[j + 1] = Uc[j * N2];
+    col[0] = cell(c, x, y, z0 - 1);
+    col[SZ + 1] = cell(c, x, y, z0 + SZ);
 #pragma unroll
     for (int j = 0; j < SZ + 2; ++j) ext[c * SL + j * PL + (y + 1) * E + x + 1] = col[j];
   }
@@ -682,12 +692,13 @@ hipError_t launch_fwd_op(int nb, int op, const OpItem* items, int64_t n, const d
   if (n == 0) return hipSuccess;
   if (!items || !w3 || op < 0 || op > 2) return hipErrorInvalidValue;
   const int64_t n3 = (int64_t)nb * nb * nb;
+  const int64_t nper = (n + 7) / 8;             // blocks per XCD (see fwd_op_kernel)
   if (op == 2) {
-    const unsigned g = (unsigned)(n * op_slabs<3>());
-    LGF_NB_DISPATCH(nb, (fwd_op_kernel<NB, 3><<<g, NB * NB, 0, st>>>(items, op, u, out, n * n3, w3)));
+    const unsigned g = (unsigned)(8 * nper * op_slabs<3>());
+    LGF_NB_DISPATCH(nb, (fwd_op_kernel<NB, 3><<<g, NB * NB, 0, st>>>(items, n, op, u, out, n * n3, w3)));
   } else {
-    const unsigned g = (unsigned)(n * op_slabs<1>());
-    LGF_NB_DISPATCH(nb, (fwd_op_kernel<NB, 1><<<g, NB * NB, 0, st>>>(items, op, u, out, n * n3, w3)));
+    const unsigned g = (unsigned)(8 * nper * op_slabs<1>());
+    LGF_NB_DISPATCH(nb, (fwd_op_kernel<NB, 1><<<g, NB * NB, 0, st>>>(items, n, op, u, out, n * n3, w3)));
   }
   return hipGetLastError();
 }
