@@ -437,9 +437,14 @@ __global__ __launch_bounds__(NB * NB) void residual_kernel(SetTable sets) {
   __shared__ double ext[(SZ + 2) * E * E];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
+  // XCD x (workgroup w runs on XCD w mod 8; set starts are multiples of 8) takes the items
+  // [x nper, (x + 1) nper): neighbour blocks, mostly nearby in layout order, share its L2
   const int64_t local = blockIdx.x - ws.wg_begin;
-  const ResidualItem& it = ((const ResidualItem*)ws.items)[local / kResidualSlabs];
-  const int z0 = (int)(local % kResidualSlabs) * SZ;
+  const int64_t nper = (ws.count + 7) / 8, jw = local >> 3;
+  const int64_t item = (local & 7) * nper + jw / kResidualSlabs;
+  if (item >= ws.count) return;
+  const ResidualItem& it = ((const ResidualItem*)ws.items)[item];
+  const int z0 = (int)(jw % kResidualSlabs) * SZ;
   const gview<double> r = gl(it.r);
   const gview<float> conv = gl(it.conv);
   if (!r && !conv) return;
@@ -569,7 +574,11 @@ template <typename T> hipError_t launch_correct(int nb, SetTable& t, hipStream_t
   LGF_LAUNCH_SIMPLE(correct_kernel<NB, T>)
 }
 hipError_t launch_residual(int nb, SetTable& t, hipStream_t st) {
-  const int64_t wg = assign_wg(t, kResidualSlabs);
+  int64_t wg = 0;                                // 8 ceil(count / 8) blocks of slabs per set
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (t.s[i].count + 7) / 8 * 8 * kResidualSlabs;
+  }
   if (wg == 0) return hipSuccess;
   LGF_NB_DISPATCH(nb, residual_kernel<NB><<<(unsigned)wg, NB * NB, 0, st>>>(t));
   return hipGetLastError();
