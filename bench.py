@@ -359,6 +359,9 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="one stream per solve (no base-level/far-field overlap), so that a "
                          "profiler's kernel durations are those of kernels running alone")
+    ap.add_argument("--profiler-exit", action="store_true",
+                    help="end through the interpreter's normal exit (a profiler such as rocprofv3 "
+                         "writes its results there) instead of exiting at once")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (counter calibration)")
     args = ap.parse_args()
@@ -374,7 +377,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "copies": 3}))
-        return
+        return args
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library solves on a "
               "single GPU and has no multi-GPU sharding", file=sys.stderr)
@@ -486,11 +489,13 @@ def main():
     out.update(extra)
     out.update(out_extra)
     print(json.dumps(out), flush=True)
+    return args
 
 
 if __name__ == "__main__":
-    main()
+    a = main()
     sys.stdout.flush()
     sys.stderr.flush()
     # end at once: no library or runtime teardown left running after the result is printed
-    os._exit(0)
+    if a is None or not a.profiler_exit:
+        os._exit(0)
