@@ -179,8 +179,11 @@ lgf_status lgf_green_eval(const int32_t* n, int64_t m, double* out, lgf_stream_t
  *   octree levels; also the base level with LGF_BASE_BLOCK) whose element type has it: shape 1
  *   one target row per wavefront, 2 two rows, 4 the tile's four rows (FP32 steps), 6 source rows
  *   split over 6 wavefronts (FP64 steps), 8 the tile's rows on 4 wavefronts sharing each source
- *   row through LDS; 0 restores the planner's and autotuner's choice.  So that every shape can
- *   be checked; results agree up to rounding order.  LGF_EINVAL for another value. */
+ *   row through LDS, 16 the LDS form (a workgroup stages a chunk of 16 frequencies of the 172
+ *   kernel spectra and of the step's source spectra once, then up to 4 tiles work from LDS;
+ *   only coarse steps of rows of 4 whose source slots lie within 64 of each other have it, the
+ *   planner's choice there); 0 restores the planner's and autotuner's choice.  So that every
+ *   shape can be checked; results agree up to rounding order.  LGF_EINVAL for another value. */
 lgf_status lgf_plan_set_mac_shape(lgf_plan_t p, int32_t shape);
 /* lgf_plan_set_near_shape: the same for the base-level super-block MAC steps: shape 2, 4 or 8
  *   rows of that many target super-blocks per wavefront, 20 or 22 tiles of 2 x 2 or 2 x 4 rows of 4

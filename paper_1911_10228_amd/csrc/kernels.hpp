@@ -10,6 +10,8 @@ constexpr int kTableKmax = 100;           // table holds |n_i| <= 100 (n.n <= 10
 constexpr int kMacL = 8;                  // target blocks per MAC row (x run, starts even)
 constexpr int kMacSlots = kMacL + 6;      // source x slots per (dy, dz) pair
 constexpr int kMacHalfRows = 32;          // MAC mode bit: tiles of rows of kMacL / 2 targets
+constexpr int kMacLds = 16;               // MAC mode: kernel and source spectra of a frequency chunk in LDS
+constexpr int kMacLdsSrc = 64;            // at most this many source slots per step for kMacLds
 
 // ----------------------------------------------------------------------------- Green function
 // Paper's policy: table for n.n <= 100^2, A_G^3 up to 600^2, A_G^2 beyond.
@@ -63,6 +65,8 @@ template <typename T> struct MacTile {
   uint64_t pair_mask;                  // bit jz*6+jy set if that source row has a source
   int32_t flags;                       // bit0: base level (near field included)
   int32_t row_mask;                    // bit r set if row r has a target
+  int32_t src_lo, src_n;               // the step's source slots lie in [src_lo, src_lo + src_n)
+                                       // (src_n = 0: more than kMacLdsSrc slots; no LDS form)
   const cpx<T>* fhat;                  // source spectra arena (slot * S)
   cpx<T>* uhat;                        // target spectra arena (slot * S)
   const cpx<T>* const* kptr;           // 343 kernel spectra of the tile's level, (dz+3)*49+(dy+3)*7+dx+3

@@ -312,6 +312,123 @@ __global__ __launch_bounds__(256) void mac_shared_kernel(SetTable sets, int S) {
   }
 }
 
+// LDS form (coarse levels with rows of 4 targets whose source slots lie within kMacLdsSrc of
+// each other, i.e. small levels): a workgroup takes one chunk of 16 frequencies and up to 4 tiles
+// (one per wavefront; lane = (row of the tile, frequency)).  It first stages, with every load
+// issued at once, the chunk's 172 kernel values (offsets d >= 0; K_{-d} = conj K_d) and the
+// chunk's values of the step's source spectra (the slots [src_lo, src_lo + src_n), plus one
+// zero entry for absent sources) and the tiles' source slot tables (as LDS entry indices), then
+// walks the source rows from LDS only: one memory round trip per workgroup instead of one per
+// source row, and every kernel spectrum read once per chunk and group of tiles.  Groups of 4
+// tiles of one chunk run on one XCD (they read the same kernel values).
+constexpr int kLdsF = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
+  constexpr int XW = kMacL / 2, NS = XW + 6, F = kLdsF, NSRC = kMacLdsSrc;
+  __shared__ cpx<T> KL[kHalfK * F];               // kernel values, [h][f]
+  __shared__ cpx<T> SL[(NSRC + 1) * F];           // source values, [entry][f]; entry NSRC: zeros
+  __shared__ uint8_t IX[4][36][NS];               // LDS entry of tile w's source row j, slot s
+  const int set = find_set(sets, blockIdx.x);
+  const WorkSet& ws = sets.s[set];
+  const int64_t local = blockIdx.x - ws.wg_begin;      // wg_begin is a multiple of 8
+  const int ngroups = (ws.count + 3) / 4;
+  const int64_t jw = local >> 3;
+  const int chunk = (int)(jw / ngroups) * 8 + (int)(local & 7);
+  const int grp = (int)(jw % ngroups);
+  if (chunk * F >= S) return;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const MacTile<T>* tiles = (const MacTile<T>*)ws.items + 4 * grp;
+  const int ntile = min(4, ws.count - 4 * grp);
+  const int lo = tiles[0].src_lo, n = tiles[0].src_n;
+  const cptr64 kp = (cptr64)tiles[0].kptr;
+  const gptr<T> Fh = (gptr<T>)tiles[0].fhat;
+  // stage: kernel values, source values, slot tables (all loads issued before the first store)
+  constexpr int NK = (kHalfK * F + 255) / 256, NV = ((NSRC + 1) * F + 255) / 256;
+  cpx<T> kv[NK], sv[NV];
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const int i = tid + 256 * j;
+    if (i < kHalfK * F) kv[j] = gload<T>((gptr<T>)kp[i / F], (int64_t)chunk * F + i % F);
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int i = tid + 256 * j, e = i / F;
+    sv[j] = cpx<T>{T(0), T(0)};
+    if (e < n) sv[j] = gload<T>(Fh, (int64_t)(lo + e) * S + (int64_t)chunk * F + i % F);
+  }
+  constexpr int NI = (4 * 36 * NS + 255) / 256;
+  int sl[NI];
+#pragma unroll
+  for (int m = 0; m < NI; ++m) {
+    const int i = tid + 256 * m, w = i / (36 * NS), r = i % (36 * NS);
+    sl[m] = (i < 4 * 36 * NS && w < ntile) ? tiles[w].src[r / NS][r % NS] : lo - 1;
+  }
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const int i = tid + 256 * j;
+    if (i < kHalfK * F) KL[i] = kv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int i = tid + 256 * j;
+    if (i < (NSRC + 1) * F) SL[i] = sv[j];
+  }
+#pragma unroll
+  for (int m = 0; m < NI; ++m) {
+    const int i = tid + 256 * m;
+    const unsigned d = (unsigned)(sl[m] - lo);
+    if (i < 4 * 36 * NS) (&IX[0][0][0])[i] = d < (unsigned)n ? (uint8_t)d : (uint8_t)NSRC;
+  }
+  __syncthreads();
+  if (wave >= ntile) return;
+  const MacTile<T>& tile = tiles[wave];
+  const int f = lane % F, r = lane / F;           // row r of the tile, frequency chunk F + f
+  const bool base = tile.flags & 1;
+  uint64_t todo = tile.pair_mask;
+  cpx<T> acc[XW];
+#pragma unroll
+  for (int i = 0; i < XW; ++i) acc[i] = {T(0), T(0)};
+  while (todo) {
+    const int pj = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int jz = pj / 6, jy = pj % 6;
+    cpx<T> fs[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) fs[q] = SL[IX[wave][pj][q] * F + f];
+    mac_row<T, XW>(acc, fs, r, jz, jy, base, [&](int dxi) {
+      const int h = kindex(r, jz, jy, dxi);
+      const bool mirror = h >= kHalfK;
+      cpx<T> v = KL[(mirror ? 342 - h : h) * F + f];
+      if (mirror) v.y = -v.y;
+      return v;
+    });
+  }
+  if (!((tile.row_mask >> r) & 1)) return;
+  gmut<T> U = (gmut<T>)tile.uhat;
+  const int64_t k = (int64_t)chunk * F + f;
+#pragma unroll
+  for (int i = 0; i < XW; ++i) {
+    const int t = tile.tgt[r][i];
+    if (t >= 0) {
+      U[2 * ((int64_t)t * S + k)] = acc[i].x;
+      U[2 * ((int64_t)t * S + k) + 1] = acc[i].y;
+    }
+  }
+}
+
+template <typename T> hipError_t launch_lds(int S, SetTable& t, hipStream_t st) {
+  if (S % kLdsF) return hipErrorInvalidValue;
+  const int chunks8 = (S / kLdsF + 7) / 8;
+  int64_t wg = 0;
+  for (int i = 0; i < t.n; ++i) {
+    t.s[i].wg_begin = wg;
+    wg += (int64_t)((t.s[i].count + 3) / 4) * chunks8 * 8;
+  }
+  if (wg == 0) return hipSuccess;
+  mac_lds_kernel<T><<<(unsigned)wg, 256, 0, st>>>(t, S);
+  return hipGetLastError();
+}
+
 template <typename T, int XW> hipError_t launch_shared(int S, SetTable& t, hipStream_t st) {
   const int chunks8 = (S / 64 + 7) / 8;
   int64_t wg = 0;
@@ -371,6 +488,7 @@ template <typename T> hipError_t launch_mac(int nb, SetTable& t, hipStream_t st,
   const bool half = mode & kMacHalfRows;
   mode &= kMacHalfRows - 1;
   if (const int o = mac_mode_override()) mode = o;
+  if (mode == kMacLds) return half ? launch_lds<T>(S, t, st) : hipErrorInvalidValue;
   if (half) {
     if constexpr (sizeof(T) == 4) {
       if (mode == 8) return launch_shared<T, 4>(S, t, st);

@@ -12,6 +12,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <limits>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -469,6 +470,7 @@ struct PendingStep {
   int64_t work;
   int mode;
   int chain;
+  bool lds = false;
 };
 
 // ----------------------------------------------------------------------------- item validation
@@ -537,6 +539,15 @@ bool validate_step(const Plan* p, int kind, int ty, int mode, const uint8_t* ite
         if (!rg(it.fhat, (nsrc[t] + 1) * 2 * S * es)) return bad("mac source arena", i);
         if (ntgt[t] && !rg(it.uhat, ntgt[t] * 2 * S * es)) return bad("mac target arena", i);
         if (!rg(it.kptr, 343 * sizeof(void*))) return bad("mac kernel table", i);
+        if ((mode & (kMacHalfRows - 1)) == kMacLds) {      // LDS form: rows of 4, compact slots
+          if (!(mode & kMacHalfRows) || it.src_n < 1 || it.src_n > kMacLdsSrc || it.src_lo < 0 ||
+              it.src_lo + it.src_n > nsrc[t])
+            return bad("mac lds source range", i);
+          for (int j = 0; j < 36; ++j)
+            for (int q = 0; q < kMacSlots; ++q)
+              if (it.src[j][q] != nsrc[t] && (it.src[j][q] < it.src_lo || it.src[j][q] >= it.src_lo + it.src_n))
+                return bad("mac lds source slot", i);
+        }
         break;
       }
       case K_ANTERP: {
@@ -1244,13 +1255,36 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
       p->n_rows += (int64_t)rows[k].size();
       const int half = wsel[k] == kMacL ? 0 : kMacHalfRows;
       // the shared-source form on coarse levels (and FP64 everywhere); FP32 per-block base
-      // levels stage the kernel spectra in LDS
-      const int shape = (ty_of(k) == TY_F64 || k > 0) ? kMacDefault64 : 0;
+      // levels stage the kernel spectra in LDS.  A coarse level of rows of 4 whose source slots
+      // lie within kMacLdsSrc of each other (small levels) takes the LDS form (kernel and source
+      // spectra of a frequency chunk staged once per workgroup).
+      int shape = (ty_of(k) == TY_F64 || k > 0) ? kMacDefault64 : 0;
+      bool lds = false;
+      if (half && k > 0 && !rows[k].empty()) {
+        const int zero = (int)nsrc[ty_of(k)];
+        int lo = std::numeric_limits<int>::max(), hi_s = -1;
+        for (const MacTile<D>& m : rows[k])
+          for (int j = 0; j < 36; ++j)
+            for (int q = 0; q < kMacSlots; ++q)
+              if (m.src[j][q] != zero) {
+                lo = std::min(lo, m.src[j][q]);
+                hi_s = std::max(hi_s, m.src[j][q]);
+              }
+        if (hi_s >= 0 && hi_s - lo < kMacLdsSrc) {
+          for (MacTile<D>& m : rows[k]) {
+            m.src_lo = lo;
+            m.src_n = hi_s - lo + 1;
+          }
+          lds = true;
+          shape = kMacLds;
+        }
+      }
       const size_t primary = steps.size();
       push(steps, l, 4, k, K_MAC, ty_of(k), hi.add(rows[k]), rows[k].size(), nullptr, work[k], half | shape);
+      if (steps.size() > primary) steps.back().lds = lds;
       if (steps.size() > primary && !alt_mac[k].empty()) {
         push(alt_steps, l, 4, k, K_MAC, ty_of(k), hi.add(alt_mac[k]), alt_mac[k].size(), nullptr, work[k],
-             (kMacHalfRows - half) | shape);
+             (kMacHalfRows - half) | (lds ? kMacDefault64 : shape));
         alt_of.push_back(primary);
       }
     }
@@ -1530,7 +1564,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
   }
   auto fin = [&](const std::vector<PendingStep>& in, std::vector<Step>& out) {
     for (const PendingStep& s : in)
-      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (int64_t)s.off, s.count, s.w, s.work, s.mode, s.chain});
+      out.push_back({s.l, s.phase, s.sub, s.kind, s.ty, (int64_t)s.off, s.count, s.w, s.work, s.mode, s.chain, s.lds});
   };
   fin(steps, p->pass);
   fin(rsteps, p->residual);
@@ -1664,7 +1698,7 @@ hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, i
 }
 
 hipError_t plan_set_mac_shape(Plan* p, int shape) {
-  if (shape != 0 && shape != 1 && shape != 2 && shape != 4 && shape != 6 && shape != 8)
+  if (shape != 0 && shape != 1 && shape != 2 && shape != 4 && shape != 6 && shape != 8 && shape != kMacLds)
     return hipErrorInvalidValue;
   if (p->corr) LGF_HIP_CHECK(plan_set_mac_shape(p->corr, shape));
   if (p->mac_mode0.empty())
@@ -1676,7 +1710,7 @@ hipError_t plan_set_mac_shape(Plan* p, int shape) {
     Step& s = p->pass[i];
     if (s.kind != K_MAC) continue;
     if (shape == 0) s.mode = p->mac_mode0[i];
-    else if (has(s.ty, shape)) s.mode = shape | (p->mac_mode0[i] & kMacHalfRows);
+    else if (shape == kMacLds ? s.lds : has(s.ty, shape)) s.mode = shape | (p->mac_mode0[i] & kMacHalfRows);
   }
   if (!p->dry) graph_forget(p);
   return hipSuccess;
@@ -2175,7 +2209,7 @@ hipError_t plan_autotune(Plan* p, Binding* bd, hipStream_t st) {
     for (Step& s : *list) {
       if (s.kind != K_MAC) continue;
       const int half = s.mode & kMacHalfRows;
-      const std::array<int64_t, 3> key{p->nb, s.ty + (half ? 10 : 0), s.count};
+      const std::array<int64_t, 3> key{p->nb, s.ty + (half ? 10 : 0) + (s.lds ? 100 : 0), s.count};
       auto it = g_tune.find(key);
       if (it != g_tune.end()) {
         s.mode = it->second | half;

@@ -61,6 +61,8 @@ struct Step {
   int mode;                            // MAC launch shape chosen by the autotuner (0: default)
   int chain;                           // 0 before the level's fork, 1 base super-block path,
                                        // 2 far field, 3 after the join
+  bool lds = false;                    // MAC step whose tiles take the kMacLds form (rows of 4,
+                                       // source slots within kMacLdsSrc of each other)
 };
 
 // Optional launch timing: when enabled, every launch is bracketed by HIP events on its stream

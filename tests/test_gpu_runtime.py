@@ -79,15 +79,15 @@ def test_autotuned_plan_matches(lgf):
 
 def test_every_mac_shape_matches_oracle(lgf):
     """Every launch shape of the tile MAC, forced on the plan, against the FP64 oracle: FP64
-    coarse levels with rows of 8 (level 1 of 16^3 blocks) and of 4 targets, and the FP32
-    per-block base level."""
+    coarse levels with rows of 8 (level 1 of 16^3 blocks) and of 4 targets (small levels: also the
+    LDS form, shape 16), and the FP32 per-block base level."""
     big = workloads.uniform_mixture(nblk=16, n_b=8, n_gauss=6, seed=23, interp_order=6)
     small = small_cases()[0]
     for L, precision, base, tol in ((big, 0, 0, 1e-12), (small, 0, 0, 1e-12), (small, 1, 1, 1e-6)):
         ref = fmm.flgf(L.blocks, L.f, L.n_b, L.interp_order)
         p = lgf.Plan(L.blocks, L.levels, L.n_b, L.interp_order, precision, 0, base_level=base)
         f = field(L)
-        for shape in (1, 2, 4, 6, 8, 0):
+        for shape in (1, 2, 4, 6, 8, 16, 0):
             print(f"case {len(L.blocks)} blocks precision {precision} base {base} shape {shape}", flush=True)
             p.set_mac_shape(shape)
             u = eager(lgf, p, f)
