@@ -144,31 +144,47 @@ __global__ __launch_bounds__(NB * NB) void anterp_kernel(SetTable sets) {
 #pragma unroll
     for (int zz = 0; zz < SL; ++zz) t1[g][zz][b][a] = zs[g][zz];
   __syncthreads();
+  // y and x passes: a thread's output (a, b) is fixed, so the weight columns w[c][.][b] and
+  // w[c][.][a] it needs are read into registers once
+  {
+    T wy[2][NB];
 #pragma unroll
-  for (int cx = 0; cx < 2; ++cx)                                 // y: sum over cy
+    for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-    for (int zz = 0; zz < SL; ++zz) {
-      T s = 0;
+      for (int Y = 0; Y < NB; ++Y) wy[cy][Y] = w[cy][Y][b];
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        if (!((gmask >> (cx + 2 * cy)) & 1)) continue;
+    for (int cx = 0; cx < 2; ++cx)                               // y: sum over cy
 #pragma unroll
-        for (int Y = 0; Y < NB; ++Y) s += w[cy][Y][b] * t1[cx + 2 * cy][zz][Y][a];
+      for (int zz = 0; zz < SL; ++zz) {
+        T s = 0;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+          if (!((gmask >> (cx + 2 * cy)) & 1)) continue;
+#pragma unroll
+          for (int Y = 0; Y < NB; ++Y) s += wy[cy][Y] * t1[cx + 2 * cy][zz][Y][a];
+        }
+        t2[cx][zz][b][a] = s;
       }
-      t2[cx][zz][b][a] = s;
-    }
+  }
   __syncthreads();
   T acc[SL];
+  {
+    T wx[2][NB];
 #pragma unroll
-  for (int zz = 0; zz < SL; ++zz) {                              // x: sum over cx
-    T s = 0;
+    for (int cx = 0; cx < 2; ++cx)
 #pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-      if (!((gmask >> cx) & 5)) continue;
+      for (int X = 0; X < NB; ++X) wx[cx][X] = w[cx][X][a];
 #pragma unroll
-      for (int X = 0; X < NB; ++X) s += w[cx][X][a] * t2[cx][zz][b][X];
+    for (int zz = 0; zz < SL; ++zz) {                            // x: sum over cx
+      T s = 0;
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        if (!((gmask >> cx) & 5)) continue;
+#pragma unroll
+        for (int X = 0; X < NB; ++X) s += wx[cx][X] * t2[cx][zz][b][X];
+      }
+      acc[zz] = s;
     }
-    acc[zz] = s;
   }
   const gview<TP> dst = gl(it.dst);
 #pragma unroll
