@@ -40,20 +40,22 @@ template <int P, typename T> __device__ __forceinline__ cpx<T> root(int m) {
   return {r[2 * m], r[2 * m + 1]};
 }
 
-// (item, z-plane) of a workgroup.  Plane-major (LM = 0): consecutive workgroups take consecutive
-// planes.  Line-major (LM = 1): every plane of an item runs on one XCD (workgroup w goes to XCD
-// w mod 8; set starts are multiples of 8), so the planes' scattered 8- or 16-byte pieces of
-// each line meet in that XCD's L2 and leave it as whole lines.
-template <int B2, bool LM>
-__device__ __forceinline__ bool plane_of(const WorkSet& ws, int64_t local, int64_t* item, int* z) {
+// (item, first z-plane) of a workgroup that transforms ZP consecutive planes.  Plane-major
+// (LM = 0, ZP = 1): consecutive workgroups take consecutive planes.  Line-major (LM = 1): every
+// plane group of an item runs on one XCD (workgroup w goes to XCD w mod 8; set starts are
+// multiples of 8), so the groups' pieces of each line meet in that XCD's L2 and leave it as
+// whole lines.
+template <int B2, bool LM, int ZP>
+__device__ __forceinline__ bool plane_of(const WorkSet& ws, int64_t local, int64_t* item, int* z0) {
   if constexpr (!LM) {
     *item = local / B2;
-    *z = (int)(local % B2);
+    *z0 = (int)(local % B2);
     return true;
   }
+  constexpr int G = B2 / ZP;
   const int64_t r = local >> 3;
-  *z = (int)(r % B2);
-  *item = (r / B2) * 8 + (local & 7);
+  *z0 = (int)(r % G) * ZP;
+  *item = (r / G) * 8 + (local & 7);
   return *item < ws.count;
 }
 
@@ -77,6 +79,14 @@ __device__ __forceinline__ bool plane_of(const WorkSet& ws, int64_t local, int64
 // inverse, each row swizzled by (row index mod 8): with these strides the accesses of every
 // stage fall on distinct banks (one 2-way case: the mirrored reads of the inverse x stage).
 // FP64: the two buffers share their space (two more barriers, twice the workgroups per CU).
+//
+// Line-major planes hold the B2 z values of a line contiguously, so a workgroup transforms ZP
+// consecutive planes (8 B2 threads and one buffer set per plane) and the stage that touches
+// the planes (the forward's last, the inverse's first) puts the plane index in the low lane
+// bits: one memory instruction then moves ZP contiguous values of each of 64 / ZP lines
+// instead of one value of each of 64 lines.  The per-plane buffers are NPL entries apart with
+// NPL = W / ZP mod W (W entries per 256 bytes, the 64 four-byte banks), so the ZP planes'
+// accesses of that stage take distinct banks as well.
 template <int B2, typename T> struct XyShape {
   static constexpr int P = 2 * B2, Q = P / 8, H = B2 + 1, NB = B2 / 2, NT = 8 * B2;
   static constexpr int RS = 9 * Q;               // exchange row: 8 Q values and Q pads
@@ -84,25 +94,34 @@ template <int B2, typename T> struct XyShape {
   static constexpr bool ALIAS = sizeof(T) == 8;
   static constexpr int NE = B2 * RS, NP = B2 * CS;
   static constexpr int NLDS = ALIAS ? (NE > NP ? NE : NP) : NE + NP;
+  static constexpr int W = 256 / (int)sizeof(cpx<T>);
+  template <int ZP> static constexpr int npl() { return ZP == 1 ? NLDS : (NLDS + W - 1) / W * W + W / ZP; }
   static_assert(P == 8 * Q && (Q == 4 || Q == 8), "line shape");
 };
+// planes per workgroup of the line-major passes (1024 threads; FP64: 148 KB of LDS, one
+// workgroup per CU; two planes per workgroup measured slower in FP64)
+template <int B2, typename T> constexpr int kXyPlanes = 4;
 __device__ __forceinline__ int xat(int m) { return m + (m >> 3); }
 
-template <int B2, typename T, typename TC, bool LM>
-__global__ __launch_bounds__(8 * B2) void sup_fwd_xy(SetTable sets) {
+template <int B2, typename T, typename TC, bool LM, int ZP>
+__global__ __launch_bounds__(8 * B2 * ZP) void sup_fwd_xy(SetTable sets) {
   using X = XyShape<B2, T>;
   constexpr int P = X::P, Q = X::Q, H = X::H, NB = X::NB, RS = X::RS, CS = X::CS;
-  __shared__ cpx<T> lds[X::NLDS];
-  cpx<T>* const E = lds;
-  cpx<T>* const PL = X::ALIAS ? lds : lds + X::NE;
+  constexpr int NPL = X::template npl<ZP>();
+  static_assert(LM || ZP == 1, "plane-major passes take one plane per workgroup");
+  __shared__ cpx<T> lds[ZP * NPL];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;
   int64_t item;
-  int z;
-  if (!plane_of<B2, LM>(ws, local, &item, &z)) return;
+  int z0;
+  if (!plane_of<B2, LM, ZP>(ws, local, &item, &z0)) return;
   const SuperFwdItem<T>& it = ((const SuperFwdItem<T>*)ws.items)[item];
-  const int t = threadIdx.x;
+  // the x stages and the first y stage: plane z0 + threadIdx.x / (8 B2)
+  const int t = threadIdx.x % (8 * B2);
+  const int z = z0 + threadIdx.x / (8 * B2);
+  cpx<T>* const E = lds + (threadIdx.x / (8 * B2)) * NPL;
+  cpx<T>* const PL = X::ALIAS ? E : E + X::NE;
   const int cz = z / NB, lz = z % NB;
   // x stage 1: lane (y, n2), the row's real values x = Q n1 + n2 (x < NB: octant cx = 0)
   if (t < B2 * Q) {
@@ -170,32 +189,34 @@ __global__ __launch_bounds__(8 * B2) void sup_fwd_xy(SetTable sets) {
     }
   }
   __syncthreads();
-  // y stage 2: lane (c, k1), outputs ky = k1 + 8 k2
-  const int c = t >> 3, k1 = t & 7;
+  // y stage 2: lane (c, k1, plane), outputs ky = k1 + 8 k2 of plane z0 + zp
+  const int zp = threadIdx.x % ZP, r = threadIdx.x / ZP;
+  const int c = r >> 3, k1 = r & 7;
+  const cpx<T>* const E2 = lds + zp * NPL;
   T zr[Q], zi[Q];
 #pragma unroll
   for (int n2 = 0; n2 < Q; ++n2) {
-    const cpx<T> v = E[c * RS + xat(8 * n2 + k1)];
+    const cpx<T> v = E2[c * RS + xat(8 * n2 + k1)];
     zr[n2] = v.x;
     zi[n2] = v.y;
   }
   fft_inreg<Q, -1>(zr, zi);
-  cpx<T>* const out = LM ? it.tmp : it.tmp + (int64_t)z * (P * H);
+  cpx<T>* const out = LM ? it.tmp : it.tmp + (int64_t)z0 * (P * H);
   auto put = [&](int ky, int kx, cpx<T> v) {
-    if constexpr (LM) gst(out, (int64_t)(ky * H + kx) * B2 + z, v);
+    if constexpr (LM) gst(out, (int64_t)(ky * H + kx) * B2 + z0 + zp, v);
     else gst(out, ky * H + kx, v);
   };
-  if ((t >> 6) == 0) {
-    // wave 0 holds the packed column (lanes 0..7): A[ky] + i B[ky] with A, B the transforms of
-    // the real columns kx = 0 and B2, so A[ky] = (Z[ky] + conj Z[-ky]) / 2 and
-    // B[ky] = (Z[ky] - conj Z[-ky]) / 2i.  Z[-ky] of ky = k1 + 8 k2 is held by lane 8 - k1
-    // (k2' = Q - 1 - k2), or for k1 = 0 by the lane itself (k2' = (Q - k2) mod Q).
+  if ((threadIdx.x >> 6) == 0) {
+    // wave 0 holds the packed columns (c = 0: lanes below 8 ZP): A[ky] + i B[ky] with A, B the
+    // transforms of the real columns kx = 0 and B2, so A[ky] = (Z[ky] + conj Z[-ky]) / 2 and
+    // B[ky] = (Z[ky] - conj Z[-ky]) / 2i.  Z[-ky] of ky = k1 + 8 k2 is held by the lane of
+    // 8 - k1 (k2' = Q - 1 - k2), or for k1 = 0 by the lane itself (k2' = (Q - k2) mod Q).
     T pr[Q], pi[Q];
-    const int src = (8 - k1) & 7;
+    const int src = ((r & ~7) | ((8 - k1) & 7)) * ZP + zp;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      pr[j] = __shfl(zr[j], src, 8);
-      pi[j] = __shfl(zi[j], src, 8);
+      pr[j] = __shfl(zr[j], src);
+      pi[j] = __shfl(zi[j], src);
     }
     if (c == 0) {
 #pragma unroll
@@ -262,48 +283,57 @@ __global__ __launch_bounds__(256) void sup_inv_z(SetTable sets) {
 // inverse (y, x) pass: one workgroup per (super-block, z-plane) as the forward pass; crop,
 // scale by 1/P^3 and write the children's cells.  LM = 0: plane z from the plane stack;
 // LM = 1: from line-major planes.
-template <int B2, typename T, typename TC, bool LM>
-__global__ __launch_bounds__(8 * B2) void sup_inv_yx(SetTable sets) {
+template <int B2, typename T, typename TC, bool LM, int ZP>
+__global__ __launch_bounds__(8 * B2 * ZP) void sup_inv_yx(SetTable sets) {
   using X = XyShape<B2, T>;
   constexpr int P = X::P, Q = X::Q, H = X::H, NB = X::NB, RS = X::RS, CS = X::CS;
-  __shared__ cpx<T> lds[X::NLDS];
-  cpx<T>* const E = lds;
-  cpx<T>* const PL = X::ALIAS ? lds : lds + X::NE;
+  constexpr int NPL = X::template npl<ZP>();
+  static_assert(LM || ZP == 1, "plane-major passes take one plane per workgroup");
+  __shared__ cpx<T> lds[ZP * NPL];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
   const int64_t local = blockIdx.x - ws.wg_begin;
   int64_t item;
-  int z;
-  if (!plane_of<B2, LM>(ws, local, &item, &z)) return;
+  int z0;
+  if (!plane_of<B2, LM, ZP>(ws, local, &item, &z0)) return;
   const SuperInvItem<T>& it = ((const SuperInvItem<T>*)ws.items)[item];
-  const int t = threadIdx.x;
-  const cpx<T>* const in = LM ? it.tmp : it.tmp + (int64_t)z * (P * H);
-  auto get = [&](int ky, int kx) {
-    if constexpr (LM) return gld(in, (int64_t)(ky * H + kx) * B2 + z);
-    else return gld(in, ky * H + kx);
-  };
-  // y stage 1: lane (c, k2), ky = Q k1 + k2; column 0 carries kx = 0 + i kx = B2
-  if (t < B2 * Q) {
-    const int c = t / Q, k2 = t % Q;
-    T zr[8], zi[8];
+  const cpx<T>* const in = LM ? it.tmp : it.tmp + (int64_t)z0 * (P * H);
+  // y stage 1: lane (c, k2, plane), ky = Q k1 + k2 of plane z0 + zp; column 0 carries
+  // kx = 0 + i kx = B2
+  {
+    const int zp = threadIdx.x % ZP, r = threadIdx.x / ZP;
+    auto get = [&](int ky, int kx) {
+      if constexpr (LM) return gld(in, (int64_t)(ky * H + kx) * B2 + z0 + zp);
+      else return gld(in, ky * H + kx);
+    };
+    if (r < B2 * Q) {
+      const int c = r / Q, k2 = r % Q;
+      cpx<T>* const E1 = lds + zp * NPL;
+      T zr[8], zi[8];
 #pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1) {
-      const int ky = Q * k1 + k2;
-      cpx<T> v = get(ky, c);
-      if (c == 0) {
-        const cpx<T> b = get(ky, B2);
-        v = cpx<T>{v.x - b.y, v.y + b.x};
+      for (int k1 = 0; k1 < 8; ++k1) {
+        const int ky = Q * k1 + k2;
+        cpx<T> v = get(ky, c);
+        if (c == 0) {
+          const cpx<T> b = get(ky, B2);
+          v = cpx<T>{v.x - b.y, v.y + b.x};
+        }
+        zr[k1] = v.x;
+        zi[k1] = v.y;
       }
-      zr[k1] = v.x;
-      zi[k1] = v.y;
-    }
-    fft_inreg<8, +1>(zr, zi);
+      fft_inreg<8, +1>(zr, zi);
 #pragma unroll
-    for (int n1 = 0; n1 < 8; ++n1) {
-      const cpx<T> w = n1 ? root<P, T>(n1 * k2) : cpx<T>{T(1), T(0)};   // conjugated below
-      E[c * RS + xat(8 * k2 + n1)] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
+      for (int n1 = 0; n1 < 8; ++n1) {
+        const cpx<T> w = n1 ? root<P, T>(n1 * k2) : cpx<T>{T(1), T(0)};   // conjugated below
+        E1[c * RS + xat(8 * k2 + n1)] = cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y};
+      }
     }
   }
+  // the remaining stages: plane z0 + threadIdx.x / (8 B2)
+  const int t = threadIdx.x % (8 * B2);
+  const int z = z0 + threadIdx.x / (8 * B2);
+  cpx<T>* const E = lds + (threadIdx.x / (8 * B2)) * NPL;
+  cpx<T>* const PL = X::ALIAS ? E : E + X::NE;
   __syncthreads();
   // y stage 2: lane (c, n1), y = n1 + 8 n2 < B2, to the plane buffer [y][c]
   {
@@ -375,12 +405,13 @@ __global__ __launch_bounds__(8 * B2) void sup_inv_yx(SetTable sets) {
   }
 }
 
-// workgroups of the line-major passes: B2 planes per item, items dealt to the 8 XCDs in turn
-inline int64_t assign_wg_lm(SetTable& t, int B2) {
+// workgroups of the line-major passes: `groups` plane groups per item, items dealt to the 8 XCDs
+// in turn
+inline int64_t assign_wg_lm(SetTable& t, int groups) {
   int64_t wg = 0;
   for (int i = 0; i < t.n; ++i) {
     t.s[i].wg_begin = wg;
-    wg += (t.s[i].count + 7) / 8 * 8 * (int64_t)B2;
+    wg += (t.s[i].count + 7) / 8 * 8 * (int64_t)groups;
   }
   return wg;
 }
@@ -401,14 +432,15 @@ __global__ __launch_bounds__(256) void kernel_columns_kernel(const cpx<T>* spec,
 template <int B2, typename T, typename TC> hipError_t fwd_b2(SetTable& t, hipStream_t st, int mode) {
   using Sh = SupShape<B2>;
   if (mode == 1) {
-    const int64_t wg = assign_wg_lm(t, B2);
+    constexpr int ZP = kXyPlanes<B2, T>;
+    const int64_t wg = assign_wg_lm(t, B2 / ZP);
     if (wg == 0) return hipSuccess;
-    sup_fwd_xy<B2, T, TC, true><<<(unsigned)wg, 8 * B2, 0, st>>>(t);
+    sup_fwd_xy<B2, T, TC, true, ZP><<<(unsigned)wg, 8 * B2 * ZP, 0, st>>>(t);
     return hipGetLastError();
   }
   const int64_t wg1 = assign_wg(t, B2);
   if (wg1 == 0) return hipSuccess;
-  sup_fwd_xy<B2, T, TC, false><<<(unsigned)wg1, 8 * B2, 0, st>>>(t);
+  sup_fwd_xy<B2, T, TC, false, 1><<<(unsigned)wg1, 8 * B2, 0, st>>>(t);
   LGF_HIP_CHECK(hipGetLastError());
   const int64_t wg2 = assign_wg(t, (Sh::PLANE + 255) / 256);
   sup_fwd_z<B2, T><<<(unsigned)wg2, 256, 0, st>>>(t);
@@ -418,9 +450,10 @@ template <int B2, typename T, typename TC> hipError_t fwd_b2(SetTable& t, hipStr
 template <int B2, typename T, typename TC> hipError_t inv_b2(SetTable& t, hipStream_t st, int mode) {
   using Sh = SupShape<B2>;
   if (mode == 1) {
-    const int64_t wg = assign_wg_lm(t, B2);
+    constexpr int ZP = kXyPlanes<B2, T>;
+    const int64_t wg = assign_wg_lm(t, B2 / ZP);
     if (wg == 0) return hipSuccess;
-    sup_inv_yx<B2, T, TC, true><<<(unsigned)wg, 8 * B2, 0, st>>>(t);
+    sup_inv_yx<B2, T, TC, true, ZP><<<(unsigned)wg, 8 * B2 * ZP, 0, st>>>(t);
     return hipGetLastError();
   }
   const int64_t wg1 = assign_wg(t, (Sh::PLANE + 255) / 256);
@@ -428,7 +461,7 @@ template <int B2, typename T, typename TC> hipError_t inv_b2(SetTable& t, hipStr
   sup_inv_z<B2, T><<<(unsigned)wg1, 256, 0, st>>>(t);
   LGF_HIP_CHECK(hipGetLastError());
   const int64_t wg2 = assign_wg(t, B2);
-  sup_inv_yx<B2, T, TC, false><<<(unsigned)wg2, 8 * B2, 0, st>>>(t);
+  sup_inv_yx<B2, T, TC, false, 1><<<(unsigned)wg2, 8 * B2, 0, st>>>(t);
   return hipGetLastError();
 }
 
