@@ -968,6 +968,22 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
       kv[h] = cpx<T>{Kc[o], Kc[o + 1]};
     }
   };
+  // With one line per unit, the 8 lanes of a column (forward steps) and the entries of a target
+  // (its accumulator store and the inverse steps) belong to one wavefront, so between those
+  // steps, and between a unit's inverse steps and the next unit's forward step 1 (which writes
+  // only the wavefront's own target entries and source entries that no other wavefront reads
+  // after the MAC's barrier), LDS needs ordering within the wavefront only; LDS operations of a
+  // wavefront complete in order.  Only the barriers around the MAC (all wavefronts read every
+  // source entry, then the targets overwrite them) order the whole workgroup.
+  auto wave_sync = [&]() {
+    if constexpr (LPW == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  };
   int64_t u = blockIdx.x;
   if (u >= units) return;
   Unit cur = unit_of(u);
@@ -993,7 +1009,7 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
     const uint32_t lv1 = tile->loff[min(lbase + 64 + lane, kTileSrcRowsMax * NS - 1)];
     // the next unit (the last one refetches its own inputs, unused)
     if (u + gridDim.x < units) cur = unit_of(u + gridDim.x);
-    __syncthreads();                             // the previous unit's reads of F are done
+    wave_sync();                                 // this wavefront's reads of its entries are done
     // 1. forward step 1 from the prefetched inputs
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -1011,7 +1027,7 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
       }
     }
     fetch_slots(cur);
-    __syncthreads();
+    wave_sync();
     // 2. forward step 2 in place: item (entry, line, k1)
     for (int i = tid; i < 8 * LPW * nreal; i += NTH) {
       const int e = i / (8 * LPW), r = i % (8 * LPW), ls = r >> 3, k1 = r & 7;
@@ -1085,7 +1101,7 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
     for (int j = 0; j < RPW; ++j)
 #pragma unroll
       for (int x = 0; x < W; ++x) F[((wave * RPW + j) * W + x) * FS + at(lane)] = acc[j][x];
-    __syncthreads();
+    wave_sync();
     // 4. inverse step 1 in place: item (target, line, k2) = this thread; Z[k2][n1] goes to the
     // position Q n1 + k2 of X[Q n1 + k2]
     __builtin_amdgcn_sched_barrier(0);
@@ -1108,7 +1124,7 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
             n1 ? cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y} : cpx<T>{zr[0], zi[0]};
       }
     }
-    __syncthreads();
+    wave_sync();
     // 5. inverse step 2: item (target, line, n1); store z = n1 + 8 n2 < B2
     {
       gmut<T> U = (gmut<T>)tile->uhat;
