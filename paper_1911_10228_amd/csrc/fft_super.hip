@@ -103,6 +103,19 @@ template <int B2, typename T> struct XyShape {
 template <int B2, typename T> constexpr int kXyPlanes = 4;
 __device__ __forceinline__ int xat(int m) { return m + (m >> 3); }
 
+// Between the two x stages a line's values move between the lanes that own the line: with
+// Q = 8 those are lanes 8 y .. 8 y + 7 of one wavefront in both stages, and the wavefront's LDS
+// operations complete in order, so ordering within the wavefront suffices.
+template <int Q> __device__ __forceinline__ void line_sync() {
+  if constexpr (Q == 8) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int B2, typename T, typename TC, bool LM, int ZP>
 __global__ __launch_bounds__(8 * B2 * ZP) void sup_fwd_xy(SetTable sets) {
   using X = XyShape<B2, T>;
@@ -145,7 +158,7 @@ __global__ __launch_bounds__(8 * B2 * ZP) void sup_fwd_xy(SetTable sets) {
       E[y * RS + xat(8 * n2 + k1)] = cpx<T>{Yr[k1] * w.x - Yi[k1] * w.y, Yr[k1] * w.y + Yi[k1] * w.x};
     }
   }
-  __syncthreads();
+  line_sync<Q>();              // the x stages: a line's 8 lanes in one wavefront
   // x stage 2: lane (y, k1); columns kx = k1 + 8 k2 <= B2 to the plane buffer [kx][y]
   {
     const int y = t >> 3, k1 = t & 7;
@@ -382,7 +395,7 @@ __global__ __launch_bounds__(8 * B2 * ZP) void sup_inv_yx(SetTable sets) {
       E[y1 * RS + xat(8 * m2 + n1)] = cpx<T>{Xr[n1] * w.x + Xi[n1] * w.y, Xi[n1] * w.x - Xr[n1] * w.y};
     }
   }
-  __syncthreads();
+  line_sync<Q>();              // the x stages: a line's 8 lanes in one wavefront
   // x stage 2: lane (y, n1), x = n1 + 8 n2 < B2 (real part), scaled, to the children
   const int y = t >> 3, n1 = t & 7;
   T Zr[Q], Zi[Q], xr[Q / 2], xi[Q / 2];
