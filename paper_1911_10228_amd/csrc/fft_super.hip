@@ -85,8 +85,10 @@ __device__ __forceinline__ bool plane_of(const WorkSet& ws, int64_t local, int64
 // the planes (the forward's last, the inverse's first) puts the plane index in the low lane
 // bits: one memory instruction then moves ZP contiguous values of each of 64 / ZP lines
 // instead of one value of each of 64 lines.  The per-plane buffers are NPL entries apart with
-// NPL = W / ZP mod W (W entries per 256 bytes, the 64 four-byte banks), so the ZP planes'
-// accesses of that stage take distinct banks as well.
+// NPL = W / ZP mod W, where W is the number of entries the LDS serves per cycle: 256 bytes for
+// reads (the forward's stage reads the buffers), 128 bytes for writes (the inverse's writes
+// them; the bank-conflict counter shows it), so the ZP planes' accesses of that stage take
+// distinct banks as well.
 template <int B2, typename T> struct XyShape {
   static constexpr int P = 2 * B2, Q = P / 8, H = B2 + 1, NB = B2 / 2, NT = 8 * B2;
   static constexpr int RS = 9 * Q;               // exchange row: 8 Q values and Q pads
@@ -94,8 +96,10 @@ template <int B2, typename T> struct XyShape {
   static constexpr bool ALIAS = sizeof(T) == 8;
   static constexpr int NE = B2 * RS, NP = B2 * CS;
   static constexpr int NLDS = ALIAS ? (NE > NP ? NE : NP) : NE + NP;
-  static constexpr int W = 256 / (int)sizeof(cpx<T>);
-  template <int ZP> static constexpr int npl() { return ZP == 1 ? NLDS : (NLDS + W - 1) / W * W + W / ZP; }
+  template <int ZP, int BYTES> static constexpr int npl() {
+    constexpr int W = BYTES / (int)sizeof(cpx<T>);
+    return ZP == 1 ? NLDS : (NLDS + W - 1) / W * W + W / ZP;
+  }
   static_assert(P == 8 * Q && (Q == 4 || Q == 8), "line shape");
 };
 // planes per workgroup of the line-major passes (1024 threads; FP64: 148 KB of LDS, one
@@ -120,7 +124,7 @@ template <int B2, typename T, typename TC, bool LM, int ZP>
 __global__ __launch_bounds__(8 * B2 * ZP) void sup_fwd_xy(SetTable sets) {
   using X = XyShape<B2, T>;
   constexpr int P = X::P, Q = X::Q, H = X::H, NB = X::NB, RS = X::RS, CS = X::CS;
-  constexpr int NPL = X::template npl<ZP>();
+  constexpr int NPL = X::template npl<ZP, 256>();
   static_assert(LM || ZP == 1, "plane-major passes take one plane per workgroup");
   __shared__ cpx<T> lds[ZP * NPL];
   const int set = find_set(sets, blockIdx.x);
@@ -300,7 +304,7 @@ template <int B2, typename T, typename TC, bool LM, int ZP>
 __global__ __launch_bounds__(8 * B2 * ZP) void sup_inv_yx(SetTable sets) {
   using X = XyShape<B2, T>;
   constexpr int P = X::P, Q = X::Q, H = X::H, NB = X::NB, RS = X::RS, CS = X::CS;
-  constexpr int NPL = X::template npl<ZP>();
+  constexpr int NPL = X::template npl<ZP, 128>();
   static_assert(LM || ZP == 1, "plane-major passes take one plane per workgroup");
   __shared__ cpx<T> lds[ZP * NPL];
   const int set = find_set(sets, blockIdx.x);
