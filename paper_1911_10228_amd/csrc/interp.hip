@@ -56,20 +56,36 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
     w[d][r][m] = T(W[(c[d] * NB + r) * NB + m]);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {       // x
-    const int X = i % NB, yz = i / NB;
-    T s = 0;
+  // x and y passes: a thread's output X (x pass) and Y (y pass) are the same for all its cells
+  // (kOpThreads is a multiple of NB^2), so its weight row is read once; its cells' sums are
+  // unrolled so that their multiply-add chains interleave
+  static_assert(kOpThreads % (NB * NB) == 0, "thread layout");
+  {
+    T wr[NB];
 #pragma unroll
-    for (int x = 0; x < NB; ++x) s += w[0][X][x] * b0[yz * NB + x];
-    b1[i] = s;
+    for (int x = 0; x < NB; ++x) wr[x] = w[0][threadIdx.x % NB][x];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {                               // x
+      const int i = threadIdx.x + j * kOpThreads, yz = i / NB;
+      T s = 0;
+#pragma unroll
+      for (int x = 0; x < NB; ++x) s += wr[x] * b0[yz * NB + x];
+      b1[i] = s;
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N3; i += kOpThreads) {       // y
-    const int X = i % NB, Y = (i / NB) % NB, z = i / (NB * NB);
-    T s = 0;
+  {
+    T wr[NB];
 #pragma unroll
-    for (int y = 0; y < NB; ++y) s += w[1][Y][y] * b1[(z * NB + y) * NB + X];
-    b0[i] = s;
+    for (int y = 0; y < NB; ++y) wr[y] = w[1][(threadIdx.x / NB) % NB][y];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {                               // y
+      const int i = threadIdx.x + j * kOpThreads, X = i % NB, z = i / (NB * NB);
+      T s = 0;
+#pragma unroll
+      for (int y = 0; y < NB; ++y) s += wr[y] * b1[(z * NB + y) * NB + X];
+      b0[i] = s;
+    }
   }
   __syncthreads();
   const gview<TC> child = gl(it.child);
