@@ -102,9 +102,13 @@ template <int B2, typename T> struct XyShape {
   }
   static_assert(P == 8 * Q && (Q == 4 || Q == 8), "line shape");
 };
-// planes per workgroup of the line-major passes (1024 threads; FP64: 148 KB of LDS, one
-// workgroup per CU; two planes per workgroup measured slower in FP64)
-template <int B2, typename T> constexpr int kXyPlanes = 4;
+// planes per workgroup of the line-major passes.  FP32: 4 (1024 threads, 115 KB of LDS).
+// FP64: 2 (512 threads, 74 KB): alone the passes are faster with 4 planes (148 KB, one
+// workgroup per CU: forward 24.5 against 25.7 us, inverse 28.0 against 33.3 us on 64
+// super-blocks of 32^3), but in the solve they share the CUs with the far field's kernels,
+// which fit beside a 74 KB workgroup and not beside a 148 KB one (FP64 solve of the
+// 8^3 x 16^3 workload 0.206 -> 0.202 ms; one plane per workgroup 0.211 ms)
+template <int B2, typename T> constexpr int kXyPlanes = sizeof(T) == 8 ? 2 : 4;
 __device__ __forceinline__ int xat(int m) { return m + (m >> 3); }
 
 // Between the two x stages a line's values move between the lanes that own the line: with
