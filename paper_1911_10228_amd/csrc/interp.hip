@@ -25,13 +25,15 @@ template <int NB> constexpr int per_thread() { return NB * NB * NB / kOpThreads;
 
 
 // child += (Wz (x) Wy (x) Wx) parent for octant c; W is [2 NB][NB] row-major (FP64).
-// Arithmetic in the parent's type TP, stored in the child's type TC.
+// Arithmetic in the parent's type TP, stored in the child's type TC.  The passes work in place
+// on one block-sized LDS array (each thread holds its pass outputs in registers across a
+// barrier): 38 KB in FP64, so that the kernel fits on a CU beside the inverse (y, x) pass of
+// the super-block transforms, with which it shares the GPU at the end of a solve.
 template <int NB, typename TC, typename TP>
 __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
   using T = TP;
   constexpr int N3 = NB * NB * NB;
   __shared__ T b0[N3];
-  __shared__ T b1[N3];
   __shared__ T w[3][NB][NB];
   const int set = find_set(sets, blockIdx.x);
   const WorkSet& ws = sets.s[set];
@@ -64,28 +66,36 @@ __global__ __launch_bounds__(kOpThreads) void interp_kernel(SetTable sets) {
     T wr[NB];
 #pragma unroll
     for (int x = 0; x < NB; ++x) wr[x] = w[0][threadIdx.x % NB][x];
+    T o[PT];
 #pragma unroll
     for (int j = 0; j < PT; ++j) {                               // x
       const int i = threadIdx.x + j * kOpThreads, yz = i / NB;
       T s = 0;
 #pragma unroll
       for (int x = 0; x < NB; ++x) s += wr[x] * b0[yz * NB + x];
-      b1[i] = s;
+      o[j] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PT; ++j) b0[threadIdx.x + j * kOpThreads] = o[j];
   }
   __syncthreads();
   {
     T wr[NB];
 #pragma unroll
     for (int y = 0; y < NB; ++y) wr[y] = w[1][(threadIdx.x / NB) % NB][y];
+    T o[PT];
 #pragma unroll
     for (int j = 0; j < PT; ++j) {                               // y
       const int i = threadIdx.x + j * kOpThreads, X = i % NB, z = i / (NB * NB);
       T s = 0;
 #pragma unroll
-      for (int y = 0; y < NB; ++y) s += wr[y] * b1[(z * NB + y) * NB + X];
-      b0[i] = s;
+      for (int y = 0; y < NB; ++y) s += wr[y] * b0[(z * NB + y) * NB + X];
+      o[j] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PT; ++j) b0[threadIdx.x + j * kOpThreads] = o[j];
   }
   __syncthreads();
   const gview<TC> child = gl(it.child);
