@@ -364,6 +364,10 @@ def main():
                          "writes its results there) instead of exiting at once")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (counter calibration)")
+    ap.add_argument("--timeline", action="store_true",
+                    help="only plan, then replay 8 FP64 plain and 8 FP32 + DC solves as the timed "
+                         "region does (captured graphs, two streams) and exit: a kernel trace of "
+                         "the overlapped solve for a profiler")
     args = ap.parse_args()
     if args.no_graph:
         os.environ["LGF_NO_GRAPH"] = "1"
@@ -398,6 +402,14 @@ def main():
     print(f"# plan: {info32}", file=sys.stderr, flush=True)
 
     stream = torch.cuda.Stream()
+    if args.timeline:
+        for p, u in ((p64, u64), (p32, u32)):
+            for _ in range(8):
+                p.solve(f, u, stream=stream)
+        torch.cuda.synchronize()
+        for p in (p32, p64, p0):
+            p.close()
+        return args
     dt32 = time_solves(p32, f, u32, args.steps, args.warmup, torch, stream)
     print(f"# fp32+dc{args.dc}: {dt32 * 1e3:.3f} ms/solve", file=sys.stderr, flush=True)
     dt64 = time_solves(p64, f, u64, args.steps, args.warmup, torch, stream)
