@@ -890,24 +890,36 @@ __global__ __launch_bounds__(128 * RZ) void near_pipe_kernel(SetTable sets, int 
 // readlane.  Every lane keeps its 8 twiddles W_P^{m k}, m = its position mod Q, for the whole
 // launch: the forward step 1 (m = n2) and the inverse step 1 (m = k2) use the same ones.
 template <typename T, int B2, int RZ, int NC, int RPW>
-__global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable sets, int64_t slot, int64_t units) {
+__global__ __launch_bounds__(128 * RZ / RPW) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && B2 == 32 ? 3 : 1)))
+void near_fused_kernel(SetTable sets, int64_t slot, int64_t units) {
   constexpr int P = 2 * B2, H = B2 + 1, PLANE = P * H, Q = P / 8;
   constexpr int LPW = 64 / P;                    // lines per unit
   constexpr int NGRP = PLANE / LPW;              // line groups
   constexpr int W = kTileW, NS = W + 2, NT = 2 * RZ * W, NTH = 128 * RZ / RPW;
   constexpr int IPT = (8 * NC + NTH - 1) / NTH;  // forward step 1 items per thread
-  // LDS column layout: value m of an entry's 64 at m + m / 8 (one pad per 8), entries 72
-  // apart: the transposes' stride-8 accesses and the MAC's stride-1 accesses then fall on
-  // distinct banks (8- and 16-byte elements alike)
-  constexpr int FS = 72;
-  auto at = [](int m) { return m + (m >> 3); };
+  // LDS column layout.  FP32: value m of an entry's 64 at m + m / 8 (one pad per 8), entries 72
+  // apart.  FP64: at m + m / 16, entries 68 apart, and the twiddles in an LDS table instead of
+  // registers: 53 KB of LDS and at most 168 registers per lane, so three workgroups share a CU
+  // (alone 71 -> 72.5 us on the 8^3 x 16^3 workload, in the solve 0.201-0.203 -> 0.197-0.198 ms:
+  // the third workgroup takes up the CUs that the far field's kernels free)
+  constexpr bool X64 = sizeof(T) == 8;
+  constexpr int FS = X64 ? 68 : 72;
+  auto at = [](int m) { return X64 ? m + (m >> 4) : m + (m >> 3); };
   static_assert(PLANE % LPW == 0 && NGRP % 8 == 0 && LPW * Q == 8 && NT <= NC && NT * 8 <= NTH, "column shape");
   __shared__ cpx<T> F[(NC + 1) * FS];            // source spectra (entry NC: zeros), then target spectra
+  __shared__ cpx<T> TWL[X64 ? 64 : 1];           // FP64 twiddles W_P^{m k} at 8 k + m
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // twiddles W_P^{m k}, k < 8, m = this thread's n2 (forward step 1) = k2 (inverse step 1)
-  cpx<T> tw[8];
-  {
+  cpx<T> tw[X64 ? 1 : 8];
+  if constexpr (X64) {
+    if (tid < 64) {
+      const int m = (tid & 7) % Q, k = tid >> 3;
+      double sn, cs;
+      sincospi(2.0 * ((m * k) % P) / P, &sn, &cs);
+      TWL[tid] = cpx<T>{T(cs), T(-sn)};
+    }
+  } else {
     const int m = (tid & 7) % Q;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -916,7 +928,12 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
       tw[k] = cpx<T>{T(cs), T(-sn)};
     }
   }
+  auto twid = [&](int k) {
+    if constexpr (X64) return TWL[8 * k + (tid & 7) % Q];
+    else return tw[k];
+  };
   if (tid < 64) F[NC * FS + at(tid)] = cpx<T>{T(0), T(0)};
+  if constexpr (X64) __syncthreads();            // the twiddle table is read by every wavefront
   struct Unit {
     const __attribute__((address_space(4))) NearCTile<T>* tile;
     int line0;
@@ -1020,7 +1037,7 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
         fwd_padded<4>(xr[j], xi[j], yr, yi);
 #pragma unroll
         for (int k1 = 0; k1 < 8; ++k1) {
-          const cpx<T> w = tw[k1];                 // W_P^{n2 k1}
+          const cpx<T> w = twid(k1);               // W_P^{n2 k1}
           F[e * FS + at(ls * P + n2 * 8 + k1)] =
               k1 ? cpx<T>{yr[k1] * w.x - yi[k1] * w.y, yr[k1] * w.y + yi[k1] * w.x} : cpx<T>{yr[0], yi[0]};
         }
@@ -1119,7 +1136,7 @@ __global__ __launch_bounds__(128 * RZ / RPW) void near_fused_kernel(SetTable set
       fft_inreg<8, +1>(zr, zi);
 #pragma unroll
       for (int n1 = 0; n1 < 8; ++n1) {
-        const cpx<T> w = tw[n1];                   // W_P^{n1 k2}, conjugated
+        const cpx<T> w = twid(n1);                 // W_P^{n1 k2}, conjugated
         F[jt * FS + at(ls * P + Q * n1 + k2)] =
             n1 ? cpx<T>{zr[n1] * w.x + zi[n1] * w.y, zi[n1] * w.x - zr[n1] * w.y} : cpx<T>{zr[0], zi[0]};
       }
