@@ -63,7 +63,9 @@ template <typename T> struct MacTile {
   int32_t src[36][kMacSlots];          // source slots of source row jz*6+jy, x' = x0 - 3 + s
                                        // (absent sources: the arena's all-zero spectrum)
   uint64_t pair_mask;                  // bit jz*6+jy set if that source row has a source
-  int32_t flags;                       // bit0: base level (near field included)
+  int32_t flags;                       // bit0: base level (near field included); bit1: every
+                                       // source of the tile lies within its rows' x extent
+                                       // (LDS form: x0 .. x0 + 3)
   int32_t row_mask;                    // bit r set if row r has a target
   int32_t src_lo, src_n;               // the step's source slots lie in [src_lo, src_lo + src_n)
                                        // (src_n = 0: more than kMacLdsSrc slots; no LDS form)

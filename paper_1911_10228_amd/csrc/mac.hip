@@ -67,8 +67,11 @@ __device__ __forceinline__ void load_k(cpx<T> (&ks)[ROWS][7], cptr64 kp, int r0,
     for (int dxi = 0; dxi < 7; ++dxi) ks[q][dxi] = kload<T>(kp, kindex(r0 + q, jz, jy, dxi), k);
 }
 
-// accumulate one source row (jz, jy) into target row r (XW targets) with kernel values kv(dxi)
-template <typename T, int XW, typename KF>
+// accumulate one source row (jz, jy) into target row r (XW targets) with kernel values kv(dxi).
+// INNER: the row's sources lie within the targets' x extent (x0 .. x0 + XW - 1), the other
+// window entries being the all-zero spectrum; their products are skipped (and fs[] outside
+// XW + 3 .. 3 need not be set), which leaves every sum's remaining terms in the same order.
+template <typename T, int XW, bool INNER = false, typename KF>
 __device__ __forceinline__ void mac_row(cpx<T> (&acc)[XW], const cpx<T> (&fs)[XW + 6], int r, int jz,
                                         int jy, bool base, KF&& kv) {
   const int ry = r & 1, rz = r >> 1;
@@ -77,12 +80,14 @@ __device__ __forceinline__ void mac_row(cpx<T> (&acc)[XW], const cpx<T> (&fs)[XW
 #pragma unroll
   for (int dxi = 0; dxi < 7; ++dxi) {
     const int dx = dxi - 3;
+    if (INNER && (dx <= -XW || dx >= XW)) continue;
     if (!base && near_zy && dx >= -1 && dx <= 1) continue;
     const cpx<T> kk = kv(dxi);
 #pragma unroll
     for (int i = 0; i < XW; ++i) {
       const int c = i & 1;
       if (dx < c - 3 || dx > c + 2) continue;
+      if (INNER && (i - dx < 0 || i - dx >= XW)) continue;
       cmac(acc[i], kk, fs[i - dx + 3]);
     }
   }
@@ -384,25 +389,31 @@ __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
   const MacTile<T>& tile = tiles[wave];
   const int f = lane % F, r = lane / F;           // row r of the tile, frequency chunk F + f
   const bool base = tile.flags & 1;
-  uint64_t todo = tile.pair_mask;
   cpx<T> acc[XW];
 #pragma unroll
   for (int i = 0; i < XW; ++i) acc[i] = {T(0), T(0)};
-  while (todo) {
-    const int pj = __builtin_ctzll(todo);
-    todo &= todo - 1;
-    const int jz = pj / 6, jy = pj % 6;
-    cpx<T> fs[NS];
+  auto walk = [&](auto inner) {
+    constexpr bool INNER = decltype(inner)::value;
+    uint64_t todo = tile.pair_mask;
+    while (todo) {
+      const int pj = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int jz = pj / 6, jy = pj % 6;
+      cpx<T> fs[NS];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) fs[q] = SL[IX[wave][pj][q] * F + f];
-    mac_row<T, XW>(acc, fs, r, jz, jy, base, [&](int dxi) {
-      const int h = kindex(r, jz, jy, dxi);
-      const bool mirror = h >= kHalfK;
-      cpx<T> v = KL[(mirror ? 342 - h : h) * F + f];
-      if (mirror) v.y = -v.y;
-      return v;
-    });
-  }
+      for (int q = 0; q < NS; ++q)
+        if (!INNER || (q >= 3 && q < 3 + XW)) fs[q] = SL[IX[wave][pj][q] * F + f];
+      mac_row<T, XW, INNER>(acc, fs, r, jz, jy, base, [&](int dxi) {
+        const int h = kindex(r, jz, jy, dxi);
+        const bool mirror = h >= kHalfK;
+        cpx<T> v = KL[(mirror ? 342 - h : h) * F + f];
+        if (mirror) v.y = -v.y;
+        return v;
+      });
+    }
+  };
+  if (tile.flags & 2) walk(std::true_type{});
+  else walk(std::false_type{});
   if (!((tile.row_mask >> r) & 1)) return;
   gmut<T> U = (gmut<T>)tile.uhat;
   const int64_t k = (int64_t)chunk * F + f;

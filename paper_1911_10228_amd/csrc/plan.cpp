@@ -1274,6 +1274,12 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
           for (MacTile<D>& m : rows[k]) {
             m.src_lo = lo;
             m.src_n = hi_s - lo + 1;
+            // rows of kMacL / 2: window slot q holds x0 - 3 + q, the targets x0 .. x0 + 3
+            bool inner = true;
+            for (int j = 0; j < 36; ++j)
+              for (int q = 0; q < kMacL / 2 + 6; ++q)
+                if ((q < 3 || q >= 3 + kMacL / 2) && m.src[j][q] != zero) inner = false;
+            if (inner) m.flags |= 2;
           }
           lds = true;
           shape = kMacLds;
