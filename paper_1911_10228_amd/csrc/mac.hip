@@ -59,6 +59,11 @@ __device__ __forceinline__ cpx<T> kload(cptr64 kp, int h, int k) {
   return v;
 }
 
+// -v where neg, else v, as an exclusive-or of the sign bit (no select)
+__device__ __forceinline__ double flip_sign(double v, bool neg) {
+  return __longlong_as_double(__double_as_longlong(v) ^ ((long long)neg << 63));
+}
+
 template <typename T, int ROWS>
 __device__ __forceinline__ void load_k(cpx<T> (&ks)[ROWS][7], cptr64 kp, int r0, int jz, int jy, int k) {
 #pragma unroll
@@ -320,17 +325,25 @@ __global__ __launch_bounds__(256) void mac_shared_kernel(SetTable sets, int S) {
 // LDS form (coarse levels with rows of 4 targets whose source slots lie within kMacLdsSrc of
 // each other, i.e. small levels): a workgroup takes one chunk of 16 frequencies and up to 4 tiles
 // (one per wavefront; lane = (row of the tile, frequency)).  It first stages, with every load
-// issued at once, the chunk's 172 kernel values (offsets d >= 0; K_{-d} = conj K_d) and the
+// issued at once, the chunk's kernel values (the 172 offsets d <= 0 lexicographically: K_{-d} =
+// conj K_d; in FP64 also d = (0, 0, 1..3) as conjugates of (0, 0, -1..-3)) and the
 // chunk's values of the step's source spectra (the slots [src_lo, src_lo + src_n), plus one
 // zero entry for absent sources) and the tiles' source slot tables (as LDS entry indices), then
 // walks the source rows from LDS only: one memory round trip per workgroup instead of one per
 // source row, and every kernel spectrum read once per chunk and group of tiles.  Groups of 4
-// tiles of one chunk run on one XCD (they read the same kernel values).
+// tiles of one chunk run on one XCD (they read the same kernel values).  With the three extra
+// entries, the 7 offsets along x of one (target row, source row) pair are either all stored or
+// all conjugates of stored ones (d > 0 lexicographically for every dx iff (dz, dy) > 0), so a
+// lane decides that once per source row instead of once per offset (bench level, FP64: 47.2 ->
+// 44.2 us).  FP32 decides per offset: with the extra entries its workgroups ran slower (30.0 ->
+// 31.7-32.5 us; they take it from 31.8 to 32.2 KB of LDS, near the share of five per CU).
 constexpr int kLdsF = 16;
+template <typename T> constexpr int kLdsK = sizeof(T) == 8 ? kHalfK + 3 : kHalfK;
 template <typename T>
 __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
   constexpr int XW = kMacL / 2, NS = XW + 6, F = kLdsF, NSRC = kMacLdsSrc;
-  __shared__ cpx<T> KL[kHalfK * F];               // kernel values, [h][f]
+  constexpr int NKE = kLdsK<T>;
+  __shared__ cpx<T> KL[NKE * F];                  // kernel values, [h][f]
   __shared__ cpx<T> SL[(NSRC + 1) * F];           // source values, [entry][f]; entry NSRC: zeros
   __shared__ uint8_t IX[4][36][NS];               // LDS entry of tile w's source row j, slot s
   const int set = find_set(sets, blockIdx.x);
@@ -348,12 +361,13 @@ __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
   const cptr64 kp = (cptr64)tiles[0].kptr;
   const gptr<T> Fh = (gptr<T>)tiles[0].fhat;
   // stage: kernel values, source values, slot tables (all loads issued before the first store)
-  constexpr int NK = (kHalfK * F + 255) / 256, NV = ((NSRC + 1) * F + 255) / 256;
+  constexpr int NK = (NKE * F + 255) / 256, NV = ((NSRC + 1) * F + 255) / 256;
   cpx<T> kv[NK], sv[NV];
 #pragma unroll
   for (int j = 0; j < NK; ++j) {
     const int i = tid + 256 * j;
-    if (i < kHalfK * F) kv[j] = gload<T>((gptr<T>)kp[i / F], (int64_t)chunk * F + i % F);
+    const int h = i / F;                          // h >= kHalfK: conj K of offset 342 - h
+    if (i < NKE * F) kv[j] = gload<T>((gptr<T>)kp[h < kHalfK ? h : 342 - h], (int64_t)chunk * F + i % F);
   }
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
@@ -371,7 +385,7 @@ __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
 #pragma unroll
   for (int j = 0; j < NK; ++j) {
     const int i = tid + 256 * j;
-    if (i < kHalfK * F) KL[i] = kv[j];
+    if (i < NKE * F) KL[i] = i < kHalfK * F ? kv[j] : cpx<T>{kv[j].x, -kv[j].y};
   }
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
@@ -403,13 +417,25 @@ __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
 #pragma unroll
       for (int q = 0; q < NS; ++q)
         if (!INNER || (q >= 3 && q < 3 + XW)) fs[q] = SL[IX[wave][pj][q] * F + f];
-      mac_row<T, XW, INNER>(acc, fs, r, jz, jy, base, [&](int dxi) {
-        const int h = kindex(r, jz, jy, dxi);
-        const bool mirror = h >= kHalfK;
-        cpx<T> v = KL[(mirror ? 342 - h : h) * F + f];
-        if (mirror) v.y = -v.y;
-        return v;
-      });
+      if constexpr (sizeof(T) == 8) {
+        const int dz = (r >> 1) + 2 - jz, dy = (r & 1) + 2 - jy;
+        const bool conj = dz > 0 || (dz == 0 && dy > 0);
+        const int h0 = kindex(r, jz, jy, 0);
+        const int kb = (conj ? 342 - h0 : h0) * F + f, ks = conj ? -F : F;
+        mac_row<T, XW, INNER>(acc, fs, r, jz, jy, base, [&](int dxi) {
+          cpx<T> v = KL[kb + ks * dxi];
+          v.y = flip_sign(v.y, conj);
+          return v;
+        });
+      } else {
+        mac_row<T, XW, INNER>(acc, fs, r, jz, jy, base, [&](int dxi) {
+          const int h = kindex(r, jz, jy, dxi);
+          const bool mirror = h >= kHalfK;
+          cpx<T> v = KL[(mirror ? 342 - h : h) * F + f];
+          if (mirror) v.y = -v.y;
+          return v;
+        });
+      }
     }
   };
   if (tile.flags & 2) walk(std::true_type{});
