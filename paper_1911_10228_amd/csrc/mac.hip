@@ -409,30 +409,31 @@ __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
   auto walk = [&](auto inner) {
     constexpr bool INNER = decltype(inner)::value;
     auto in_window = [](int q) { return !INNER || (q >= 3 && q < 3 + XW); };
-    if constexpr (sizeof(T) == 8) {
-      // Pipelined: while a row's products run, the next row's source and kernel values and the
-      // slot-table entries of the row after it are in flight (LDS reads complete in issue order,
-      // so each wait leaves the younger reads outstanding).  Past the last row the walk re-reads
-      // that row, so every step issues the same reads.
-      const int n = __builtin_popcountll(tile.pair_mask);
-      uint64_t todo = tile.pair_mask;
-      auto next = [&](int prev) {
-        if (!todo) return prev;
-        const int p = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        return p;
-      };
-      auto read_ix = [&](int pj, uint8_t (&x)[NS]) {
+    // Pipelined: while a row's products run, the next row's source and kernel values and the
+    // slot-table entries of the row after it are in flight (LDS reads complete in issue order,
+    // so each wait leaves the younger reads outstanding).  Past the last row the walk re-reads
+    // that row, so every step issues the same reads.
+    const int n = __builtin_popcountll(tile.pair_mask);
+    uint64_t todo = tile.pair_mask;
+    auto next = [&](int prev) {
+      if (!todo) return prev;
+      const int p = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      return p;
+    };
+    auto read_ix = [&](int pj, uint8_t (&x)[NS]) {
 #pragma unroll
-        for (int q = 0; q < NS; ++q)
-          if (in_window(q)) x[q] = IX[wave][pj][q];
-      };
-      // the row's source values and its 7 kernel values along x (one mirror decision per row)
-      auto read_vals = [&](int pj, const uint8_t (&x)[NS], cpx<T> (&fs)[NS], cpx<T> (&kv)[7]) {
+      for (int q = 0; q < NS; ++q)
+        if (in_window(q)) x[q] = IX[wave][pj][q];
+    };
+    // the row's source values and its 7 kernel values along x (FP64: one mirror decision per
+    // row; FP32: one per offset)
+    auto read_vals = [&](int pj, const uint8_t (&x)[NS], cpx<T> (&fs)[NS], cpx<T> (&kv)[7]) {
 #pragma unroll
-        for (int q = 0; q < NS; ++q)
-          if (in_window(q)) fs[q] = SL[x[q] * F + f];
-        const int jz = pj / 6, jy = pj % 6;
+      for (int q = 0; q < NS; ++q)
+        if (in_window(q)) fs[q] = SL[x[q] * F + f];
+      const int jz = pj / 6, jy = pj % 6;
+      if constexpr (sizeof(T) == 8) {
         const int dz = (r >> 1) + 2 - jz, dy = (r & 1) + 2 - jy;
         const bool conj = dz > 0 || (dz == 0 && dy > 0);
         const int h0 = kindex(r, jz, jy, 0);
@@ -442,46 +443,36 @@ __global__ __launch_bounds__(256) void mac_lds_kernel(SetTable sets, int S) {
           kv[d] = KL[kb + ks * d];
           kv[d].y = flip_sign(kv[d].y, conj);
         }
-      };
-      if (n == 0) return;
-      // two register sets in turn (no copies between iterations)
-      int pa = next(-1), pb = next(pa);
-      uint8_t xa[NS], xb[NS];
-      cpx<T> fa[NS], ka[7], fb[NS], kb[7];
-      read_ix(pa, xa);
-      read_vals(pa, xa, fa, ka);
-      read_ix(pb, xb);
-      for (int i = 0; i < n; i += 2) {
-        const int pc = next(pb);
-        read_vals(pb, xb, fb, kb);
-        read_ix(pc, xa);
-        mac_row<T, XW, INNER>(acc, fa, r, pa / 6, pa % 6, base, [&](int dxi) { return ka[dxi]; });
-        if (i + 1 >= n) break;
-        const int pd = next(pc);
-        read_vals(pc, xa, fa, ka);
-        read_ix(pd, xb);
-        mac_row<T, XW, INNER>(acc, fb, r, pb / 6, pb % 6, base, [&](int dxi) { return kb[dxi]; });
-        pa = pc;
-        pb = pd;
-      }
-    } else {
-      uint64_t todo = tile.pair_mask;
-      while (todo) {
-        const int pj = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        const int jz = pj / 6, jy = pj % 6;
-        cpx<T> fs[NS];
+      } else {
 #pragma unroll
-        for (int q = 0; q < NS; ++q)
-          if (in_window(q)) fs[q] = SL[IX[wave][pj][q] * F + f];
-        mac_row<T, XW, INNER>(acc, fs, r, jz, jy, base, [&](int dxi) {
-          const int h = kindex(r, jz, jy, dxi);
+        for (int d = 0; d < 7; ++d) {
+          const int h = kindex(r, jz, jy, d);
           const bool mirror = h >= kHalfK;
-          cpx<T> v = KL[(mirror ? 342 - h : h) * F + f];
-          if (mirror) v.y = -v.y;
-          return v;
-        });
+          kv[d] = KL[(mirror ? 342 - h : h) * F + f];
+          if (mirror) kv[d].y = -kv[d].y;
+        }
       }
+    };
+    if (n == 0) return;
+    // two register sets in turn (no copies between iterations)
+    int pa = next(-1), pb = next(pa);
+    uint8_t xa[NS], xb[NS];
+    cpx<T> fa[NS], ka[7], fb[NS], kb[7];
+    read_ix(pa, xa);
+    read_vals(pa, xa, fa, ka);
+    read_ix(pb, xb);
+    for (int i = 0; i < n; i += 2) {
+      const int pc = next(pb);
+      read_vals(pb, xb, fb, kb);
+      read_ix(pc, xa);
+      mac_row<T, XW, INNER>(acc, fa, r, pa / 6, pa % 6, base, [&](int dxi) { return ka[dxi]; });
+      if (i + 1 >= n) break;
+      const int pd = next(pc);
+      read_vals(pc, xa, fa, ka);
+      read_ix(pd, xb);
+      mac_row<T, XW, INNER>(acc, fb, r, pb / 6, pb % 6, base, [&](int dxi) { return kb[dxi]; });
+      pa = pc;
+      pb = pd;
     }
   };
   if (tile.flags & 2) walk(std::true_type{});
