@@ -100,6 +100,10 @@ typedef struct {
   int64_t super_inverse;      /* inverse super-block FFTs per solve pass */
   int64_t near_rows;          /* rows of 8 target super-blocks in the base-level MAC */
   int64_t near_pairs;         /* (target, source) super-block pairs in the base-level MAC */
+  int64_t mac_lds_tiles;      /* coarse-level MAC tiles that stage their spectra in LDS */
+  int64_t mac_lds_inner;      /* of those, tiles whose sources all lie within their rows' x
+                                 extent (their products with the window's outer, all-zero
+                                 entries are skipped) */
 } lgf_plan_info;
 
 /* Builds the FP64 LGF table on the current device (Sec. 2: quadrature of eq. GL_B for

@@ -172,6 +172,8 @@ lgf_status lgf_plan_get_info(lgf_plan_t p, lgf_plan_info* out) {
   out->super_inverse = q->n_sup_inv;
   out->near_rows = q->n_near_rows;
   out->near_pairs = q->near_pairs;
+  out->mac_lds_tiles = q->n_lds_tiles;
+  out->mac_lds_inner = q->n_lds_inner;
   return LGF_OK;
 }
 

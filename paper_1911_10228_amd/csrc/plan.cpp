@@ -1280,7 +1280,9 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
               for (int q = 0; q < kMacL / 2 + 6; ++q)
                 if ((q < 3 || q >= 3 + kMacL / 2) && m.src[j][q] != zero) inner = false;
             if (inner) m.flags |= 2;
+            p->n_lds_inner += inner;
           }
+          p->n_lds_tiles += (int64_t)rows[k].size();
           lds = true;
           shape = kMacLds;
         }

@@ -157,6 +157,7 @@ struct Plan {
   // statistics
   int64_t interactions = 0, n_fwd = 0, n_inv = 0, n_rows = 0, n_spectra = 0;
   int64_t n_sup_fwd = 0, n_sup_inv = 0, n_near_rows = 0, near_pairs = 0;
+  int64_t n_lds_tiles = 0, n_lds_inner = 0;   // coarse MAC tiles of the LDS form, inner-window ones
 };
 
 hipError_t plan_build(const int32_t* blocks, const int32_t* levels, int64_t n, int nb, int n_i,

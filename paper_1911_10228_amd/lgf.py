@@ -49,7 +49,8 @@ class PlanInfo(C.Structure):
                 ("fft_forward", C.c_int64), ("fft_inverse", C.c_int64), ("mac_rows", C.c_int64),
                 ("workspace_bytes", C.c_int64), ("spectra", C.c_int64),
                 ("super_forward", C.c_int64), ("super_inverse", C.c_int64),
-                ("near_rows", C.c_int64), ("near_pairs", C.c_int64)]
+                ("near_rows", C.c_int64), ("near_pairs", C.c_int64),
+                ("mac_lds_tiles", C.c_int64), ("mac_lds_inner", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

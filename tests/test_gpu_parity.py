@@ -131,7 +131,9 @@ def test_uniform_multilevel_fp64(lgf, nblk, n_b, order, base_level):
     ref = fmm.flgf(L.blocks, L.f, L.n_b, order)
     assert rel_linf(u, ref) <= 1e-12
     counts = fmm.count_interactions(L.blocks)
-    assert p.info()["interactions"] == sum(a + b for _, a, b in counts)
+    info = p.info()
+    assert info["interactions"] == sum(a + b for _, a, b in counts)
+    assert info["mac_lds_inner"] == info["mac_lds_tiles"]   # inner-window walk (if any LDS tiles)
 
 
 @pytest.mark.parametrize("base_level", [0, 1])
@@ -144,9 +146,11 @@ def test_sparse_negative_ragged_layout_fp64(lgf, base_level):
     f = workloads.gaussian_mixture(pos, [(-10, 5, 0), (20, -30, 10)], [3.0, 2.0], [1.0, -0.5])
     f = f + 0.01 * rng.normal(size=f.shape)
     L = workloads.Layout(blocks, levels, n_b, f, 6)
-    u, _ = gpu_solve(lgf, L, base_level=base_level)
+    u, p = gpu_solve(lgf, L, base_level=base_level)
     ref = fmm.flgf(blocks, f, n_b, 6)
     assert rel_linf(u, ref) <= 1e-12
+    info = p.info()                  # the coarse LDS-form MAC walks its full source window here
+    assert info["mac_lds_tiles"] > 0 and info["mac_lds_inner"] == 0
 
 
 @pytest.mark.parametrize("base_level", [0, 1])

@@ -64,6 +64,19 @@ def test_uniform_layouts_validate_and_count(name, precision, dc, tune):
     assert info["blocks"] == len(L.blocks)
 
 
+def test_coarse_lds_tiles_take_the_inner_window_only_where_sources_allow():
+    """The coarse MAC's LDS form skips the products of a tile's outer window entries only when
+    all of the tile's sources lie within its rows' x extent: on the 8^3 layout (level 1 is one
+    row of 4 wide) every tile does, on the scattered layout none does, so the GPU parity tests
+    of those two layouts run both walks."""
+    L = LAYOUTS["box8x16"]()
+    info = lgf.plan_check(L.blocks, np.zeros(len(L.blocks), np.int32), L.n_b, L.interp_order)
+    assert info["mac_lds_tiles"] == info["mac_lds_inner"] == 4
+    L = LAYOUTS["sparse_neg"]()
+    info = lgf.plan_check(L.blocks, np.zeros(len(L.blocks), np.int32), L.n_b, L.interp_order)
+    assert info["mac_lds_tiles"] > 0 and info["mac_lds_inner"] == 0
+
+
 def multi_layouts():
     out = []
     base = workloads.box_blocks(4, 4, 4)
