@@ -364,6 +364,10 @@ def main():
                          "writes its results there) instead of exiting at once")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (counter calibration)")
+    ap.add_argument("--torus-only", action="store_true",
+                    help="only plan the multi-resolution torus layout (FP64 plain, then FP32 + DC; "
+                         "autotuned) and solve it --steps times with each plan, then exit: a "
+                         "kernel profile of the refined levels")
     ap.add_argument("--timeline", action="store_true",
                     help="only plan, then replay 8 FP64 plain and 8 FP32 + DC solves as the timed "
                          "region does (captured graphs, two streams) and exit: a kernel trace of "
@@ -391,6 +395,19 @@ def main():
     from paper_1911_10228_amd import lgf, workloads
 
     torch.cuda.set_device(0)
+    if args.torus_only:
+        T = workloads.torus()
+        ft = torch.from_numpy(np.ascontiguousarray(T.f)).cuda()
+        ut = torch.zeros_like(ft)
+        st = torch.cuda.Stream()
+        for precision, dc in ((lgf.LGF_FP64_PLAIN, 0), (lgf.LGF_FP32_REFINE, args.dc)):
+            p = lgf.Plan(T.blocks, T.levels, T.n_b, T.interp_order, precision, dc, autotune=1)
+            print(f"# torus plan (precision {precision}, dc {dc}): {p.info()}", file=sys.stderr, flush=True)
+            for _ in range(args.steps):
+                p.solve(ft, ut, stream=st)
+            torch.cuda.synchronize()
+            p.close()
+        return args
     L = workloads.uniform_mixture(nblk=8, n_b=16, n_gauss=16, seed=2, interp_order=8)
     f = torch.from_numpy(np.ascontiguousarray(L.f)).cuda()
     u32, u64, u0 = torch.zeros_like(f), torch.zeros_like(f), torch.zeros_like(f)
