@@ -12,7 +12,7 @@
 // window in registers and reuses them against the 7 kernel offsets along x and its rows.  The next source row's spectra (and,
 // without LDS staging, its kernel spectra) are loaded before the current row's arithmetic, so a
 // single wait per source row covers the memory latency.  In FP32 the kernel spectra of the
-// level are staged in LDS for the workgroup's 64 frequencies; only offsets d >= 0
+// level are staged in LDS for the workgroup's 64 frequencies; only offsets d <= 0
 // (lexicographically) are stored: the kernel is real and even in every coordinate, so
 // K_{-d}[k] = conj(K_d[k]).  All control flow is uniform per wavefront.
 #include <algorithm>
@@ -26,7 +26,7 @@ namespace lgf {
 
 namespace {
 
-constexpr int kHalfK = 172;      // offsets with (dz, dy, dx) >= 0 lexicographically: index <= 171
+constexpr int kHalfK = 172;      // offsets with (dz, dy, dx) <= 0 lexicographically: index <= 171
 
 template <typename T> using gptr = const __attribute__((address_space(1))) T*;
 template <typename T> using gmut = __attribute__((address_space(1))) T*;
@@ -334,8 +334,8 @@ __global__ __launch_bounds__(256) void mac_shared_kernel(SetTable sets, int S) {
 // tiles of one chunk run on one XCD (they read the same kernel values).  With the three extra
 // entries, the 7 offsets along x of one (target row, source row) pair are either all stored or
 // all conjugates of stored ones (d > 0 lexicographically for every dx iff (dz, dy) > 0), so a
-// lane decides that once per source row instead of once per offset (bench level, FP64: 47.2 ->
-// 44.2 us).  FP32 decides per offset: with the extra entries its workgroups ran slower (30.0 ->
+// lane decides that once per source row instead of once per offset (level 1 of the 8^3 layout
+// of 16^3 blocks, FP64: 47.2 -> 44.2 us).  FP32 decides per offset: with the extra entries its workgroups ran slower (30.0 ->
 // 31.7-32.5 us; they take it from 31.8 to 32.2 KB of LDS, near the share of five per CU).
 constexpr int kLdsF = 16;
 template <typename T> constexpr int kLdsK = sizeof(T) == 8 ? kHalfK + 3 : kHalfK;

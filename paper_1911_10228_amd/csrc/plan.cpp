@@ -1357,7 +1357,7 @@ hipError_t build_plan(Plan* p, const std::vector<I3>& coords, const std::vector<
         // compact tiles (only the source super-blocks that exist staged), 2 x 4 rows first.
         // FP64 spectra: the fused form where every tile fits (z transforms, MAC and inverse z
         // transforms per line in one kernel: the spectra never go through HBM; FP64 solve of
-        // the bench workload 0.31 -> 0.27 ms), else rows.  FP32 spectra: the pipelined near MAC
+        // the 8^3 layout of 16^3 blocks 0.31 -> 0.27 ms), else rows.  FP32 spectra: the pipelined near MAC
         // on the same compact tiles (the fused form ties with it there), else the one-chunk
         // tiles.  The autotuner times each candidate with its level's transforms.
         std::vector<NearCTile<D>> ct[2];           // [0]: 2 x 2 rows, [1]: 2 x 4 rows
