@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
 METRIC = "grid points/s per Poisson solve, FP32+refine vs FP64 plain; p50/p99 latency"
-HOST_CORES_MAX = 16          # the GPU machine's CPU share for one GPU
+HOST_CORES_MAX = 16          # host cores available to one GPU's process
 
 
 def measured_traffic(name, source):
