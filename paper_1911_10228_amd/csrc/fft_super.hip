@@ -107,7 +107,8 @@ template <int B2, typename T> struct XyShape {
 // workgroup per CU: forward 24.5 against 25.7 us, inverse 28.0 against 33.3 us on 64
 // super-blocks of 32^3), but in the solve they share the CUs with the far field's kernels,
 // which fit beside a 74 KB workgroup and not beside a 148 KB one (FP64 solve of the
-// 8^3 x 16^3 workload 0.206 -> 0.202 ms; one plane per workgroup 0.211 ms)
+// 8^3 x 16^3 workload 0.206 -> 0.202 ms; one plane per workgroup 0.211 ms; four planes in the
+// inverse only: the pass 32.1 -> 27.4 us alone, the solve 0.191 -> 0.196 ms)
 template <int B2, typename T> constexpr int kXyPlanes = sizeof(T) == 8 ? 2 : 4;
 __device__ __forceinline__ int xat(int m) { return m + (m >> 3); }
 
