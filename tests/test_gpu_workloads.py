@@ -3,15 +3,18 @@
 * uniform 8^3 blocks of 16^3 (2,097,152 unknowns): FP64 against the FP64 oracle (1e-12), FP32
   against the oracle (1e-6) and FP32 + one defect-correction iteration against the oracle's
   defect correction with FP64 inner solves (1e-6);
-* the torus layout (8^3 base blocks of 16^3, two refinement levels): FP32 forms against the FP64
-  GPU solve and its FP64 defect correction (1e-6; the oracle's multi-level solve at this size
-  takes minutes), and second-order convergence of the FP32 + defect-correction solve to the
-  manufactured solution;
+* the torus layout (8^3 base blocks of 16^3, two refinement levels): FP64 and FP32 against the
+  FP64 oracle's solve at sampled cells (tests/golden/torus_oracle_samples.txt; the oracle's
+  multi-level solve at this size takes over a minute on one core), the FP32 forms against the
+  FP64 GPU solve and its FP64 defect correction (1e-6), and second-order convergence of the
+  FP32 + defect-correction solve to the manufactured solution;
 * 64 independent layouts solved in shared launches: equal to each solved alone, and the
   smallest against the oracle;
 * a Poisson-arrival request stream through the server: every result equal to its solve alone,
   and the smallest served layouts against the oracle.
 """
+import importlib.util
+import os
 import time
 
 import numpy as np
@@ -22,6 +25,7 @@ from paper_1911_10228_amd import workloads
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -81,6 +85,49 @@ def test_torus_full_size(lgf):
     r = np.where(mask, L.f - multires.apply_laplace(L.blocks, L.levels, u64, L.n_b), 0.0)
     u1 = u64 + solve(lgf, L, 0, 0, f=r)
     assert rel(solve(lgf, L, 1, 1), u1) <= 1e-6
+
+
+def torus_oracle_samples():
+    """(input digest, max |u| of the oracle's solve, [(block, cell, u)]) from the fixture written
+    by tests/golden/make_torus_samples.py, and that script's input digest function."""
+    spec = importlib.util.spec_from_file_location("make_torus_samples", os.path.join(GOLDEN, "make_torus_samples.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    digest, umax, rows = None, None, []
+    for line in open(os.path.join(GOLDEN, "torus_oracle_samples.txt")):
+        p = line.split()
+        if not p or p[0].startswith("#"):
+            continue
+        if p[0] == "input_sha256":
+            digest = p[1]
+        elif p[0] == "max_abs_u":
+            umax = float(p[1])
+        else:
+            rows.append((int(p[0]), int(p[1]), float(p[2])))
+    return digest, umax, rows, mk.input_digest
+
+
+def test_torus_full_size_matches_oracle_samples(lgf):
+    """The full torus layout against the FP64 oracle's multi-resolution solve (Algorithm 2) at
+    510 sampled cells, 170 per refinement level: FP64 to 1e-12 and FP32 without defect
+    correction to 1e-6 of max |u|."""
+    L = workloads.torus()
+    digest, umax, rows, input_digest = torus_oracle_samples()
+    assert digest == input_digest(L), "torus input changed: rerun tests/golden/make_torus_samples.py"
+    b = np.array([r[0] for r in rows])
+    c = np.array([r[1] for r in rows])
+    ref = np.array([r[2] for r in rows])
+    n3 = L.n_b ** 3
+    print(f"case: {L.name} FP64 against {len(rows)} oracle samples", flush=True)
+    u64 = solve(lgf, L, 0, 0).reshape(len(L.blocks), n3)
+    e64 = np.abs(u64[b, c] - ref).max() / umax
+    print(f"FP64: {e64:.2e} of max |u|", flush=True)
+    assert e64 <= 1e-12
+    print(f"case: {L.name} FP32 against {len(rows)} oracle samples", flush=True)
+    u32 = solve(lgf, L, 1, 0).reshape(len(L.blocks), n3)
+    e32 = np.abs(u32[b, c] - ref).max() / umax
+    print(f"FP32: {e32:.2e} of max |u|", flush=True)
+    assert e32 <= 1e-6
 
 
 def test_torus_second_order_convergence(lgf):
